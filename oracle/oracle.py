@@ -1,0 +1,262 @@
+"""ctypes wrapper of the FP64 CPU oracle (h2oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg use it; the HIP library never does.  It imports nothing from
+the HIP package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "h2oracle.c")
+
+KERNEL_EXP, KERNEL_POLY2 = 0, 1
+STORE_FP64, STORE_FP32, STORE_BF16 = 0, 1, 2
+
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
+                               "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        L.or_cheb_nodes.argtypes = [C.c_int, _f64p]
+        L.or_lagrange_1d.argtypes = [C.c_int, _f64p, C.c_int, C.c_double]
+        L.or_lagrange_1d.restype = C.c_double
+        L.or_kernel.argtypes = [C.c_int, C.c_int, C.c_double, _f64p, _f64p]
+        L.or_kernel.restype = C.c_double
+        L.or_quantize_block.argtypes = [C.c_int, C.c_int64, _f64p]
+        L.or_round_bf16.argtypes = [C.c_double]
+        L.or_round_bf16.restype = C.c_double
+        L.or_build.argtypes = [_f64p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                               C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
+        L.or_build.restype = C.c_int
+        L.or_free.argtypes = [C.c_void_p]
+        L.or_sizes.argtypes = [C.c_void_p, _i64p]
+        L.or_perm.argtypes = [C.c_void_p, _i64p]
+        L.or_ranges.argtypes = [C.c_void_p, _i64p, _i64p]
+        L.or_boxes.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.or_coupling_count.argtypes = [C.c_void_p, C.c_int]
+        L.or_coupling_count.restype = C.c_int64
+        L.or_coupling_bsr.argtypes = [C.c_void_p, C.c_int, _i32p, _i32p]
+        L.or_dense_count.argtypes = [C.c_void_p]
+        L.or_dense_count.restype = C.c_int64
+        L.or_dense_bsr.argtypes = [C.c_void_p, _i32p, _i32p]
+        L.or_near_ties.argtypes = [C.c_void_p]
+        L.or_near_ties.restype = C.c_int64
+        L.or_flat_tree.argtypes = [C.c_void_p, _i64p, _i64p, _i64p, _i64p]
+        L.or_bsr_assemble.argtypes = [C.c_int32, C.c_int64, _i32p, _i32p, _i32p, _i32p, _i64p]
+        L.or_leaf_basis.argtypes = [C.c_void_p, C.c_int64, _f64p]
+        L.or_transfer.argtypes = [C.c_void_p, C.c_int64, _f64p]
+        L.or_coupling_block.argtypes = [C.c_void_p, C.c_int, C.c_int64, _f64p]
+        L.or_dense_block.argtypes = [C.c_void_p, C.c_int64, _f64p]
+        L.or_explicit_basis.argtypes = [C.c_void_p, C.c_int64, C.c_int, _f64p]
+        L.or_matvec.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.or_matvec_leaves.argtypes = [C.c_void_p, _f64p, C.c_int64, _i64p, _f64p]
+        L.or_matvec_parts.argtypes = [C.c_void_p, _f64p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_dense_expand.argtypes = [C.c_void_p, _f64p]
+        L.or_kernel_matvec.argtypes = [_f64p, C.c_int64, C.c_int, C.c_double, C.c_int, _f64p,
+                                       C.c_int64, _i64p, _f64p]
+        _lib = L
+    return _lib
+
+
+def cheb_nodes(p: int) -> np.ndarray:
+    t = np.zeros(p)
+    lib().or_cheb_nodes(p, t)
+    return t
+
+
+def lagrange_1d(t: np.ndarray, a: int, s: float) -> float:
+    return lib().or_lagrange_1d(len(t), np.ascontiguousarray(t, dtype=np.float64), a, s)
+
+
+def quantize(storage: int, vals: np.ndarray) -> np.ndarray:
+    v = np.array(vals, dtype=np.float64, copy=True).ravel()
+    lib().or_quantize_block(storage, v.size, v)
+    return v.reshape(np.shape(vals))
+
+
+def kernel_matvec(pts, x, ell, rows=None, kernel=KERNEL_EXP) -> np.ndarray:
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    n, d = pts.shape
+    rows = np.arange(n, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    y = np.zeros(len(rows))
+    lib().or_kernel_matvec(pts, n, d, ell, kernel, np.ascontiguousarray(x, dtype=np.float64),
+                           len(rows), rows, y)
+    return y
+
+
+class OracleH2:
+    """An H^2 matrix built by the oracle from points; see h2oracle.h."""
+
+    def __init__(self, pts, leaf, cheb_p, eta, corr_len, kernel=KERNEL_EXP,
+                 storage=STORE_FP64, keep_blocks=True):
+        pts = np.ascontiguousarray(pts, dtype=np.float64)
+        n, d = pts.shape
+        h = C.c_void_p()
+        rc = lib().or_build(pts, n, d, leaf, cheb_p, eta, corr_len, kernel, storage,
+                            1 if keep_blocks else 0, C.byref(h))
+        if rc != 0:
+            raise ValueError(f"oracle build rejected its arguments (rc={rc})")
+        self._h = h
+        s = np.zeros(9, dtype=np.int64)
+        lib().or_sizes(h, s)
+        (self.n, self.d, self.m, self.p, self.k, self.q, self.lmin, self.nnodes,
+         self.n_coupling) = (int(v) for v in s)
+        self.eta, self.corr_len, self.storage = eta, corr_len, storage
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.or_free(h)
+            self._h = None
+
+    # structure
+    def perm(self):
+        p = np.zeros(self.n, dtype=np.int64)
+        lib().or_perm(self._h, p)
+        return p
+
+    def ranges(self):
+        b = np.zeros(self.nnodes, dtype=np.int64)
+        e = np.zeros(self.nnodes, dtype=np.int64)
+        lib().or_ranges(self._h, b, e)
+        return b, e
+
+    def boxes(self):
+        lo = np.zeros((self.nnodes, self.d))
+        hi = np.zeros((self.nnodes, self.d))
+        lib().or_boxes(self._h, lo, hi)
+        return lo, hi
+
+    def coupling_bsr(self, level):
+        cnt = lib().or_coupling_count(self._h, level)
+        rp = np.zeros((1 << level) + 1, dtype=np.int32)
+        ci = np.zeros(max(cnt, 1), dtype=np.int32)
+        lib().or_coupling_bsr(self._h, level, rp, ci)
+        return rp, ci[:cnt]
+
+    def dense_bsr(self):
+        cnt = lib().or_dense_count(self._h)
+        rp = np.zeros((1 << self.q) + 1, dtype=np.int32)
+        ci = np.zeros(max(cnt, 1), dtype=np.int32)
+        lib().or_dense_bsr(self._h, rp, ci)
+        return rp, ci[:cnt]
+
+    def near_ties(self):
+        return int(lib().or_near_ties(self._h))
+
+    def flat_tree(self):
+        lp = np.zeros(self.q + 2, dtype=np.int64)
+        par = np.zeros(self.nnodes, dtype=np.int64)
+        head = np.zeros(self.nnodes, dtype=np.int64)
+        nxt = np.zeros(self.nnodes, dtype=np.int64)
+        lib().or_flat_tree(self._h, lp, par, head, nxt)
+        return lp, par, head, nxt
+
+    def leaf_nodes(self):
+        f = (1 << self.q) - 1
+        return np.arange(f, f + (1 << self.q), dtype=np.int64)
+
+    # data
+    def node_size(self, v):
+        b, e = self.ranges()
+        return int(e[v] - b[v])
+
+    def leaf_basis(self, node):
+        U = np.zeros(self.node_size(node) * self.k)
+        lib().or_leaf_basis(self._h, node, U)
+        return U.reshape(self.k, -1).T          # column-major m_i x k
+
+    def transfer(self, node):
+        E = np.zeros(self.k * self.k)
+        lib().or_transfer(self._h, node, E)
+        return E.reshape(self.k, self.k).T
+
+    def coupling_block(self, level, idx):
+        S = np.zeros(self.k * self.k)
+        lib().or_coupling_block(self._h, level, idx, S)
+        return S.reshape(self.k, self.k).T
+
+    def dense_block(self, idx, rows, cols):
+        D = np.zeros(rows * cols)
+        lib().or_dense_block(self._h, idx, D)
+        return D.reshape(cols, rows).T
+
+    def explicit_basis(self, node, method):
+        U = np.zeros(self.node_size(node) * self.k)
+        lib().or_explicit_basis(self._h, node, method, U)
+        return U.reshape(self.k, -1).T
+
+    # products (tree order)
+    def matvec(self, x_tree):
+        y = np.zeros(self.n)
+        lib().or_matvec(self._h, np.ascontiguousarray(x_tree, dtype=np.float64), y)
+        return y
+
+    def matvec_parts(self, x_tree):
+        xh = np.zeros((self.nnodes, self.k))
+        yh = np.zeros((self.nnodes, self.k))
+        yn = np.zeros(self.n)
+        yf = np.zeros(self.n)
+        lib().or_matvec_parts(self._h, np.ascontiguousarray(x_tree, dtype=np.float64),
+                              xh.ctypes.data, yh.ctypes.data, yn.ctypes.data, yf.ctypes.data)
+        return xh, yh, yn, yf
+
+    def matvec_leaves(self, x_tree, leaves):
+        leaves = np.ascontiguousarray(leaves, dtype=np.int64)
+        b, e = self.ranges()
+        y = np.zeros(int(np.sum(e[leaves] - b[leaves])))
+        lib().or_matvec_leaves(self._h, np.ascontiguousarray(x_tree, dtype=np.float64),
+                               len(leaves), leaves, y)
+        return y
+
+    def leaf_rows(self, leaves):
+        """Tree positions of the rows of the listed leaves, in matvec_leaves order."""
+        b, e = self.ranges()
+        return np.concatenate([np.arange(b[v], e[v]) for v in leaves]).astype(np.int64)
+
+    def dense_expand(self):
+        A = np.zeros((self.n, self.n))
+        lib().or_dense_expand(self._h, A)
+        return A
+
+
+def bsr_assemble(nrows, rows, cols):
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    rp = np.zeros(nrows + 1, dtype=np.int32)
+    ci = np.zeros(max(len(rows), 1), dtype=np.int32)
+    order = np.zeros(max(len(rows), 1), dtype=np.int64)
+    lib().or_bsr_assemble(nrows, len(rows), rows, cols, rp, ci, order)
+    return rp, ci[:len(rows)], order[:len(rows)]
+
+
+def rel_err(y, ref) -> float:
+    """Relative 2-norm error |y - ref| / |ref| (the error measure of Sec. 4.6)."""
+    ref = np.asarray(ref)
+    return float(np.linalg.norm(np.asarray(y) - ref) / np.linalg.norm(ref))
