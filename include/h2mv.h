@@ -1,0 +1,156 @@
+/*
+ * h2mv.h -- C ABI of an MI355X (gfx950) library for the H^2 hierarchical
+ * matrix-vector product of Boukaram, Turkiyyah and Keyes, "Hierarchical Matrix
+ * Operations on GPUs: Matrix-Vector Multiplication and Compression"
+ * (arXiv:1902.01829).
+ *
+ * The matrix A ~ K(P, P) is the covariance of n points P under the isotropic
+ * exponential kernel K(a, b) = exp(-|a - b| / corr_len) (Sec. 4.6).  It is held
+ * as an H^2 matrix (Sec. 2.2): a binary cluster tree, explicit leaf bases U = V
+ * and transfer matrices E = F (Eq. (1)), a matrix tree of k x k coupling blocks
+ * S stored per level as block-sparse rows (Sec. 4.3, Fig. 5), and dense m x m
+ * near-field blocks D at the finest level.  The product y = A x is computed as
+ * leaf projection and upsweep (Sec. 4.2), tree multiplication (Sec. 4.3),
+ * downsweep and leaf expansion (Sec. 4.4), plus the dense part, all added in
+ * FP64 at the end (Sec. 4.1, Sec. 4.5).
+ *
+ * Conventions
+ *  - Ordering.  Vectors are in cluster-tree order: x_tree[i] = x_input[perm[i]],
+ *    with perm from h2_get_perm.
+ *  - Pointers.  "host" pointers are read or written before the call returns;
+ *    "device" pointers are HIP device memory owned by the caller.  Input host
+ *    arrays are copied; the handle owns all device memory it allocates (the
+ *    representation and its workspace) until h2_free.
+ *  - Streams.  Every device operation is enqueued on the given hipStream_t
+ *    (NULL = default stream) and is asynchronous.  A handle's workspace is shared
+ *    by its calls: do not run two calls on one handle concurrently.
+ *  - Errors.  Every call returns an h2_status; no C++ exception crosses the ABI.
+ *    On error *out is set to NULL, nothing is leaked, outputs are untouched,
+ *    and h2_last_error() describes the failure (thread-local text).
+ *  - Limits.  rank k = cheb_p^dim <= 64 and leaf_size <= 64, else
+ *    H2_ERR_UNSUPPORTED; n < 2^31.
+ */
+#ifndef H2MV_H
+#define H2MV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct h2_matrix_ *h2_handle;
+
+typedef enum {
+    H2_OK = 0,
+    H2_ERR_INVALID_ARG = 1,   /* a bad size, pointer, parameter or NaN input          */
+    H2_ERR_OOM = 2,           /* device allocation failed (or exceeded a set cap)     */
+    H2_ERR_DEVICE = 3,        /* a HIP runtime error; text in h2_last_error()         */
+    H2_ERR_UNSUPPORTED = 4,   /* rank or leaf size beyond the compiled limit (64)     */
+    H2_ERR_INTERNAL = 5       /* any other failure                                    */
+} h2_status;
+
+/* Storage of the coupling blocks S and dense blocks D (an extension of the
+ * paper, which stores all blocks in the working precision).  H2_FP64: all in
+ * FP64, FP64 arithmetic.  H2_FP32: S, D and the bases in FP32, FP32 products.
+ * H2_BF16_SCALED: S and D in BF16 with one FP32 scale per block (the block's
+ * max-abs), bases in FP32, FP32 products.  In the reduced modes, partial sums
+ * of one block are FP32, sums over blocks are FP64, and the near and far
+ * fields are added in FP64. */
+typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16_SCALED = 2 } h2_storage;
+
+/* flags */
+#define H2_FLAG_STRUCTURE_ONLY 1u   /* build the host-side structure only: no device
+                                       memory, matvec/matmat then return INVALID_ARG */
+
+/* Construction parameters (Sec. 4.6): dim in {2,3}; leaf_size m >= 2 (the tree
+ * is bisected until every leaf holds at most m points); cheb_p >= 1 Chebyshev
+ * points per axis (rank k = cheb_p^dim); eta > 0, a pair of clusters (s, t) is
+ * admissible when max(diam s, diam t) <= eta * dist(s, t) over their tight
+ * boxes; corr_len > 0. */
+typedef struct {
+    int dim;
+    int leaf_size;
+    int cheb_p;
+    double eta;
+    double corr_len;
+    int storage;          /* h2_storage */
+    unsigned flags;
+} h2_params;
+
+/* Sizes of a built matrix.  bytes_* are the bytes one product streams from
+ * HBM for that part of the representation (for bandwidth figures). */
+typedef struct {
+    int64_t n;
+    int dim, leaf_size, cheb_p, rank, levels_q, lmin, storage;
+    int64_t nnodes;            /* 2^(q+1) - 1                                      */
+    int64_t coupling_blocks;   /* all levels                                       */
+    int64_t dense_blocks;
+    int64_t bytes_coupling, bytes_dense, bytes_leaf_bases, bytes_transfers;
+    int64_t bytes_device_total; /* all device memory held by the handle           */
+    int64_t near_ties;         /* admissibility tests within 1e-12 of equality     */
+} h2_info;
+
+/* Build an H^2 matrix from points (Sec. 4.6).
+ *  points  host, n x dim, row-major, input order; finite values.
+ *  n       1 <= n < 2^31.
+ *  prm     host; see h2_params.
+ *  stream  hipStream_t for the uploads and the fill kernels.
+ *  out     host; receives the handle (NULL on error).
+ * The call returns after the device representation is complete.
+ * Errors: INVALID_ARG for n < 1, dim not in {2,3}, leaf_size < 2, cheb_p < 1,
+ * eta <= 0 or NaN, corr_len <= 0 or NaN, storage out of range, non-finite
+ * coordinates or NULL pointers; UNSUPPORTED for rank or leaf_size > 64; OOM;
+ * DEVICE. */
+h2_status h2_build_from_points(const double *points, int64_t n, const h2_params *prm,
+                               void *stream, h2_handle *out);
+
+/* y = A x (Sec. 4, Fig. 4).
+ *  x  device, n doubles, tree order.   y  device, n doubles, tree order.
+ * x and y must not overlap.  Errors: INVALID_ARG for NULL pointers or a
+ * structure-only handle; DEVICE. */
+h2_status h2_matvec(h2_handle A, const double *x, double *y, void *stream);
+
+/* Y = A X for nrhs right-hand sides at once: the same phases with every
+ * per-node vector replaced by a k x nrhs tile, so each block product becomes a
+ * dense contraction.
+ *  X  device, column-major n x nrhs, leading dimension ldx >= n, tree order.
+ *  Y  device, column-major n x nrhs, leading dimension ldy >= n.
+ * Errors: INVALID_ARG for nrhs < 1, ldx < n, ldy < n, NULL pointers or a
+ * structure-only handle; DEVICE. */
+h2_status h2_matmat(h2_handle A, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                    int nrhs, void *stream);
+
+/* Release every device and host resource of A.  NULL is a no-op.  The caller
+ * must make sure no enqueued work on A is still running. */
+void h2_free(h2_handle A);
+
+/* Sizes and byte counts of A (host struct). */
+h2_status h2_get_info(h2_handle A, h2_info *info);
+
+/* perm: host, n int64 (tree position -> input index). */
+h2_status h2_get_perm(h2_handle A, int64_t *perm);
+
+/* Block-sparse-row structure of one level of the matrix tree (Sec. 4.3,
+ * Fig. 5), 0-based: rowptr host (2^level + 1 values), colidx host (count
+ * values); level = -1 gives the dense near-field blocks (rows = leaves).
+ * count (host) receives the number of blocks; rowptr/colidx may be NULL to
+ * query the count only. */
+h2_status h2_get_level_bsr(h2_handle A, int level, int64_t *count, int32_t *rowptr,
+                           int32_t *colidx);
+
+/* Per-phase device times of the products on A, measured with HIP events on
+ * the call's stream while enabled (enable != 0 starts recording and clears the
+ * totals).  ms: host, 8 doubles: leaf projection + upsweep, coupling and dense
+ * streaming, downsweep, leaf expansion and sum, whole call; then calls: host
+ * int64 number of calls recorded.  Reading the totals synchronizes the device. */
+h2_status h2_profile(h2_handle A, int enable);
+h2_status h2_profile_read(h2_handle A, double *ms, int64_t *calls);
+
+/* Text of the last failure on this thread ("" if none). */
+const char *h2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

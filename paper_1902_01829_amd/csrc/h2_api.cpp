@@ -1,0 +1,554 @@
+// C ABI of libh2mv (include/h2mv.h): builds the H^2 representation on the
+// device from points and runs the product y = A x as a fixed sequence of
+// block-row launches over work lists built once at construction (the paper's
+// per-call marshaling of pointer batches, Sec. 3.2, becomes static lists).
+#include "h2mv.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "h2_device.h"
+#include "h2_structure.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Failure {
+    h2_status code;
+    std::string what;
+};
+
+[[noreturn]] void fail(h2_status code, const std::string &what) { throw Failure{code, what}; }
+
+void check_hip(hipError_t e, const char *where) {
+    if (e != hipSuccess) fail(H2_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Device allocations of one owner; a test-only cap (environment variable
+// H2MV_DEVICE_BYTE_CAP, bytes) turns any allocation past it into H2_ERR_OOM.
+struct DeviceArena {
+    std::vector<void *> ptrs;
+    int64_t bytes = 0;
+    int64_t cap = -1;
+
+    DeviceArena() {
+        if (const char *c = std::getenv("H2MV_DEVICE_BYTE_CAP")) cap = std::atoll(c);
+    }
+    DeviceArena(const DeviceArena &) = delete;
+    DeviceArena &operator=(const DeviceArena &) = delete;
+    ~DeviceArena() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    void *alloc(int64_t nbytes) {
+        if (nbytes <= 0) nbytes = 16;
+        nbytes = (nbytes + 255) / 256 * 256;
+        if (cap >= 0 && bytes + nbytes > cap) fail(H2_ERR_OOM, "device byte cap exceeded");
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, size_t(nbytes));
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+            (void)hipGetLastError();
+            fail(H2_ERR_OOM, "hipMalloc of " + std::to_string(nbytes) + " bytes failed");
+        }
+        check_hip(e, "hipMalloc");
+        ptrs.push_back(p);
+        bytes += nbytes;
+        return p;
+    }
+    template <typename T>
+    T *upload(const std::vector<T> &v, hipStream_t st) {
+        T *d = static_cast<T *>(alloc(int64_t(v.size() * sizeof(T))));
+        if (!v.empty())
+            check_hip(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st),
+                      "hipMemcpyAsync");
+        return d;
+    }
+};
+
+enum Phase { PH_UP = 0, PH_STREAM = 1, PH_DOWN = 2, PH_LEAF = 3, PH_COUNT = 4 };
+
+struct WorkList {
+    Phase phase;
+    int kind;   // element kind of its data
+    const void *data;
+    const h2::RowDesc *rows;
+    int64_t nrows;
+    const h2::BlkDesc *blks;
+};
+
+}  // namespace
+
+struct h2_matrix_ {
+    h2::Structure st;
+    int storage = H2_FP64;
+    bool structure_only = false;
+    int basis_kind = h2::ELEM_F64, block_kind = h2::ELEM_F64;
+    bool vec_f64 = true;
+    DeviceArena mem;
+    void *basis = nullptr, *blocks = nullptr;
+    float *scales = nullptr;
+    void *xh = nullptr, *yh = nullptr, *ynear = nullptr;
+    std::vector<WorkList> lists;
+    int64_t bytes_coupling = 0, bytes_dense = 0, bytes_leaf = 0, bytes_transfer = 0;
+    // profiling: PH_COUNT + 1 events per recorded call
+    bool prof = false;
+    std::vector<hipEvent_t> pending, spare;
+    double prof_ms[8] = {0};
+    int64_t prof_calls = 0;
+
+    ~h2_matrix_() {
+        for (hipEvent_t e : pending) (void)hipEventDestroy(e);
+        for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+using h2::BlkDesc;
+using h2::RowDesc;
+using h2::Structure;
+
+// Layout of the representation, generation on the device, and the work lists
+// of one product in launch order.
+void build_device(h2_matrix_ &A, hipStream_t stream) {
+    const Structure &s = A.st;
+    const int k = s.rank, q = s.q;
+    const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
+    const bool lowrank = s.lmin <= q;
+    const int bk = A.basis_kind, sk = A.block_kind;
+
+    // basis region: U_j, V_j^T per leaf; E_c, F_c^T per node of levels lmin+1..q
+    std::vector<int64_t> leaf_node(nleaves), off_U(nleaves), off_VT(nleaves);
+    std::vector<int64_t> off_E(s.nnodes, -1), off_FT(s.nnodes, -1);
+    int64_t nb = 0;
+    for (int64_t j = 0; j < nleaves; ++j) {
+        const int m = int(s.size(lf + j));
+        leaf_node[j] = lf + j;
+        off_U[j] = nb;
+        nb += h2::block_elems(m, k, bk);
+        off_VT[j] = nb;
+        nb += h2::block_elems(k, m, bk);
+    }
+    const int64_t leaf_elems = nb;
+    if (lowrank)
+        for (int l = s.lmin + 1; l <= q; ++l)
+            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
+                off_E[c] = nb;
+                nb += h2::block_elems(k, k, bk);
+                off_FT[c] = nb;
+                nb += h2::block_elems(k, k, bk);
+            }
+    const int64_t eb = h2::elem_bytes(bk), sb = h2::elem_bytes(sk);
+    A.bytes_leaf = lowrank ? leaf_elems * eb : 0;
+    A.bytes_transfer = (nb - leaf_elems) * eb;
+
+    // block region: coupling blocks level by level in BSR order, then dense blocks
+    std::vector<h2::FillDesc> fill;
+    int64_t ns = 0;
+    for (int l = 0; l <= q; ++l) {
+        const h2::Bsr &B = s.coupling[l];
+        const int64_t f = Structure::first(l);
+        for (int64_t i = 0; i < (int64_t(1) << l); ++i)
+            for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b) {
+                fill.push_back({ns, int32_t(f + i), int32_t(f + B.colidx[b]), int32_t(fill.size()),
+                                h2::FILL_COUPLING});
+                ns += h2::block_elems(k, k, sk);
+            }
+    }
+    const int64_t coupling_elems = ns, ncoupling = int64_t(fill.size());
+    for (int64_t i = 0; i < nleaves; ++i)
+        for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b) {
+            const int64_t t = lf + s.dense.colidx[b];
+            fill.push_back({ns, int32_t(lf + i), int32_t(t), int32_t(fill.size()), h2::FILL_DENSE});
+            ns += h2::block_elems(int(s.size(lf + i)), int(s.size(t)), sk);
+        }
+    const int64_t scale_bytes = sk == h2::ELEM_BF16 ? 4 : 0;
+    A.bytes_coupling = coupling_elems * sb + scale_bytes * ncoupling;
+    A.bytes_dense = (ns - coupling_elems) * sb + scale_bytes * (int64_t(fill.size()) - ncoupling);
+
+    // generation of the representation on the device
+    std::vector<double> cheb(s.cheb_p);
+    for (int a = 0; a < s.cheb_p; ++a) cheb[a] = std::cos((2.0 * a + 1.0) * M_PI / (2.0 * s.cheb_p));
+    A.basis = A.mem.alloc(nb * eb);
+    A.blocks = A.mem.alloc(ns * sb);
+    A.scales = static_cast<float *>(A.mem.alloc(std::max<int64_t>(1, int64_t(fill.size())) * 4));
+    {
+        DeviceArena scratch;   // geometry and fill lists, freed after the build
+        if (A.mem.cap >= 0) scratch.cap = std::max<int64_t>(0, A.mem.cap - A.mem.bytes);
+        h2::Geometry g;
+        g.pts = scratch.upload(s.pts, stream);
+        g.lo = scratch.upload(s.lo, stream);
+        g.hi = scratch.upload(s.hi, stream);
+        g.begin = scratch.upload(s.begin, stream);
+        g.end = scratch.upload(s.end, stream);
+        g.cheb = scratch.upload(cheb, stream);
+        g.dim = s.dim;
+        g.cheb_p = s.cheb_p;
+        g.rank = k;
+        g.corr_len = s.corr_len;
+        const int64_t *d_leaf = scratch.upload(leaf_node, stream);
+        const int64_t *d_offU = scratch.upload(off_U, stream);
+        const int64_t *d_offVT = scratch.upload(off_VT, stream);
+        const int64_t *d_offE = scratch.upload(off_E, stream);
+        const int64_t *d_offFT = scratch.upload(off_FT, stream);
+        const h2::FillDesc *d_fill = scratch.upload(fill, stream);
+        check_hip(h2::launch_fill_bases(g, bk, A.basis, d_leaf, d_offU, d_offVT, nleaves, d_offE, d_offFT,
+                                        lowrank ? s.nnodes : 0, stream),
+                  "fill bases");
+        check_hip(h2::launch_fill_blocks(g, sk, A.blocks, A.scales, d_fill, int64_t(fill.size()), stream),
+                  "fill blocks");
+        check_hip(hipStreamSynchronize(stream), "fill");
+    }
+
+    // workspace: vector trees x^ and y^ (nnodes x k) and the near field (n)
+    const int64_t vb = A.vec_f64 ? 8 : 4;
+    A.xh = A.mem.alloc(s.nnodes * k * vb);
+    A.yh = A.mem.alloc(s.nnodes * k * vb);
+    A.ynear = A.mem.alloc(s.n * vb);
+
+    std::vector<RowDesc> rows;
+    std::vector<BlkDesc> blks;
+    auto flush = [&](Phase ph, int kind, const void *data) {
+        WorkList w;
+        w.phase = ph;
+        w.kind = kind;
+        w.data = data;
+        w.nrows = int64_t(rows.size());
+        w.rows = A.mem.upload(rows, stream);
+        w.blks = A.mem.upload(blks, stream);
+        A.lists.push_back(w);
+        rows.clear();
+        blks.clear();
+    };
+    auto row = [&](int64_t out, int64_t init, int R, int sel) {
+        const int32_t b = int32_t(blks.size());
+        rows.push_back({out, init, b, b, R, sel});
+    };
+    auto blk = [&](int64_t a, int64_t in, int C, int64_t sidx) {
+        blks.push_back({a, int32_t(in), C, int32_t(sidx), 0});
+        rows.back().b1 = int32_t(blks.size());
+    };
+
+    if (lowrank) {
+        // leaf projection x^_j = V_j^T x(j)   (Sec. 4.2)
+        for (int64_t j = 0; j < nleaves; ++j) {
+            const int64_t v = lf + j;
+            row(v * k, -1, k, h2::ROW_IN_X);
+            blk(off_VT[j], s.begin[v], int(s.size(v)), 0);
+        }
+        flush(PH_UP, bk, A.basis);
+        // upsweep x^_p = F_c1^T x^_c1 + F_c2^T x^_c2 for levels q .. lmin+1   (Sec. 4.2)
+        for (int l = q; l > s.lmin; --l) {
+            for (int64_t p = Structure::first(l - 1); p < Structure::first(l); ++p) {
+                row(p * k, -1, k, 0);
+                for (int64_t c = 2 * p + 1; c <= 2 * p + 2; ++c) blk(off_FT[c], c * k, k, 0);
+            }
+            flush(PH_UP, bk, A.basis);
+        }
+    }
+    // tree multiplication y^_i = sum_j S_ij x^_j on all levels (Sec. 4.3) and the
+    // dense near field y_near(i) = sum_j D_ij x(j) (Sec. 4.1) in one launch
+    {
+        int64_t fi = 0;
+        if (lowrank)
+            for (int l = s.lmin; l <= q; ++l) {
+                const h2::Bsr &B = s.coupling[l];
+                const int64_t f = Structure::first(l);
+                for (int64_t i = 0; i < (int64_t(1) << l); ++i) {
+                    row((f + i) * k, -1, k, 0);
+                    for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b, ++fi)
+                        blk(fill[fi].a, (f + B.colidx[b]) * k, k, fill[fi].sidx);
+                }
+            }
+        fi = ncoupling;
+        for (int64_t i = 0; i < nleaves; ++i) {
+            const int64_t v = lf + i;
+            row(s.begin[v], -1, int(s.size(v)), h2::ROW_IN_X | h2::ROW_OUT_P);
+            for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++fi) {
+                const int64_t t = lf + s.dense.colidx[b];
+                blk(fill[fi].a, s.begin[t], int(s.size(t)), fill[fi].sidx);
+            }
+        }
+        // longest rows first: the wavefronts that start last are the short ones
+        std::stable_sort(rows.begin(), rows.end(),
+                         [](const RowDesc &a, const RowDesc &b) { return a.b1 - a.b0 > b.b1 - b.b0; });
+        flush(PH_STREAM, sk, A.blocks);
+    }
+    if (lowrank) {
+        // downsweep y^_c += E_c y^_parent for levels lmin+1 .. q   (Sec. 4.4)
+        for (int l = s.lmin + 1; l <= q; ++l) {
+            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
+                row(c * k, c * k, k, 0);
+                blk(off_E[c], ((c - 1) / 2) * k, k, 0);
+            }
+            flush(PH_DOWN, bk, A.basis);
+        }
+    }
+    // leaf expansion and sum: y(i) = y_near(i) + U_i y^_i   (Sec. 4.4, Sec. 4.1)
+    for (int64_t j = 0; j < nleaves; ++j) {
+        const int64_t v = lf + j;
+        row(s.begin[v], s.begin[v], int(s.size(v)), h2::ROW_OUT_P);
+        if (lowrank) blk(off_U[j], v * k, k, 0);
+    }
+    flush(PH_LEAF, bk, A.basis);
+    check_hip(hipStreamSynchronize(stream), "upload work lists");
+}
+
+void validate_params(const double *points, int64_t n, const h2_params *prm) {
+    if (!points || !prm) fail(H2_ERR_INVALID_ARG, "NULL points or params");
+    if (n < 1 || n >= (int64_t(1) << 31)) fail(H2_ERR_INVALID_ARG, "n must be in [1, 2^31)");
+    if (prm->dim != 2 && prm->dim != 3) fail(H2_ERR_INVALID_ARG, "dim must be 2 or 3");
+    if (prm->leaf_size < 2) fail(H2_ERR_INVALID_ARG, "leaf_size must be >= 2");
+    if (prm->cheb_p < 1) fail(H2_ERR_INVALID_ARG, "cheb_p must be >= 1");
+    if (!(prm->eta > 0.0) || !std::isfinite(prm->eta)) fail(H2_ERR_INVALID_ARG, "eta must be > 0");
+    if (!(prm->corr_len > 0.0) || !std::isfinite(prm->corr_len))
+        fail(H2_ERR_INVALID_ARG, "corr_len must be > 0");
+    if (prm->storage < H2_FP64 || prm->storage > H2_BF16_SCALED) fail(H2_ERR_INVALID_ARG, "bad storage");
+    if (prm->flags & ~unsigned(H2_FLAG_STRUCTURE_ONLY)) fail(H2_ERR_INVALID_ARG, "unknown flags");
+    for (int64_t i = 0; i < n * prm->dim; ++i)
+        if (!std::isfinite(points[i])) fail(H2_ERR_INVALID_ARG, "non-finite coordinate");
+    int64_t k = 1;
+    for (int a = 0; a < prm->dim; ++a) {
+        k *= prm->cheb_p;
+        if (k > 64) fail(H2_ERR_UNSUPPORTED, "rank cheb_p^dim above 64");
+    }
+    if (prm->leaf_size > 64) fail(H2_ERR_UNSUPPORTED, "leaf_size above 64");
+}
+
+hipEvent_t take_event(h2_matrix_ &A) {
+    if (!A.spare.empty()) {
+        hipEvent_t e = A.spare.back();
+        A.spare.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    check_hip(hipEventCreate(&e), "hipEventCreate");
+    return e;
+}
+
+// Enqueues the whole product on st.  x is the point vector, y the result.
+void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st) {
+    hipEvent_t ev[PH_COUNT + 1] = {};
+    if (A.prof)
+        for (auto &e : ev) e = take_event(A);
+    int next_phase = 0;   // lists are in phase order; each phase's event precedes its lists
+    for (const WorkList &w : A.lists) {
+        while (A.prof && next_phase <= int(w.phase))
+            check_hip(hipEventRecord(ev[next_phase++], st), "hipEventRecord");
+        h2::RowLaunch L;
+        L.rows = w.rows;
+        L.nrows = w.nrows;
+        L.blks = w.blks;
+        L.data = w.data;
+        L.scales = A.scales;
+        L.in1 = x;
+        L.init = nullptr;
+        L.out1 = nullptr;
+        switch (w.phase) {
+            case PH_UP:
+                L.in0 = A.xh;
+                L.out0 = A.xh;
+                break;
+            case PH_STREAM:
+                L.in0 = A.xh;
+                L.out0 = A.yh;
+                L.out1 = A.ynear;
+                break;
+            case PH_DOWN:
+                L.in0 = A.yh;
+                L.init = A.yh;
+                L.out0 = A.yh;
+                break;
+            default:
+                L.in0 = A.yh;
+                L.init = A.ynear;
+                L.out0 = A.yh;
+                L.out1 = y;
+                break;
+        }
+        check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, w.phase == PH_LEAF, st), "blockrow launch");
+    }
+    if (A.prof) {
+        while (next_phase <= PH_COUNT) check_hip(hipEventRecord(ev[next_phase++], st), "hipEventRecord");
+        A.pending.insert(A.pending.end(), ev, ev + PH_COUNT + 1);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *h2_last_error(void) { return g_last_error.c_str(); }
+
+h2_status h2_build_from_points(const double *points, int64_t n, const h2_params *prm, void *stream,
+                               h2_handle *out) {
+    if (out) *out = nullptr;
+    h2_matrix_ *A = nullptr;
+    try {
+        if (!out) fail(H2_ERR_INVALID_ARG, "NULL out");
+        validate_params(points, n, prm);
+        A = new h2_matrix_();
+        A->storage = prm->storage;
+        A->structure_only = (prm->flags & H2_FLAG_STRUCTURE_ONLY) != 0;
+        A->basis_kind = prm->storage == H2_FP64 ? h2::ELEM_F64 : h2::ELEM_F32;
+        A->block_kind = prm->storage == H2_FP64   ? h2::ELEM_F64
+                        : prm->storage == H2_FP32 ? h2::ELEM_F32
+                                                  : h2::ELEM_BF16;
+        A->vec_f64 = prm->storage == H2_FP64;
+        std::string err = h2::build_structure(points, n, prm->dim, prm->leaf_size, prm->cheb_p, prm->eta,
+                                              prm->corr_len, A->st);
+        if (!err.empty()) fail(H2_ERR_UNSUPPORTED, err);
+        if (!A->structure_only) build_device(*A, static_cast<hipStream_t>(stream));
+        *out = A;
+        g_last_error.clear();
+        return H2_OK;
+    } catch (const Failure &f) {
+        delete A;
+        g_last_error = f.what;
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        delete A;
+        g_last_error = "host allocation failed";
+        return H2_ERR_OOM;
+    } catch (...) {
+        delete A;
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+h2_status h2_matvec(h2_handle A, const double *x, double *y, void *stream) {
+    try {
+        if (!A || !x || !y) fail(H2_ERR_INVALID_ARG, "NULL argument");
+        if (A->structure_only) fail(H2_ERR_INVALID_ARG, "structure-only handle");
+        run_product(*A, x, y, static_cast<hipStream_t>(stream));
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (...) {
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+h2_status h2_matmat(h2_handle A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs,
+                    void *stream) {
+    try {
+        if (!A || !X || !Y) fail(H2_ERR_INVALID_ARG, "NULL argument");
+        if (A->structure_only) fail(H2_ERR_INVALID_ARG, "structure-only handle");
+        if (nrhs < 1) fail(H2_ERR_INVALID_ARG, "nrhs must be >= 1");
+        if (ldx < A->st.n || ldy < A->st.n) fail(H2_ERR_INVALID_ARG, "leading dimension below n");
+        for (int j = 0; j < nrhs; ++j)
+            run_product(*A, X + int64_t(j) * ldx, Y + int64_t(j) * ldy, static_cast<hipStream_t>(stream));
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (...) {
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+void h2_free(h2_handle A) { delete A; }
+
+h2_status h2_get_info(h2_handle A, h2_info *info) {
+    if (!A || !info) {
+        g_last_error = "NULL argument";
+        return H2_ERR_INVALID_ARG;
+    }
+    const h2::Structure &s = A->st;
+    h2_info r;
+    std::memset(&r, 0, sizeof(r));
+    r.n = s.n;
+    r.dim = s.dim;
+    r.leaf_size = s.leaf;
+    r.cheb_p = s.cheb_p;
+    r.rank = s.rank;
+    r.levels_q = s.q;
+    r.lmin = s.lmin;
+    r.storage = A->storage;
+    r.nnodes = s.nnodes;
+    for (const auto &B : s.coupling) r.coupling_blocks += B.blocks();
+    r.dense_blocks = s.dense.blocks();
+    r.bytes_coupling = A->bytes_coupling;
+    r.bytes_dense = A->bytes_dense;
+    r.bytes_leaf_bases = A->bytes_leaf;
+    r.bytes_transfers = A->bytes_transfer;
+    r.bytes_device_total = A->mem.bytes;
+    r.near_ties = s.near_ties;
+    *info = r;
+    return H2_OK;
+}
+
+h2_status h2_get_perm(h2_handle A, int64_t *perm) {
+    if (!A || !perm) {
+        g_last_error = "NULL argument";
+        return H2_ERR_INVALID_ARG;
+    }
+    std::memcpy(perm, A->st.perm.data(), A->st.perm.size() * sizeof(int64_t));
+    return H2_OK;
+}
+
+h2_status h2_get_level_bsr(h2_handle A, int level, int64_t *count, int32_t *rowptr, int32_t *colidx) {
+    if (!A || !count || level < -1 || level > A->st.q) {
+        g_last_error = "bad argument";
+        return H2_ERR_INVALID_ARG;
+    }
+    const h2::Bsr &B = level < 0 ? A->st.dense : A->st.coupling[level];
+    *count = B.blocks();
+    if (rowptr) std::memcpy(rowptr, B.rowptr.data(), B.rowptr.size() * sizeof(int32_t));
+    if (colidx) std::memcpy(colidx, B.colidx.data(), B.colidx.size() * sizeof(int32_t));
+    return H2_OK;
+}
+
+h2_status h2_profile(h2_handle A, int enable) {
+    if (!A) {
+        g_last_error = "NULL handle";
+        return H2_ERR_INVALID_ARG;
+    }
+    A->prof = enable != 0;
+    if (A->prof) {
+        std::fill(A->prof_ms, A->prof_ms + 8, 0.0);
+        A->prof_calls = 0;
+    }
+    return H2_OK;
+}
+
+h2_status h2_profile_read(h2_handle A, double *ms, int64_t *calls) {
+    try {
+        if (!A || !ms || !calls) fail(H2_ERR_INVALID_ARG, "NULL argument");
+        for (size_t i = 0; i + PH_COUNT < A->pending.size(); i += PH_COUNT + 1) {
+            hipEvent_t *ev = &A->pending[i];
+            check_hip(hipEventSynchronize(ev[PH_COUNT]), "hipEventSynchronize");
+            for (int p = 0; p < PH_COUNT; ++p) {
+                float t = 0.0f;
+                // end of phase p = start of the next recorded phase
+                check_hip(hipEventElapsedTime(&t, ev[p], ev[p + 1]), "hipEventElapsedTime");
+                A->prof_ms[p] += t;
+            }
+            float tot = 0.0f;
+            check_hip(hipEventElapsedTime(&tot, ev[0], ev[PH_COUNT]), "hipEventElapsedTime");
+            A->prof_ms[PH_COUNT] += tot;
+            ++A->prof_calls;
+        }
+        A->spare.insert(A->spare.end(), A->pending.begin(), A->pending.end());
+        A->pending.clear();
+        std::copy(A->prof_ms, A->prof_ms + 8, ms);
+        *calls = A->prof_calls;
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    }
+}
+
+}  // extern "C"

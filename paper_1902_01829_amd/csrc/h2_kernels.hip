@@ -1,0 +1,390 @@
+// HIP kernels of libh2mv for gfx950 (MI355X): generation of the H^2
+// representation on the device, and the block-row streaming kernel that runs
+// every phase of the product (Sec. 4): leaf projection and upsweep (Sec. 4.2),
+// tree multiplication with all levels in one launch together with the dense
+// near field (Sec. 4.3, Sec. 4.1), downsweep and leaf expansion (Sec. 4.4).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "h2_device.h"
+
+namespace h2 {
+namespace {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- geometry
+// 1-D Lagrange polynomial a over the Chebyshev nodes t, at s.
+__device__ double lagrange_1d(const double *t, int p, int a, double s) {
+    double v = 1.0;
+    for (int b = 0; b < p; ++b)
+        if (b != a) v *= (s - t[b]) / (t[a] - t[b]);
+    return v;
+}
+
+// Tensor Lagrange polynomial nu (axis 0 fastest) of node v's box at x.
+__device__ double lagrange_box(const Geometry &g, int64_t v, int nu, const double *x) {
+    double val = 1.0;
+    for (int ax = 0; ax < g.dim; ++ax) {
+        const int a = nu % g.cheb_p;
+        nu /= g.cheb_p;
+        const double lo = g.lo[v * g.dim + ax], hi = g.hi[v * g.dim + ax];
+        const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+        val *= lagrange_1d(g.cheb, g.cheb_p, a, (x[ax] - c) / h);
+    }
+    return val;
+}
+
+// Chebyshev interpolation node nu of node v's box.
+__device__ void cheb_point(const Geometry &g, int64_t v, int nu, double *xi) {
+    for (int ax = 0; ax < g.dim; ++ax) {
+        const int a = nu % g.cheb_p;
+        nu /= g.cheb_p;
+        const double lo = g.lo[v * g.dim + ax], hi = g.hi[v * g.dim + ax];
+        xi[ax] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * g.cheb[a];
+    }
+}
+
+// Exponential covariance exp(-|a - b| / corr_len) (Sec. 4.6).
+__device__ double kernel_exp(const double *a, const double *b, int dim, double corr_len) {
+    double r2 = 0.0;
+    for (int i = 0; i < dim; ++i) r2 += (a[i] - b[i]) * (a[i] - b[i]);
+    return exp(-sqrt(r2) / corr_len);
+}
+
+// Round-to-nearest-even of an FP32 value to its upper 16 bits (BF16 code).
+__device__ uint16_t bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Element kinds: storage type T, the 16-byte item type V holding W elements,
+// and the arithmetic type P of a block's partial sums.
+template <int KIND> struct Elem;
+template <> struct Elem<ELEM_F64> {
+    using T = double;
+    using V = f64x2;
+    using P = double;
+    static constexpr int W = 2;
+    __device__ static void unpack(const V &r, double *v) {
+        v[0] = r.x;
+        v[1] = r.y;
+    }
+    __device__ static T store(double v) { return v; }
+};
+template <> struct Elem<ELEM_F32> {
+    using T = float;
+    using V = f32x4;
+    using P = float;
+    static constexpr int W = 4;
+    __device__ static void unpack(const V &r, float *v) {
+        v[0] = r.x;
+        v[1] = r.y;
+        v[2] = r.z;
+        v[3] = r.w;
+    }
+    __device__ static T store(double v) { return float(v); }
+};
+template <> struct Elem<ELEM_BF16> {
+    using T = uint16_t;
+    using V = u32x4;
+    using P = float;
+    static constexpr int W = 8;
+    __device__ static void unpack(const V &r, float *v) {
+        v[0] = __uint_as_float(r.x << 16);
+        v[1] = __uint_as_float(r.x & 0xffff0000u);
+        v[2] = __uint_as_float(r.y << 16);
+        v[3] = __uint_as_float(r.y & 0xffff0000u);
+        v[4] = __uint_as_float(r.z << 16);
+        v[5] = __uint_as_float(r.z & 0xffff0000u);
+        v[6] = __uint_as_float(r.w << 16);
+        v[7] = __uint_as_float(r.w & 0xffff0000u);
+    }
+};
+
+// Decodes element index e of an R-row block in 16-byte column groups of W.
+__device__ inline void decode(int e, int R, int W, int &r, int &c) {
+    const int w = e % W, t = e / W;
+    r = t % R;
+    c = (t / R) * W + w;
+}
+
+// ---------------------------------------------------------------- fill kernels
+// Leaf bases: U_j (m_j x k) with U[r, nu] = L^(j)_nu(point r), and V_j^T
+// (k x m_j), the same values transposed (V = U: one tree for rows and columns,
+// the symmetric case of Sec. 2.2).
+template <int KIND>
+__global__ __launch_bounds__(256) void fill_leaf_bases_kernel(
+    Geometry g, typename Elem<KIND>::T *basis, const int64_t *leaf_node, const int64_t *off_U,
+    const int64_t *off_VT, int64_t nleaves) {
+    using E = Elem<KIND>;
+    constexpr int W = E::W;
+    const int64_t j = blockIdx.x;
+    if (j >= nleaves) return;
+    const int64_t v = leaf_node[j], b = g.begin[v];
+    const int m = int(g.end[v] - b), k = g.rank;
+    const int nU = m * ((k + W - 1) / W) * W, nVT = k * ((m + W - 1) / W) * W;
+    for (int e = threadIdx.x; e < nU; e += blockDim.x) {
+        int r, c;
+        decode(e, m, W, r, c);
+        const double val = c < k ? lagrange_box(g, v, c, g.pts + (b + r) * g.dim) : 0.0;
+        basis[off_U[j] + e] = E::store(val);
+    }
+    for (int e = threadIdx.x; e < nVT; e += blockDim.x) {
+        int r, c;
+        decode(e, k, W, r, c);
+        const double val = c < m ? lagrange_box(g, v, r, g.pts + (b + c) * g.dim) : 0.0;
+        basis[off_VT[j] + e] = E::store(val);
+    }
+}
+
+// Transfers (Eq. (1) of Sec. 2.2): E_c[mu, nu] = L^(parent)_nu(xi^(c)_mu), a
+// k x k block with U_parent = [U_c1 E_c1; U_c2 E_c2]; F_c^T = E_c^T is stored
+// next to it for the upsweep.
+template <int KIND>
+__global__ __launch_bounds__(256) void fill_transfers_kernel(
+    Geometry g, typename Elem<KIND>::T *basis, const int64_t *off_E, const int64_t *off_FT,
+    int64_t nnodes) {
+    using E = Elem<KIND>;
+    constexpr int W = E::W;
+    const int64_t c = int64_t(blockIdx.x) + 1;
+    if (c >= nnodes || off_E[c] < 0) return;
+    const int64_t par = (c - 1) / 2;
+    const int k = g.rank, nE = k * ((k + W - 1) / W) * W;
+    for (int e = threadIdx.x; e < nE; e += blockDim.x) {
+        int r, col;
+        decode(e, k, W, r, col);
+        double xi[3];
+        double ev = 0.0, fv = 0.0;
+        if (col < k) {
+            cheb_point(g, c, r, xi);               // E[r, col]
+            ev = lagrange_box(g, par, col, xi);
+            cheb_point(g, c, col, xi);             // F^T[r, col] = E[col, r]
+            fv = lagrange_box(g, par, r, xi);
+        }
+        basis[off_E[c] + e] = E::store(ev);
+        basis[off_FT[c] + e] = E::store(fv);
+    }
+}
+
+// Coupling blocks S_st[mu, nu] = K(xi^(s)_mu, xi^(t)_nu) and dense blocks
+// D_st[a, b] = K(p_a, p_b) (Sec. 4.6), stored as FP64 / FP32 values.
+template <int KIND>
+__global__ __launch_bounds__(256) void fill_blocks_kernel(Geometry g, typename Elem<KIND>::T *out,
+                                                           const FillDesc *desc, int64_t nblocks) {
+    using E = Elem<KIND>;
+    constexpr int W = E::W;
+    const int64_t blk = blockIdx.x;
+    if (blk >= nblocks) return;
+    const FillDesc d = desc[blk];
+    const bool dense = d.kind == FILL_DENSE;
+    const int R = dense ? int(g.end[d.s] - g.begin[d.s]) : g.rank;
+    const int C = dense ? int(g.end[d.t] - g.begin[d.t]) : g.rank;
+    const int ne = R * ((C + W - 1) / W) * W;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        int r, c;
+        decode(e, R, W, r, c);
+        double val = 0.0;
+        if (c < C) {
+            if (dense) {
+                val = kernel_exp(g.pts + (g.begin[d.s] + r) * g.dim, g.pts + (g.begin[d.t] + c) * g.dim,
+                                 g.dim, g.corr_len);
+            } else {
+                double xs[3], xt[3];
+                cheb_point(g, d.s, r, xs);
+                cheb_point(g, d.t, c, xt);
+                val = kernel_exp(xs, xt, g.dim, g.corr_len);
+            }
+        }
+        out[d.a + e] = E::store(val);
+    }
+}
+
+// BF16 with one FP32 scale per block: s = max |fp32(a)|, code = bf16(fp32(a) / s).
+__global__ __launch_bounds__(256) void fill_blocks_bf16_kernel(Geometry g, uint16_t *out, float *scales,
+                                                                const FillDesc *desc, int64_t nblocks) {
+    constexpr int W = 8;
+    __shared__ float vals[64 * 64];
+    __shared__ float wmax[4];
+    const int64_t blk = blockIdx.x;
+    if (blk >= nblocks) return;
+    const FillDesc d = desc[blk];
+    const bool dense = d.kind == FILL_DENSE;
+    const int R = dense ? int(g.end[d.s] - g.begin[d.s]) : g.rank;
+    const int C = dense ? int(g.end[d.t] - g.begin[d.t]) : g.rank;
+    const int ne = R * ((C + W - 1) / W) * W;
+    float mx = 0.0f;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        int r, c;
+        decode(e, R, W, r, c);
+        double val = 0.0;
+        if (c < C) {
+            if (dense) {
+                val = kernel_exp(g.pts + (g.begin[d.s] + r) * g.dim, g.pts + (g.begin[d.t] + c) * g.dim,
+                                 g.dim, g.corr_len);
+            } else {
+                double xs[3], xt[3];
+                cheb_point(g, d.s, r, xs);
+                cheb_point(g, d.t, c, xt);
+                val = kernel_exp(xs, xt, g.dim, g.corr_len);
+            }
+        }
+        const float f = float(val);
+        vals[e] = f;
+        mx = fmaxf(mx, fabsf(f));
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    const float s = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    for (int e = threadIdx.x; e < ne; e += blockDim.x)
+        out[d.a + e] = s == 0.0f ? uint16_t(0) : bf16_rne(vals[e] / s);
+    if (threadIdx.x == 0) scales[d.sidx] = s;
+}
+
+// ---------------------------------------------------------------- block-row product
+// One wavefront per output segment.  For every block of the row, the input
+// segment (<= 64 values) is staged in the wave's LDS slot; each lane then
+// streams its row's 16-byte items of the block with non-temporal loads and
+// accumulates the block's dot products.  One block's partial sum is kept in
+// the block arithmetic type, sums over blocks in FP64.
+template <int KIND, typename TV, typename TO1>
+__global__ __launch_bounds__(256) void blockrow_kernel(
+    const RowDesc *__restrict__ rows, int64_t nrows, const BlkDesc *__restrict__ blks,
+    const typename Elem<KIND>::T *__restrict__ data, const float *__restrict__ scales,
+    const TV *__restrict__ in0, const double *__restrict__ in1, const TV *__restrict__ init,
+    TV *__restrict__ out0, TO1 *__restrict__ out1) {
+    using E = Elem<KIND>;
+    using P = typename E::P;
+    constexpr int W = E::W;
+    __shared__ __attribute__((aligned(16))) P xs[4][64];
+    __shared__ double red[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t row = int64_t(blockIdx.x) * 4 + wv;
+    if (row >= nrows) return;
+    const RowDesc rd = rows[row];
+    const int R = rd.R, G = 64 / R, grp = lane / R, rr = lane - grp * R;
+    const bool in_x = (rd.sel & ROW_IN_X) != 0;
+    double acc = 0.0;
+    for (int b = rd.b0; b < rd.b1; ++b) {
+        const BlkDesc bd = blks[b];
+        const int C = bd.C, CW = (C + W - 1) / W;
+        P xv = P(0);
+        if (lane < C) xv = in_x ? P(in1[bd.in + lane]) : P(in0[bd.in + lane]);
+        xs[wv][lane] = xv;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        P part = P(0);
+        if (grp < G) {
+            using V = typename E::V;
+            const V *p = reinterpret_cast<const V *>(data + bd.a) + (grp * R + rr);
+            const int stride = G * R;
+#pragma unroll 8
+            for (int cw = grp; cw < CW; cw += G, p += stride) {
+                const V raw = __builtin_nontemporal_load(p);
+                P v[W];
+                E::unpack(raw, v);
+#pragma unroll
+                for (int w = 0; w < W; ++w) part = fma(v[w], xs[wv][cw * W + w], part);
+            }
+        }
+        if constexpr (KIND == ELEM_BF16)
+            acc += double(part) * double(scales[bd.sidx]);
+        else
+            acc += double(part);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (G > 1) {
+        red[wv][lane] = acc;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < R)
+            for (int g2 = 1; g2 < G; ++g2) acc += red[wv][g2 * R + lane];
+    }
+    if (lane < R) {
+        const double res = rd.init >= 0 ? double(init[rd.init + lane]) + acc : acc;
+        if (rd.sel & ROW_OUT_P)
+            out1[rd.out + lane] = TO1(res);
+        else
+            out0[rd.out + lane] = TV(res);
+    }
+}
+
+constexpr int kRowsPerBlock = 4;
+
+template <int KIND, typename TV, typename TO1>
+hipError_t run_blockrow(const RowLaunch &L, hipStream_t st) {
+    if (L.nrows <= 0) return hipSuccess;
+    const int64_t grid = (L.nrows + kRowsPerBlock - 1) / kRowsPerBlock;
+    hipLaunchKernelGGL((blockrow_kernel<KIND, TV, TO1>), dim3(unsigned(grid)), dim3(256), 0, st, L.rows,
+                       L.nrows, L.blks, static_cast<const typename Elem<KIND>::T *>(L.data), L.scales,
+                       static_cast<const TV *>(L.in0), L.in1, static_cast<const TV *>(L.init),
+                       static_cast<TV *>(L.out0), static_cast<TO1 *>(L.out1));
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fill_bases(const Geometry &g, int basis_kind, void *basis, const int64_t *leaf_node,
+                             const int64_t *off_U, const int64_t *off_VT, int64_t nleaves,
+                             const int64_t *off_E, const int64_t *off_FT, int64_t nnodes, hipStream_t st) {
+    if (nleaves > 0) {
+        if (basis_kind == ELEM_F64)
+            hipLaunchKernelGGL(fill_leaf_bases_kernel<ELEM_F64>, dim3(unsigned(nleaves)), dim3(256), 0, st, g,
+                               static_cast<double *>(basis), leaf_node, off_U, off_VT, nleaves);
+        else
+            hipLaunchKernelGGL(fill_leaf_bases_kernel<ELEM_F32>, dim3(unsigned(nleaves)), dim3(256), 0, st, g,
+                               static_cast<float *>(basis), leaf_node, off_U, off_VT, nleaves);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (nnodes > 1) {
+        if (basis_kind == ELEM_F64)
+            hipLaunchKernelGGL(fill_transfers_kernel<ELEM_F64>, dim3(unsigned(nnodes - 1)), dim3(256), 0, st, g,
+                               static_cast<double *>(basis), off_E, off_FT, nnodes);
+        else
+            hipLaunchKernelGGL(fill_transfers_kernel<ELEM_F32>, dim3(unsigned(nnodes - 1)), dim3(256), 0, st, g,
+                               static_cast<float *>(basis), off_E, off_FT, nnodes);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_fill_blocks(const Geometry &g, int block_kind, void *blocks, float *scales,
+                              const FillDesc *desc, int64_t nblocks, hipStream_t st) {
+    if (nblocks <= 0) return hipSuccess;
+    // launch in chunks: a grid dimension times the block size must stay below 2^32
+    const int64_t chunk = int64_t(1) << 22;
+    for (int64_t b0 = 0; b0 < nblocks; b0 += chunk) {
+        const int64_t nb = nblocks - b0 < chunk ? nblocks - b0 : chunk;
+        if (block_kind == ELEM_F64)
+            hipLaunchKernelGGL(fill_blocks_kernel<ELEM_F64>, dim3(unsigned(nb)), dim3(256), 0, st, g,
+                               static_cast<double *>(blocks), desc + b0, nb);
+        else if (block_kind == ELEM_F32)
+            hipLaunchKernelGGL(fill_blocks_kernel<ELEM_F32>, dim3(unsigned(nb)), dim3(256), 0, st, g,
+                               static_cast<float *>(blocks), desc + b0, nb);
+        else
+            hipLaunchKernelGGL(fill_blocks_bf16_kernel, dim3(unsigned(nb)), dim3(256), 0, st, g,
+                               static_cast<uint16_t *>(blocks), scales, desc + b0, nb);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_blockrow(const RowLaunch &L, int kind, bool vec_f64, bool out1_f64, hipStream_t st) {
+    if (vec_f64) return run_blockrow<ELEM_F64, double, double>(L, st);
+    if (kind == ELEM_F32)
+        return out1_f64 ? run_blockrow<ELEM_F32, float, double>(L, st) : run_blockrow<ELEM_F32, float, float>(L, st);
+    return out1_f64 ? run_blockrow<ELEM_BF16, float, double>(L, st) : run_blockrow<ELEM_BF16, float, float>(L, st);
+}
+
+}  // namespace h2

@@ -1,0 +1,38 @@
+// Host-side structure of an H^2 matrix: cluster tree, boxes and the
+// block-sparse-row partition.  Internal to libh2mv.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace h2 {
+
+struct Bsr {
+    std::vector<int32_t> rowptr;   // rows + 1
+    std::vector<int32_t> colidx;   // blocks, sorted by (row, col)
+    int64_t blocks() const { return static_cast<int64_t>(colidx.size()); }
+};
+
+struct Structure {
+    int64_t n = 0;
+    int dim = 0, leaf = 0, cheb_p = 0, rank = 0, q = 0, lmin = 0;
+    double eta = 0, corr_len = 0;
+    int64_t nnodes = 0;
+    std::vector<int64_t> perm;           // tree position -> input index
+    std::vector<int64_t> begin, end;     // node ranges in tree order
+    std::vector<double> pts;             // n x dim, tree order
+    std::vector<double> lo, hi;          // nnodes x dim, widened tight boxes
+    std::vector<Bsr> coupling;           // per level 0..q, rows = nodes of the level
+    Bsr dense;                           // rows = leaves
+    int64_t near_ties = 0;
+
+    static int64_t first(int level) { return (int64_t(1) << level) - 1; }
+    int64_t size(int64_t v) const { return end[v] - begin[v]; }
+};
+
+// Builds the structure; returns an empty string on success, else the reason.
+std::string build_structure(const double *points, int64_t n, int dim, int leaf, int cheb_p,
+                            double eta, double corr_len, Structure &s);
+
+}  // namespace h2

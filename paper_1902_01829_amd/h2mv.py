@@ -1,0 +1,197 @@
+"""Thin ctypes binding of libh2mv (include/h2mv.h).
+
+Argument marshalling only: every step of the product runs in the library's
+HIP kernels.  Device buffers and streams come from PyTorch; the functions
+take raw device pointers and hipStream_t handles (ints), like the C ABI.
+Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libh2mv.so")
+
+H2_OK, H2_ERR_INVALID_ARG, H2_ERR_OOM, H2_ERR_DEVICE, H2_ERR_UNSUPPORTED, H2_ERR_INTERNAL = range(6)
+H2_FP64, H2_FP32, H2_BF16_SCALED = 0, 1, 2
+H2_FLAG_STRUCTURE_ONLY = 1
+STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
+
+# Every function declared in include/h2mv.h.
+EXPORTS = ("h2_build_from_points", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
+           "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_last_error")
+
+
+class h2_params(C.Structure):
+    _fields_ = [("dim", C.c_int), ("leaf_size", C.c_int), ("cheb_p", C.c_int), ("eta", C.c_double),
+                ("corr_len", C.c_double), ("storage", C.c_int), ("flags", C.c_uint)]
+
+
+class h2_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dim", C.c_int), ("leaf_size", C.c_int), ("cheb_p", C.c_int),
+                ("rank", C.c_int), ("levels_q", C.c_int), ("lmin", C.c_int), ("storage", C.c_int),
+                ("nnodes", C.c_int64), ("coupling_blocks", C.c_int64), ("dense_blocks", C.c_int64),
+                ("bytes_coupling", C.c_int64), ("bytes_dense", C.c_int64), ("bytes_leaf_bases", C.c_int64),
+                ("bytes_transfers", C.c_int64), ("bytes_device_total", C.c_int64), ("near_ties", C.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class H2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"h2mv error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if libh2mv.so has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1902_01829_amd.build` (there is no fallback path)")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.h2_build_from_points.argtypes = [vp, i64, C.POINTER(h2_params), vp, C.POINTER(vp)]
+        L.h2_matvec.argtypes = [vp, vp, vp, vp]
+        L.h2_matmat.argtypes = [vp, vp, i64, vp, i64, C.c_int, vp]
+        L.h2_free.argtypes = [vp]
+        L.h2_free.restype = None
+        L.h2_get_info.argtypes = [vp, C.POINTER(h2_info)]
+        L.h2_get_perm.argtypes = [vp, vp]
+        L.h2_get_level_bsr.argtypes = [vp, C.c_int, C.POINTER(i64), vp, vp]
+        L.h2_profile.argtypes = [vp, C.c_int]
+        L.h2_profile_read.argtypes = [vp, vp, C.POINTER(i64)]
+        L.h2_last_error.argtypes = []
+        L.h2_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name != "h2_free" and name != "h2_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != H2_OK:
+        raise H2Error(code, lib().h2_last_error().decode())
+
+
+def h2_last_error() -> str:
+    return lib().h2_last_error().decode()
+
+
+def h2_build_from_points(points, dim, leaf_size, cheb_p, eta, corr_len, storage=H2_FP64, flags=0,
+                         stream=0):
+    """points: host array n x dim (float64).  Returns the handle (an int)."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n = pts.shape[0] if pts.ndim == 2 else 0
+    prm = h2_params(dim, leaf_size, cheb_p, eta, corr_len, storage, flags)
+    h = C.c_void_p()
+    _check(lib().h2_build_from_points(pts.ctypes.data if pts.size else None, n, C.byref(prm),
+                                      C.c_void_p(stream), C.byref(h)))
+    return h.value
+
+
+def h2_matvec(h, x_ptr, y_ptr, stream=0):
+    _check(lib().h2_matvec(C.c_void_p(h), C.c_void_p(x_ptr), C.c_void_p(y_ptr), C.c_void_p(stream)))
+
+
+def h2_matmat(h, X_ptr, ldx, Y_ptr, ldy, nrhs, stream=0):
+    _check(lib().h2_matmat(C.c_void_p(h), C.c_void_p(X_ptr), ldx, C.c_void_p(Y_ptr), ldy, nrhs,
+                           C.c_void_p(stream)))
+
+
+def h2_free(h):
+    lib().h2_free(C.c_void_p(h))
+
+
+def h2_get_info(h) -> h2_info:
+    info = h2_info()
+    _check(lib().h2_get_info(C.c_void_p(h), C.byref(info)))
+    return info
+
+
+def h2_get_perm(h, n) -> np.ndarray:
+    perm = np.zeros(n, dtype=np.int64)
+    _check(lib().h2_get_perm(C.c_void_p(h), perm.ctypes.data))
+    return perm
+
+
+def h2_get_level_bsr(h, level, nrows):
+    """(rowptr, colidx) of one level of the matrix tree; level -1 = dense blocks."""
+    cnt = C.c_int64()
+    _check(lib().h2_get_level_bsr(C.c_void_p(h), level, C.byref(cnt), None, None))
+    rp = np.zeros(nrows + 1, dtype=np.int32)
+    ci = np.zeros(max(cnt.value, 1), dtype=np.int32)
+    _check(lib().h2_get_level_bsr(C.c_void_p(h), level, C.byref(cnt), rp.ctypes.data, ci.ctypes.data))
+    return rp, ci[:cnt.value]
+
+
+def h2_profile(h, enable):
+    _check(lib().h2_profile(C.c_void_p(h), 1 if enable else 0))
+
+
+def h2_profile_read(h):
+    """(ms per phase [up, stream, down, leaf, whole call], calls)."""
+    ms = np.zeros(8)
+    calls = C.c_int64()
+    _check(lib().h2_profile_read(C.c_void_p(h), ms.ctypes.data, C.byref(calls)))
+    return ms[:5], calls.value
+
+
+class H2Matrix:
+    """Owns one handle; products take and return torch tensors on the GPU."""
+
+    def __init__(self, points, dim, leaf_size, cheb_p, eta, corr_len, storage=H2_FP64, flags=0,
+                 stream=None):
+        import torch
+        self._torch = torch
+        st = stream if stream is not None else (torch.cuda.current_stream().cuda_stream
+                                                if torch.cuda.is_available() else 0)
+        self.handle = h2_build_from_points(points, dim, leaf_size, cheb_p, eta, corr_len, storage, flags, st)
+        self.info = h2_get_info(self.handle)
+        self.n = self.info.n
+
+    def close(self):
+        if getattr(self, "handle", None):
+            h2_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def perm(self):
+        return h2_get_perm(self.handle, self.n)
+
+    def level_bsr(self, level):
+        nrows = (1 << self.info.levels_q) if level < 0 else (1 << level)
+        return h2_get_level_bsr(self.handle, level, nrows)
+
+    def _stream(self):
+        return self._torch.cuda.current_stream().cuda_stream
+
+    def matvec(self, x, out=None):
+        """x: float64 CUDA tensor (n,), tree order."""
+        torch = self._torch
+        assert x.dtype == torch.float64 and x.is_cuda and x.is_contiguous() and x.numel() == self.n
+        y = out if out is not None else torch.empty_like(x)
+        h2_matvec(self.handle, x.data_ptr(), y.data_ptr(), self._stream())
+        return y
+
+    def matmat(self, X, out=None):
+        """X: float64 CUDA tensor (nrhs, n) (each row one right-hand side, i.e.
+        column-major n x nrhs with leading dimension n)."""
+        torch = self._torch
+        assert X.dtype == torch.float64 and X.is_cuda and X.is_contiguous() and X.shape[1] == self.n
+        Y = out if out is not None else torch.empty_like(X)
+        h2_matmat(self.handle, X.data_ptr(), self.n, Y.data_ptr(), self.n, X.shape[0], self._stream())
+        return Y
