@@ -9,9 +9,11 @@ vector.  The default workload is the 2-D covariance of 2^20 uniform points
 bases: rank 64, eta 0.9), FP64.  value = algorithmic bytes per product / time
 (GB/s): the bytes of D, S, U, V, E, F, x and y.
 
-Prints one JSON line.  Also reports the dominant kernel (coupling + dense
-streaming) against the HBM roofline, and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+Prints one JSON line.  Besides the headline it reports the dominant kernel
+(coupling + dense streaming) against the HBM roofline, the FP64 CPU oracle
+timed on a bounded sample of the same workload, and the reduced-storage modes
+of the 3-D workload with their speedup over FP64 and their error against the
+FP64 oracle.
 """
 from __future__ import annotations
 
@@ -31,10 +33,17 @@ from paper_1902_01829_amd import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 STORAGE = {"fp64": 0, "fp32": 1, "bf16": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16xf32scale"}
-# Fraction of HBM traffic per algorithmic byte of the streaming kernel, from
-# rocprofv3 FETCH_SIZE/WRITE_SIZE counters; None until measured for the
-# current kernel.
-MEASURED_TRAFFIC = {}
+# HBM bytes per launch of the streaming kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, scaled by the factors a 1 GiB device copy
+# gives: x2.0 for FETCH_SIZE, x1.0 for WRITE_SIZE).  Keyed by workload and
+# storage; valid for the kernel as measured (drop the entry when it changes).
+MEASURED_TRAFFIC = {
+    ("2d-n1048576-m64-k64", "fp64"): (21551794.5 * 2.0 + 24568.0) * 1024,
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def algorithmic_bytes(info, n, nrhs=1):
@@ -50,11 +59,58 @@ def stream_kernel_bytes(info, n, storage):
     return info.bytes_coupling + info.bytes_dense + 8 * n + vb * n
 
 
+def run_matvec(w, storage, steps, warmup):
+    """Builds the workload, times `steps` products after `warmup`, returns a dict."""
+    import torch
+    from paper_1902_01829_amd import h2mv
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=storage)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = A.info
+    perm = A.perm()
+    xt = W.rhs(w, 1)[perm]
+    x = torch.from_numpy(xt).cuda()
+    y = torch.empty_like(x)
+    log(f"{w.name} storage={storage}: built in {build_s:.1f} s, {info.coupling_blocks} coupling + "
+        f"{info.dense_blocks} dense blocks, {info.bytes_device_total / 1e9:.2f} GB on device")
+    for _ in range(warmup):
+        A.matvec(x, out=y)
+    torch.cuda.synchronize()
+    h2mv.h2_profile(A.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h2mv.h2_matvec(A.handle, x.data_ptr(), y.data_ptr(), stream.cuda_stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phase_ms, calls = h2mv.h2_profile_read(A.handle)
+    h2mv.h2_profile(A.handle, False)
+    y_host = y.cpu().numpy()
+    A.close()
+    del x, y
+    torch.cuda.empty_cache()
+    ms = (t1 - t0) * 1e3 / steps
+    return {"ms": ms, "phase_ms": phase_ms / max(calls, 1), "info": info, "perm": perm, "xt": xt,
+            "y": y_host, "build_s": build_s}
+
+
+def oracle_sample(w, perm, xt, nleaves, storage=0, seed=7):
+    """FP64 oracle rows of a seeded sample of leaves (matrix-free)."""
+    from oracle import oracle as O
+    o = O.OracleH2(W.points(w), w.leaf, w.cheb_p, w.eta, w.corr_len, storage=storage, keep_blocks=False)
+    assert np.array_equal(perm, o.perm())
+    rng = np.random.Generator(np.random.PCG64(seed))
+    leaves = np.sort(rng.choice(o.leaf_nodes(), size=min(nleaves, 1 << o.q), replace=False))
+    return o.leaf_rows(leaves), o.matvec_leaves(xt, leaves)
+
+
 def cpu_baseline(w, perm, xt, budget_s=20.0):
     """FP64 oracle (matrix-free, all host threads) on a sample of leaves: the
     full upsweep plus the rows of the sampled leaves (their dense blocks and
     the coupling rows of their ancestors).  Reported in GB/s of the blocks,
-    bases and transfers that sample touches, as if they were stored."""
+    bases and transfers that sample touches, counted at their stored size."""
     from oracle import oracle as O
     t0 = time.perf_counter()
     o = O.OracleH2(W.points(w), w.leaf, w.cheb_p, w.eta, w.corr_len, keep_blocks=False)
@@ -63,26 +119,30 @@ def cpu_baseline(w, perm, xt, budget_s=20.0):
     k, q = o.k, o.q
     eb = 8
     rps = [o.coupling_bsr(l)[0] for l in range(q + 1)]
-    drp, _ = o.dense_bsr()
+    drp, dci = o.dense_bsr()
     b, e = o.ranges()
     sizes = e - b
+    lf = (1 << q) - 1
     rng = np.random.Generator(np.random.PCG64(11))
     leaves_all = rng.permutation(o.leaf_nodes())
 
     def touched_bytes(leaves):
-        up = (2 * k * int(sizes[(1 << q) - 1:].sum()) + 2 * k * k * max(0, (1 << (q + 1)) - (1 << (o.lmin + 1)))) * eb
-        tot = up
+        ntransfer = max(0, (1 << (q + 1)) - (1 << (o.lmin + 1)))     # nodes of levels lmin+1 .. q
+        tot = (k * int(sizes[lf:].sum()) + k * k * ntransfer) * eb   # upsweep: V and F
         for v in leaves:
-            j = v - ((1 << q) - 1)
-            tot += int(drp[j + 1] - drp[j]) * int(sizes[v]) * w.leaf * eb   # dense row (approx. leaf size cols)
+            j = v - lf
+            cols = dci[drp[j]:drp[j + 1]]
+            tot += int(sizes[v]) * int(sizes[lf + cols].sum()) * eb   # dense row
+            tot += int(sizes[v]) * k * eb                              # U of the leaf
             a = v
             for l in range(q, o.lmin - 1, -1):
                 i = a - ((1 << l) - 1)
-                tot += int(rps[l][i + 1] - rps[l][i]) * k * k * eb
+                tot += int(rps[l][i + 1] - rps[l][i]) * k * k * eb     # coupling row of the ancestor
+                if l > o.lmin:
+                    tot += k * k * eb                                  # its E
                 a = (a - 1) // 2
         return tot
 
-    # calibrate on a few leaves, then size the sample to the budget
     nl = 4
     t0 = time.perf_counter()
     o.matvec_leaves(xt, leaves_all[:nl])
@@ -96,10 +156,31 @@ def cpu_baseline(w, perm, xt, budget_s=20.0):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": round(nbytes / t / 1e9, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
-        "sample": f"FP64 oracle, matrix-free (blocks regenerated), full upsweep + rows of {nl} of "
-                  f"{1 << q} leaves ({len(o.leaf_rows(leaves))} rows); {t:.1f} s for "
-                  f"{nbytes / 1e9:.2f} GB of blocks touched; oracle build {build_s:.1f} s",
-    }, leaves, o.leaf_rows(leaves), y_ref
+        "sample": f"FP64 oracle, matrix-free (blocks regenerated from the kernel), full upsweep + rows of "
+                  f"{nl} of {1 << q} leaves ({len(o.leaf_rows(leaves))} rows): {t:.1f} s for "
+                  f"{nbytes / 1e9:.2f} GB of blocks, bases and transfers touched (at FP64 stored size); "
+                  f"oracle build {build_s:.1f} s",
+    }, o.leaf_rows(leaves), y_ref
+
+
+def storage_modes(steps, warmup, nleaves=16):
+    """The 3-D workload (2^19 points, rank 64) in FP64, FP32 and BF16 storage."""
+    w = W.C3
+    out = {}
+    for name in ("fp64", "fp32", "bf16"):
+        r = run_matvec(w, STORAGE[name], steps, warmup)
+        rows, ref = oracle_sample(w, r["perm"], r["xt"], nleaves)
+        rel = float(np.linalg.norm(r["y"][rows] - ref) / np.linalg.norm(ref))
+        nbytes = algorithmic_bytes(r["info"], w.n)
+        out[name] = {"ms": round(r["ms"], 4), "GB_per_s": round(nbytes / (r["ms"] * 1e-3) / 1e9, 1),
+                     "algorithmic_bytes": nbytes, "rel_err_vs_fp64_oracle": rel,
+                     "stream_ms": round(float(r["phase_ms"][1]), 4)}
+        log(f"{w.name} {name}: {r['ms']:.3f} ms, rel err {rel:.2e}")
+    for name in ("fp32", "bf16"):
+        out[name]["speedup_vs_fp64"] = round(out["fp64"]["ms"] / out[name]["ms"], 3)
+    out["workload"] = w.name
+    out["error_sample"] = f"all rows of {nleaves} seeded leaves vs the FP64 oracle"
+    return out
 
 
 def main():
@@ -110,7 +191,11 @@ def main():
     ap.add_argument("--workload", default=W.C2.name, choices=sorted(W.WORKLOADS))
     ap.add_argument("--storage", default="fp64", choices=sorted(STORAGE))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-modes", action="store_true", help="skip the 3-D storage-mode comparison")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="first run one device-to-device copy of this many GiB (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -118,48 +203,28 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1902_01829_amd import h2mv
+    torch.cuda.set_device(0)
+    if args.calibrate_copy_gib > 0:
+        nel = int(args.calibrate_copy_gib * (1 << 30)) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nel * 8} bytes read, {nel * 8} bytes written")
+        del src, dst
 
     w = W.WORKLOADS[args.workload]
-    storage = STORAGE[args.storage]
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    print(f"[bench] building {w.name} storage={args.storage}", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=storage)
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
-    info = A.info
-    perm = A.perm()
-    xt = W.rhs(w, 1)[perm]
-    x = torch.from_numpy(xt).cuda()
-    y = torch.empty_like(x)
-    print(f"[bench] built in {build_s:.1f} s: {info.coupling_blocks} coupling, {info.dense_blocks} dense blocks, "
-          f"{info.bytes_device_total / 1e9:.2f} GB on device", file=sys.stderr, flush=True)
-
-    for _ in range(args.warmup):
-        A.matvec(x, out=y)
-    torch.cuda.synchronize()
-    h2mv.h2_profile(A.handle, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        h2mv.h2_matvec(A.handle, x.data_ptr(), y.data_ptr(), stream.cuda_stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    phase_ms, calls = h2mv.h2_profile_read(A.handle)
-    h2mv.h2_profile(A.handle, False)
-    ms = (t1 - t0) * 1e3 / args.steps
+    log(f"building {w.name} storage={args.storage}")
+    r = run_matvec(w, STORAGE[args.storage], args.steps, args.warmup)
+    info, ms, phase = r["info"], r["ms"], r["phase_ms"]
     nbytes = algorithmic_bytes(info, w.n)
     value = nbytes / (ms * 1e-3) / 1e9
-    stream_ms = phase_ms[1] / max(calls, 1)
-    sk_bytes = stream_kernel_bytes(info, w.n, storage)
-    achieved = sk_bytes / (stream_ms * 1e-3) / 1e9
-    y_host = y.cpu().numpy()
-    print(f"[bench] {ms:.3f} ms/step, {value:.1f} GB/s; phases ms/call up {phase_ms[0] / calls:.3f} "
-          f"stream {stream_ms:.3f} down {phase_ms[2] / calls:.3f} leaf {phase_ms[3] / calls:.3f}",
-          file=sys.stderr, flush=True)
-
+    sk_bytes = stream_kernel_bytes(info, w.n, STORAGE[args.storage])
+    achieved = sk_bytes / (phase[1] * 1e-3) / 1e9
+    log(f"{ms:.3f} ms/step, {value:.1f} GB/s; phases ms/call up {phase[0]:.3f} stream {phase[1]:.3f} "
+        f"down {phase[2]:.3f} leaf {phase[3]:.3f}")
+    traffic = MEASURED_TRAFFIC.get((w.name, args.storage))
     result = {
         "metric": "H2 matvec GB/s & % HBM peak; BF16/FP32/batched vs FP64 speedup at rel err",
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -169,22 +234,24 @@ def main():
                    "corr_len": w.corr_len, "eta": w.eta, "nrhs": 1, "storage": args.storage,
                    "coupling_blocks": info.coupling_blocks, "dense_blocks": info.dense_blocks,
                    "algorithmic_bytes": nbytes, "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
-                   "build_s": round(build_s, 2)},
-        "phases_ms": {"upsweep": round(phase_ms[0] / calls, 4), "stream": round(stream_ms, 4),
-                      "downsweep": round(phase_ms[2] / calls, 4), "leaf_expand": round(phase_ms[3] / calls, 4),
-                      "call": round(phase_ms[4] / calls, 4)},
-        "roofline": {"bound": "hbm", "kernel": "blockrow_kernel (coupling all levels + dense)",
+                   "build_s": round(r["build_s"], 2)},
+        "phases_ms": {"upsweep": round(float(phase[0]), 4), "stream": round(float(phase[1]), 4),
+                      "downsweep": round(float(phase[2]), 4), "leaf_expand": round(float(phase[3]), 4),
+                      "call": round(float(phase[4]), 4)},
+        "roofline": {"bound": "hbm", "kernel": "stream_kernel (coupling blocks of all levels + dense blocks)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": MEASURED_TRAFFIC.get((w.name, args.storage))},
+                     "traffic": None if traffic is None else int(traffic),
+                     "algorithmic_bytes": int(sk_bytes)},
     }
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        cb, leaves, rows, y_ref = cpu_baseline(w, perm, xt, args.cpu_budget)
+        log("timing the CPU oracle on a sample")
+        cb, rows, y_ref = cpu_baseline(w, r["perm"], r["xt"], args.cpu_budget)
         result["cpu_baseline"] = cb
-        result["rel_err_vs_oracle_sample"] = float(np.linalg.norm(y_host[rows] - y_ref) / np.linalg.norm(y_ref))
+        result["rel_err_vs_oracle_sample"] = float(np.linalg.norm(r["y"][rows] - y_ref) / np.linalg.norm(y_ref))
+    if not args.no_modes:
+        result["storage_modes"] = storage_modes(args.steps, args.warmup)
     print(json.dumps(result), flush=True)
-    A.close()
 
 
 if __name__ == "__main__":

@@ -373,7 +373,7 @@ void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st) {
                 L.out1 = y;
                 break;
         }
-        check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, w.phase == PH_LEAF, st), "blockrow launch");
+        check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, int(w.phase), st), "blockrow launch");
     }
     if (A.prof) {
         while (next_phase <= PH_COUNT) check_hip(hipEventRecord(ev[next_phase++], st), "hipEventRecord");

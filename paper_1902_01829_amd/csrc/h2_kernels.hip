@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void fill_blocks_bf16_kernel(Geometry g, uint1
 // accumulates the block's dot products.  One block's partial sum is kept in
 // the block arithmetic type, sums over blocks in FP64.
 template <int KIND, typename TV, typename TO1>
-__global__ __launch_bounds__(256) void blockrow_kernel(
+__device__ __forceinline__ void blockrow_body(
     const RowDesc *__restrict__ rows, int64_t nrows, const BlkDesc *__restrict__ blks,
     const typename Elem<KIND>::T *__restrict__ data, const float *__restrict__ scales,
     const TV *__restrict__ in0, const double *__restrict__ in1, const TV *__restrict__ init,
@@ -318,16 +318,52 @@ __global__ __launch_bounds__(256) void blockrow_kernel(
     }
 }
 
+// One kernel name per phase of the product, so that traces and per-kernel
+// statistics separate them; all share the block-row body.
+#define H2_BLOCKROW_KERNEL(NAME)                                                                         \
+    template <int KIND, typename TV, typename TO1>                                                      \
+    __global__ __launch_bounds__(256) void NAME(                                                        \
+        const RowDesc *__restrict__ rows, int64_t nrows, const BlkDesc *__restrict__ blks,              \
+        const typename Elem<KIND>::T *__restrict__ data, const float *__restrict__ scales,               \
+        const TV *__restrict__ in0, const double *__restrict__ in1, const TV *__restrict__ init,         \
+        TV *__restrict__ out0, TO1 *__restrict__ out1) {                                                 \
+        blockrow_body<KIND, TV, TO1>(rows, nrows, blks, data, scales, in0, in1, init, out0, out1);      \
+    }
+H2_BLOCKROW_KERNEL(upsweep_kernel)
+H2_BLOCKROW_KERNEL(stream_kernel)
+H2_BLOCKROW_KERNEL(downsweep_kernel)
+H2_BLOCKROW_KERNEL(leafexpand_kernel)
+#undef H2_BLOCKROW_KERNEL
+
 constexpr int kRowsPerBlock = 4;
 
 template <int KIND, typename TV, typename TO1>
-hipError_t run_blockrow(const RowLaunch &L, hipStream_t st) {
+hipError_t run_blockrow(const RowLaunch &L, int phase, hipStream_t st) {
     if (L.nrows <= 0) return hipSuccess;
-    const int64_t grid = (L.nrows + kRowsPerBlock - 1) / kRowsPerBlock;
-    hipLaunchKernelGGL((blockrow_kernel<KIND, TV, TO1>), dim3(unsigned(grid)), dim3(256), 0, st, L.rows,
-                       L.nrows, L.blks, static_cast<const typename Elem<KIND>::T *>(L.data), L.scales,
-                       static_cast<const TV *>(L.in0), L.in1, static_cast<const TV *>(L.init),
-                       static_cast<TV *>(L.out0), static_cast<TO1 *>(L.out1));
+    const dim3 grid(unsigned((L.nrows + kRowsPerBlock - 1) / kRowsPerBlock)), block(256);
+    const auto *data = static_cast<const typename Elem<KIND>::T *>(L.data);
+    const auto *in0 = static_cast<const TV *>(L.in0);
+    const auto *init = static_cast<const TV *>(L.init);
+    auto *out0 = static_cast<TV *>(L.out0);
+    auto *out1 = static_cast<TO1 *>(L.out1);
+    switch (phase) {
+        case PHASE_UP:
+            hipLaunchKernelGGL((upsweep_kernel<KIND, TV, TO1>), grid, block, 0, st, L.rows, L.nrows, L.blks, data,
+                               L.scales, in0, L.in1, init, out0, out1);
+            break;
+        case PHASE_STREAM:
+            hipLaunchKernelGGL((stream_kernel<KIND, TV, TO1>), grid, block, 0, st, L.rows, L.nrows, L.blks, data,
+                               L.scales, in0, L.in1, init, out0, out1);
+            break;
+        case PHASE_DOWN:
+            hipLaunchKernelGGL((downsweep_kernel<KIND, TV, TO1>), grid, block, 0, st, L.rows, L.nrows, L.blks,
+                               data, L.scales, in0, L.in1, init, out0, out1);
+            break;
+        default:
+            hipLaunchKernelGGL((leafexpand_kernel<KIND, TV, TO1>), grid, block, 0, st, L.rows, L.nrows, L.blks,
+                               data, L.scales, in0, L.in1, init, out0, out1);
+            break;
+    }
     return hipGetLastError();
 }
 
@@ -380,11 +416,14 @@ hipError_t launch_fill_blocks(const Geometry &g, int block_kind, void *blocks, f
     return hipSuccess;
 }
 
-hipError_t launch_blockrow(const RowLaunch &L, int kind, bool vec_f64, bool out1_f64, hipStream_t st) {
-    if (vec_f64) return run_blockrow<ELEM_F64, double, double>(L, st);
+hipError_t launch_blockrow(const RowLaunch &L, int kind, bool vec_f64, int phase, hipStream_t st) {
+    const bool out1_f64 = phase == PHASE_LEAF;
+    if (vec_f64) return run_blockrow<ELEM_F64, double, double>(L, phase, st);
     if (kind == ELEM_F32)
-        return out1_f64 ? run_blockrow<ELEM_F32, float, double>(L, st) : run_blockrow<ELEM_F32, float, float>(L, st);
-    return out1_f64 ? run_blockrow<ELEM_BF16, float, double>(L, st) : run_blockrow<ELEM_BF16, float, float>(L, st);
+        return out1_f64 ? run_blockrow<ELEM_F32, float, double>(L, phase, st)
+                        : run_blockrow<ELEM_F32, float, float>(L, phase, st);
+    return out1_f64 ? run_blockrow<ELEM_BF16, float, double>(L, phase, st)
+                    : run_blockrow<ELEM_BF16, float, float>(L, phase, st);
 }
 
 }  // namespace h2
