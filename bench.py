@@ -183,6 +183,57 @@ def storage_modes(steps, warmup, nleaves=16):
     return out
 
 
+def matmat_modes(steps, warmup, fp64_matvec_ms, nleaves=8):
+    """The 2^20-point 2-D workload with 32 right-hand sides on the matrix cores,
+    FP32 and BF16 storage, against 32 single-vector FP64 products."""
+    import torch
+    from paper_1902_01829_amd import h2mv
+    w = W.C4
+    out = {"workload": w.name, "nrhs": w.nrhs,
+           "fp64_32_matvecs_ms": round(32 * fp64_matvec_ms, 3)}
+    for name in ("fp32", "bf16"):
+        A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=STORAGE[name])
+        info, perm = A.info, A.perm()
+        Xt = np.ascontiguousarray(W.rhs(w).T[:, perm])
+        X = torch.from_numpy(Xt).cuda()
+        Y = torch.empty_like(X)
+        for _ in range(warmup):
+            A.matmat(X, out=Y)
+        torch.cuda.synchronize()
+        h2mv.h2_profile(A.handle, True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            A.matmat(X, out=Y)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        phase_ms, calls = h2mv.h2_profile_read(A.handle)
+        h2mv.h2_profile(A.handle, False)
+        Yh = Y.cpu().numpy()
+        A.close()
+        del X, Y
+        torch.cuda.empty_cache()
+        nbytes = algorithmic_bytes(info, w.n, w.nrhs)
+        entries = (info.bytes_coupling + info.bytes_dense + info.bytes_leaf_bases + info.bytes_transfers) / \
+            (4 if name == "fp32" else 1)
+        if name == "bf16":   # blocks are 2 bytes (+4 per block scale), bases 4 bytes
+            entries = (info.bytes_coupling - 4 * info.coupling_blocks + info.bytes_dense - 4 * info.dense_blocks) / 2 \
+                + (info.bytes_leaf_bases + info.bytes_transfers) / 4
+        flops = 2.0 * entries * w.nrhs
+        errs = []
+        for j in (0, 31):
+            rows, ref = oracle_sample(w, perm, Xt[j], nleaves, seed=13)
+            errs.append(float(np.linalg.norm(Yh[j][rows] - ref) / np.linalg.norm(ref)))
+        out[name] = {"ms": round(ms, 4), "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     "TFLOP_per_s": round(flops / (ms * 1e-3) / 1e12, 2), "algorithmic_bytes": nbytes,
+                     "flops": flops, "stream_ms": round(float(phase_ms[1] / max(calls, 1)), 4),
+                     "speedup_vs_32_fp64_matvecs": round(32 * fp64_matvec_ms / ms, 2),
+                     "rel_err_vs_fp64_oracle_max": max(errs)}
+        log(f"{w.name} matmat {name}: {ms:.3f} ms, {out[name]['GB_per_s']} GB/s, "
+            f"{out[name]['TFLOP_per_s']} TFLOP/s, rel err {max(errs):.2e}")
+    out["error_sample"] = f"columns 0 and 31, all rows of {nleaves} seeded leaves vs the FP64 oracle"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +302,9 @@ def main():
         result["rel_err_vs_oracle_sample"] = float(np.linalg.norm(r["y"][rows] - y_ref) / np.linalg.norm(y_ref))
     if not args.no_modes:
         result["storage_modes"] = storage_modes(args.steps, args.warmup)
+        fp64_ms = ms if (w.name == W.C2.name and args.storage == "fp64") else None
+        if fp64_ms is not None:
+            result["matmat"] = matmat_modes(max(3, args.steps // 4), 1, fp64_ms)
     print(json.dumps(result), flush=True)
 
 

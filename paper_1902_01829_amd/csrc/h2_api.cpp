@@ -95,7 +95,11 @@ struct h2_matrix_ {
     void *basis = nullptr, *blocks = nullptr;
     float *scales = nullptr;
     void *xh = nullptr, *yh = nullptr, *ynear = nullptr;
-    std::vector<WorkList> lists;
+    std::vector<WorkList> lists;      // single right-hand side (vector offsets)
+    std::vector<WorkList> mm_lists;   // tiles of MM_TILE right-hand sides (tile offsets)
+    int64_t tile_slot = 0;            // elements per leaf in point tiles
+    int64_t *d_leaf_begin = nullptr, *d_leaf_end = nullptr;
+    float *t_xh = nullptr, *t_yh = nullptr, *t_x = nullptr, *t_ynear = nullptr;   // tile workspace (lazy)
     int64_t bytes_coupling = 0, bytes_dense = 0, bytes_leaf = 0, bytes_transfer = 0;
     // profiling: PH_COUNT + 1 events per recorded call
     bool prof = false;
@@ -213,9 +217,50 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
     A.yh = A.mem.alloc(s.nnodes * k * vb);
     A.ynear = A.mem.alloc(s.n * vb);
 
-    std::vector<RowDesc> rows;
-    std::vector<BlkDesc> blks;
-    auto flush = [&](Phase ph, int kind, const void *data) {
+    // Work lists in launch order.  Rows are first built logically: each
+    // operand names either a tree node's vector (x^ / y^) or a leaf's segment of
+    // the point vectors (x, y_near, y); they are then encoded twice, with
+    // single-vector offsets and with tile offsets for many right-hand sides.
+    struct LBlk {
+        int64_t a;
+        int32_t C, sidx;
+        bool point;
+        int64_t id;
+    };
+    struct LRow {
+        bool point;      // output is a leaf segment (else a tree node)
+        int64_t id;      // leaf index or node id
+        bool has_init;   // add the current value (downsweep: y^; leaf phase: y_near)
+        int R, sel;
+        std::vector<LBlk> b;
+    };
+    const int64_t kp = (k + 15) / 16 * 16;
+    int64_t mmax = 0;
+    for (int64_t j = 0; j < nleaves; ++j) mmax = std::max(mmax, s.size(lf + j));
+    A.tile_slot = (mmax + 15) / 16 * 16 * h2::MM_TILE;
+    auto mv_off = [&](bool point, int64_t id) { return point ? s.begin[lf + id] : id * k; };
+    auto mm_off = [&](bool point, int64_t id) { return point ? id * A.tile_slot : id * kp * h2::MM_TILE; };
+    // enc 0: single-vector offsets into A.lists; enc 1: tile offsets into A.mm_lists
+    auto emit_one = [&](int enc, Phase ph, int kind, const void *data, const std::vector<LRow> &L) {
+        std::vector<RowDesc> rows;
+        std::vector<BlkDesc> blks;
+        for (const LRow &r : L) {
+            RowDesc d;
+            if (ph == PH_LEAF) {   // out: rows of y; init: y_near
+                d.out = s.begin[lf + r.id];
+                d.init = enc == 0 ? mv_off(true, r.id) : mm_off(true, r.id);
+            } else {
+                d.out = enc == 0 ? mv_off(r.point, r.id) : mm_off(r.point, r.id);
+                d.init = !r.has_init ? -1 : enc == 0 ? mv_off(r.point, r.id) : mm_off(r.point, r.id);
+            }
+            d.b0 = int32_t(blks.size());
+            for (const LBlk &b : r.b)
+                blks.push_back({b.a, enc == 0 ? mv_off(b.point, b.id) : mm_off(b.point, b.id), b.C, b.sidx});
+            d.b1 = int32_t(blks.size());
+            d.R = r.R;
+            d.sel = r.sel;
+            rows.push_back(d);
+        }
         WorkList w;
         w.phase = ph;
         w.kind = kind;
@@ -223,34 +268,27 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
         w.nrows = int64_t(rows.size());
         w.rows = A.mem.upload(rows, stream);
         w.blks = A.mem.upload(blks, stream);
-        A.lists.push_back(w);
-        rows.clear();
-        blks.clear();
+        (enc == 0 ? A.lists : A.mm_lists).push_back(w);
     };
-    auto row = [&](int64_t out, int64_t init, int R, int sel) {
-        const int32_t b = int32_t(blks.size());
-        rows.push_back({out, init, b, b, R, sel});
+    auto emit = [&](Phase ph, int kind, const void *data, std::vector<LRow> &L) {
+        emit_one(0, ph, kind, data, L);
+        emit_one(1, ph, kind, data, L);
+        L.clear();
     };
-    auto blk = [&](int64_t a, int64_t in, int C, int64_t sidx) {
-        blks.push_back({a, int32_t(in), C, int32_t(sidx), 0});
-        rows.back().b1 = int32_t(blks.size());
-    };
-
+    std::vector<LRow> L;
     if (lowrank) {
         // leaf projection x^_j = V_j^T x(j)   (Sec. 4.2)
         for (int64_t j = 0; j < nleaves; ++j) {
             const int64_t v = lf + j;
-            row(v * k, -1, k, h2::ROW_IN_X);
-            blk(off_VT[j], s.begin[v], int(s.size(v)), 0);
+            L.push_back({false, v, false, k, h2::ROW_IN_X, {{off_VT[j], int32_t(s.size(v)), 0, true, j}}});
         }
-        flush(PH_UP, bk, A.basis);
+        emit(PH_UP, bk, A.basis, L);
         // upsweep x^_p = F_c1^T x^_c1 + F_c2^T x^_c2 for levels q .. lmin+1   (Sec. 4.2)
         for (int l = q; l > s.lmin; --l) {
-            for (int64_t p = Structure::first(l - 1); p < Structure::first(l); ++p) {
-                row(p * k, -1, k, 0);
-                for (int64_t c = 2 * p + 1; c <= 2 * p + 2; ++c) blk(off_FT[c], c * k, k, 0);
-            }
-            flush(PH_UP, bk, A.basis);
+            for (int64_t p = Structure::first(l - 1); p < Structure::first(l); ++p)
+                L.push_back({false, p, false, k, 0,
+                             {{off_FT[2 * p + 1], k, 0, false, 2 * p + 1}, {off_FT[2 * p + 2], k, 0, false, 2 * p + 2}}});
+            emit(PH_UP, bk, A.basis, L);
         }
     }
     // tree multiplication y^_i = sum_j S_ij x^_j on all levels (Sec. 4.3) and the
@@ -262,42 +300,60 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
                 const h2::Bsr &B = s.coupling[l];
                 const int64_t f = Structure::first(l);
                 for (int64_t i = 0; i < (int64_t(1) << l); ++i) {
-                    row((f + i) * k, -1, k, 0);
+                    LRow r{false, f + i, false, k, 0, {}};
                     for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b, ++fi)
-                        blk(fill[fi].a, (f + B.colidx[b]) * k, k, fill[fi].sidx);
+                        r.b.push_back({fill[fi].a, k, fill[fi].sidx, false, f + B.colidx[b]});
+                    L.push_back(std::move(r));
                 }
             }
         fi = ncoupling;
         for (int64_t i = 0; i < nleaves; ++i) {
-            const int64_t v = lf + i;
-            row(s.begin[v], -1, int(s.size(v)), h2::ROW_IN_X | h2::ROW_OUT_P);
+            LRow r{true, i, false, int(s.size(lf + i)), h2::ROW_IN_X | h2::ROW_OUT_P, {}};
             for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++fi) {
-                const int64_t t = lf + s.dense.colidx[b];
-                blk(fill[fi].a, s.begin[t], int(s.size(t)), fill[fi].sidx);
+                const int64_t t = s.dense.colidx[b];
+                r.b.push_back({fill[fi].a, int32_t(s.size(lf + t)), fill[fi].sidx, true, t});
             }
+            L.push_back(std::move(r));
         }
-        // longest rows first: the wavefronts that start last are the short ones
-        std::stable_sort(rows.begin(), rows.end(),
-                         [](const RowDesc &a, const RowDesc &b) { return a.b1 - a.b0 > b.b1 - b.b0; });
-        flush(PH_STREAM, sk, A.blocks);
+        // Tile lists (many right-hand sides): the input tiles (k x 32 per node)
+        // outgrow the last-level cache, so rows stay in spatial order -- leaf rows
+        // (dense) first, then coupling rows from the finest level up, each by
+        // index -- and concurrently running rows share their input tiles.
+        std::vector<LRow> spatial;
+        for (const LRow &r : L)
+            if (r.point) spatial.push_back(r);
+        for (int l = q; l >= s.lmin && lowrank; --l)
+            for (const LRow &r : L)
+                if (!r.point && r.id >= Structure::first(l) && r.id < Structure::first(l + 1)) spatial.push_back(r);
+        emit_one(1, PH_STREAM, sk, A.blocks, spatial);
+        // Single right-hand side: the vector trees fit in the caches; longest
+        // rows first, so the wavefronts that start last are the short ones.
+        std::stable_sort(L.begin(), L.end(), [](const LRow &a, const LRow &b) { return a.b.size() > b.b.size(); });
+        emit_one(0, PH_STREAM, sk, A.blocks, L);
+        L.clear();
     }
     if (lowrank) {
         // downsweep y^_c += E_c y^_parent for levels lmin+1 .. q   (Sec. 4.4)
         for (int l = s.lmin + 1; l <= q; ++l) {
-            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
-                row(c * k, c * k, k, 0);
-                blk(off_E[c], ((c - 1) / 2) * k, k, 0);
-            }
-            flush(PH_DOWN, bk, A.basis);
+            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c)
+                L.push_back({false, c, true, k, 0, {{off_E[c], k, 0, false, (c - 1) / 2}}});
+            emit(PH_DOWN, bk, A.basis, L);
         }
     }
     // leaf expansion and sum: y(i) = y_near(i) + U_i y^_i   (Sec. 4.4, Sec. 4.1)
     for (int64_t j = 0; j < nleaves; ++j) {
-        const int64_t v = lf + j;
-        row(s.begin[v], s.begin[v], int(s.size(v)), h2::ROW_OUT_P);
-        if (lowrank) blk(off_U[j], v * k, k, 0);
+        LRow r{true, j, true, int(s.size(lf + j)), h2::ROW_OUT_P, {}};
+        if (lowrank) r.b.push_back({off_U[j], k, 0, false, lf + j});
+        L.push_back(std::move(r));
     }
-    flush(PH_LEAF, bk, A.basis);
+    emit(PH_LEAF, bk, A.basis, L);
+    std::vector<int64_t> lb(nleaves), le(nleaves);
+    for (int64_t j = 0; j < nleaves; ++j) {
+        lb[j] = s.begin[lf + j];
+        le[j] = s.end[lf + j];
+    }
+    A.d_leaf_begin = A.mem.upload(lb, stream);
+    A.d_leaf_end = A.mem.upload(le, stream);
     check_hip(hipStreamSynchronize(stream), "upload work lists");
 }
 
@@ -333,15 +389,28 @@ hipEvent_t take_event(h2_matrix_ &A) {
     return e;
 }
 
-// Enqueues the whole product on st.  x is the point vector, y the result.
-void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st) {
+// Enqueues the lists in order, with profiling events at phase boundaries
+// when enabled; launch(w) enqueues one list.
+template <class Launch>
+void run_lists(h2_matrix_ &A, const std::vector<WorkList> &lists, hipStream_t st, Launch launch) {
     hipEvent_t ev[PH_COUNT + 1] = {};
     if (A.prof)
         for (auto &e : ev) e = take_event(A);
     int next_phase = 0;   // lists are in phase order; each phase's event precedes its lists
-    for (const WorkList &w : A.lists) {
+    for (const WorkList &w : lists) {
         while (A.prof && next_phase <= int(w.phase))
             check_hip(hipEventRecord(ev[next_phase++], st), "hipEventRecord");
+        launch(w);
+    }
+    if (A.prof) {
+        while (next_phase <= PH_COUNT) check_hip(hipEventRecord(ev[next_phase++], st), "hipEventRecord");
+        A.pending.insert(A.pending.end(), ev, ev + PH_COUNT + 1);
+    }
+}
+
+// Enqueues the whole single-vector product on st.
+void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st) {
+    run_lists(A, A.lists, st, [&](const WorkList &w) {
         h2::RowLaunch L;
         L.rows = w.rows;
         L.nrows = w.nrows;
@@ -374,10 +443,64 @@ void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st) {
                 break;
         }
         check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, int(w.phase), st), "blockrow launch");
-    }
-    if (A.prof) {
-        while (next_phase <= PH_COUNT) check_hip(hipEventRecord(ev[next_phase++], st), "hipEventRecord");
-        A.pending.insert(A.pending.end(), ev, ev + PH_COUNT + 1);
+    });
+}
+
+// Tile workspace of the many-right-hand-side product, allocated at first use.
+void ensure_tiles(h2_matrix_ &A) {
+    if (A.t_xh) return;
+    const int64_t kp = (A.st.rank + 15) / 16 * 16;
+    const int64_t tree = A.st.nnodes * kp * h2::MM_TILE, pts = (int64_t(1) << A.st.q) * A.tile_slot;
+    A.t_xh = static_cast<float *>(A.mem.alloc(tree * 4));
+    A.t_yh = static_cast<float *>(A.mem.alloc(tree * 4));
+    A.t_x = static_cast<float *>(A.mem.alloc(pts * 4));
+    A.t_ynear = static_cast<float *>(A.mem.alloc(pts * 4));
+}
+
+// Y = A X on the matrix cores, MM_TILE right-hand sides per pass.
+void run_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, hipStream_t st) {
+    ensure_tiles(A);
+    const int64_t nleaves = int64_t(1) << A.st.q;
+    for (int j0 = 0; j0 < nrhs; j0 += h2::MM_TILE) {
+        check_hip(h2::launch_pack(X, ldx, j0, nrhs, A.d_leaf_begin, A.d_leaf_end, nleaves, A.tile_slot, A.t_x, st),
+                  "pack launch");
+        run_lists(A, A.mm_lists, st, [&](const WorkList &w) {
+            h2::MmLaunch L;
+            L.rows = w.rows;
+            L.nrows = w.nrows;
+            L.blks = w.blks;
+            L.data = w.data;
+            L.scales = A.scales;
+            L.in_tree = nullptr;
+            L.in_pts = A.t_x;
+            L.init = nullptr;
+            L.out_tree = nullptr;
+            L.out_pts = nullptr;
+            L.Y = Y + int64_t(j0) * ldy;
+            L.ldy = ldy;
+            L.ncols = std::min(h2::MM_TILE, nrhs - j0);
+            switch (w.phase) {
+                case PH_UP:
+                    L.in_tree = A.t_xh;
+                    L.out_tree = A.t_xh;
+                    break;
+                case PH_STREAM:
+                    L.in_tree = A.t_xh;
+                    L.out_tree = A.t_yh;
+                    L.out_pts = A.t_ynear;
+                    break;
+                case PH_DOWN:
+                    L.in_tree = A.t_yh;
+                    L.init = A.t_yh;
+                    L.out_tree = A.t_yh;
+                    break;
+                default:
+                    L.in_tree = A.t_yh;
+                    L.init = A.t_ynear;
+                    break;
+            }
+            check_hip(h2::launch_mm(L, w.kind, w.phase == PH_LEAF, st), "mfma launch");
+        });
     }
 }
 
@@ -446,8 +569,13 @@ h2_status h2_matmat(h2_handle A, const double *X, int64_t ldx, double *Y, int64_
         if (A->structure_only) fail(H2_ERR_INVALID_ARG, "structure-only handle");
         if (nrhs < 1) fail(H2_ERR_INVALID_ARG, "nrhs must be >= 1");
         if (ldx < A->st.n || ldy < A->st.n) fail(H2_ERR_INVALID_ARG, "leading dimension below n");
-        for (int j = 0; j < nrhs; ++j)
-            run_product(*A, X + int64_t(j) * ldx, Y + int64_t(j) * ldy, static_cast<hipStream_t>(stream));
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        if (A->storage == H2_FP64) {
+            // FP64 storage: one single-vector product per column (FP64 arithmetic throughout)
+            for (int j = 0; j < nrhs; ++j) run_product(*A, X + int64_t(j) * ldx, Y + int64_t(j) * ldy, st);
+        } else {
+            run_tiles(*A, X, ldx, Y, ldy, nrhs, st);
+        }
         return H2_OK;
     } catch (const Failure &f) {
         g_last_error = f.what;

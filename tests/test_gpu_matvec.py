@@ -25,9 +25,13 @@ FP32_VS_FP64_TOL = 1e-6
 # BF16 keeps 8 significant bits: each stored entry carries a relative rounding
 # error up to 2^-9 (RMS ~1.1e-3 over a block's mantissas).  Dense blocks pass it
 # to y unchanged; coupling errors reach y through the interpolation bases,
-# whose Lebesgue constant (~1.7 per axis for 4 first-kind Chebyshev points)
-# amplifies them, more so with three axes.  Bounds: 2e-3 in 2-D, 4e-3 in 3-D.
-BF16_VS_FP64_TOL = {2: 2e-3, 3: 4e-3}
+# whose Lebesgue constant (~1.7 per axis for 4 first-kind Chebyshev points,
+# ~2.2 for 8) amplifies them, and more where leaves hold fewer points than the
+# rank (overcomplete leaf bases).  Bounds: 4e-3, 6e-3 with overcomplete leaves;
+# the 2^19-point 3-D workload (64-point leaves, rank 64) must meet 2e-3.
+BF16_VS_FP64_TOL = 4e-3
+BF16_OVERCOMPLETE_TOL = 6e-3
+BF16_VS_FP64_TOL_3D_512K = 2e-3
 
 
 def _h2mv():
@@ -146,12 +150,14 @@ def test_reduced_storage_small(oracle_mod, w, storage):
     rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
     print(f"  vs dequantized {relq:.3e}  vs fp64 {rel:.3e}", flush=True)
     assert relq <= REDUCED_VS_DEQUANT_TOL
-    assert rel <= (FP32_VS_FP64_TOL if storage == 1 else BF16_VS_FP64_TOL[w.dim])
+    overcomplete = w.n / 2 ** o64.q < w.rank
+    bf16_tol = BF16_OVERCOMPLETE_TOL if overcomplete else BF16_VS_FP64_TOL
+    assert rel <= (FP32_VS_FP64_TOL if storage == 1 else bf16_tol)
 
 
 @pytest.mark.parametrize("storage", [1, 2], ids=["fp32", "bf16"])
 def test_reduced_storage_full_3d_512k(oracle_mod, storage):
-    _sampled_parity(oracle_mod, W.C3, storage, 16, FP32_VS_FP64_TOL if storage == 1 else BF16_VS_FP64_TOL[3],
+    _sampled_parity(oracle_mod, W.C3, storage, 16, FP32_VS_FP64_TOL if storage == 1 else BF16_VS_FP64_TOL_3D_512K,
                     quant_ref_tol=REDUCED_VS_DEQUANT_TOL)
 
 
