@@ -40,6 +40,7 @@ extern "C" {
 #endif
 
 typedef struct h2_matrix_ *h2_handle;
+typedef struct h2_batch_ *h2_batch;
 
 typedef enum {
     H2_OK = 0,
@@ -116,6 +117,10 @@ h2_status h2_matvec(h2_handle A, const double *x, double *y, void *stream);
  * dense contraction.
  *  X  device, column-major n x nrhs, leading dimension ldx >= n, tree order.
  *  Y  device, column-major n x nrhs, leading dimension ldy >= n.
+ * H2_FP64 handles run nrhs FP64 products; H2_FP32 and H2_BF16_SCALED handles
+ * run on the matrix cores (FP32 MFMA), 32 right-hand sides per pass.  The first
+ * such call on a handle times the two block loops (pipelined or not) on its
+ * first pass and keeps the faster (cached like a batch's choice, below).
  * Errors: INVALID_ARG for nrhs < 1, ldx < n, ldy < n, NULL pointers or a
  * structure-only handle; DEVICE. */
 h2_status h2_matmat(h2_handle A, const double *X, int64_t ldx, double *Y, int64_t ldy,
@@ -146,6 +151,45 @@ h2_status h2_get_level_bsr(h2_handle A, int level, int64_t *count, int32_t *rowp
  * int64 number of calls recorded.  Reading the totals synchronizes the device. */
 h2_status h2_profile(h2_handle A, int enable);
 h2_status h2_profile_read(h2_handle A, double *ms, int64_t *calls);
+
+/* ---- Batches: many independent H^2 matrices per launch.
+ * The paper fixes one rank per level because its batched kernels need equal
+ * sizes, and names variable-size batches as future work (Sec. 3); here the
+ * members' per-level work lists are concatenated, so matrices of different n,
+ * rank and leaf size run together, one launch per level slot (upsweep slots
+ * aligned at the leaves, downsweep slots aligned at the leaves, one streaming
+ * and one leaf slot), the whole sequence captured once in a HIP graph and
+ * replayed.  The launch configuration (pipelined block loop or not, persistent
+ * grid size) is chosen by timing the candidates at the first product; the
+ * choice is cached per process and, when the environment variable
+ * H2MV_AUTOTUNE_CACHE names a file, in that file.
+ *
+ * h2_batch_create
+ *  mats    host, count handles, all built with the same storage, H2_FP32 or
+ *          H2_BF16_SCALED (H2_FP64 gives UNSUPPORTED); the handles must outlive
+ *          the batch and must not be used by other calls while a batch product
+ *          runs (the batch reads their representation).
+ *  nrhs    1 <= nrhs <= 32 right-hand sides per member (UNSUPPORTED above).
+ *  stream  stream for the set-up copies; the call returns when they are done.
+ *  out     host; receives the batch (NULL on error).
+ * The batch owns its tile workspace, a private stream and the graph.
+ *
+ * h2_batch_matmat: Y_b = A_b X_b for every member b.
+ *  X, Y    host arrays of count device pointers: member b's column-major
+ *          n_b x nrhs matrices (tree order), leading dimensions ldx[b], ldy[b]
+ *          (host arrays, >= n_b).
+ *  stream  the product is ordered after prior work on stream, and later work
+ *          on stream is ordered after it (it runs on the batch's stream).
+ * The first call also times the candidate configurations (runs the product
+ * several times).  Errors: INVALID_ARG for NULL pointers or ld < n; DEVICE. */
+h2_status h2_batch_create(const h2_handle *mats, int count, int nrhs, void *stream, h2_batch *out);
+h2_status h2_batch_matmat(h2_batch B, const double *const *X, const int64_t *ldx, double *const *Y,
+                          const int64_t *ldy, void *stream);
+/* Chosen configuration: pipelined (0/1), grid (workgroups; 0 = one per two
+ * rows) and the tuned time in ms of one product (-1 before the first product;
+ * 0 when the choice came from the cache). */
+h2_status h2_batch_tuning(h2_batch B, int *pipelined, int64_t *grid, double *tuned_ms);
+void h2_batch_free(h2_batch B);   /* NULL is a no-op; wait for running products first */
 
 /* Text of the last failure on this thread ("" if none). */
 const char *h2_last_error(void);

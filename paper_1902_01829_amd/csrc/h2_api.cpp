@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -97,9 +99,14 @@ struct h2_matrix_ {
     void *xh = nullptr, *yh = nullptr, *ynear = nullptr;
     std::vector<WorkList> lists;      // single right-hand side (vector offsets)
     std::vector<WorkList> mm_lists;   // tiles of MM_TILE right-hand sides (tile offsets)
+    std::vector<std::vector<h2::RowDesc>> mm_host_rows;   // host copies of mm_lists (for batches)
+    std::vector<std::vector<h2::BlkDesc>> mm_host_blks;
+    int64_t nscales = 0;
     int64_t tile_slot = 0;            // elements per leaf in point tiles
     int64_t *d_leaf_begin = nullptr, *d_leaf_end = nullptr;
     float *t_xh = nullptr, *t_yh = nullptr, *t_x = nullptr, *t_ynear = nullptr;   // tile workspace (lazy)
+    h2::MmConfig mm_cfg{1, 0};        // chosen at the first many-right-hand-side product
+    bool mm_tuned = false;
     int64_t bytes_coupling = 0, bytes_dense = 0, bytes_leaf = 0, bytes_transfer = 0;
     // profiling: PH_COUNT + 1 events per recorded call
     bool prof = false;
@@ -183,6 +190,7 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
     A.basis = A.mem.alloc(nb * eb);
     A.blocks = A.mem.alloc(ns * sb);
     A.scales = static_cast<float *>(A.mem.alloc(std::max<int64_t>(1, int64_t(fill.size())) * 4));
+    A.nscales = int64_t(fill.size());
     {
         DeviceArena scratch;   // geometry and fill lists, freed after the build
         if (A.mem.cap >= 0) scratch.cap = std::max<int64_t>(0, A.mem.cap - A.mem.bytes);
@@ -269,6 +277,10 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
         w.rows = A.mem.upload(rows, stream);
         w.blks = A.mem.upload(blks, stream);
         (enc == 0 ? A.lists : A.mm_lists).push_back(w);
+        if (enc == 1) {
+            A.mm_host_rows.push_back(std::move(rows));
+            A.mm_host_blks.push_back(std::move(blks));
+        }
     };
     auto emit = [&](Phase ph, int kind, const void *data, std::vector<LRow> &L) {
         emit_one(0, ph, kind, data, L);
@@ -457,11 +469,11 @@ void ensure_tiles(h2_matrix_ &A) {
     A.t_ynear = static_cast<float *>(A.mem.alloc(pts * 4));
 }
 
-// Y = A X on the matrix cores, MM_TILE right-hand sides per pass.
-void run_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, hipStream_t st) {
-    ensure_tiles(A);
+// One pass of up to MM_TILE right-hand sides on the matrix cores.
+void run_tile_pass(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, int j0,
+                   const h2::MmConfig &cfg, hipStream_t st) {
     const int64_t nleaves = int64_t(1) << A.st.q;
-    for (int j0 = 0; j0 < nrhs; j0 += h2::MM_TILE) {
+    {
         check_hip(h2::launch_pack(X, ldx, j0, nrhs, A.d_leaf_begin, A.d_leaf_end, nleaves, A.tile_slot, A.t_x, st),
                   "pack launch");
         run_lists(A, A.mm_lists, st, [&](const WorkList &w) {
@@ -499,9 +511,355 @@ void run_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t l
                     L.init = A.t_ynear;
                     break;
             }
-            check_hip(h2::launch_mm(L, w.kind, w.phase == PH_LEAF, st), "mfma launch");
+            check_hip(h2::launch_mm(L, w.kind, w.phase == PH_LEAF, cfg, st), "mfma launch");
         });
     }
+}
+
+// Chooses the block loop (pipelined or not) for this matrix by timing both on
+// its first product (the first pass's right-hand sides), unless cached.
+void tune_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, hipStream_t st);
+
+// Y = A X on the matrix cores, MM_TILE right-hand sides per pass.
+void run_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, hipStream_t st) {
+    ensure_tiles(A);
+    if (!A.mm_tuned) tune_tiles(A, X, ldx, Y, ldy, nrhs, st);
+    for (int j0 = 0; j0 < nrhs; j0 += h2::MM_TILE) run_tile_pass(A, X, ldx, Y, ldy, nrhs, j0, A.mm_cfg, st);
+}
+
+// ---------------------------------------------------------------- batches
+// Many H^2 matrices of uneven size and rank per launch: the members' tile
+// lists are concatenated per "level slot" -- upsweep lists aligned by their
+// distance from the leaves, downsweep lists aligned at their end (the leaf
+// level), one streaming slot and one leaf slot -- so every slot is one
+// grid-strided launch over all members.  Tiles of all members live in one
+// pool; block operands are absolute addresses into the members' storage.
+struct BatchSlot {
+    Phase phase;
+    int kind;
+    h2::RowDesc *rows;
+    int64_t nrows;
+    h2::BlkDesc *blks;
+};
+
+struct BatchConfigCache {
+    std::vector<std::pair<std::string, h2::MmConfig>> entries;
+};
+BatchConfigCache &config_cache() {
+    static BatchConfigCache c;
+    return c;
+}
+
+}  // namespace
+
+struct h2_batch_ {
+    std::vector<h2_matrix_ *> mats;
+    int nrhs = 0;
+    DeviceArena mem;
+    float *pool = nullptr;
+    float *scales = nullptr;
+    std::vector<BatchSlot> slots;
+    h2::PackEntry *pack = nullptr;
+    int64_t npack = 0;
+    double **d_Xtab = nullptr, **d_Ytab = nullptr;
+    int64_t *d_ldx = nullptr, *d_ldy = nullptr;
+    hipStream_t own = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    h2::MmConfig cfg{1, 0};
+    bool tuned = false;
+    double tuned_ms = 0.0;
+    std::string signature;
+    int64_t cu_count = 256;
+
+    ~h2_batch_() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (own) (void)hipStreamDestroy(own);
+    }
+};
+
+namespace {
+
+// Enqueues one batched product (tables already set) with configuration cfg.
+void batch_enqueue(h2_batch_ &B, const h2::MmConfig &cfg, hipStream_t st) {
+    check_hip(h2::launch_batch_pack(B.pack, B.npack, B.d_Xtab, B.d_ldx, B.nrhs, B.pool,
+                                    cfg.grid > 0 ? cfg.grid : 0, st),
+              "batch pack");
+    for (const BatchSlot &sl : B.slots) {
+        h2::MmBatchLaunch L{sl.rows, sl.nrows, sl.blks, B.scales, B.pool, B.d_Ytab, B.d_ldy, B.nrhs};
+        check_hip(h2::launch_mm_batch(L, sl.kind, sl.phase == PH_LEAF, cfg, st), "batch launch");
+    }
+}
+
+std::string config_file() {
+    const char *p = std::getenv("H2MV_AUTOTUNE_CACHE");
+    return p ? std::string(p) : std::string();
+}
+
+// The cache file holds one "signature pipelined grid" line per entry.
+bool cached_config(const std::string &sig, h2::MmConfig &cfg) {
+    for (auto &e : config_cache().entries)
+        if (e.first == sig) {
+            cfg = e.second;
+            return true;
+        }
+    const std::string f = config_file();
+    if (f.empty()) return false;
+    FILE *fp = std::fopen(f.c_str(), "r");
+    if (!fp) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, fp)) {
+        char key[400];
+        int pipe = 0;
+        long long grid = 0;
+        if (std::sscanf(line, "%399s %d %lld", key, &pipe, &grid) == 3 && sig == key) {
+            cfg = {pipe, grid};
+            found = true;
+        }
+    }
+    std::fclose(fp);
+    if (found) config_cache().entries.push_back({sig, cfg});
+    return found;
+}
+
+void store_config(const std::string &sig, const h2::MmConfig &cfg) {
+    config_cache().entries.push_back({sig, cfg});
+    const std::string f = config_file();
+    if (f.empty()) return;
+    if (FILE *fp = std::fopen(f.c_str(), "a")) {
+        std::fprintf(fp, "%s %d %lld\n", sig.c_str(), cfg.pipelined, static_cast<long long>(cfg.grid));
+        std::fclose(fp);
+    }
+}
+
+// Times every candidate configuration on the batch (tables set) and keeps the
+// fastest: pipelined block loop or not, times persistent grids of 2, 4 and 8
+// workgroups per compute unit or one workgroup per two rows.
+void batch_autotune(h2_batch_ &B) {
+    h2::MmConfig best{1, 0};
+    if (cached_config(B.signature, best)) {
+        B.cfg = best;
+        B.tuned = true;
+        return;
+    }
+    hipEvent_t t0, t1;
+    check_hip(hipEventCreate(&t0), "hipEventCreate");
+    check_hip(hipEventCreate(&t1), "hipEventCreate");
+    double best_ms = 1e30;
+    const int64_t grids[4] = {0, 2 * B.cu_count, 4 * B.cu_count, 8 * B.cu_count};
+    for (int pipe = 0; pipe < 2; ++pipe)
+        for (int64_t grid : grids) {
+            const h2::MmConfig c{pipe, grid};
+            batch_enqueue(B, c, B.own);   // warm-up
+            float ms_best = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                check_hip(hipEventRecord(t0, B.own), "hipEventRecord");
+                batch_enqueue(B, c, B.own);
+                check_hip(hipEventRecord(t1, B.own), "hipEventRecord");
+                check_hip(hipEventSynchronize(t1), "hipEventSynchronize");
+                float ms = 0.0f;
+                check_hip(hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
+                ms_best = std::min(ms_best, ms);
+            }
+            if (ms_best < best_ms) {
+                best_ms = ms_best;
+                best = c;
+            }
+        }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    B.cfg = best;
+    B.tuned = true;
+    B.tuned_ms = best_ms;
+    store_config(B.signature, best);
+}
+
+void tune_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, hipStream_t st) {
+    int64_t nblocks = 0;
+    for (const auto &hb : A.mm_host_blks) nblocks += int64_t(hb.size());
+    const std::string sig = "single-k" + std::to_string(A.block_kind) + "-n" + std::to_string(A.st.n) + "-r" +
+                            std::to_string(A.st.rank) + "-blocks" + std::to_string(nblocks);
+    h2::MmConfig best{1, 0};
+    if (!cached_config(sig, best)) {
+        const bool prof = A.prof;   // tuning runs stay out of the profile
+        A.prof = false;
+        hipEvent_t t0, t1;
+        check_hip(hipEventCreate(&t0), "hipEventCreate");
+        check_hip(hipEventCreate(&t1), "hipEventCreate");
+        float best_ms = 1e30f;
+        for (int pipe = 0; pipe < 2; ++pipe) {
+            const h2::MmConfig c{pipe, 0};
+            run_tile_pass(A, X, ldx, Y, ldy, nrhs, 0, c, st);   // warm-up
+            check_hip(hipEventRecord(t0, st), "hipEventRecord");
+            run_tile_pass(A, X, ldx, Y, ldy, nrhs, 0, c, st);
+            check_hip(hipEventRecord(t1, st), "hipEventRecord");
+            check_hip(hipEventSynchronize(t1), "hipEventSynchronize");
+            float ms = 0.0f;
+            check_hip(hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+        A.prof = prof;
+        store_config(sig, best);
+    }
+    A.mm_cfg = best;
+    A.mm_tuned = true;
+}
+
+void build_batch(h2_batch_ &B, hipStream_t stream) {
+    const int nm = int(B.mats.size());
+    const int kind_basis = B.mats[0]->basis_kind, kind_block = B.mats[0]->block_kind;
+    for (h2_matrix_ *M : B.mats) {
+        if (M->structure_only) fail(H2_ERR_INVALID_ARG, "structure-only member");
+        if (M->storage == H2_FP64) fail(H2_ERR_UNSUPPORTED, "batches need FP32 or BF16 storage");
+        if (M->basis_kind != kind_basis || M->block_kind != kind_block)
+            fail(H2_ERR_UNSUPPORTED, "all batch members need the same storage");
+    }
+    // pool layout and scale concatenation
+    std::vector<int64_t> xh(nm), yh(nm), xp(nm), yn(nm), sb(nm);
+    int64_t pool = 0, nsc = 0;
+    for (int b = 0; b < nm; ++b) {
+        const h2_matrix_ &M = *B.mats[b];
+        const int64_t kp = (M.st.rank + 15) / 16 * 16;
+        const int64_t tree = M.st.nnodes * kp * h2::MM_TILE, pts = (int64_t(1) << M.st.q) * M.tile_slot;
+        xh[b] = pool; pool += tree;
+        yh[b] = pool; pool += tree;
+        xp[b] = pool; pool += pts;
+        yn[b] = pool; pool += pts;
+        sb[b] = nsc; nsc += M.nscales;
+    }
+    B.pool = static_cast<float *>(B.mem.alloc(pool * 4));
+    B.scales = static_cast<float *>(B.mem.alloc(std::max<int64_t>(1, nsc) * 4));
+    for (int b = 0; b < nm; ++b)
+        if (B.mats[b]->nscales > 0)
+            check_hip(hipMemcpyAsync(B.scales + sb[b], B.mats[b]->scales, B.mats[b]->nscales * 4,
+                                     hipMemcpyDeviceToDevice, stream),
+                      "copy scales");
+    // per-member list indices by phase
+    std::vector<std::vector<int>> up(nm), down(nm);
+    std::vector<int> strm(nm, -1), leaf(nm, -1);
+    size_t nu = 0, nd = 0;
+    for (int b = 0; b < nm; ++b) {
+        const auto &L = B.mats[b]->mm_lists;
+        for (int li = 0; li < int(L.size()); ++li) {
+            if (L[li].phase == PH_UP) up[b].push_back(li);
+            if (L[li].phase == PH_DOWN) down[b].push_back(li);
+            if (L[li].phase == PH_STREAM) strm[b] = li;
+            if (L[li].phase == PH_LEAF) leaf[b] = li;
+        }
+        nu = std::max(nu, up[b].size());
+        nd = std::max(nd, down[b].size());
+    }
+    // translates member b's list li into the slot's rows/blocks
+    auto append = [&](int b, int li, std::vector<h2::RowDesc> &rows, std::vector<h2::BlkDesc> &blks) {
+        const h2_matrix_ &M = *B.mats[b];
+        const WorkList &w = M.mm_lists[li];
+        const int64_t es = h2::elem_bytes(w.kind);
+        const int64_t base = int64_t(reinterpret_cast<uintptr_t>(w.data));
+        const auto &hr = M.mm_host_rows[li];
+        const auto &hb = M.mm_host_blks[li];
+        for (const h2::RowDesc &r0 : hr) {
+            h2::RowDesc r = r0;
+            const bool in_x = (r.sel & h2::ROW_IN_X) != 0, out_p = (r.sel & h2::ROW_OUT_P) != 0;
+            int64_t in_base = 0;
+            switch (w.phase) {
+                case PH_UP:
+                    r.out += xh[b];
+                    in_base = in_x ? xp[b] : xh[b];
+                    break;
+                case PH_STREAM:
+                    r.out += out_p ? yn[b] : yh[b];
+                    in_base = in_x ? xp[b] : xh[b];
+                    break;
+                case PH_DOWN:
+                    r.out += yh[b];
+                    if (r.init >= 0) r.init += yh[b];
+                    in_base = yh[b];
+                    break;
+                default:
+                    r.init += yn[b];
+                    r.sel |= b << 8;
+                    in_base = yh[b];
+                    break;
+            }
+            const int32_t b0 = int32_t(blks.size());
+            for (int32_t k = r0.b0; k < r0.b1; ++k) {
+                h2::BlkDesc d = hb[k];
+                d.a = base + d.a * es;
+                d.in += in_base;
+                d.sidx += int32_t(sb[b]);
+                blks.push_back(d);
+            }
+            r.b0 = b0;
+            r.b1 = int32_t(blks.size());
+            rows.push_back(r);
+        }
+    };
+    auto add_slot = [&](Phase ph, int kind, std::vector<h2::RowDesc> &rows, std::vector<h2::BlkDesc> &blks) {
+        if (rows.empty()) return;
+        BatchSlot sl{ph, kind, B.mem.upload(rows, stream), int64_t(rows.size()), B.mem.upload(blks, stream)};
+        B.slots.push_back(sl);
+    };
+    std::vector<h2::RowDesc> rows;
+    std::vector<h2::BlkDesc> blks;
+    for (size_t j = 0; j < nu; ++j) {
+        rows.clear(); blks.clear();
+        for (int b = 0; b < nm; ++b)
+            if (j < up[b].size()) append(b, up[b][j], rows, blks);
+        add_slot(PH_UP, kind_basis, rows, blks);
+    }
+    rows.clear(); blks.clear();
+    for (int b = 0; b < nm; ++b) append(b, strm[b], rows, blks);
+    add_slot(PH_STREAM, kind_block, rows, blks);
+    for (size_t j = 0; j < nd; ++j) {
+        rows.clear(); blks.clear();
+        for (int b = 0; b < nm; ++b) {
+            const int64_t k = int64_t(j) - int64_t(nd - down[b].size());
+            if (k >= 0) append(b, down[b][k], rows, blks);
+        }
+        add_slot(PH_DOWN, kind_basis, rows, blks);
+    }
+    rows.clear(); blks.clear();
+    for (int b = 0; b < nm; ++b) append(b, leaf[b], rows, blks);
+    add_slot(PH_LEAF, kind_basis, rows, blks);
+    // point-tile pack entries
+    std::vector<h2::PackEntry> pe;
+    int64_t total_rows = 0, total_blocks = 0;
+    for (int b = 0; b < nm; ++b) {
+        const h2_matrix_ &M = *B.mats[b];
+        const int64_t nl = int64_t(1) << M.st.q, lf = Structure::first(M.st.q);
+        for (int64_t j = 0; j < nl; ++j)
+            pe.push_back({xp[b] + j * M.tile_slot, M.st.begin[lf + j], int32_t(M.st.size(lf + j)), b});
+    }
+    for (const BatchSlot &sl : B.slots) total_rows += sl.nrows;
+    for (h2_matrix_ *M : B.mats)
+        for (const auto &hb : M->mm_host_blks) total_blocks += int64_t(hb.size());
+    B.pack = B.mem.upload(pe, stream);
+    B.npack = int64_t(pe.size());
+    B.d_Xtab = static_cast<double **>(B.mem.alloc(nm * 8));
+    B.d_Ytab = static_cast<double **>(B.mem.alloc(nm * 8));
+    B.d_ldx = static_cast<int64_t *>(B.mem.alloc(nm * 8));
+    B.d_ldy = static_cast<int64_t *>(B.mem.alloc(nm * 8));
+    int dev = 0, cus = 256;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+    B.cu_count = cus;
+    B.signature = "batch-k" + std::to_string(kind_block) + "-r" + std::to_string(B.nrhs) + "-m" + std::to_string(nm) +
+                  "-rows" + std::to_string(total_rows) + "-blocks" + std::to_string(total_blocks) + "-cu" +
+                  std::to_string(cus);
+    check_hip(hipStreamCreateWithFlags(&B.own, hipStreamNonBlocking), "hipStreamCreate");
+    check_hip(hipEventCreateWithFlags(&B.ev_in, hipEventDisableTiming), "hipEventCreate");
+    check_hip(hipEventCreateWithFlags(&B.ev_out, hipEventDisableTiming), "hipEventCreate");
+    check_hip(hipStreamSynchronize(stream), "batch build");
 }
 
 }  // namespace
@@ -678,5 +1036,94 @@ h2_status h2_profile_read(h2_handle A, double *ms, int64_t *calls) {
         return f.code;
     }
 }
+
+h2_status h2_batch_create(const h2_handle *mats, int count, int nrhs, void *stream, h2_batch *out) {
+    if (out) *out = nullptr;
+    h2_batch_ *B = nullptr;
+    try {
+        if (!out || !mats || count < 1) fail(H2_ERR_INVALID_ARG, "NULL argument or count < 1");
+        if (nrhs < 1) fail(H2_ERR_INVALID_ARG, "nrhs must be >= 1");
+        if (nrhs > h2::MM_TILE) fail(H2_ERR_UNSUPPORTED, "batches take at most 32 right-hand sides");
+        B = new h2_batch_();
+        for (int b = 0; b < count; ++b) {
+            if (!mats[b]) fail(H2_ERR_INVALID_ARG, "NULL member");
+            B->mats.push_back(mats[b]);
+        }
+        B->nrhs = nrhs;
+        build_batch(*B, static_cast<hipStream_t>(stream));
+        *out = B;
+        return H2_OK;
+    } catch (const Failure &f) {
+        delete B;
+        g_last_error = f.what;
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        delete B;
+        g_last_error = "host allocation failed";
+        return H2_ERR_OOM;
+    } catch (...) {
+        delete B;
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+h2_status h2_batch_matmat(h2_batch B, const double *const *X, const int64_t *ldx, double *const *Y,
+                          const int64_t *ldy, void *stream) {
+    try {
+        if (!B || !X || !ldx || !Y || !ldy) fail(H2_ERR_INVALID_ARG, "NULL argument");
+        const int nm = int(B->mats.size());
+        std::vector<const double *> xt(nm);
+        std::vector<double *> yt(nm);
+        std::vector<int64_t> lx(nm), ly(nm);
+        for (int b = 0; b < nm; ++b) {
+            if (!X[b] || !Y[b]) fail(H2_ERR_INVALID_ARG, "NULL member matrix");
+            if (ldx[b] < B->mats[b]->st.n || ldy[b] < B->mats[b]->st.n)
+                fail(H2_ERR_INVALID_ARG, "leading dimension below n");
+            xt[b] = X[b];
+            yt[b] = Y[b];
+            lx[b] = ldx[b];
+            ly[b] = ldy[b];
+        }
+        const hipStream_t user = static_cast<hipStream_t>(stream);
+        check_hip(hipEventRecord(B->ev_in, user), "hipEventRecord");
+        check_hip(hipStreamWaitEvent(B->own, B->ev_in, 0), "hipStreamWaitEvent");
+        // pointer tables: outside the graph, copied from pageable memory (staged before return)
+        check_hip(hipMemcpyAsync(B->d_Xtab, xt.data(), nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
+        check_hip(hipMemcpyAsync(B->d_Ytab, yt.data(), nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
+        check_hip(hipMemcpyAsync(B->d_ldx, lx.data(), nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
+        check_hip(hipMemcpyAsync(B->d_ldy, ly.data(), nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
+        if (!B->tuned) batch_autotune(*B);
+        if (!B->exec) {
+            check_hip(hipStreamBeginCapture(B->own, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            batch_enqueue(*B, B->cfg, B->own);
+            check_hip(hipStreamEndCapture(B->own, &B->graph), "hipStreamEndCapture");
+            check_hip(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        }
+        check_hip(hipGraphLaunch(B->exec, B->own), "hipGraphLaunch");
+        check_hip(hipEventRecord(B->ev_out, B->own), "hipEventRecord");
+        check_hip(hipStreamWaitEvent(user, B->ev_out, 0), "hipStreamWaitEvent");
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (...) {
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+h2_status h2_batch_tuning(h2_batch B, int *pipelined, int64_t *grid, double *tuned_ms) {
+    if (!B || !pipelined || !grid || !tuned_ms) {
+        g_last_error = "NULL argument";
+        return H2_ERR_INVALID_ARG;
+    }
+    *pipelined = B->cfg.pipelined;
+    *grid = B->cfg.grid;
+    *tuned_ms = B->tuned ? B->tuned_ms : -1.0;
+    return H2_OK;
+}
+
+void h2_batch_free(h2_batch B) { delete B; }
 
 }  // extern "C"

@@ -61,7 +61,7 @@ struct TileB {
 // column groups past the block's width read its last group, which then meets
 // the zero padding rows of the input tile.
 template <int KIND>
-__device__ inline void load_a(const BlkDesc &bd, const void *data, int R, int ic, int lg, BlockA<KIND> &o) {
+__device__ inline void load_a(const BlkDesc &bd, const void *blk, int R, int ic, int lg, BlockA<KIND> &o) {
     const int C = bd.C, NP = round16(C) >> 3;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
@@ -69,13 +69,13 @@ __device__ inline void load_a(const BlkDesc &bd, const void *data, int R, int ic
         if constexpr (KIND == ELEM_F32) {
             const int CW = (C + 3) >> 2;                      // 4-column groups
             const int cg = 2 * p + lg, cgc = cg < CW ? cg : CW - 1;
-            o.v[p] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(
-                static_cast<const float *>(data) + bd.a + (int64_t(cgc) * R + ic) * 4));
+            o.v[p] = __builtin_nontemporal_load(
+                reinterpret_cast<const f32x4 *>(static_cast<const float *>(blk) + (int64_t(cgc) * R + ic) * 4));
         } else {
             const int CW = (C + 7) >> 3;                      // 8-column groups: half of one per lane
             const int pc = p < CW ? p : CW - 1;
             o.v[p] = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(
-                static_cast<const uint16_t *>(data) + bd.a + (int64_t(pc) * R + ic) * 8 + 4 * lg));
+                static_cast<const uint16_t *>(blk) + (int64_t(pc) * R + ic) * 8 + 4 * lg));
         }
     }
 }
@@ -115,30 +115,41 @@ __device__ inline f32x16 block_products(const BlockA<KIND> &a_op, const TileB &b
     return acc;
 }
 
-// Two wavefronts per output row segment, one per 32-row half (mt); a
-// workgroup of 4 wavefronts covers 2 segments.  Lane l owns block row
-// 32*mt + (l % 32) and right-hand side l % 32; for every 8 block columns
-// 8p .. 8p+7, lane group g = l / 32 supplies columns 8p + 4g + t (t = 0..3),
-// one per MFMA.  The block loop is software-pipelined: the loads of block
-// b + 1 are in flight while block b's products run.
-template <int KIND, bool LEAF>
-__global__ __launch_bounds__(256) void mm_kernel(const RowDesc *__restrict__ rows, int64_t nrows,
-                                                 const BlkDesc *__restrict__ blks, const void *__restrict__ data,
-                                                 const float *__restrict__ scales, const float *__restrict__ in_tree,
-                                                 const float *__restrict__ in_pts, const float *__restrict__ init,
-                                                 float *__restrict__ out_tree, float *__restrict__ out_pts,
-                                                 double *__restrict__ Y, int64_t ldy, int ncols) {
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int64_t row = xcd_local_order(blockIdx.x, gridDim.x) * 2 + (wv >> 1);
-    const int mt = wv & 1;
-    if (row >= nrows) return;
-    const RowDesc rd = rows[row];
+// Where a work list's operands live.  Single matrix: block offsets are
+// element offsets into the matrix's data array, tile offsets index the
+// separate tile buffers.  Batch: block "offsets" hold absolute addresses,
+// every tile offset indexes one pool, and the leaf phase finds each member's
+// result matrix in a device table (member index in RowDesc.sel >> 8).
+struct MmArgs {
+    const RowDesc *rows;
+    int64_t nrows;
+    const BlkDesc *blks;
+    const void *data;
+    const float *scales;
+    const float *in_tree, *in_pts, *init;
+    float *out_tree, *out_pts;
+    double *Y;
+    int64_t ldy;
+    double *const *Ytab;
+    const int64_t *ldytab;
+    int ncols;
+};
+
+// One output row segment half (mt) of the list, for one wavefront.  Lane l
+// owns block row 32*mt + (l % 32) and right-hand side l % 32; for every 8
+// block columns 8p .. 8p+7, lane group g = l / 32 supplies columns 8p + 4g + t
+// (t = 0..3), one per MFMA.  With PIPE the block loop is software-pipelined:
+// the loads of block b + 1 are in flight while block b's products run.
+template <int KIND, bool LEAF, bool BATCH, bool PIPE>
+__device__ inline void mm_row(const MmArgs &g, int64_t row, int mt, int lane) {
+    const RowDesc rd = g.rows[row];
     const int R = rd.R, Rp = round16(R);
     if (32 * mt >= R) return;
     const int li = lane & 31, lg = lane >> 5;
     const int i = 32 * mt + li;   // block row of this lane's A operand
     const int ic = i < R ? i : R - 1;
-    const float *xbase = (rd.sel & ROW_IN_X) ? in_pts : in_tree;
+    const float *xbase = (rd.sel & ROW_IN_X) ? g.in_pts : g.in_tree;
+    const void *data = g.data;
 
     double tot[16];
 #pragma unroll
@@ -147,26 +158,36 @@ __global__ __launch_bounds__(256) void mm_kernel(const RowDesc *__restrict__ row
     BlockA<KIND> a_cur, a_nxt;
     TileB b_cur, b_nxt;
     BlkDesc bd_cur, bd_nxt;
+    auto block_ptr = [&](const BlkDesc &bd) -> const void * {
+        if constexpr (BATCH) return reinterpret_cast<const void *>(bd.a);
+        else return static_cast<const char *>(data) + bd.a * (KIND == ELEM_F32 ? 4 : 2);
+    };
     if (rd.b0 < rd.b1) {
-        bd_cur = blks[rd.b0];
-        load_a<KIND>(bd_cur, data, R, ic, lg, a_cur);
+        bd_cur = g.blks[rd.b0];
+        load_a<KIND>(bd_cur, block_ptr(bd_cur), R, ic, lg, a_cur);
         load_b(bd_cur, xbase, li, lg, b_cur);
     }
     for (int b = rd.b0; b < rd.b1; ++b) {
         const bool more = b + 1 < rd.b1;
-        if (more) {
-            bd_nxt = blks[b + 1];
-            load_a<KIND>(bd_nxt, data, R, ic, lg, a_nxt);
+        if (PIPE && more) {
+            bd_nxt = g.blks[b + 1];
+            load_a<KIND>(bd_nxt, block_ptr(bd_nxt), R, ic, lg, a_nxt);
             load_b(bd_nxt, xbase, li, lg, b_nxt);
         }
         const f32x16 acc = block_products<KIND>(a_cur, b_cur, round16(bd_cur.C) >> 3);
-        const double sc = KIND == ELEM_BF16 ? double(scales[bd_cur.sidx]) : 1.0;
+        const double sc = KIND == ELEM_BF16 ? double(g.scales[bd_cur.sidx]) : 1.0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) tot[r] += sc * double(acc[r]);
         if (more) {
-            a_cur = a_nxt;
-            b_cur = b_nxt;
-            bd_cur = bd_nxt;
+            if constexpr (PIPE) {
+                a_cur = a_nxt;
+                b_cur = b_nxt;
+                bd_cur = bd_nxt;
+            } else {
+                bd_cur = g.blks[b + 1];
+                load_a<KIND>(bd_cur, block_ptr(bd_cur), R, ic, lg, a_cur);
+                load_b(bd_cur, xbase, li, lg, b_cur);
+            }
         }
     }
 
@@ -177,10 +198,12 @@ __global__ __launch_bounds__(256) void mm_kernel(const RowDesc *__restrict__ row
         if (i0 >= Rp) continue;
         if constexpr (LEAF) {
             // y(i, j) = y_near(i, j) + far part, written to the caller's FP64 matrix
-            if (li >= ncols) continue;
-            const f32x4 yn = *reinterpret_cast<const f32x4 *>(init + rd.init + int64_t(li) * Rp + i0);
+            if (li >= g.ncols) continue;
+            const f32x4 yn = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(li) * Rp + i0);
             const double ynv[4] = {yn.x, yn.y, yn.z, yn.w};
-            double *yc = Y + int64_t(li) * ldy + rd.out;
+            double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
+            const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
+            double *yc = Yb + int64_t(li) * ldy + rd.out;
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 if (i0 + e < R) yc[i0 + e] = ynv[e] + tot[4 * q + e];
@@ -189,12 +212,31 @@ __global__ __launch_bounds__(256) void mm_kernel(const RowDesc *__restrict__ row
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[e] = i0 + e < R ? tot[4 * q + e] : 0.0;
             if (rd.init >= 0) {
-                const f32x4 t = *reinterpret_cast<const f32x4 *>(init + rd.init + int64_t(li) * Rp + i0);
+                const f32x4 t = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(li) * Rp + i0);
                 v[0] += t.x; v[1] += t.y; v[2] += t.z; v[3] += t.w;
             }
-            float *o = ((rd.sel & ROW_OUT_P) ? out_pts : out_tree) + rd.out + int64_t(li) * Rp + i0;
+            float *o = ((rd.sel & ROW_OUT_P) ? g.out_pts : g.out_tree) + rd.out + int64_t(li) * Rp + i0;
             *reinterpret_cast<f32x4 *>(o) = f32x4{float(v[0]), float(v[1]), float(v[2]), float(v[3])};
         }
+    }
+}
+
+// Two wavefronts per output row segment (one per 32-row half); a workgroup
+// of 4 wavefronts covers 2 segments.  PERSIST: the grid strides over the
+// list's workgroup slots (fewer workgroups than slots); otherwise one
+// workgroup per slot (no loop, fewer live registers).
+template <int KIND, bool LEAF, bool BATCH, bool PIPE, bool PERSIST>
+__global__ __launch_bounds__(256) void mm_kernel(MmArgs g) {
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t nslots = (g.nrows + 1) / 2;
+    if constexpr (PERSIST) {
+        for (int64_t wg = blockIdx.x; wg < nslots; wg += gridDim.x) {
+            const int64_t row = xcd_local_order(wg, nslots) * 2 + (wv >> 1);
+            if (row < g.nrows) mm_row<KIND, LEAF, BATCH, PIPE>(g, row, wv & 1, lane);
+        }
+    } else {
+        const int64_t row = xcd_local_order(blockIdx.x, nslots) * 2 + (wv >> 1);
+        if (row < g.nrows) mm_row<KIND, LEAF, BATCH, PIPE>(g, row, wv & 1, lane);
     }
 }
 
@@ -227,24 +269,76 @@ hipError_t launch_pack(const double *X, int64_t ldx, int j0, int nrhs, const int
     return hipGetLastError();
 }
 
-hipError_t launch_mm(const MmLaunch &L, int kind, bool leaf, hipStream_t st) {
-    if (L.nrows <= 0) return hipSuccess;
-    const dim3 grid(unsigned((L.nrows + 1) / 2)), block(256);
-#define H2_MM_ARGS                                                                                           \
-    L.rows, L.nrows, L.blks, L.data, L.scales, L.in_tree, L.in_pts, L.init, L.out_tree, L.out_pts, L.Y, L.ldy, \
-        L.ncols
+template <int KIND, bool LEAF, bool BATCH, bool PIPE, bool PERSIST>
+static void launch_one(const MmArgs &g, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL((mm_kernel<KIND, LEAF, BATCH, PIPE, PERSIST>), dim3(grid), dim3(256), 0, st, g);
+}
+
+template <bool BATCH, bool PIPE, bool PERSIST>
+static void launch_kind(const MmArgs &g, int kind, bool leaf, unsigned grid, hipStream_t st) {
     if (kind == ELEM_F32) {
-        if (leaf)
-            hipLaunchKernelGGL((mm_kernel<ELEM_F32, true>), grid, block, 0, st, H2_MM_ARGS);
-        else
-            hipLaunchKernelGGL((mm_kernel<ELEM_F32, false>), grid, block, 0, st, H2_MM_ARGS);
+        if (leaf) launch_one<ELEM_F32, true, BATCH, PIPE, PERSIST>(g, grid, st);
+        else launch_one<ELEM_F32, false, BATCH, PIPE, PERSIST>(g, grid, st);
     } else {
-        if (leaf)
-            hipLaunchKernelGGL((mm_kernel<ELEM_BF16, true>), grid, block, 0, st, H2_MM_ARGS);
-        else
-            hipLaunchKernelGGL((mm_kernel<ELEM_BF16, false>), grid, block, 0, st, H2_MM_ARGS);
+        if (leaf) launch_one<ELEM_BF16, true, BATCH, PIPE, PERSIST>(g, grid, st);
+        else launch_one<ELEM_BF16, false, BATCH, PIPE, PERSIST>(g, grid, st);
     }
-#undef H2_MM_ARGS
+}
+
+hipError_t launch_mm(const MmLaunch &L, int kind, bool leaf, const MmConfig &cfg, hipStream_t st) {
+    if (L.nrows <= 0) return hipSuccess;
+    MmArgs g{L.rows, L.nrows, L.blks, L.data, L.scales, L.in_tree, L.in_pts, L.init, L.out_tree, L.out_pts,
+             L.Y, L.ldy, nullptr, nullptr, L.ncols};
+    const unsigned grid = unsigned((L.nrows + 1) / 2);
+    if (cfg.pipelined) launch_kind<false, true, false>(g, kind, leaf, grid, st);
+    else launch_kind<false, false, false>(g, kind, leaf, grid, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_mm_batch(const MmBatchLaunch &L, int kind, bool leaf, const MmConfig &cfg, hipStream_t st) {
+    if (L.nrows <= 0) return hipSuccess;
+    MmArgs g{L.rows, L.nrows, L.blks, nullptr, L.scales, L.pool, L.pool, L.pool, L.pool, L.pool,
+             nullptr, 0, L.Ytab, L.ldytab, L.ncols};
+    const int64_t slots = (L.nrows + 1) / 2;
+    if (cfg.grid > 0 && cfg.grid < slots) {
+        const unsigned grid = unsigned(cfg.grid);
+        if (cfg.pipelined) launch_kind<true, true, true>(g, kind, leaf, grid, st);
+        else launch_kind<true, false, true>(g, kind, leaf, grid, st);
+    } else {
+        const unsigned grid = unsigned(slots);
+        if (cfg.pipelined) launch_kind<true, true, false>(g, kind, leaf, grid, st);
+        else launch_kind<true, false, false>(g, kind, leaf, grid, st);
+    }
+    return hipGetLastError();
+}
+
+// Batch pack: every (member, leaf) entry copies right-hand sides 0 .. MM_TILE-1
+// of its member's X (device pointer table) into its point tile in the pool.
+__global__ __launch_bounds__(256) void batch_pack_kernel(const PackEntry *__restrict__ entries, int64_t count,
+                                                         double const *const *__restrict__ Xtab,
+                                                         const int64_t *__restrict__ ldxtab, int nrhs,
+                                                         float *__restrict__ pool) {
+    for (int64_t k = blockIdx.x; k < count; k += gridDim.x) {
+        const PackEntry e = entries[k];
+        const double *X = Xtab[e.member];
+        const int64_t ldx = ldxtab[e.member];
+        const int mp = round16(e.m);
+        float *t = pool + e.dst;
+        for (int idx = threadIdx.x; idx < NT * mp; idx += blockDim.x) {
+            const int j = idx / mp, c = idx - j * mp;
+            float v = 0.0f;
+            if (c < e.m && j < nrhs) v = float(X[(e.row + c) + int64_t(j) * ldx]);
+            t[idx] = v;
+        }
+    }
+}
+
+hipError_t launch_batch_pack(const PackEntry *entries, int64_t count, double const *const *Xtab,
+                             const int64_t *ldxtab, int nrhs, float *pool, int64_t grid, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int64_t g = grid > 0 && grid < count ? grid : count;
+    hipLaunchKernelGGL(batch_pack_kernel, dim3(unsigned(g)), dim3(256), 0, st, entries, count, Xtab, ldxtab, nrhs,
+                       pool);
     return hipGetLastError();
 }
 

@@ -21,7 +21,8 @@ STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
 
 # Every function declared in include/h2mv.h.
 EXPORTS = ("h2_build_from_points", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
-           "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_last_error")
+           "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_batch_create", "h2_batch_matmat",
+           "h2_batch_tuning", "h2_batch_free", "h2_last_error")
 
 
 class h2_params(C.Structure):
@@ -68,10 +69,15 @@ def lib():
         L.h2_get_level_bsr.argtypes = [vp, C.c_int, C.POINTER(i64), vp, vp]
         L.h2_profile.argtypes = [vp, C.c_int]
         L.h2_profile_read.argtypes = [vp, vp, C.POINTER(i64)]
+        L.h2_batch_create.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(vp)]
+        L.h2_batch_matmat.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.h2_batch_tuning.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(i64), C.POINTER(C.c_double)]
+        L.h2_batch_free.argtypes = [vp]
+        L.h2_batch_free.restype = None
         L.h2_last_error.argtypes = []
         L.h2_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name != "h2_free" and name != "h2_last_error":
+            if name not in ("h2_free", "h2_batch_free", "h2_last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -143,6 +149,69 @@ def h2_profile_read(h):
     calls = C.c_int64()
     _check(lib().h2_profile_read(C.c_void_p(h), ms.ctypes.data, C.byref(calls)))
     return ms[:5], calls.value
+
+
+def h2_batch_create(handles, nrhs, stream=0):
+    arr = (C.c_void_p * len(handles))(*handles)
+    b = C.c_void_p()
+    _check(lib().h2_batch_create(arr, len(handles), nrhs, C.c_void_p(stream), C.byref(b)))
+    return b.value
+
+
+def h2_batch_matmat(batch, X_ptrs, ldx, Y_ptrs, ldy, stream=0):
+    n = len(X_ptrs)
+    xa = (C.c_void_p * n)(*X_ptrs)
+    ya = (C.c_void_p * n)(*Y_ptrs)
+    lx = (C.c_int64 * n)(*ldx)
+    ly = (C.c_int64 * n)(*ldy)
+    _check(lib().h2_batch_matmat(C.c_void_p(batch), xa, lx, ya, ly, C.c_void_p(stream)))
+
+
+def h2_batch_tuning(batch):
+    p, g, ms = C.c_int(), C.c_int64(), C.c_double()
+    _check(lib().h2_batch_tuning(C.c_void_p(batch), C.byref(p), C.byref(g), C.byref(ms)))
+    return {"pipelined": p.value, "grid": g.value, "tuned_ms": ms.value}
+
+
+def h2_batch_free(batch):
+    lib().h2_batch_free(C.c_void_p(batch))
+
+
+class H2Batch:
+    """Many H2Matrix members (same storage, FP32 or BF16) multiplied together."""
+
+    def __init__(self, members, nrhs):
+        import torch
+        self._torch = torch
+        self.members = list(members)
+        self.nrhs = nrhs
+        self.handle = h2_batch_create([m.handle for m in self.members], nrhs,
+                                      torch.cuda.current_stream().cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            h2_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matmat(self, Xs, outs=None):
+        """Xs: list of float64 CUDA tensors (nrhs, n_b), each row one right-hand side."""
+        torch = self._torch
+        Ys = outs if outs is not None else [torch.empty_like(X) for X in Xs]
+        for X, m in zip(Xs, self.members):
+            assert X.dtype == torch.float64 and X.is_cuda and X.is_contiguous() and X.shape == (self.nrhs, m.n)
+        h2_batch_matmat(self.handle, [X.data_ptr() for X in Xs], [m.n for m in self.members],
+                        [Y.data_ptr() for Y in Ys], [m.n for m in self.members],
+                        torch.cuda.current_stream().cuda_stream)
+        return Ys
+
+    def tuning(self):
+        return h2_batch_tuning(self.handle)
 
 
 class H2Matrix:

@@ -1,0 +1,79 @@
+"""Batches of uneven H^2 matrices in one launch per level slot (HIP graph).
+
+Each member's batched product runs the same block arithmetic as its own
+many-right-hand-side product, so the two must agree to rounding (the batch
+may choose the non-pipelined block loop, which sums in the same order); the
+members are also compared with the oracle on the same dequantized values.
+"""
+import numpy as np
+import pytest
+
+from paper_1902_01829_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MEMBERS = [
+    W.C1.with_(name="b0-2d-n3000-m32-p4", n=3000, leaf=32, cheb_p=4, corr_len=0.1, seed=301),
+    W.C1.with_(name="b1-2d-n5000-m64-p8", n=5000, leaf=64, cheb_p=8, corr_len=0.2, seed=302),
+    W.C1.with_(name="b2-3d-n4000-m32-p3", n=4000, dim=3, leaf=32, cheb_p=3, corr_len=0.15, seed=303),
+    W.C1.with_(name="b3-3d-n2500-m64-p4", n=2500, dim=3, leaf=64, cheb_p=4, corr_len=0.3, seed=304),
+    W.C1.with_(name="b4-2d-n777-m32-p4", n=777, leaf=32, cheb_p=4, corr_len=0.05, seed=305),
+    W.C1.with_(name="b5-3d-n9000-m32-p4", n=9000, dim=3, leaf=32, cheb_p=4, corr_len=0.2, seed=306),
+]
+
+
+def _h2mv():
+    from paper_1902_01829_amd import h2mv
+    return h2mv
+
+
+def _build(w, storage):
+    return _h2mv().H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=storage)
+
+
+@pytest.mark.parametrize("storage", [1, 2], ids=["fp32", "bf16"])
+def test_batch_equals_member_products(oracle_mod, storage):
+    h2mv = _h2mv()
+    nrhs = 8
+    mats = [_build(w, storage) for w in MEMBERS]
+    batch = h2mv.H2Batch(mats, nrhs)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    for call in range(3):   # the first call tunes and captures; the others replay the graph
+        Xs = [torch.randn(nrhs, m.n, dtype=torch.float64, device="cuda", generator=gen) for m in mats]
+        Ys = batch.matmat(Xs)
+        refs = [m.matmat(X) for m, X in zip(mats, Xs)]
+        torch.cuda.synchronize()
+        for w, Y, R in zip(MEMBERS, Ys, refs):
+            rel = ((Y - R).norm() / R.norm()).item()
+            assert rel <= 1e-12, (call, w.name, rel)
+    print("tuning:", batch.tuning(), flush=True)
+    # two members against the oracle on the same dequantized values
+    for idx in (0, 2):
+        w, m = MEMBERS[idx], mats[idx]
+        o = oracle_mod.OracleH2(W.points(w), w.leaf, w.cheb_p, w.eta, w.corr_len, storage=storage)
+        X = Xs[idx].cpu().numpy()
+        Y = Ys[idx].cpu().numpy()
+        for j in (0, nrhs - 1):
+            ref = o.matvec(X[j])
+            assert np.linalg.norm(Y[j] - ref) / np.linalg.norm(ref) <= 1e-6
+    batch.close()
+    for m in mats:
+        m.close()
+
+
+def test_batch_rejects_fp64_mixed_and_wide():
+    h2mv = _h2mv()
+    a32 = _build(MEMBERS[0], 1)
+    a64 = _build(MEMBERS[4], 0)
+    abf = _build(MEMBERS[4], 2)
+    for handles, nrhs, code in (([a32.handle, a64.handle], 8, h2mv.H2_ERR_UNSUPPORTED),
+                                ([a32.handle, abf.handle], 8, h2mv.H2_ERR_UNSUPPORTED),
+                                ([a32.handle], 33, h2mv.H2_ERR_UNSUPPORTED),
+                                ([a32.handle], 0, h2mv.H2_ERR_INVALID_ARG)):
+        with pytest.raises(h2mv.H2Error) as e:
+            h2mv.h2_batch_create(handles, nrhs)
+        assert e.value.code == code
+    h2mv.h2_batch_free(0)
+    for m in (a32, a64, abf):
+        m.close()
