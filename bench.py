@@ -11,9 +11,10 @@ bases: rank 64, eta 0.9), FP64.  value = algorithmic bytes per product / time
 
 Prints one JSON line.  Besides the headline it reports the dominant kernel
 (coupling + dense streaming) against the HBM roofline, the FP64 CPU oracle
-timed on a bounded sample of the same workload, and the reduced-storage modes
-of the 3-D workload with their speedup over FP64 and their error against the
-FP64 oracle.
+timed on a bounded sample of the same workload, the reduced-storage modes of
+the 3-D workload with their speedup over FP64 and their error against the FP64
+oracle, the 32-right-hand-side product on the matrix cores, and a batch of 64
+uneven matrices with 8 right-hand sides each.
 """
 from __future__ import annotations
 
@@ -190,7 +191,7 @@ def matmat_modes(steps, warmup, fp64_matvec_ms, nleaves=8):
     from paper_1902_01829_amd import h2mv
     w = W.C4
     out = {"workload": w.name, "nrhs": w.nrhs,
-           "fp64_32_matvecs_ms": round(32 * fp64_matvec_ms, 3)}
+           "fp64_32_matvecs_ms": None if fp64_matvec_ms is None else round(32 * fp64_matvec_ms, 3)}
     for name in ("fp32", "bf16"):
         A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=STORAGE[name])
         info, perm = A.info, A.perm()
@@ -226,11 +227,106 @@ def matmat_modes(steps, warmup, fp64_matvec_ms, nleaves=8):
         out[name] = {"ms": round(ms, 4), "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
                      "TFLOP_per_s": round(flops / (ms * 1e-3) / 1e12, 2), "algorithmic_bytes": nbytes,
                      "flops": flops, "stream_ms": round(float(phase_ms[1] / max(calls, 1)), 4),
-                     "speedup_vs_32_fp64_matvecs": round(32 * fp64_matvec_ms / ms, 2),
+                     "speedup_vs_32_fp64_matvecs": None if fp64_matvec_ms is None
+                     else round(32 * fp64_matvec_ms / ms, 2),
                      "rel_err_vs_fp64_oracle_max": max(errs)}
         log(f"{w.name} matmat {name}: {ms:.3f} ms, {out[name]['GB_per_s']} GB/s, "
             f"{out[name]['TFLOP_per_s']} TFLOP/s, rel err {max(errs):.2e}")
     out["error_sample"] = f"columns 0 and 31, all rows of {nleaves} seeded leaves vs the FP64 oracle"
+    return out
+
+
+def batch_modes(steps, warmup, nleaves=4):
+    """64 uneven H^2 matrices (2-D and 3-D, ranks 16, 27 and 64, leaf sizes 32
+    and 64), 8 right-hand sides each, FP32 storage: one batched product (one
+    launch per level slot, replayed from a HIP graph, launch shape chosen by
+    the autotuner) against the same members multiplied one after another, and
+    against 8 FP64 single-vector products per member."""
+    import torch
+    from paper_1902_01829_amd import h2mv
+    members = W.batch_members()
+    nrhs = members[0].nrhs
+    t0 = time.perf_counter()
+    mats = [h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=1) for w in members]
+    perms = [m.perm() for m in mats]
+    Xt = [np.ascontiguousarray(W.rhs(w).T[:, p]) for w, p in zip(members, perms)]
+    Xs = [torch.from_numpy(x).cuda() for x in Xt]
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    infos = [m.info for m in mats]
+    nbytes = sum(algorithmic_bytes(i, w.n, nrhs) for i, w in zip(infos, members))
+    log(f"batch: {len(members)} members, {sum(w.n for w in members)} points, "
+        f"{sum(i.bytes_device_total for i in infos) / 1e9:.2f} GB on device, built in {build_s:.1f} s")
+    batch = h2mv.H2Batch(mats, nrhs)
+    Ys = batch.matmat(Xs)            # tunes the launch shape and captures the graph
+    for _ in range(warmup):
+        batch.matmat(Xs, outs=Ys)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.matmat(Xs, outs=Ys)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    tuning = batch.tuning()
+    # the same members, one many-right-hand-side product after another
+    Rs = [m.matmat(X) for m, X in zip(mats, Xs)]
+    for _ in range(warmup):
+        for m, X, R in zip(mats, Xs, Rs):
+            m.matmat(X, out=R)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for m, X, R in zip(mats, Xs, Rs):
+            m.matmat(X, out=R)
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3 / steps
+    diff = max(float(((Y - R).norm() / R.norm()).item()) for Y, R in zip(Ys, Rs))
+    Yh = [Y.cpu().numpy() for Y in Ys]
+    batch.close()
+    for m in mats:
+        m.close()
+    del Ys, Rs, mats, batch
+    torch.cuda.empty_cache()
+    # 8 FP64 single-vector products per member, members built one at a time
+    fp64_ms = 0.0
+    reps = 2
+    for w, X in zip(members, Xs):
+        A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=0)
+        cols = [X[j].contiguous() for j in range(nrhs)]
+        y = torch.empty_like(cols[0])
+        for c in cols:
+            A.matvec(c, out=y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for c in cols:
+                A.matvec(c, out=y)
+        torch.cuda.synchronize()
+        fp64_ms += (time.perf_counter() - t0) * 1e3 / reps
+        A.close()
+        del cols, y
+        torch.cuda.empty_cache()
+    # error of a few members against the FP64 oracle
+    order = np.argsort([w.n for w in members])
+    picks = sorted({int(order[0]), int(order[len(order) // 2]), int(order[-1]),
+                    max(range(len(members)), key=lambda b: (members[b].dim, members[b].rank, members[b].n))})
+    errs = []
+    for b in picks:
+        for j in (0, nrhs - 1):
+            rows, ref = oracle_sample(members[b], perms[b], Xt[b][j], nleaves, seed=17)
+            errs.append(float(np.linalg.norm(Yh[b][j][rows] - ref) / np.linalg.norm(ref)))
+    out = {"members": len(members), "nrhs": nrhs, "points_total": int(sum(w.n for w in members)),
+           "storage": "fp32", "ms": round(ms, 4), "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+           "algorithmic_bytes": nbytes, "unbatched_members_ms": round(seq_ms, 4),
+           "speedup_vs_unbatched": round(seq_ms / ms, 2),
+           "fp64_8_matvecs_per_member_ms": round(fp64_ms, 3),
+           "speedup_vs_fp64_matvecs": round(fp64_ms / ms, 2),
+           "max_rel_diff_vs_member_products": diff,
+           "rel_err_vs_fp64_oracle_max": max(errs), "tuning": tuning,
+           "error_sample": f"members {picks}, columns 0 and {nrhs - 1}, all rows of {nleaves} seeded leaves "
+                           "vs the FP64 oracle"}
+    log(f"batch fp32: {ms:.3f} ms ({out['GB_per_s']} GB/s), unbatched {seq_ms:.3f} ms, "
+        f"FP64 matvecs {fp64_ms:.2f} ms, rel err {max(errs):.2e}, tuning {tuning}")
     return out
 
 
@@ -242,8 +338,12 @@ def main():
     ap.add_argument("--workload", default=W.C2.name, choices=sorted(W.WORKLOADS))
     ap.add_argument("--storage", default="fp64", choices=sorted(STORAGE))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-modes", action="store_true", help="skip the 3-D storage-mode comparison")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the storage-mode, many-right-hand-side and batch sections")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--only", choices=["modes", "matmat", "batch"], default=None,
+                    help="run one section alone and print its JSON (for profiling runs); "
+                         "the headline line is not printed")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first run one device-to-device copy of this many GiB (a known-size "
                          "reference for hardware byte counters)")
@@ -264,6 +364,16 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nel * 8} bytes read, {nel * 8} bytes written")
         del src, dst
+
+    if args.only is not None:
+        if args.only == "modes":
+            out = storage_modes(args.steps, args.warmup)
+        elif args.only == "matmat":
+            out = matmat_modes(args.steps, args.warmup, None)
+        else:
+            out = batch_modes(args.steps, args.warmup)
+        print(json.dumps({"section": args.only, **out}), flush=True)
+        return
 
     w = W.WORKLOADS[args.workload]
     log(f"building {w.name} storage={args.storage}")
@@ -305,6 +415,7 @@ def main():
         fp64_ms = ms if (w.name == W.C2.name and args.storage == "fp64") else None
         if fp64_ms is not None:
             result["matmat"] = matmat_modes(max(3, args.steps // 4), 1, fp64_ms)
+        result["batch"] = batch_modes(max(3, args.steps // 2), 1)
     print(json.dumps(result), flush=True)
 
 

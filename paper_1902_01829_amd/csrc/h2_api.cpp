@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -65,11 +66,15 @@ struct DeviceArena {
         return p;
     }
     template <typename T>
+    // Copies v to new device memory; returns once v may be released (set-up
+    // only, never inside a product).
     T *upload(const std::vector<T> &v, hipStream_t st) {
         T *d = static_cast<T *>(alloc(int64_t(v.size() * sizeof(T))));
-        if (!v.empty())
+        if (!v.empty()) {
             check_hip(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st),
                       "hipMemcpyAsync");
+            check_hip(hipStreamSynchronize(st), "upload");
+        }
         return d;
     }
 };
@@ -83,7 +88,49 @@ struct WorkList {
     const h2::RowDesc *rows;
     int64_t nrows;
     const h2::BlkDesc *blks;
+    const int32_t *items = nullptr;   // tile lists: wavefront items in dispatch order
+    int64_t nitems = 0;
 };
+
+// Wavefront items of a tile list in dispatch order (see h2::MmLaunch): one
+// item per 32-row half of each row, the list cut into MM_XCDS contiguous
+// ranges of about equal work (per block: its columns rounded up to the
+// 16-column MFMA step, plus a fixed cost), each range padded to whole
+// workgroups, and range x's l-th workgroup placed at workgroup l * MM_XCDS + x.
+std::vector<int32_t> wave_items(const std::vector<h2::RowDesc> &rows, const std::vector<h2::BlkDesc> &blks) {
+    constexpr int X = h2::MM_XCDS;
+    if (rows.size() >= (size_t(1) << 30)) fail(H2_ERR_UNSUPPORTED, "too many rows in one tile list");
+    std::vector<int32_t> items;
+    std::vector<double> work;
+    double total = 0.0;
+    for (size_t r = 0; r < rows.size(); ++r) {
+        double w = 0.0;
+        for (int32_t b = rows[r].b0; b < rows[r].b1; ++b) w += double((blks[b].C + 15) / 16 * 16 + 8);
+        for (int mt = 0; mt * 32 < std::max(rows[r].R, 1); ++mt) {
+            items.push_back(int32_t(r << 1) | mt);
+            work.push_back(w);
+            total += w;
+        }
+    }
+    // cut points: range x = [cut[x], cut[x+1])
+    std::vector<size_t> cut(X + 1, items.size());
+    cut[0] = 0;
+    double acc = 0.0;
+    int x = 1;
+    for (size_t i = 0; i < items.size() && x < X; ++i) {
+        while (x < X && acc >= total * x / X) cut[x++] = i;
+        acc += work[i];
+    }
+    size_t per = 0;   // workgroups per XCD
+    for (int r = 0; r < X; ++r) per = std::max(per, (cut[r + 1] - cut[r] + 3) / 4);
+    std::vector<int32_t> out(per * X * 4, -1);
+    for (int r = 0; r < X; ++r)
+        for (size_t i = cut[r]; i < cut[r + 1]; ++i) {
+            const size_t l = (i - cut[r]) / 4, v = (i - cut[r]) % 4;
+            out[(l * X + r) * 4 + v] = items[i];
+        }
+    return out;
+}
 
 }  // namespace
 
@@ -276,6 +323,11 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
         w.nrows = int64_t(rows.size());
         w.rows = A.mem.upload(rows, stream);
         w.blks = A.mem.upload(blks, stream);
+        if (enc == 1) {
+            const std::vector<int32_t> it = wave_items(rows, blks);
+            w.items = A.mem.upload(it, stream);
+            w.nitems = int64_t(it.size());
+        }
         (enc == 0 ? A.lists : A.mm_lists).push_back(w);
         if (enc == 1) {
             A.mm_host_rows.push_back(std::move(rows));
@@ -479,7 +531,8 @@ void run_tile_pass(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64
         run_lists(A, A.mm_lists, st, [&](const WorkList &w) {
             h2::MmLaunch L;
             L.rows = w.rows;
-            L.nrows = w.nrows;
+            L.items = w.items;
+            L.nitems = w.nitems;
             L.blks = w.blks;
             L.data = w.data;
             L.scales = A.scales;
@@ -511,7 +564,7 @@ void run_tile_pass(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64
                     L.init = A.t_ynear;
                     break;
             }
-            check_hip(h2::launch_mm(L, w.kind, w.phase == PH_LEAF, cfg, st), "mfma launch");
+            check_hip(h2::launch_mm(L, w.kind, int(w.phase), cfg, st), "mfma launch");
         });
     }
 }
@@ -540,9 +593,12 @@ struct BatchSlot {
     h2::RowDesc *rows;
     int64_t nrows;
     h2::BlkDesc *blks;
+    int32_t *items;
+    int64_t nitems;
 };
 
 struct BatchConfigCache {
+    std::mutex mu;   // handles may be tuned from several host threads
     std::vector<std::pair<std::string, h2::MmConfig>> entries;
 };
 BatchConfigCache &config_cache() {
@@ -590,8 +646,8 @@ void batch_enqueue(h2_batch_ &B, const h2::MmConfig &cfg, hipStream_t st) {
                                     cfg.grid > 0 ? cfg.grid : 0, st),
               "batch pack");
     for (const BatchSlot &sl : B.slots) {
-        h2::MmBatchLaunch L{sl.rows, sl.nrows, sl.blks, B.scales, B.pool, B.d_Ytab, B.d_ldy, B.nrhs};
-        check_hip(h2::launch_mm_batch(L, sl.kind, sl.phase == PH_LEAF, cfg, st), "batch launch");
+        h2::MmBatchLaunch L{sl.rows, sl.items, sl.nitems, sl.blks, B.scales, B.pool, B.d_Ytab, B.d_ldy, B.nrhs};
+        check_hip(h2::launch_mm_batch(L, sl.kind, int(sl.phase), cfg, st), "batch launch");
     }
 }
 
@@ -602,6 +658,7 @@ std::string config_file() {
 
 // The cache file holds one "signature pipelined grid" line per entry.
 bool cached_config(const std::string &sig, h2::MmConfig &cfg) {
+    std::lock_guard<std::mutex> lock(config_cache().mu);
     for (auto &e : config_cache().entries)
         if (e.first == sig) {
             cfg = e.second;
@@ -628,6 +685,7 @@ bool cached_config(const std::string &sig, h2::MmConfig &cfg) {
 }
 
 void store_config(const std::string &sig, const h2::MmConfig &cfg) {
+    std::lock_guard<std::mutex> lock(config_cache().mu);
     config_cache().entries.push_back({sig, cfg});
     const std::string f = config_file();
     if (f.empty()) return;
@@ -651,7 +709,8 @@ void batch_autotune(h2_batch_ &B) {
     check_hip(hipEventCreate(&t0), "hipEventCreate");
     check_hip(hipEventCreate(&t1), "hipEventCreate");
     double best_ms = 1e30;
-    const int64_t grids[4] = {0, 2 * B.cu_count, 4 * B.cu_count, 8 * B.cu_count};
+    const int64_t cu = (B.cu_count + h2::MM_XCDS - 1) / h2::MM_XCDS * h2::MM_XCDS;
+    const int64_t grids[4] = {0, 2 * cu, 4 * cu, 8 * cu};
     for (int pipe = 0; pipe < 2; ++pipe)
         for (int64_t grid : grids) {
             const h2::MmConfig c{pipe, grid};
@@ -806,7 +865,9 @@ void build_batch(h2_batch_ &B, hipStream_t stream) {
     };
     auto add_slot = [&](Phase ph, int kind, std::vector<h2::RowDesc> &rows, std::vector<h2::BlkDesc> &blks) {
         if (rows.empty()) return;
-        BatchSlot sl{ph, kind, B.mem.upload(rows, stream), int64_t(rows.size()), B.mem.upload(blks, stream)};
+        const std::vector<int32_t> it = wave_items(rows, blks);
+        BatchSlot sl{ph, kind, B.mem.upload(rows, stream), int64_t(rows.size()), B.mem.upload(blks, stream),
+                     B.mem.upload(it, stream), int64_t(it.size())};
         B.slots.push_back(sl);
     };
     std::vector<h2::RowDesc> rows;

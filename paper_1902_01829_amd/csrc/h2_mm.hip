@@ -6,11 +6,15 @@
 // single-vector product; only the arithmetic changes:
 //   - tiles hold 32 right-hand sides (one MFMA N dimension), FP32, stored
 //     [rhs][row] with a leading dimension rounded up to 16 rows (zero-padded);
-//   - v_mfma_f32_32x32x2_f32 does the products on FP32 operands: FP32 blocks
-//     as stored, BF16 blocks widened exactly to FP32 (the scale is applied per
-//     block).  Splitting the operands into BF16 pieces for the faster BF16
-//     MFMA loses accuracy as the tree deepens (measured: 2.5e-6 against 4.7e-7
-//     on 2^20 points); the FP32 path matches the single-vector kernels;
+//   - FP32 blocks: v_mfma_f32_32x32x2_f32 on FP32 operands.  (Splitting both
+//     operands into two BF16 pieces each for the faster BF16 MFMA drops bits
+//     of the products: measured 2.5e-6 against 4.7e-7 on 2^20 points.)
+//   - BF16 blocks are exact BF16 values (the scale is applied per block), so
+//     only the FP32 input tile needs splitting: x = hi + mid + lo exactly, each
+//     piece a BF16 value (truncation leaves exact residues of 16 and then 8
+//     significant bits).  Three v_mfma_f32_32x32x16_bf16 per 16 block columns
+//     then form the products exactly and accumulate them in FP32, the accuracy
+//     of the FP32 path at a sixth of its matrix-core time;
 //   - one block's products accumulate in FP32, sums over blocks in FP64;
 //   - each 32-row half of an output segment has its own wavefront; the two
 //     read disjoint halves of every block and share its input tile, which the
@@ -27,30 +31,25 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int NT = MM_TILE;   // right-hand sides per tile
 
 __device__ inline int round16(int v) { return (v + 15) & ~15; }
 
-// Workgroup -> position in the (spatially ordered) list such that each XCD
-// works through one contiguous range: the hardware deals workgroups to the 8
-// XCDs round-robin, so workgroup wg runs on XCD wg % 8.
-__device__ inline int64_t xcd_local_order(int64_t wg, int64_t nwg) {
-    constexpr int64_t kXcds = 8;
-    const int64_t x = wg % kXcds, local = wg / kXcds;
-    const int64_t base = nwg / kXcds, extra = nwg % kXcds;
-    return x * base + (x < extra ? x : extra) + local;
-}
-
-// Block operand of one wavefront: 8 column steps of 4 values (FP32 items, or
-// raw BF16 words widened at use), and the matching input-tile operand.
+// Block operand of one wavefront and the matching input-tile operand.
+// FP32 blocks: 8 column steps of 4 values (lane group g holds columns
+// 8p + 4g + t of step p, one per K = 2 MFMA).  BF16 blocks: 4 steps of 16
+// columns, lane group g holding the 8 columns 16s + 8g .. 16s + 8g + 7 (one
+// 16-byte item of the block, the K = 16 operand of one BF16 MFMA); the tile
+// operand then holds the same 8 columns as two f32x4.
 template <int KIND> struct BlockA;
 template <> struct BlockA<ELEM_F32> {
     f32x4 v[8];
 };
 template <> struct BlockA<ELEM_BF16> {
-    u32x2 v[8];
+    u32x4 v[4];
 };
 struct TileB {
     f32x4 v[8];
@@ -62,55 +61,93 @@ struct TileB {
 // the zero padding rows of the input tile.
 template <int KIND>
 __device__ inline void load_a(const BlkDesc &bd, const void *blk, int R, int ic, int lg, BlockA<KIND> &o) {
-    const int C = bd.C, NP = round16(C) >> 3;
+    const int C = bd.C;
+    if constexpr (KIND == ELEM_F32) {
+        const int NP = round16(C) >> 3, CW = (C + 3) >> 2;    // 4-column groups
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        if (p >= NP) break;   // wave-uniform
-        if constexpr (KIND == ELEM_F32) {
-            const int CW = (C + 3) >> 2;                      // 4-column groups
+        for (int p = 0; p < 8; ++p) {
+            if (p >= NP) break;   // wave-uniform
             const int cg = 2 * p + lg, cgc = cg < CW ? cg : CW - 1;
             o.v[p] = __builtin_nontemporal_load(
                 reinterpret_cast<const f32x4 *>(static_cast<const float *>(blk) + (int64_t(cgc) * R + ic) * 4));
-        } else {
-            const int CW = (C + 7) >> 3;                      // 8-column groups: half of one per lane
-            const int pc = p < CW ? p : CW - 1;
-            o.v[p] = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(
-                static_cast<const uint16_t *>(blk) + (int64_t(pc) * R + ic) * 8 + 4 * lg));
+        }
+    } else {
+        const int NS = round16(C) >> 4, CW = (C + 7) >> 3;    // 8-column groups
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (s >= NS) break;
+            const int cg = 2 * s + lg, cgc = cg < CW ? cg : CW - 1;
+            o.v[s] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(
+                static_cast<const uint16_t *>(blk) + (int64_t(cgc) * R + ic) * 8));
         }
     }
 }
 
+template <int KIND>
 __device__ inline void load_b(const BlkDesc &bd, const float *xbase, int li, int lg, TileB &o) {
     const int Cp = round16(bd.C), NP = Cp >> 3;
-    const float *xb = xbase + bd.in + li * Cp + 4 * lg;
+    const float *xb = xbase + bd.in + li * Cp;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
         if (p >= NP) break;
-        o.v[p] = *reinterpret_cast<const f32x4 *>(xb + 8 * p);
+        // FP32 blocks: columns 8p + 4g .. +3; BF16 blocks: step p/2, half p%2
+        const int col = KIND == ELEM_F32 ? 8 * p + 4 * lg : 16 * (p >> 1) + 8 * lg + 4 * (p & 1);
+        o.v[p] = *reinterpret_cast<const f32x4 *>(xb + col);
     }
 }
 
-// The block's products (K = 2 per MFMA: one column per lane group).
+// Splits 8 FP32 values into three BF16 vectors with x = hi + mid + lo exactly.
+__device__ inline void split3(const f32x4 &x0, const f32x4 &x1, bf16x8 &hi, bf16x8 &mid, bf16x8 &lo) {
+    const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+    unsigned h[8], m[8], l[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        h[e] = __float_as_uint(x[e]) & 0xffff0000u;
+        const float r1 = x[e] - __uint_as_float(h[e]);
+        m[e] = __float_as_uint(r1) & 0xffff0000u;
+        l[e] = __float_as_uint(r1 - __uint_as_float(m[e]));   // at most 8 significant bits: low half zero
+    }
+    u32x4 ph, pm, pl;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        ph[t] = (h[2 * t] >> 16) | h[2 * t + 1];
+        pm[t] = (m[2 * t] >> 16) | m[2 * t + 1];
+        pl[t] = (l[2 * t] >> 16) | (l[2 * t + 1] & 0xffff0000u);
+    }
+    hi = __builtin_bit_cast(bf16x8, ph);
+    mid = __builtin_bit_cast(bf16x8, pm);
+    lo = __builtin_bit_cast(bf16x8, pl);
+}
+
+// The block's products, accumulated in FP32.
 template <int KIND>
-__device__ inline f32x16 block_products(const BlockA<KIND> &a_op, const TileB &b_op, int NP) {
+__device__ inline f32x16 block_products(const BlockA<KIND> &a_op, const TileB &b_op, int C) {
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    if constexpr (KIND == ELEM_F32) {
+        const int NP = round16(C) >> 3;
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        if (p >= NP) break;
-        f32x4 a;
-        if constexpr (KIND == ELEM_BF16) {
-            const u32x2 w = a_op.v[p];
-            a = f32x4{__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u),
-                      __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xffff0000u)};
-        } else {
-            a = a_op.v[p];
+        for (int p = 0; p < 8; ++p) {
+            if (p >= NP) break;
+            const f32x4 a = a_op.v[p];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b_op.v[p].x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b_op.v[p].y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b_op.v[p].z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b_op.v[p].w, acc, 0, 0, 0);
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b_op.v[p].x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b_op.v[p].y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b_op.v[p].z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b_op.v[p].w, acc, 0, 0, 0);
+    } else {
+        const int NS = round16(C) >> 4;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (s >= NS) break;
+            const bf16x8 a = __builtin_bit_cast(bf16x8, a_op.v[s]);
+            bf16x8 hi, mid, lo;
+            split3(b_op.v[2 * s], b_op.v[2 * s + 1], hi, mid, lo);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, lo, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, mid, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hi, acc, 0, 0, 0);
+        }
     }
     return acc;
 }
@@ -122,7 +159,8 @@ __device__ inline f32x16 block_products(const BlockA<KIND> &a_op, const TileB &b
 // result matrix in a device table (member index in RowDesc.sel >> 8).
 struct MmArgs {
     const RowDesc *rows;
-    int64_t nrows;
+    const int32_t *items;
+    int64_t nitems;
     const BlkDesc *blks;
     const void *data;
     const float *scales;
@@ -165,16 +203,16 @@ __device__ inline void mm_row(const MmArgs &g, int64_t row, int mt, int lane) {
     if (rd.b0 < rd.b1) {
         bd_cur = g.blks[rd.b0];
         load_a<KIND>(bd_cur, block_ptr(bd_cur), R, ic, lg, a_cur);
-        load_b(bd_cur, xbase, li, lg, b_cur);
+        load_b<KIND>(bd_cur, xbase, li, lg, b_cur);
     }
     for (int b = rd.b0; b < rd.b1; ++b) {
         const bool more = b + 1 < rd.b1;
         if (PIPE && more) {
             bd_nxt = g.blks[b + 1];
             load_a<KIND>(bd_nxt, block_ptr(bd_nxt), R, ic, lg, a_nxt);
-            load_b(bd_nxt, xbase, li, lg, b_nxt);
+            load_b<KIND>(bd_nxt, xbase, li, lg, b_nxt);
         }
-        const f32x16 acc = block_products<KIND>(a_cur, b_cur, round16(bd_cur.C) >> 3);
+        const f32x16 acc = block_products<KIND>(a_cur, b_cur, bd_cur.C);
         const double sc = KIND == ELEM_BF16 ? double(g.scales[bd_cur.sidx]) : 1.0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) tot[r] += sc * double(acc[r]);
@@ -186,7 +224,7 @@ __device__ inline void mm_row(const MmArgs &g, int64_t row, int mt, int lane) {
             } else {
                 bd_cur = g.blks[b + 1];
                 load_a<KIND>(bd_cur, block_ptr(bd_cur), R, ic, lg, a_cur);
-                load_b(bd_cur, xbase, li, lg, b_cur);
+                load_b<KIND>(bd_cur, xbase, li, lg, b_cur);
             }
         }
     }
@@ -221,24 +259,39 @@ __device__ inline void mm_row(const MmArgs &g, int64_t row, int mt, int lane) {
     }
 }
 
-// Two wavefronts per output row segment (one per 32-row half); a workgroup
-// of 4 wavefronts covers 2 segments.  PERSIST: the grid strides over the
-// list's workgroup slots (fewer workgroups than slots); otherwise one
-// workgroup per slot (no loop, fewer live registers).
+// One wavefront per work item (a 32-row half of an output row segment), 4
+// per workgroup, in the dispatch order laid out by the host.  PERSIST: the
+// grid strides over the list's workgroups (fewer workgroups than slots; a
+// grid that is a multiple of the XCD count keeps each workgroup on its XCD's
+// range); otherwise one workgroup per 4 items.
 template <int KIND, bool LEAF, bool BATCH, bool PIPE, bool PERSIST>
-__global__ __launch_bounds__(256) void mm_kernel(MmArgs g) {
+__device__ inline void mm_body(const MmArgs &g) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int64_t nslots = (g.nrows + 1) / 2;
+    const int64_t nwg = g.nitems >> 2;
     if constexpr (PERSIST) {
-        for (int64_t wg = blockIdx.x; wg < nslots; wg += gridDim.x) {
-            const int64_t row = xcd_local_order(wg, nslots) * 2 + (wv >> 1);
-            if (row < g.nrows) mm_row<KIND, LEAF, BATCH, PIPE>(g, row, wv & 1, lane);
+        for (int64_t wg = blockIdx.x; wg < nwg; wg += gridDim.x) {
+            const int32_t it = g.items[wg * 4 + wv];
+            if (it >= 0) mm_row<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
         }
     } else {
-        const int64_t row = xcd_local_order(blockIdx.x, nslots) * 2 + (wv >> 1);
-        if (row < g.nrows) mm_row<KIND, LEAF, BATCH, PIPE>(g, row, wv & 1, lane);
+        const int32_t it = g.items[int64_t(blockIdx.x) * 4 + wv];
+        if (it >= 0) mm_row<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
     }
 }
+
+// One kernel name per phase, so that traces attribute time to phases:
+// leaf projection + upsweep and downsweep (FP32 bases), coupling + dense
+// streaming (block kind), leaf expansion + FP64 sum.
+#define H2_MM_PHASE_KERNEL(NAME, LEAF)                                                   \
+    template <int KIND, bool BATCH, bool PIPE, bool PERSIST>                             \
+    __global__ __launch_bounds__(256) void NAME(MmArgs g) {                              \
+        mm_body<KIND, LEAF, BATCH, PIPE, PERSIST>(g);                                    \
+    }
+H2_MM_PHASE_KERNEL(mm_upsweep_kernel, false)
+H2_MM_PHASE_KERNEL(mm_stream_kernel, false)
+H2_MM_PHASE_KERNEL(mm_downsweep_kernel, false)
+H2_MM_PHASE_KERNEL(mm_leafexpand_kernel, true)
+#undef H2_MM_PHASE_KERNEL
 
 // Copies right-hand sides j0 .. j0+NT-1 of the caller's column-major FP64 X
 // into point tiles: leaf j at j * slot, [rhs][row] with a leading dimension of
@@ -269,45 +322,54 @@ hipError_t launch_pack(const double *X, int64_t ldx, int j0, int nrhs, const int
     return hipGetLastError();
 }
 
-template <int KIND, bool LEAF, bool BATCH, bool PIPE, bool PERSIST>
-static void launch_one(const MmArgs &g, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((mm_kernel<KIND, LEAF, BATCH, PIPE, PERSIST>), dim3(grid), dim3(256), 0, st, g);
-}
-
 template <bool BATCH, bool PIPE, bool PERSIST>
-static void launch_kind(const MmArgs &g, int kind, bool leaf, unsigned grid, hipStream_t st) {
-    if (kind == ELEM_F32) {
-        if (leaf) launch_one<ELEM_F32, true, BATCH, PIPE, PERSIST>(g, grid, st);
-        else launch_one<ELEM_F32, false, BATCH, PIPE, PERSIST>(g, grid, st);
-    } else {
-        if (leaf) launch_one<ELEM_BF16, true, BATCH, PIPE, PERSIST>(g, grid, st);
-        else launch_one<ELEM_BF16, false, BATCH, PIPE, PERSIST>(g, grid, st);
+static void launch_phase(const MmArgs &g, int kind, int phase, unsigned grid, hipStream_t st) {
+    const dim3 gd(grid), bd(256);
+    switch (phase) {
+    case PHASE_UP:
+        hipLaunchKernelGGL((mm_upsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST>), gd, bd, 0, st, g);
+        break;
+    case PHASE_DOWN:
+        hipLaunchKernelGGL((mm_downsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST>), gd, bd, 0, st, g);
+        break;
+    case PHASE_LEAF:
+        hipLaunchKernelGGL((mm_leafexpand_kernel<ELEM_F32, BATCH, PIPE, PERSIST>), gd, bd, 0, st, g);
+        break;
+    default:
+        if (kind == ELEM_F32)
+            hipLaunchKernelGGL((mm_stream_kernel<ELEM_F32, BATCH, PIPE, PERSIST>), gd, bd, 0, st, g);
+        else
+            hipLaunchKernelGGL((mm_stream_kernel<ELEM_BF16, BATCH, PIPE, PERSIST>), gd, bd, 0, st, g);
     }
 }
 
-hipError_t launch_mm(const MmLaunch &L, int kind, bool leaf, const MmConfig &cfg, hipStream_t st) {
-    if (L.nrows <= 0) return hipSuccess;
-    MmArgs g{L.rows, L.nrows, L.blks, L.data, L.scales, L.in_tree, L.in_pts, L.init, L.out_tree, L.out_pts,
-             L.Y, L.ldy, nullptr, nullptr, L.ncols};
-    const unsigned grid = unsigned((L.nrows + 1) / 2);
-    if (cfg.pipelined) launch_kind<false, true, false>(g, kind, leaf, grid, st);
-    else launch_kind<false, false, false>(g, kind, leaf, grid, st);
+hipError_t launch_mm(const MmLaunch &L, int kind, int phase, const MmConfig &cfg, hipStream_t st) {
+    if (L.nitems <= 0) return hipSuccess;
+    if (L.nitems % (4 * MM_XCDS) != 0) return hipErrorInvalidValue;
+    if (phase != PHASE_STREAM && kind != ELEM_F32) return hipErrorInvalidValue;   // bases are FP32
+    MmArgs g{L.rows, L.items, L.nitems, L.blks, L.data, L.scales, L.in_tree, L.in_pts, L.init, L.out_tree,
+             L.out_pts, L.Y, L.ldy, nullptr, nullptr, L.ncols};
+    const unsigned grid = unsigned(L.nitems / 4);
+    if (cfg.pipelined) launch_phase<false, true, false>(g, kind, phase, grid, st);
+    else launch_phase<false, false, false>(g, kind, phase, grid, st);
     return hipGetLastError();
 }
 
-hipError_t launch_mm_batch(const MmBatchLaunch &L, int kind, bool leaf, const MmConfig &cfg, hipStream_t st) {
-    if (L.nrows <= 0) return hipSuccess;
-    MmArgs g{L.rows, L.nrows, L.blks, nullptr, L.scales, L.pool, L.pool, L.pool, L.pool, L.pool,
+hipError_t launch_mm_batch(const MmBatchLaunch &L, int kind, int phase, const MmConfig &cfg, hipStream_t st) {
+    if (L.nitems <= 0) return hipSuccess;
+    if (L.nitems % (4 * MM_XCDS) != 0) return hipErrorInvalidValue;
+    if (phase != PHASE_STREAM && kind != ELEM_F32) return hipErrorInvalidValue;
+    MmArgs g{L.rows, L.items, L.nitems, L.blks, nullptr, L.scales, L.pool, L.pool, L.pool, L.pool, L.pool,
              nullptr, 0, L.Ytab, L.ldytab, L.ncols};
-    const int64_t slots = (L.nrows + 1) / 2;
+    const int64_t slots = L.nitems / 4;
     if (cfg.grid > 0 && cfg.grid < slots) {
         const unsigned grid = unsigned(cfg.grid);
-        if (cfg.pipelined) launch_kind<true, true, true>(g, kind, leaf, grid, st);
-        else launch_kind<true, false, true>(g, kind, leaf, grid, st);
+        if (cfg.pipelined) launch_phase<true, true, true>(g, kind, phase, grid, st);
+        else launch_phase<true, false, true>(g, kind, phase, grid, st);
     } else {
         const unsigned grid = unsigned(slots);
-        if (cfg.pipelined) launch_kind<true, true, false>(g, kind, leaf, grid, st);
-        else launch_kind<true, false, false>(g, kind, leaf, grid, st);
+        if (cfg.pipelined) launch_phase<true, true, false>(g, kind, phase, grid, st);
+        else launch_phase<true, false, false>(g, kind, phase, grid, st);
     }
     return hipGetLastError();
 }

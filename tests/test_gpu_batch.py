@@ -77,3 +77,61 @@ def test_batch_rejects_fp64_mixed_and_wide():
     h2mv.h2_batch_free(0)
     for m in (a32, a64, abf):
         m.close()
+
+
+DEGENERATE = [
+    W.C1.with_(name="d0-2d-n1", n=1, seed=311),
+    W.C1.with_(name="d1-2d-n3-m2-p1", n=3, leaf=2, cheb_p=1, seed=312),
+    W.C1.with_(name="d2-3d-n50-m64", n=50, dim=3, leaf=64, seed=313),
+    W.C1.with_(name="d3-2d-n4096-m32-p4", seed=314),
+]
+
+
+@pytest.mark.parametrize("nrhs", [1, 32])
+@pytest.mark.parametrize("storage", [1, 2], ids=["fp32", "bf16"])
+def test_batch_degenerate_members(storage, nrhs):
+    """Members of one point, of leaves holding one or two points and of a
+    single leaf, batched with a regular one; one and 32 right-hand sides."""
+    h2mv = _h2mv()
+    mats = [_build(w, storage) for w in DEGENERATE]
+    batch = h2mv.H2Batch(mats, nrhs)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    Xs = [torch.randn(nrhs, m.n, dtype=torch.float64, device="cuda", generator=gen) for m in mats]
+    for _ in range(2):
+        Ys = batch.matmat(Xs)
+        refs = [m.matmat(X) for m, X in zip(mats, Xs)]
+        torch.cuda.synchronize()
+        for w, Y, R in zip(DEGENERATE, Ys, refs):
+            rel = ((Y - R).norm() / R.norm()).item()
+            assert rel <= 1e-12, (w.name, rel)
+    batch.close()
+    for m in mats:
+        m.close()
+
+
+def test_batch_tuning_cache_file(tmp_path, monkeypatch):
+    """The chosen launch shape is appended to the file named by
+    H2MV_AUTOTUNE_CACHE, and a second batch of the same members reuses it."""
+    h2mv = _h2mv()
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("H2MV_AUTOTUNE_CACHE", str(cache))
+    members = [W.C1.with_(name=f"c{i}", n=1500 + 250 * i, seed=320 + i) for i in range(3)]
+    mats = [_build(w, 1) for w in members]
+    Xs = [torch.randn(4, m.n, dtype=torch.float64, device="cuda") for m in mats]
+    b1 = h2mv.H2Batch(mats, 4)
+    assert b1.tuning()["tuned_ms"] < 0          # nothing chosen before the first product
+    Y1 = b1.matmat(Xs)
+    t1 = b1.tuning()
+    assert t1["tuned_ms"] > 0
+    lines = cache.read_text().split("\n")
+    assert any(line.endswith(f" {t1['pipelined']} {t1['grid']}") for line in lines if line)
+    b2 = h2mv.H2Batch(mats, 4)
+    Y2 = b2.matmat(Xs)
+    t2 = b2.tuning()
+    assert (t2["pipelined"], t2["grid"], t2["tuned_ms"]) == (t1["pipelined"], t1["grid"], 0.0)
+    for a, b in zip(Y1, Y2):
+        assert torch.equal(a, b)
+    b1.close()
+    b2.close()
+    for m in mats:
+        m.close()

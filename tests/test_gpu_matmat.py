@@ -111,3 +111,63 @@ def test_matmat_full_2d_1m_32rhs(oracle_mod, storage):
         print(f"  column {j}: vs dequantized {eq:.3e}, vs fp64 {e64:.3e}", flush=True)
         assert eq <= MM_VS_DEQUANT_TOL
         assert e64 <= VS_FP64_TOL[storage]
+
+
+DEGENERATE = [
+    W.C1.with_(name="2d-n1", n=1, seed=85),
+    W.C1.with_(name="2d-n3-m2-p1", n=3, leaf=2, cheb_p=1, seed=84),
+    W.C1.with_(name="3d-n50-m64-single-leaf", n=50, dim=3, leaf=64, seed=86),
+    W.C1.with_(name="2d-n33-m32-two-leaves", n=33, seed=87),
+    W.C1.with_(name="3d-n700-m32-p4-overcomplete", n=700, dim=3, leaf=32, cheb_p=4, corr_len=0.2, seed=88),
+]
+
+
+@pytest.mark.parametrize("storage", [1, 2], ids=["fp32", "bf16"])
+@pytest.mark.parametrize("w", DEGENERATE, ids=lambda w: w.name)
+def test_matmat_degenerate_sizes(oracle_mod, w, storage):
+    """A single point, leaves of one or two points, a tree of one leaf, and a
+    rank above the leaf size, with 1, 32 and 33 right-hand sides (one pass,
+    a full tile, and a second pass holding one column)."""
+    print(f"case {w.name} storage {storage}", flush=True)
+    A = _build(w, storage)
+    oq = oracle_mod.OracleH2(W.points(w), w.leaf, w.cheb_p, w.eta, w.corr_len, storage=storage)
+    for nrhs in (1, 32, 33):
+        X = _rhs(w.n, nrhs, 700 + nrhs)
+        Y = A.matmat(torch.from_numpy(X).cuda()).cpu().numpy()
+        for j in sorted({0, nrhs // 2, nrhs - 1}):
+            ref = oq.matvec(X[j])
+            rel = np.linalg.norm(Y[j] - ref) / np.linalg.norm(ref)
+            assert rel <= MM_VS_DEQUANT_TOL, (nrhs, j, rel)
+    A.close()
+
+
+@pytest.mark.parametrize("storage", [1, 2], ids=["fp32", "bf16"])
+def test_matmat_columns_independent_and_zero(storage):
+    """Column j of Y depends on column j of X alone (bitwise), and X = 0 gives
+    Y = 0 exactly."""
+    w = W.C1.with_(name="3d-n3000-m24-p3", n=3000, dim=3, leaf=24, cheb_p=3, corr_len=0.2, seed=77)
+    A = _build(w, storage)
+    X = torch.randn(9, w.n, dtype=torch.float64, device="cuda")
+    X2 = X.clone()
+    X2[1:] = torch.randn(8, w.n, dtype=torch.float64, device="cuda") * 1e3
+    Y, Y2 = A.matmat(X), A.matmat(X2)
+    assert torch.equal(Y[0], Y2[0])
+    Z = A.matmat(torch.zeros(4, w.n, dtype=torch.float64, device="cuda"))
+    assert torch.count_nonzero(Z).item() == 0
+    A.close()
+
+
+def test_matmat_rejects_bad_sizes():
+    from paper_1902_01829_amd import h2mv
+    w = W.C1
+    A = _build(w, 1)
+    X = torch.zeros(2, w.n, dtype=torch.float64, device="cuda")
+    Y = torch.zeros_like(X)
+    st = torch.cuda.current_stream().cuda_stream
+    for ldx, ldy, nrhs in ((w.n, w.n, 0), (w.n - 1, w.n, 2), (w.n, w.n - 1, 2), (w.n, w.n, -3)):
+        with pytest.raises(h2mv.H2Error) as e:
+            h2mv.h2_matmat(A.handle, X.data_ptr(), ldx, Y.data_ptr(), ldy, nrhs, st)
+        assert e.value.code == h2mv.H2_ERR_INVALID_ARG
+    with pytest.raises(h2mv.H2Error):
+        h2mv.h2_matmat(A.handle, 0, w.n, Y.data_ptr(), w.n, 2, st)
+    A.close()
