@@ -144,11 +144,16 @@ def cpu_baseline(w, perm, xt, budget_s=20.0):
                 a = (a - 1) // 2
         return tot
 
-    nl = 4
-    t0 = time.perf_counter()
-    o.matvec_leaves(xt, leaves_all[:nl])
-    t_cal = time.perf_counter() - t0
-    nl = int(max(4, min(len(leaves_all), nl * budget_s / max(t_cal, 1e-3))))
+    # sample size from two calibration runs: t(nl) = fixed (upsweep) + nl * per-leaf
+    def timed(count):
+        t0 = time.perf_counter()
+        o.matvec_leaves(xt, np.sort(leaves_all[:count]))
+        return time.perf_counter() - t0
+    n_small, n_large = 4, min(64, len(leaves_all))
+    t_small, t_large = timed(n_small), timed(n_large)
+    per_leaf = max((t_large - t_small) / max(n_large - n_small, 1), 1e-6)
+    fixed = max(t_small - n_small * per_leaf, 0.0)
+    nl = int(max(4, min(len(leaves_all), (budget_s - fixed) / per_leaf)))
     leaves = np.sort(leaves_all[:nl])
     t0 = time.perf_counter()
     y_ref = o.matvec_leaves(xt, leaves)
