@@ -152,8 +152,10 @@ struct h2_matrix_ {
     int64_t tile_slot = 0;            // elements per leaf in point tiles
     int64_t *d_leaf_begin = nullptr, *d_leaf_end = nullptr;
     float *t_xh = nullptr, *t_yh = nullptr, *t_x = nullptr, *t_ynear = nullptr;   // tile workspace (lazy)
-    h2::MmConfig mm_cfg{1, 0};        // chosen at the first many-right-hand-side product
-    bool mm_tuned = false;
+    // block loop chosen at the first pass of each tile width (32, or 16 for
+    // passes of at most 16 right-hand sides)
+    h2::MmConfig mm_cfg[2] = {{1, 0}, {1, 0}};
+    bool mm_tuned[2] = {false, false};
     int64_t bytes_coupling = 0, bytes_dense = 0, bytes_leaf = 0, bytes_transfer = 0;
     // profiling: PH_COUNT + 1 events per recorded call
     bool prof = false;
@@ -569,15 +571,19 @@ void run_tile_pass(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64
     }
 }
 
-// Chooses the block loop (pipelined or not) for this matrix by timing both on
-// its first product (the first pass's right-hand sides), unless cached.
-void tune_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, hipStream_t st);
+// Chooses the block loop (pipelined or not) for this matrix and the tile
+// width of pass j0 by timing both on that pass, unless cached.
+void tune_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, int j0,
+                hipStream_t st);
 
 // Y = A X on the matrix cores, MM_TILE right-hand sides per pass.
 void run_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, hipStream_t st) {
     ensure_tiles(A);
-    if (!A.mm_tuned) tune_tiles(A, X, ldx, Y, ldy, nrhs, st);
-    for (int j0 = 0; j0 < nrhs; j0 += h2::MM_TILE) run_tile_pass(A, X, ldx, Y, ldy, nrhs, j0, A.mm_cfg, st);
+    for (int j0 = 0; j0 < nrhs; j0 += h2::MM_TILE) {
+        const int w = std::min(h2::MM_TILE, nrhs - j0) <= 16 ? 1 : 0;
+        if (!A.mm_tuned[w]) tune_tiles(A, X, ldx, Y, ldy, nrhs, j0, st);
+        run_tile_pass(A, X, ldx, Y, ldy, nrhs, j0, A.mm_cfg[w], st);
+    }
 }
 
 // ---------------------------------------------------------------- batches
@@ -738,11 +744,14 @@ void batch_autotune(h2_batch_ &B) {
     store_config(B.signature, best);
 }
 
-void tune_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, hipStream_t st) {
+void tune_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, int j0,
+                hipStream_t st) {
+    const int w = std::min(h2::MM_TILE, nrhs - j0) <= 16 ? 1 : 0;
     int64_t nblocks = 0;
     for (const auto &hb : A.mm_host_blks) nblocks += int64_t(hb.size());
     const std::string sig = "single-k" + std::to_string(A.block_kind) + "-n" + std::to_string(A.st.n) + "-r" +
-                            std::to_string(A.st.rank) + "-blocks" + std::to_string(nblocks);
+                            std::to_string(A.st.rank) + "-blocks" + std::to_string(nblocks) + "-nt" +
+                            std::to_string(w ? 16 : 32);
     h2::MmConfig best{1, 0};
     if (!cached_config(sig, best)) {
         const bool prof = A.prof;   // tuning runs stay out of the profile
@@ -753,9 +762,9 @@ void tune_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t 
         float best_ms = 1e30f;
         for (int pipe = 0; pipe < 2; ++pipe) {
             const h2::MmConfig c{pipe, 0};
-            run_tile_pass(A, X, ldx, Y, ldy, nrhs, 0, c, st);   // warm-up
+            run_tile_pass(A, X, ldx, Y, ldy, nrhs, j0, c, st);   // warm-up
             check_hip(hipEventRecord(t0, st), "hipEventRecord");
-            run_tile_pass(A, X, ldx, Y, ldy, nrhs, 0, c, st);
+            run_tile_pass(A, X, ldx, Y, ldy, nrhs, j0, c, st);
             check_hip(hipEventRecord(t1, st), "hipEventRecord");
             check_hip(hipEventSynchronize(t1), "hipEventSynchronize");
             float ms = 0.0f;
@@ -770,8 +779,8 @@ void tune_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t 
         A.prof = prof;
         store_config(sig, best);
     }
-    A.mm_cfg = best;
-    A.mm_tuned = true;
+    A.mm_cfg[w] = best;
+    A.mm_tuned[w] = true;
 }
 
 void build_batch(h2_batch_ &B, hipStream_t stream) {

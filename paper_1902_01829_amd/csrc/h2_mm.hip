@@ -259,23 +259,247 @@ __device__ inline void mm_row(const MmArgs &g, int64_t row, int mt, int lane) {
     }
 }
 
+// ---- 16 right-hand sides (passes of at most 16 columns, batches of <= 16)
+// The tiles keep their layout; only their first 16 right-hand sides are
+// used.  A wavefront still owns a 32-row half of an output segment, as two
+// 16-row MFMA tiles h = 0, 1: lane l owns block row 32*mt + 16*h + (l % 16)
+// and right-hand side l % 16, and lane group q = l / 16 supplies K values.
+// FP32 blocks: v_mfma_f32_16x16x4_f32; per 16 block columns, lane group q
+// loads the 4 columns 16c + 4q .. 16c + 4q + 3 (one 16-byte item) and step t
+// uses column 16c + 4q + t.  BF16 blocks: v_mfma_f32_16x16x32_bf16 with the
+// exact three-way split of the input tile; per 32 block columns lane group q
+// holds columns 32c + 8q .. 32c + 8q + 7 (one 16-byte item).
+template <int KIND> struct BlockA16;
+template <> struct BlockA16<ELEM_F32> {
+    f32x4 v[2][4];   // [row tile][16-column chunk]
+};
+template <> struct BlockA16<ELEM_BF16> {
+    u32x4 v[2][2];   // [row tile][32-column chunk]
+};
+struct TileB16 {
+    f32x4 v[4];      // FP32: one per 16-column chunk; BF16: two per 32-column chunk
+};
+
+template <int KIND>
+__device__ inline void load_a16(const BlkDesc &bd, const void *blk, int R, const int (&ic)[2], int nh, int kq,
+                                BlockA16<KIND> &o) {
+    const int C = bd.C;
+    if constexpr (KIND == ELEM_F32) {
+        const int NC = round16(C) >> 4, CW = (C + 3) >> 2;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c >= NC) break;   // wave-uniform
+            const int cg = 4 * c + kq, cgc = cg < CW ? cg : CW - 1;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h >= nh) break;
+                o.v[h][c] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(
+                    static_cast<const float *>(blk) + (int64_t(cgc) * R + ic[h]) * 4));
+            }
+        }
+    } else {
+        const int NC = (C + 31) >> 5, CW = (C + 7) >> 3;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (c >= NC) break;
+            const int cg = 4 * c + kq, cgc = cg < CW ? cg : CW - 1;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h >= nh) break;
+                o.v[h][c] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(
+                    static_cast<const uint16_t *>(blk) + (int64_t(cgc) * R + ic[h]) * 8));
+            }
+        }
+    }
+}
+
+// Input-tile operand.  BF16 chunks may reach past the tile's padded height
+// (a multiple of 16): such lanes read the chunk's first columns instead and
+// zero them at use.
+template <int KIND>
+__device__ inline void load_b16(const BlkDesc &bd, const float *xbase, int n, int kq, TileB16 &o) {
+    const int Cp = round16(bd.C);
+    const float *xb = xbase + bd.in + n * Cp;
+    if constexpr (KIND == ELEM_F32) {
+        const int NC = Cp >> 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c >= NC) break;
+            o.v[c] = *reinterpret_cast<const f32x4 *>(xb + 16 * c + 4 * kq);
+        }
+    } else {
+        const int NC = (bd.C + 31) >> 5;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (c >= NC) break;
+            const int col = 32 * c + 8 * kq, colc = col < Cp ? col : 32 * c;
+            o.v[2 * c] = *reinterpret_cast<const f32x4 *>(xb + colc);
+            o.v[2 * c + 1] = *reinterpret_cast<const f32x4 *>(xb + colc + 4);
+        }
+    }
+}
+
+template <int KIND>
+__device__ inline void block_products16(const BlockA16<KIND> &a_op, const TileB16 &b_op, int C, int nh, int kq,
+                                        f32x4 (&acc)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) acc[h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (KIND == ELEM_F32) {
+        const int NC = round16(C) >> 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c >= NC) break;
+            const f32x4 b = b_op.v[c];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h >= nh) break;
+                const f32x4 a = a_op.v[h][c];
+                acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[h], 0, 0, 0);
+                acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[h], 0, 0, 0);
+                acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[h], 0, 0, 0);
+                acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[h], 0, 0, 0);
+            }
+        }
+    } else {
+        const int NC = (C + 31) >> 5, Cp = round16(C);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (c >= NC) break;
+            bf16x8 hi, mid, lo;
+            split3(b_op.v[2 * c], b_op.v[2 * c + 1], hi, mid, lo);
+            if (32 * c + 8 * kq >= Cp) {   // past the tile: zero (see load_b16)
+                const u32x4 z = {0u, 0u, 0u, 0u};
+                hi = mid = lo = __builtin_bit_cast(bf16x8, z);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h >= nh) break;
+                const bf16x8 a = __builtin_bit_cast(bf16x8, a_op.v[h][c]);
+                acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, lo, acc[h], 0, 0, 0);
+                acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, mid, acc[h], 0, 0, 0);
+                acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hi, acc[h], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// One 32-row half (mt) of an output row segment with 16 right-hand sides.
+// Accumulator element e of row tile h holds row 32*mt + 16*h + 4*(l/16) + e
+// of right-hand side l % 16.
+template <int KIND, bool LEAF, bool BATCH, bool PIPE>
+__device__ inline void mm_row16(const MmArgs &g, int64_t row, int mt, int lane) {
+    const RowDesc rd = g.rows[row];
+    const int R = rd.R, Rp = round16(R);
+    if (32 * mt >= R) return;
+    const int n = lane & 15, kq = lane >> 4;
+    const int nh = 32 * mt + 16 < R ? 2 : 1;   // wave-uniform
+    int ic[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = 32 * mt + 16 * h + n;
+        ic[h] = i < R ? i : R - 1;
+    }
+    const float *xbase = (rd.sel & ROW_IN_X) ? g.in_pts : g.in_tree;
+    const void *data = g.data;
+
+    double tot[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tot[h][e] = 0.0;
+
+    BlockA16<KIND> a_cur, a_nxt;
+    TileB16 b_cur, b_nxt;
+    BlkDesc bd_cur, bd_nxt;
+    auto block_ptr = [&](const BlkDesc &bd) -> const void * {
+        if constexpr (BATCH) return reinterpret_cast<const void *>(bd.a);
+        else return static_cast<const char *>(data) + bd.a * (KIND == ELEM_F32 ? 4 : 2);
+    };
+    if (rd.b0 < rd.b1) {
+        bd_cur = g.blks[rd.b0];
+        load_a16<KIND>(bd_cur, block_ptr(bd_cur), R, ic, nh, kq, a_cur);
+        load_b16<KIND>(bd_cur, xbase, n, kq, b_cur);
+    }
+    for (int b = rd.b0; b < rd.b1; ++b) {
+        const bool more = b + 1 < rd.b1;
+        if (PIPE && more) {
+            bd_nxt = g.blks[b + 1];
+            load_a16<KIND>(bd_nxt, block_ptr(bd_nxt), R, ic, nh, kq, a_nxt);
+            load_b16<KIND>(bd_nxt, xbase, n, kq, b_nxt);
+        }
+        f32x4 acc[2];
+        block_products16<KIND>(a_cur, b_cur, bd_cur.C, nh, kq, acc);
+        const double sc = KIND == ELEM_BF16 ? double(g.scales[bd_cur.sidx]) : 1.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            tot[h][0] += sc * double(acc[h].x);
+            tot[h][1] += sc * double(acc[h].y);
+            tot[h][2] += sc * double(acc[h].z);
+            tot[h][3] += sc * double(acc[h].w);
+        }
+        if (more) {
+            if constexpr (PIPE) {
+                a_cur = a_nxt;
+                b_cur = b_nxt;
+                bd_cur = bd_nxt;
+            } else {
+                bd_cur = g.blks[b + 1];
+                load_a16<KIND>(bd_cur, block_ptr(bd_cur), R, ic, nh, kq, a_cur);
+                load_b16<KIND>(bd_cur, xbase, n, kq, b_cur);
+            }
+        }
+    }
+
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h >= nh) break;
+        const int i0 = 32 * mt + 16 * h + 4 * kq;
+        if (i0 >= Rp) continue;
+        if constexpr (LEAF) {
+            if (n >= g.ncols) continue;
+            const f32x4 yn = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(n) * Rp + i0);
+            const double ynv[4] = {yn.x, yn.y, yn.z, yn.w};
+            double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
+            const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
+            double *yc = Yb + int64_t(n) * ldy + rd.out;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (i0 + e < R) yc[i0 + e] = ynv[e] + tot[h][e];
+        } else {
+            double v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = i0 + e < R ? tot[h][e] : 0.0;
+            if (rd.init >= 0) {
+                const f32x4 t = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(n) * Rp + i0);
+                v[0] += t.x; v[1] += t.y; v[2] += t.z; v[3] += t.w;
+            }
+            float *o = ((rd.sel & ROW_OUT_P) ? g.out_pts : g.out_tree) + rd.out + int64_t(n) * Rp + i0;
+            *reinterpret_cast<f32x4 *>(o) = f32x4{float(v[0]), float(v[1]), float(v[2]), float(v[3])};
+        }
+    }
+}
+
 // One wavefront per work item (a 32-row half of an output row segment), 4
 // per workgroup, in the dispatch order laid out by the host.  PERSIST: the
 // grid strides over the list's workgroups (fewer workgroups than slots; a
 // grid that is a multiple of the XCD count keeps each workgroup on its XCD's
 // range); otherwise one workgroup per 4 items.
-template <int KIND, bool LEAF, bool BATCH, bool PIPE, bool PERSIST>
+template <int KIND, bool LEAF, bool BATCH, bool PIPE, bool PERSIST, int NT>
 __device__ inline void mm_body(const MmArgs &g) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t nwg = g.nitems >> 2;
+    auto one = [&](int32_t it) {
+        if constexpr (NT == 16) mm_row16<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
+        else mm_row<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
+    };
     if constexpr (PERSIST) {
         for (int64_t wg = blockIdx.x; wg < nwg; wg += gridDim.x) {
             const int32_t it = g.items[wg * 4 + wv];
-            if (it >= 0) mm_row<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
+            if (it >= 0) one(it);
         }
     } else {
         const int32_t it = g.items[int64_t(blockIdx.x) * 4 + wv];
-        if (it >= 0) mm_row<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
+        if (it >= 0) one(it);
     }
 }
 
@@ -283,9 +507,9 @@ __device__ inline void mm_body(const MmArgs &g) {
 // leaf projection + upsweep and downsweep (FP32 bases), coupling + dense
 // streaming (block kind), leaf expansion + FP64 sum.
 #define H2_MM_PHASE_KERNEL(NAME, LEAF)                                                   \
-    template <int KIND, bool BATCH, bool PIPE, bool PERSIST>                             \
+    template <int KIND, bool BATCH, bool PIPE, bool PERSIST, int NT>                     \
     __global__ __launch_bounds__(256) void NAME(MmArgs g) {                              \
-        mm_body<KIND, LEAF, BATCH, PIPE, PERSIST>(g);                                    \
+        mm_body<KIND, LEAF, BATCH, PIPE, PERSIST, NT>(g);                                \
     }
 H2_MM_PHASE_KERNEL(mm_upsweep_kernel, false)
 H2_MM_PHASE_KERNEL(mm_stream_kernel, false)
@@ -322,36 +546,44 @@ hipError_t launch_pack(const double *X, int64_t ldx, int j0, int nrhs, const int
     return hipGetLastError();
 }
 
-template <bool BATCH, bool PIPE, bool PERSIST>
-static void launch_phase(const MmArgs &g, int kind, int phase, unsigned grid, hipStream_t st) {
+template <bool BATCH, bool PIPE, bool PERSIST, int NT>
+static void launch_phase_nt(const MmArgs &g, int kind, int phase, unsigned grid, hipStream_t st) {
     const dim3 gd(grid), bd(256);
     switch (phase) {
     case PHASE_UP:
-        hipLaunchKernelGGL((mm_upsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST>), gd, bd, 0, st, g);
+        hipLaunchKernelGGL((mm_upsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g);
         break;
     case PHASE_DOWN:
-        hipLaunchKernelGGL((mm_downsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST>), gd, bd, 0, st, g);
+        hipLaunchKernelGGL((mm_downsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g);
         break;
     case PHASE_LEAF:
-        hipLaunchKernelGGL((mm_leafexpand_kernel<ELEM_F32, BATCH, PIPE, PERSIST>), gd, bd, 0, st, g);
+        hipLaunchKernelGGL((mm_leafexpand_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g);
         break;
     default:
         if (kind == ELEM_F32)
-            hipLaunchKernelGGL((mm_stream_kernel<ELEM_F32, BATCH, PIPE, PERSIST>), gd, bd, 0, st, g);
+            hipLaunchKernelGGL((mm_stream_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g);
         else
-            hipLaunchKernelGGL((mm_stream_kernel<ELEM_BF16, BATCH, PIPE, PERSIST>), gd, bd, 0, st, g);
+            hipLaunchKernelGGL((mm_stream_kernel<ELEM_BF16, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g);
     }
+}
+
+template <bool BATCH, bool PIPE, bool PERSIST>
+static void launch_phase(const MmArgs &g, int kind, int phase, int nt, unsigned grid, hipStream_t st) {
+    if (nt == 16) launch_phase_nt<BATCH, PIPE, PERSIST, 16>(g, kind, phase, grid, st);
+    else launch_phase_nt<BATCH, PIPE, PERSIST, 32>(g, kind, phase, grid, st);
 }
 
 hipError_t launch_mm(const MmLaunch &L, int kind, int phase, const MmConfig &cfg, hipStream_t st) {
     if (L.nitems <= 0) return hipSuccess;
     if (L.nitems % (4 * MM_XCDS) != 0) return hipErrorInvalidValue;
     if (phase != PHASE_STREAM && kind != ELEM_F32) return hipErrorInvalidValue;   // bases are FP32
+    if (L.ncols < 1 || L.ncols > MM_TILE) return hipErrorInvalidValue;
     MmArgs g{L.rows, L.items, L.nitems, L.blks, L.data, L.scales, L.in_tree, L.in_pts, L.init, L.out_tree,
              L.out_pts, L.Y, L.ldy, nullptr, nullptr, L.ncols};
     const unsigned grid = unsigned(L.nitems / 4);
-    if (cfg.pipelined) launch_phase<false, true, false>(g, kind, phase, grid, st);
-    else launch_phase<false, false, false>(g, kind, phase, grid, st);
+    const int nt = L.ncols <= 16 ? 16 : 32;
+    if (cfg.pipelined) launch_phase<false, true, false>(g, kind, phase, nt, grid, st);
+    else launch_phase<false, false, false>(g, kind, phase, nt, grid, st);
     return hipGetLastError();
 }
 
@@ -361,15 +593,17 @@ hipError_t launch_mm_batch(const MmBatchLaunch &L, int kind, int phase, const Mm
     if (phase != PHASE_STREAM && kind != ELEM_F32) return hipErrorInvalidValue;
     MmArgs g{L.rows, L.items, L.nitems, L.blks, nullptr, L.scales, L.pool, L.pool, L.pool, L.pool, L.pool,
              nullptr, 0, L.Ytab, L.ldytab, L.ncols};
+    if (L.ncols < 1 || L.ncols > MM_TILE) return hipErrorInvalidValue;
+    const int nt = L.ncols <= 16 ? 16 : 32;
     const int64_t slots = L.nitems / 4;
     if (cfg.grid > 0 && cfg.grid < slots) {
         const unsigned grid = unsigned(cfg.grid);
-        if (cfg.pipelined) launch_phase<true, true, true>(g, kind, phase, grid, st);
-        else launch_phase<true, false, true>(g, kind, phase, grid, st);
+        if (cfg.pipelined) launch_phase<true, true, true>(g, kind, phase, nt, grid, st);
+        else launch_phase<true, false, true>(g, kind, phase, nt, grid, st);
     } else {
         const unsigned grid = unsigned(slots);
-        if (cfg.pipelined) launch_phase<true, true, false>(g, kind, phase, grid, st);
-        else launch_phase<true, false, false>(g, kind, phase, grid, st);
+        if (cfg.pipelined) launch_phase<true, true, false>(g, kind, phase, nt, grid, st);
+        else launch_phase<true, false, false>(g, kind, phase, nt, grid, st);
     }
     return hipGetLastError();
 }
