@@ -735,6 +735,138 @@ void or_matvec(const or_h2 *h, const double *x, double *y) {
     free(yn); free(yf);
 }
 
+/* ---- Product of an H^2 matrix given by its arrays (Sec. 2.2 with Eq. (1);
+ * the flattened per-level storage of Sec. 3 and Fig. 3; every level of the
+ * matrix tree as block-sparse rows, Fig. 5), 0-based, with a rank k_l per
+ * level.  Layout: leaf j's U_j, V_j are m_j x k_q column-major, concatenated
+ * in leaf order; node c >= 1 of level l has E_c, F_c, k_l x k_(l-1)
+ * column-major, concatenated in node order; level l's coupling blocks are
+ * k_l x k_l column-major in BSR order; dense blocks m_i x m_j column-major in
+ * BSR order.  The sweeps of Sec. 4 in the paper's order: leaf projection and
+ * upsweep to the root (x^ from zero, children c1 then c2; Sec. 4.2), tree
+ * multiplication of every level (blocks in row order; Sec. 4.3), downsweep
+ * from the root (Sec. 4.4), leaf expansion, and y = y_near + y_far (Sec. 4.1).
+ * Returns 0, or -1 on invalid sizes. */
+int or_arrays_matvec(int64_t n, int q, const int32_t *lrank, const int64_t *begin, const int64_t *end,
+                     const double *U, const double *V, const double *E, const double *F,
+                     const int32_t *const *S_rowptr, const int32_t *const *S_colidx,
+                     const double *const *S, const int32_t *D_rowptr, const int32_t *D_colidx,
+                     const double *D, const double *x, double *y) {
+    if (n < 1 || q < 0 || q > 29) return -1;
+    int64_t nn = ((int64_t)2 << q) - 1, nleaves = (int64_t)1 << q, lf = first_of(q);
+    int kmax = 0;
+    for (int l = 0; l <= q; l++) {
+        if (lrank[l] < 1) return -1;
+        if (lrank[l] > kmax) kmax = lrank[l];
+    }
+    double *xh = calloc((size_t)nn * kmax, sizeof(double));
+    double *yh = calloc((size_t)nn * kmax, sizeof(double));
+    int64_t *eoff = calloc((size_t)nn, sizeof(int64_t));   /* start of E_c / F_c */
+    int64_t *uoff = calloc((size_t)nleaves, sizeof(int64_t));
+    int64_t acc = 0;
+    for (int l = 1; l <= q; l++)
+        for (int64_t c = first_of(l); c < first_of(l + 1); c++) {
+            eoff[c] = acc;
+            acc += (int64_t)lrank[l] * lrank[l - 1];
+        }
+    acc = 0;
+    for (int64_t j = 0; j < nleaves; j++) {
+        uoff[j] = acc;
+        acc += (end[lf + j] - begin[lf + j]) * lrank[q];
+    }
+    int kq = lrank[q];
+    int has_low_rank = 0;
+    for (int l = 0; l <= q; l++)
+        if (S_rowptr[l][(int64_t)1 << l] > 0) has_low_rank = 1;
+    if (has_low_rank) {
+        /* leaf projection x^_j = V_j^T x(j) */
+        for (int64_t j = 0; j < nleaves; j++) {
+            int64_t v = lf + j, mj = end[v] - begin[v];
+            const double *Vj = V + uoff[j];
+            for (int nu = 0; nu < kq; nu++) {
+                double s = 0.0;
+                for (int64_t r = 0; r < mj; r++) s += Vj[nu * mj + r] * x[begin[v] + r];
+                xh[v * kmax + nu] = s;
+            }
+        }
+        /* upsweep x^_p = F_c1^T x^_c1 + F_c2^T x^_c2, levels q .. 1 */
+        for (int l = q; l >= 1; l--) {
+            int kc = lrank[l], kp = lrank[l - 1];
+            for (int64_t p = first_of(l - 1); p < first_of(l); p++) {
+                for (int nu = 0; nu < kp; nu++) xh[p * kmax + nu] = 0.0;
+                for (int c = 0; c < 2; c++) {
+                    int64_t ch = 2 * p + 1 + c;
+                    const double *Fc = F + eoff[ch];   /* kc x kp column-major */
+                    for (int nu = 0; nu < kp; nu++) {
+                        double s = 0.0;
+                        for (int mu = 0; mu < kc; mu++) s += Fc[nu * kc + mu] * xh[ch * kmax + mu];
+                        xh[p * kmax + nu] += s;
+                    }
+                }
+            }
+        }
+        /* tree multiplication y^_i = sum_j S_ij x^_j on every level */
+        for (int l = 0; l <= q; l++) {
+            int k = lrank[l];
+            int64_t fl = first_of(l);
+            for (int64_t i = 0; i < ((int64_t)1 << l); i++)
+                for (int32_t b = S_rowptr[l][i]; b < S_rowptr[l][i + 1]; b++) {
+                    const double *Sb = S[l] + (int64_t)b * k * k;
+                    int64_t jn = fl + S_colidx[l][b];
+                    for (int mu = 0; mu < k; mu++) {
+                        double s = 0.0;
+                        for (int nu = 0; nu < k; nu++) s += Sb[nu * k + mu] * xh[jn * kmax + nu];
+                        yh[(fl + i) * kmax + mu] += s;
+                    }
+                }
+        }
+        /* downsweep y^_c += E_c y^_parent, levels 1 .. q */
+        for (int l = 1; l <= q; l++) {
+            int kc = lrank[l], kp = lrank[l - 1];
+            for (int64_t c = first_of(l); c < first_of(l + 1); c++) {
+                const double *Ec = E + eoff[c];   /* kc x kp column-major */
+                int64_t par = (c - 1) / 2;
+                for (int mu = 0; mu < kc; mu++) {
+                    double s = 0.0;
+                    for (int nu = 0; nu < kp; nu++) s += Ec[nu * kc + mu] * yh[par * kmax + nu];
+                    yh[c * kmax + mu] += s;
+                }
+            }
+        }
+    }
+    /* leaf expansion and dense near field: y(i) = y_near(i) + U_i y^_i */
+    int64_t doff = 0;
+    for (int64_t i = 0; i < nleaves; i++) {
+        int64_t s = lf + i, ms = end[s] - begin[s];
+        for (int64_t a = 0; a < ms; a++) {
+            double yf = 0.0;
+            if (has_low_rank) {
+                const double *Ui = U + uoff[i];
+                for (int nu = 0; nu < kq; nu++) yf += Ui[nu * ms + a] * yh[s * kmax + nu];
+            }
+            y[begin[s] + a] = yf;
+        }
+        for (int64_t a = 0; a < ms; a++) {
+            double yn = 0.0;
+            int64_t o = doff;
+            for (int32_t b = D_rowptr[i]; b < D_rowptr[i + 1]; b++) {
+                int64_t t = lf + D_colidx[b], mt = end[t] - begin[t];
+                double sacc = 0.0;
+                for (int64_t c = 0; c < mt; c++) sacc += D[o + c * ms + a] * x[begin[t] + c];
+                yn += sacc;
+                o += ms * mt;
+            }
+            y[begin[s] + a] = yn + y[begin[s] + a];
+        }
+        for (int32_t b = D_rowptr[i]; b < D_rowptr[i + 1]; b++) {
+            int64_t t = lf + D_colidx[b];
+            doff += ms * (end[t] - begin[t]);
+        }
+    }
+    free(xh); free(yh); free(eoff); free(uoff);
+    return 0;
+}
+
 /* Same operations as or_matvec, restricted to the rows of the listed leaves:
  * the full upsweep, then the tree multiply and downsweep along each leaf's
  * chain of ancestors only. */

@@ -93,6 +93,14 @@ void or_explicit_basis(const or_h2 *h, int64_t node, int method, double *Uhat);
 
 /* y = A x in tree order (O(n) sweeps). */
 void or_matvec(const or_h2 *h, const double *x, double *y);
+
+/* y = A x for an H^2 matrix given by its arrays, with a rank per level
+ * (layout in h2oracle.c).  Returns 0, or -1 on invalid sizes. */
+int or_arrays_matvec(int64_t n, int q, const int32_t *lrank, const int64_t *begin, const int64_t *end,
+                     const double *U, const double *V, const double *E, const double *F,
+                     const int32_t *const *S_rowptr, const int32_t *const *S_colidx,
+                     const double *const *S, const int32_t *D_rowptr, const int32_t *D_colidx,
+                     const double *D, const double *x, double *y);
 /* Rows of y = A x for the listed leaves only: y holds the leaves' rows in the
  * order given (sum of leaf sizes values). */
 void or_matvec_leaves(const or_h2 *h, const double *x, int64_t nleaves,

@@ -80,6 +80,10 @@ def lib():
         L.or_dense_expand.argtypes = [C.c_void_p, _f64p]
         L.or_kernel_matvec.argtypes = [_f64p, C.c_int64, C.c_int, C.c_double, C.c_int, _f64p,
                                        C.c_int64, _i64p, _f64p]
+        vp = C.c_void_p
+        L.or_arrays_matvec.argtypes = [C.c_int64, C.c_int, _i32p, _i64p, _i64p, vp, vp, vp, vp,
+                                       C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), _i32p, vp, vp, _f64p, _f64p]
+        L.or_arrays_matvec.restype = C.c_int
         _lib = L
     return _lib
 
@@ -240,10 +244,72 @@ class OracleH2:
         b, e = self.ranges()
         return np.concatenate([np.arange(b[v], e[v]) for v in leaves]).astype(np.int64)
 
+    def export_arrays(self):
+        """The representation as flattened arrays (column-major blocks; see
+        arrays_matvec), FP64 values as stored (dequantized in reduced modes)."""
+        q, k = self.q, self.k
+        b, e = self.ranges()
+        lf = (1 << q) - 1
+        U = np.concatenate([self.leaf_basis(v).ravel(order="F") for v in range(lf, 2 * lf + 1)])
+        E = np.concatenate([self.transfer(c).ravel(order="F") for c in range(1, self.nnodes)]) \
+            if q > 0 else np.zeros(0)
+        S_rowptr, S_colidx, S = [], [], []
+        for l in range(q + 1):
+            rp, ci = self.coupling_bsr(l)
+            S_rowptr.append(rp)
+            S_colidx.append(ci)
+            S.append(np.concatenate([self.coupling_block(l, i).ravel(order="F") for i in range(len(ci))])
+                     if len(ci) else np.zeros(0))
+        drp, dci = self.dense_bsr()
+        sizes = e - b
+        blocks = []
+        for i in range(1 << q):
+            for t in range(drp[i], drp[i + 1]):
+                blocks.append(self.dense_block(t, int(sizes[lf + i]), int(sizes[lf + dci[t]])).ravel(order="F"))
+        return {"n": self.n, "q": q, "level_rank": np.full(q + 1, k, dtype=np.int32), "begin": b, "end": e,
+                "U": U, "V": U, "E": E, "F": E, "S_rowptr": S_rowptr, "S_colidx": S_colidx, "S": S,
+                "D_rowptr": drp, "D_colidx": dci, "D": np.concatenate(blocks) if blocks else np.zeros(0)}
+
     def dense_expand(self):
         A = np.zeros((self.n, self.n))
         lib().or_dense_expand(self._h, A)
         return A
+
+
+def _ptr(a):
+    return None if a is None or a.size == 0 else a.ctypes.data
+
+
+def arrays_matvec(arr, x):
+    """y = A x for an H^2 matrix given by its arrays (dict with n, q,
+    level_rank, begin, end, U, V, E, F, S_rowptr, S_colidx, S (lists over
+    levels), D_rowptr, D_colidx, D; layout as in or_arrays_matvec)."""
+    q = int(arr["q"])
+    keep = []
+
+    def f64(a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return a
+
+    def i32(a):
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        keep.append(a)
+        return a
+    VP = C.c_void_p * (q + 1)
+    rp = VP(*[_ptr(i32(r)) for r in arr["S_rowptr"]])
+    ci = VP(*[_ptr(i32(c)) for c in arr["S_colidx"]])
+    sv = VP(*[_ptr(f64(v)) for v in arr["S"]])
+    y = np.zeros(int(arr["n"]))
+    rc = lib().or_arrays_matvec(int(arr["n"]), q, i32(arr["level_rank"]),
+                                np.ascontiguousarray(arr["begin"], dtype=np.int64),
+                                np.ascontiguousarray(arr["end"], dtype=np.int64),
+                                _ptr(f64(arr["U"])), _ptr(f64(arr["V"])), _ptr(f64(arr["E"])), _ptr(f64(arr["F"])),
+                                rp, ci, sv, i32(arr["D_rowptr"]), _ptr(i32(arr["D_colidx"])), _ptr(f64(arr["D"])),
+                                np.ascontiguousarray(x, dtype=np.float64), y)
+    if rc != 0:
+        raise ValueError("or_arrays_matvec rejected the arrays")
+    return y
 
 
 def bsr_assemble(nrows, rows, cols):

@@ -76,3 +76,28 @@ def batch_members(count: int = 64, seed: int = 5000, nmin_log2: float = 12.0,
         out.append(Workload(f"batch{b}-{dim}d-n{n}-m{leaf}-p{p}", n, dim, leaf, p, ell,
                             nrhs=nrhs, seed=seed + 1 + b))
     return out
+
+
+def random_h2_values(seed: int, sizes_leaf: np.ndarray, level_rank: np.ndarray, coupling_counts: list,
+                     dense_shapes: list) -> dict:
+    """Random N(0,1) entries for an H^2 matrix whose structure is given:
+    leaf sizes m_j (leaf order), ranks k_l per level, the number of coupling
+    blocks per level, and the (rows, cols) of every dense block in order.
+    Returns the value arrays in the column-major layout of h2_arrays (U, V,
+    E, F, S per level, D).  Bases and transfers are scaled by 1/sqrt(rank)
+    so that products keep unit size."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    q = len(level_rank) - 1
+    kq = int(level_rank[q])
+    nU = int(np.sum(sizes_leaf)) * kq
+    nE = sum(int(level_rank[l]) * int(level_rank[l - 1]) << l for l in range(1, q + 1))
+    U = rng.standard_normal(nU) / np.sqrt(kq)
+    V = rng.standard_normal(nU) / np.sqrt(kq)
+    E = np.concatenate([rng.standard_normal((int(level_rank[l]) * int(level_rank[l - 1])) << l)
+                        / np.sqrt(level_rank[l - 1]) for l in range(1, q + 1)]) if q > 0 else np.zeros(0)
+    F = np.concatenate([rng.standard_normal((int(level_rank[l]) * int(level_rank[l - 1])) << l)
+                        / np.sqrt(level_rank[l - 1]) for l in range(1, q + 1)]) if q > 0 else np.zeros(0)
+    assert E.size == nE
+    S = [rng.standard_normal(int(c) * int(level_rank[l]) ** 2) for l, c in enumerate(coupling_counts)]
+    D = np.concatenate([rng.standard_normal(r * c) for r, c in dense_shapes]) if dense_shapes else np.zeros(0)
+    return {"U": U, "V": V, "E": E, "F": F, "S": S, "D": D}

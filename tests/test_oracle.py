@@ -390,3 +390,109 @@ def test_invalid_arguments_rejected(oracle_mod, kw):
         P[3, 1] = np.nan
     with pytest.raises(ValueError):
         oracle_mod.OracleH2(P, kw.get("m", 4), kw.get("p", 2), kw.get("eta", 0.9), kw.get("ell", 0.1))
+
+
+# ---- the product of an H^2 matrix given by its arrays (Sec. 2.2, Eq. (1),
+# Fig. 3 and Fig. 5 layouts), with a rank per level
+
+def _dense_from_arrays(arr):
+    """A written out from the definition: nested bases of every node by Eq. (1)
+    (U_parent = [U_c1 E_c1; U_c2 E_c2]), then A = sum of the dense blocks plus
+    U_s S_st V_t^T over every coupling block."""
+    n, q, kr = int(arr["n"]), int(arr["q"]), [int(k) for k in arr["level_rank"]]
+    b, e = arr["begin"], arr["end"]
+    lf = (1 << q) - 1
+    Uh, Vh = {}, {}
+    off = 0
+    for j in range(1 << q):
+        v = lf + j
+        m = int(e[v] - b[v])
+        Uh[v] = arr["U"][off:off + m * kr[q]].reshape(kr[q], m).T
+        Vh[v] = arr["V"][off:off + m * kr[q]].reshape(kr[q], m).T
+        off += m * kr[q]
+    eo = {}
+    off = 0
+    for l in range(1, q + 1):
+        for c in range((1 << l) - 1, (2 << l) - 1):
+            eo[c] = off
+            off += kr[l] * kr[l - 1]
+
+    def transfer(name, c, l):
+        return arr[name][eo[c]:eo[c] + kr[l] * kr[l - 1]].reshape(kr[l - 1], kr[l]).T   # k_l x k_(l-1)
+    for l in range(q - 1, -1, -1):
+        for p in range((1 << l) - 1, (2 << l) - 1):
+            c1, c2 = 2 * p + 1, 2 * p + 2
+            Uh[p] = np.vstack([Uh[c1] @ transfer("E", c1, l + 1), Uh[c2] @ transfer("E", c2, l + 1)])
+            Vh[p] = np.vstack([Vh[c1] @ transfer("F", c1, l + 1), Vh[c2] @ transfer("F", c2, l + 1)])
+    A = np.zeros((n, n))
+    for l in range(q + 1):
+        f, k = (1 << l) - 1, kr[l]
+        rp, ci, S = arr["S_rowptr"][l], arr["S_colidx"][l], arr["S"][l]
+        for i in range(1 << l):
+            for t in range(rp[i], rp[i + 1]):
+                s_, t_ = f + i, f + int(ci[t])
+                Sb = S[t * k * k:(t + 1) * k * k].reshape(k, k).T
+                A[b[s_]:e[s_], b[t_]:e[t_]] += Uh[s_] @ Sb @ Vh[t_].T
+    off = 0
+    for i in range(1 << q):
+        for t in range(arr["D_rowptr"][i], arr["D_rowptr"][i + 1]):
+            s_, t_ = lf + i, lf + int(arr["D_colidx"][t])
+            ms, mt = int(e[s_] - b[s_]), int(e[t_] - b[t_])
+            A[b[s_]:e[s_], b[t_]:e[t_]] += arr["D"][off:off + ms * mt].reshape(mt, ms).T
+            off += ms * mt
+    return A
+
+
+def _random_arrays(oracle_mod, n, d, m, ranks_seed, values_seed, kmax=12):
+    """The block structure of an oracle H^2 (a valid partition), a random rank
+    per level and random values."""
+    o = oracle_mod.OracleH2(_pts(n, d, 40 + n), m, 2, 0.9, 0.2)
+    b, e = o.ranges()
+    q, lf = o.q, (1 << o.q) - 1
+    rng = np.random.Generator(np.random.PCG64(ranks_seed))
+    level_rank = rng.integers(1, kmax + 1, size=q + 1).astype(np.int32)
+    S_rowptr, S_colidx = [], []
+    for l in range(q + 1):
+        rp, ci = o.coupling_bsr(l)
+        S_rowptr.append(rp)
+        S_colidx.append(ci)
+    drp, dci = o.dense_bsr()
+    sizes = e - b
+    shapes = [(int(sizes[lf + i]), int(sizes[lf + dci[t]])) for i in range(1 << q) for t in range(drp[i], drp[i + 1])]
+    vals = W.random_h2_values(values_seed, sizes[lf:], level_rank, [len(c) for c in S_colidx], shapes)
+    return {"n": n, "q": q, "level_rank": level_rank, "begin": b, "end": e, "S_rowptr": S_rowptr,
+            "S_colidx": S_colidx, "D_rowptr": drp, "D_colidx": dci, **vals}
+
+
+@pytest.mark.parametrize("n,d,m", [(1500, 2, 32), (900, 3, 16)])
+def test_arrays_product_equals_oracle_product(oracle_mod, n, d, m):
+    o = oracle_mod.OracleH2(_pts(n, d, 7), m, 3, 0.9, 0.15)
+    arr = o.export_arrays()
+    x = _x(n, 8)
+    y, ref = oracle_mod.arrays_matvec(arr, x), o.matvec(x)
+    assert np.linalg.norm(y - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("n,d,m,seed", [(600, 2, 16, 1), (700, 3, 16, 2), (257, 2, 8, 3)])
+def test_arrays_product_with_level_ranks_equals_definition(oracle_mod, n, d, m, seed):
+    arr = _random_arrays(oracle_mod, n, d, m, seed, 100 + seed)
+    assert len(set(arr["level_rank"].tolist())) > 1
+    x = _x(n, 9)
+    y = oracle_mod.arrays_matvec(arr, x)
+    ref = _dense_from_arrays(arr) @ x
+    assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_arrays_product_single_leaf_is_dense(oracle_mod):
+    rng = np.random.Generator(np.random.PCG64(4))
+    n = 7
+    D = rng.standard_normal((n, n))
+    arr = {"n": n, "q": 0, "level_rank": np.array([3], dtype=np.int32), "begin": np.array([0]),
+           "end": np.array([n]), "U": np.zeros(3 * n), "V": np.zeros(3 * n), "E": np.zeros(0), "F": np.zeros(0),
+           "S_rowptr": [np.array([0, 0], dtype=np.int32)], "S_colidx": [np.zeros(0, dtype=np.int32)],
+           "S": [np.zeros(0)], "D_rowptr": np.array([0, 1], dtype=np.int32),
+           "D_colidx": np.array([0], dtype=np.int32), "D": D.ravel(order="F")}
+    x = rng.standard_normal(n)
+    y = oracle_mod.arrays_matvec(arr, x)
+    ref = np.array([sum(D[i, j] * x[j] for j in range(n)) for i in range(n)])
+    assert np.allclose(y, ref, rtol=0, atol=1e-14 * np.abs(ref).max())
