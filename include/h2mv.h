@@ -106,6 +106,60 @@ typedef struct {
 h2_status h2_build_from_points(const double *points, int64_t n, const h2_params *prm,
                                void *stream, h2_handle *out);
 
+/* An H^2 matrix given by its arrays (Sec. 2.2; the flattened per-level
+ * storage of Sec. 3 and Fig. 3; the matrix tree as per-level block-sparse
+ * rows, Fig. 5), 0-based, all host memory, read during the call only.
+ *  n           rows (= columns) of A, 1 <= n < 2^31; vectors are in the tree
+ *              order these arrays define (h2_get_perm then gives the identity).
+ *  q           leaf level, 0 <= q <= 29.  Nodes 0 .. 2^(q+1)-2 in heap order:
+ *              level l holds nodes 2^l-1 .. 2^(l+1)-2, children of v are
+ *              2v+1 and 2v+2.
+ *  level_rank  q+1 ranks k_0 .. k_q of the levels' bases, 1 <= k_l <= 64.
+ *  node_begin, node_end  2^(q+1)-1 values each: node v holds rows
+ *              [begin, end); the root holds [0, n), children split their
+ *              parent into two non-empty consecutive ranges, leaves hold at
+ *              most 64 rows.
+ *  U, V        leaf bases: leaf j (node 2^q-1+j) has U_j and V_j, m_j x k_q
+ *              column-major, concatenated in leaf order (V may equal U).
+ *  E, F        transfers (Eq. (1)): every node c >= 1 of level l has E_c and
+ *              F_c, k_l x k_(l-1) column-major, concatenated in node order
+ *              (F may equal E); U_parent = [U_c1 E_c1; U_c2 E_c2].  May be NULL
+ *              when q = 0.
+ *  S_rowptr, S_colidx, S   q+1 pointers each: for level l, 2^l+1 row offsets,
+ *              the level-local column node of every block, and the k_l x k_l
+ *              column-major coupling blocks S_ij in that order (a level
+ *              without blocks may have NULL colidx and S).
+ *  D_rowptr, D_colidx, D   dense blocks over the leaves: 2^q+1 row offsets,
+ *              leaf-local columns, m_i x m_j column-major blocks in that order.
+ * A = sum of D_ij over dense blocks + sum over levels and coupling blocks of
+ * U^l_i S_ij (V^l_j)^T, with the nested bases of Eq. (1).  U and V may be
+ * NULL when no level has a coupling block.  Values are not checked (NaN in,
+ * NaN out); the partition of A into blocks is the caller's (a pair listed
+ * twice is added twice). */
+typedef struct {
+    int64_t n;
+    int q;
+    const int32_t *level_rank;
+    const int64_t *node_begin, *node_end;
+    const double *U, *V, *E, *F;
+    const int32_t *const *S_rowptr;
+    const int32_t *const *S_colidx;
+    const double *const *S;
+    const int32_t *D_rowptr, *D_colidx;
+    const double *D;
+} h2_arrays;
+
+/* Build a handle from arrays (values converted to the storage's layout and
+ * element type on the host and uploaded in pieces of at most 64 MiB).
+ *  storage  h2_storage; H2_FP32 / H2_BF16_SCALED round as described above.
+ *  stream   stream of the uploads; the call returns when they are done.
+ * h2_get_info reports dim 0, cheb_p 0, leaf_size = the largest leaf and rank
+ * = the largest level rank.  Errors: INVALID_ARG for NULL required pointers,
+ * inconsistent node ranges, BSR offsets that are not non-decreasing from 0,
+ * or block columns out of range; UNSUPPORTED for ranks or leaves above 64 or
+ * q > 29; OOM; DEVICE. */
+h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *stream, h2_handle *out);
+
 /* y = A x (Sec. 4, Fig. 4).
  *  x  device, n doubles, tree order.   y  device, n doubles, tree order.
  * x and y must not overlap.  Errors: INVALID_ARG for NULL pointers or a

@@ -175,11 +175,81 @@ using h2::BlkDesc;
 using h2::RowDesc;
 using h2::Structure;
 
-// Layout of the representation, generation on the device, and the work lists
-// of one product in launch order.
-void build_device(h2_matrix_ &A, hipStream_t stream) {
+// Host conversion of a column-major FP64 block (R x C, leading dimension R)
+// into the device layout of its element kind: 16-byte column groups (see
+// block_elems), transposed on request, FP32 rounded to nearest even, BF16
+// with one FP32 scale (max |fp32(a)|) and codes rounded to nearest even --
+// the same rules as the device fill kernels.
+uint16_t host_bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+void convert_block(const double *src, int R, int C, bool transpose, int kind, void *dst, float *scale) {
+    // element (r, c) of the stored block: src[r + c * R] (or src[c + r * C] transposed)
+    auto val = [&](int r, int c) { return transpose ? src[c + int64_t(r) * C] : src[r + int64_t(c) * R]; };
+    const int W = 16 / h2::elem_bytes(kind);
+    const int64_t ne = h2::block_elems(R, C, kind);
+    float s = 0.0f;
+    if (kind == h2::ELEM_BF16)
+        for (int c = 0; c < C; ++c)
+            for (int r = 0; r < R; ++r) s = std::max(s, std::fabs(float(val(r, c))));
+    for (int64_t e = 0; e < ne; ++e) {
+        const int w = int(e % W);
+        const int64_t t = e / W;
+        const int r = int(t % R), c = int(t / R) * W + w;
+        const double v = c < C ? val(r, c) : 0.0;
+        if (kind == h2::ELEM_F64) static_cast<double *>(dst)[e] = v;
+        else if (kind == h2::ELEM_F32) static_cast<float *>(dst)[e] = float(v);
+        else static_cast<uint16_t *>(dst)[e] = s == 0.0f ? uint16_t(0) : host_bf16_rne(float(v) / s);
+    }
+    if (scale) *scale = s;
+}
+
+// Uploads converted blocks through a bounded host staging buffer.
+struct Stager {
+    char *dev;
+    int64_t elem;
+    hipStream_t st;
+    std::vector<char> buf;
+    int64_t buf_off = 0;   // element offset of buf[0] on the device
+    int64_t used = 0;      // bytes in buf
+    static constexpr int64_t kCap = int64_t(64) << 20;
+    Stager(void *d, int kind, hipStream_t s) : dev(static_cast<char *>(d)), elem(h2::elem_bytes(kind)), st(s) {
+        buf.resize(kCap);
+    }
+    void flush() {
+        if (used > 0) {
+            check_hip(hipMemcpyAsync(dev + buf_off * elem, buf.data(), size_t(used), hipMemcpyHostToDevice, st),
+                      "hipMemcpyAsync");
+            check_hip(hipStreamSynchronize(st), "upload blocks");
+        }
+        buf_off += used / elem;
+        used = 0;
+    }
+    // Room for a block of ne elements placed at element offset off (blocks arrive in offset order).
+    void *place(int64_t off, int64_t ne) {
+        const int64_t bytes = ne * elem;
+        if (off * elem != buf_off * elem + used || used + bytes > kCap) {
+            flush();
+            buf_off = off;
+        }
+        if (bytes > kCap) fail(H2_ERR_INTERNAL, "block larger than the staging buffer");
+        void *p = buf.data() + used;
+        used += bytes;
+        return p;
+    }
+};
+
+// Layout of the representation, generation on the device (from points) or
+// conversion of caller arrays (src), and the work lists of one product in
+// launch order.  Ranks may differ per level (k_l); vectors and tiles use the
+// largest rank as their node stride.
+void build_device(h2_matrix_ &A, const h2_arrays *src, hipStream_t stream) {
     const Structure &s = A.st;
-    const int k = s.rank, q = s.q;
+    const int k = s.rank, q = s.q;   // k: largest level rank
+    const std::vector<int> &kl = s.lrank;
     const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
     const bool lowrank = s.lmin <= q;
     const int bk = A.basis_kind, sk = A.block_kind;
@@ -192,18 +262,18 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
         const int m = int(s.size(lf + j));
         leaf_node[j] = lf + j;
         off_U[j] = nb;
-        nb += h2::block_elems(m, k, bk);
+        nb += h2::block_elems(m, kl[q], bk);
         off_VT[j] = nb;
-        nb += h2::block_elems(k, m, bk);
+        nb += h2::block_elems(kl[q], m, bk);
     }
     const int64_t leaf_elems = nb;
     if (lowrank)
         for (int l = s.lmin + 1; l <= q; ++l)
             for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
                 off_E[c] = nb;
-                nb += h2::block_elems(k, k, bk);
+                nb += h2::block_elems(kl[l], kl[l - 1], bk);
                 off_FT[c] = nb;
-                nb += h2::block_elems(k, k, bk);
+                nb += h2::block_elems(kl[l - 1], kl[l], bk);
             }
     const int64_t eb = h2::elem_bytes(bk), sb = h2::elem_bytes(sk);
     A.bytes_leaf = lowrank ? leaf_elems * eb : 0;
@@ -219,7 +289,7 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
             for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b) {
                 fill.push_back({ns, int32_t(f + i), int32_t(f + B.colidx[b]), int32_t(fill.size()),
                                 h2::FILL_COUPLING});
-                ns += h2::block_elems(k, k, sk);
+                ns += h2::block_elems(kl[l], kl[l], sk);
             }
     }
     const int64_t coupling_elems = ns, ncoupling = int64_t(fill.size());
@@ -233,14 +303,14 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
     A.bytes_coupling = coupling_elems * sb + scale_bytes * ncoupling;
     A.bytes_dense = (ns - coupling_elems) * sb + scale_bytes * (int64_t(fill.size()) - ncoupling);
 
-    // generation of the representation on the device
-    std::vector<double> cheb(s.cheb_p);
-    for (int a = 0; a < s.cheb_p; ++a) cheb[a] = std::cos((2.0 * a + 1.0) * M_PI / (2.0 * s.cheb_p));
     A.basis = A.mem.alloc(nb * eb);
     A.blocks = A.mem.alloc(ns * sb);
     A.scales = static_cast<float *>(A.mem.alloc(std::max<int64_t>(1, int64_t(fill.size())) * 4));
     A.nscales = int64_t(fill.size());
-    {
+    if (!src) {
+        // generation of the representation on the device (Sec. 4.6)
+        std::vector<double> cheb(s.cheb_p);
+        for (int a = 0; a < s.cheb_p; ++a) cheb[a] = std::cos((2.0 * a + 1.0) * M_PI / (2.0 * s.cheb_p));
         DeviceArena scratch;   // geometry and fill lists, freed after the build
         if (A.mem.cap >= 0) scratch.cap = std::max<int64_t>(0, A.mem.cap - A.mem.bytes);
         h2::Geometry g;
@@ -266,6 +336,59 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
         check_hip(h2::launch_fill_blocks(g, sk, A.blocks, A.scales, d_fill, int64_t(fill.size()), stream),
                   "fill blocks");
         check_hip(hipStreamSynchronize(stream), "fill");
+    } else {
+        // caller arrays (column-major FP64) converted to the device layout
+        {
+            Stager up(A.basis, bk, stream);
+            const int kq = kl[q];
+            int64_t uoff = 0;   // offset of leaf j's m_j x k_q block in U and V
+            for (int64_t j = 0; j < nleaves && lowrank; ++j) {
+                const int m = int(s.size(lf + j));
+                convert_block(src->U + uoff, m, kq, false, bk, up.place(off_U[j], h2::block_elems(m, kq, bk)),
+                              nullptr);
+                convert_block(src->V + uoff, kq, m, true, bk, up.place(off_VT[j], h2::block_elems(kq, m, bk)),
+                              nullptr);
+                uoff += int64_t(m) * kq;
+            }
+            int64_t eoff = 0;   // offset of node c's k_l x k_(l-1) block in E and F
+            for (int l = 1; l <= q; ++l)
+                for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
+                    if (off_E[c] >= 0) {
+                        convert_block(src->E + eoff, kl[l], kl[l - 1], false, bk,
+                                      up.place(off_E[c], h2::block_elems(kl[l], kl[l - 1], bk)), nullptr);
+                        convert_block(src->F + eoff, kl[l - 1], kl[l], true, bk,
+                                      up.place(off_FT[c], h2::block_elems(kl[l - 1], kl[l], bk)), nullptr);
+                    }
+                    eoff += int64_t(kl[l]) * kl[l - 1];
+                }
+            up.flush();
+        }
+        {
+            Stager up(A.blocks, sk, stream);
+            std::vector<float> scales(fill.size(), 1.0f);
+            int64_t fi = 0;
+            for (int l = 0; l <= q; ++l) {
+                const h2::Bsr &B = s.coupling[l];
+                const int64_t kk = int64_t(kl[l]) * kl[l];
+                for (int64_t b = 0; b < B.blocks(); ++b, ++fi)
+                    convert_block(src->S[l] + b * kk, kl[l], kl[l], false, sk,
+                                  up.place(fill[fi].a, h2::block_elems(kl[l], kl[l], sk)), &scales[fi]);
+            }
+            int64_t doff = 0;
+            for (int64_t i = 0; i < nleaves; ++i)
+                for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++fi) {
+                    const int R = int(s.size(lf + i)), C = int(s.size(lf + s.dense.colidx[b]));
+                    convert_block(src->D + doff, R, C, false, sk, up.place(fill[fi].a, h2::block_elems(R, C, sk)),
+                                  &scales[fi]);
+                    doff += int64_t(R) * C;
+                }
+            up.flush();
+            if (sk == h2::ELEM_BF16 && !scales.empty()) {
+                check_hip(hipMemcpyAsync(A.scales, scales.data(), scales.size() * 4, hipMemcpyHostToDevice, stream),
+                          "hipMemcpyAsync");
+                check_hip(hipStreamSynchronize(stream), "upload scales");
+            }
+        }
     }
 
     // workspace: vector trees x^ and y^ (nnodes x k) and the near field (n)
@@ -346,14 +469,15 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
         // leaf projection x^_j = V_j^T x(j)   (Sec. 4.2)
         for (int64_t j = 0; j < nleaves; ++j) {
             const int64_t v = lf + j;
-            L.push_back({false, v, false, k, h2::ROW_IN_X, {{off_VT[j], int32_t(s.size(v)), 0, true, j}}});
+            L.push_back({false, v, false, kl[q], h2::ROW_IN_X, {{off_VT[j], int32_t(s.size(v)), 0, true, j}}});
         }
         emit(PH_UP, bk, A.basis, L);
         // upsweep x^_p = F_c1^T x^_c1 + F_c2^T x^_c2 for levels q .. lmin+1   (Sec. 4.2)
         for (int l = q; l > s.lmin; --l) {
             for (int64_t p = Structure::first(l - 1); p < Structure::first(l); ++p)
-                L.push_back({false, p, false, k, 0,
-                             {{off_FT[2 * p + 1], k, 0, false, 2 * p + 1}, {off_FT[2 * p + 2], k, 0, false, 2 * p + 2}}});
+                L.push_back({false, p, false, kl[l - 1], 0,
+                             {{off_FT[2 * p + 1], kl[l], 0, false, 2 * p + 1},
+                              {off_FT[2 * p + 2], kl[l], 0, false, 2 * p + 2}}});
             emit(PH_UP, bk, A.basis, L);
         }
     }
@@ -366,9 +490,9 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
                 const h2::Bsr &B = s.coupling[l];
                 const int64_t f = Structure::first(l);
                 for (int64_t i = 0; i < (int64_t(1) << l); ++i) {
-                    LRow r{false, f + i, false, k, 0, {}};
+                    LRow r{false, f + i, false, kl[l], 0, {}};
                     for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b, ++fi)
-                        r.b.push_back({fill[fi].a, k, fill[fi].sidx, false, f + B.colidx[b]});
+                        r.b.push_back({fill[fi].a, kl[l], fill[fi].sidx, false, f + B.colidx[b]});
                     L.push_back(std::move(r));
                 }
             }
@@ -402,14 +526,14 @@ void build_device(h2_matrix_ &A, hipStream_t stream) {
         // downsweep y^_c += E_c y^_parent for levels lmin+1 .. q   (Sec. 4.4)
         for (int l = s.lmin + 1; l <= q; ++l) {
             for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c)
-                L.push_back({false, c, true, k, 0, {{off_E[c], k, 0, false, (c - 1) / 2}}});
+                L.push_back({false, c, true, kl[l], 0, {{off_E[c], kl[l - 1], 0, false, (c - 1) / 2}}});
             emit(PH_DOWN, bk, A.basis, L);
         }
     }
     // leaf expansion and sum: y(i) = y_near(i) + U_i y^_i   (Sec. 4.4, Sec. 4.1)
     for (int64_t j = 0; j < nleaves; ++j) {
         LRow r{true, j, true, int(s.size(lf + j)), h2::ROW_OUT_P, {}};
-        if (lowrank) r.b.push_back({off_U[j], k, 0, false, lf + j});
+        if (lowrank) r.b.push_back({off_U[j], kl[q], 0, false, lf + j});
         L.push_back(std::move(r));
     }
     emit(PH_LEAF, bk, A.basis, L);
@@ -956,7 +1080,101 @@ h2_status h2_build_from_points(const double *points, int64_t n, const h2_params 
         std::string err = h2::build_structure(points, n, prm->dim, prm->leaf_size, prm->cheb_p, prm->eta,
                                               prm->corr_len, A->st);
         if (!err.empty()) fail(H2_ERR_UNSUPPORTED, err);
-        if (!A->structure_only) build_device(*A, static_cast<hipStream_t>(stream));
+        if (!A->structure_only) build_device(*A, nullptr, static_cast<hipStream_t>(stream));
+        *out = A;
+        g_last_error.clear();
+        return H2_OK;
+    } catch (const Failure &f) {
+        delete A;
+        g_last_error = f.what;
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        delete A;
+        g_last_error = "host allocation failed";
+        return H2_ERR_OOM;
+    } catch (...) {
+        delete A;
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+// Checks the arrays and fills the host structure from them.
+void structure_from_arrays(const h2_arrays *a, h2::Structure &s) {
+    if (!a) fail(H2_ERR_INVALID_ARG, "NULL arrays");
+    if (a->n < 1 || a->n >= (int64_t(1) << 31)) fail(H2_ERR_INVALID_ARG, "n out of range");
+    if (a->q < 0) fail(H2_ERR_INVALID_ARG, "q < 0");
+    if (a->q > 29) fail(H2_ERR_UNSUPPORTED, "q above 29");
+    if ((int64_t(1) << a->q) > a->n) fail(H2_ERR_INVALID_ARG, "more leaves than rows");
+    if (!a->level_rank || !a->node_begin || !a->node_end || !a->S_rowptr || !a->S_colidx || !a->S ||
+        !a->D_rowptr || (!a->D_colidx && a->D_rowptr[int64_t(1) << a->q] > 0) ||
+        (!a->D && a->D_rowptr[int64_t(1) << a->q] > 0))
+        fail(H2_ERR_INVALID_ARG, "NULL array");
+    s = h2::Structure();
+    s.n = a->n;
+    s.q = a->q;
+    s.nnodes = (int64_t(2) << a->q) - 1;
+    s.lrank.resize(a->q + 1);
+    s.rank = 0;
+    for (int l = 0; l <= a->q; ++l) {
+        const int k = a->level_rank[l];
+        if (k < 1) fail(H2_ERR_INVALID_ARG, "level rank < 1");
+        if (k > 64) fail(H2_ERR_UNSUPPORTED, "level rank above 64");
+        s.lrank[l] = k;
+        s.rank = std::max(s.rank, k);
+    }
+    s.begin.assign(a->node_begin, a->node_begin + s.nnodes);
+    s.end.assign(a->node_end, a->node_end + s.nnodes);
+    if (s.begin[0] != 0 || s.end[0] != a->n) fail(H2_ERR_INVALID_ARG, "root must hold rows [0, n)");
+    for (int64_t v = 0; v < s.nnodes; ++v) {
+        if (s.end[v] <= s.begin[v]) fail(H2_ERR_INVALID_ARG, "empty node");
+        if (2 * v + 2 < s.nnodes) {
+            const int64_t c1 = 2 * v + 1, c2 = 2 * v + 2;
+            if (s.begin[c1] != s.begin[v] || s.end[c1] != s.begin[c2] || s.end[c2] != s.end[v])
+                fail(H2_ERR_INVALID_ARG, "children must split their parent into consecutive ranges");
+        } else {
+            s.leaf = int(std::max<int64_t>(s.leaf, s.size(v)));
+        }
+    }
+    if (s.leaf > 64) fail(H2_ERR_UNSUPPORTED, "leaf above 64 rows");
+    auto take_bsr = [&](int64_t rows, const int32_t *rp, const int32_t *ci, h2::Bsr &B) {
+        if (rp[0] != 0) fail(H2_ERR_INVALID_ARG, "BSR offsets must start at 0");
+        B.rowptr.assign(rp, rp + rows + 1);
+        for (int64_t i = 0; i < rows; ++i)
+            if (B.rowptr[i + 1] < B.rowptr[i]) fail(H2_ERR_INVALID_ARG, "BSR offsets must not decrease");
+        B.colidx.assign(ci, ci + B.rowptr[rows]);
+        for (int32_t c : B.colidx)
+            if (c < 0 || c >= rows) fail(H2_ERR_INVALID_ARG, "BSR column out of range");
+    };
+    s.coupling.resize(a->q + 1);
+    s.lmin = a->q + 1;
+    for (int l = a->q; l >= 0; --l) {
+        if (!a->S_rowptr[l]) fail(H2_ERR_INVALID_ARG, "NULL S_rowptr");
+        if (a->S_rowptr[l][int64_t(1) << l] > 0 && (!a->S_colidx[l] || !a->S[l]))
+            fail(H2_ERR_INVALID_ARG, "NULL S_colidx / S for a level with blocks");
+        take_bsr(int64_t(1) << l, a->S_rowptr[l], a->S_colidx[l], s.coupling[l]);
+        if (s.coupling[l].blocks() > 0) s.lmin = l;
+    }
+    take_bsr(int64_t(1) << a->q, a->D_rowptr, a->D_colidx, s.dense);
+    if (s.lmin <= a->q && (!a->U || !a->V)) fail(H2_ERR_INVALID_ARG, "NULL U / V with coupling blocks");
+    if (s.lmin < a->q && (!a->E || !a->F)) fail(H2_ERR_INVALID_ARG, "NULL E / F with coupling blocks above the leaves");
+    s.perm.resize(a->n);
+    for (int64_t i = 0; i < a->n; ++i) s.perm[i] = i;
+}
+
+h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *stream, h2_handle *out) {
+    if (out) *out = nullptr;
+    h2_matrix_ *A = nullptr;
+    try {
+        if (!out) fail(H2_ERR_INVALID_ARG, "NULL out");
+        if (storage < H2_FP64 || storage > H2_BF16_SCALED) fail(H2_ERR_INVALID_ARG, "storage out of range");
+        A = new h2_matrix_();
+        structure_from_arrays(arrays, A->st);
+        A->storage = storage;
+        A->basis_kind = storage == H2_FP64 ? h2::ELEM_F64 : h2::ELEM_F32;
+        A->block_kind = storage == H2_FP64 ? h2::ELEM_F64 : storage == H2_FP32 ? h2::ELEM_F32 : h2::ELEM_BF16;
+        A->vec_f64 = storage == H2_FP64;
+        build_device(*A, arrays, static_cast<hipStream_t>(stream));
         *out = A;
         g_last_error.clear();
         return H2_OK;

@@ -169,6 +169,7 @@ std::string build_structure(const double *points, int64_t n, int dim, int leaf, 
     while ((int64_t(leaf) << s.q) < n) ++s.q;
     if (s.q > 29) return "tree deeper than 29 levels";
     s.nnodes = (int64_t(2) << s.q) - 1;
+    s.lrank.assign(s.q + 1, s.rank);
     s.perm.resize(n);
     std::iota(s.perm.begin(), s.perm.end(), int64_t(0));
     s.begin.assign(s.nnodes, 0);

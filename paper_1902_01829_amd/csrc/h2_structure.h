@@ -25,6 +25,7 @@ struct Structure {
     std::vector<double> lo, hi;          // nnodes x dim, widened tight boxes
     std::vector<Bsr> coupling;           // per level 0..q, rows = nodes of the level
     Bsr dense;                           // rows = leaves
+    std::vector<int> lrank;              // rank of every level 0..q (rank = their maximum)
     int64_t near_ties = 0;
 
     static int64_t first(int level) { return (int64_t(1) << level) - 1; }

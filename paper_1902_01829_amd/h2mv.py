@@ -20,7 +20,7 @@ H2_FLAG_STRUCTURE_ONLY = 1
 STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
 
 # Every function declared in include/h2mv.h.
-EXPORTS = ("h2_build_from_points", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
+EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
            "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_batch_create", "h2_batch_matmat",
            "h2_batch_tuning", "h2_batch_free", "h2_last_error")
 
@@ -28,6 +28,13 @@ EXPORTS = ("h2_build_from_points", "h2_matvec", "h2_matmat", "h2_free", "h2_get_
 class h2_params(C.Structure):
     _fields_ = [("dim", C.c_int), ("leaf_size", C.c_int), ("cheb_p", C.c_int), ("eta", C.c_double),
                 ("corr_len", C.c_double), ("storage", C.c_int), ("flags", C.c_uint)]
+
+
+class h2_arrays(C.Structure):
+    _fields_ = [("n", C.c_int64), ("q", C.c_int), ("level_rank", C.c_void_p), ("node_begin", C.c_void_p),
+                ("node_end", C.c_void_p), ("U", C.c_void_p), ("V", C.c_void_p), ("E", C.c_void_p),
+                ("F", C.c_void_p), ("S_rowptr", C.c_void_p), ("S_colidx", C.c_void_p), ("S", C.c_void_p),
+                ("D_rowptr", C.c_void_p), ("D_colidx", C.c_void_p), ("D", C.c_void_p)]
 
 
 class h2_info(C.Structure):
@@ -60,6 +67,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
         L.h2_build_from_points.argtypes = [vp, i64, C.POINTER(h2_params), vp, C.POINTER(vp)]
+        L.h2_build_from_arrays.argtypes = [C.POINTER(h2_arrays), C.c_int, vp, C.POINTER(vp)]
         L.h2_matvec.argtypes = [vp, vp, vp, vp]
         L.h2_matmat.argtypes = [vp, vp, i64, vp, i64, C.c_int, vp]
         L.h2_free.argtypes = [vp]
@@ -101,6 +109,34 @@ def h2_build_from_points(points, dim, leaf_size, cheb_p, eta, corr_len, storage=
     h = C.c_void_p()
     _check(lib().h2_build_from_points(pts.ctypes.data if pts.size else None, n, C.byref(prm),
                                       C.c_void_p(stream), C.byref(h)))
+    return h.value
+
+
+def h2_build_from_arrays(arr, storage=H2_FP64, stream=0):
+    """arr: dict with n, q, level_rank, begin, end, U, V, E, F, S_rowptr,
+    S_colidx, S (lists over levels), D_rowptr, D_colidx, D (host arrays,
+    column-major blocks; see include/h2mv.h).  Returns the handle (an int)."""
+    keep = []
+
+    def arr_of(a, dtype):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dtype)
+        keep.append(a)
+        return a.ctypes.data if a.size else None
+    q = int(arr["q"])
+    nl = max(1, len(arr["S_rowptr"]))
+    rp = (C.c_void_p * nl)(*[arr_of(r, np.int32) for r in arr["S_rowptr"]])
+    ci = (C.c_void_p * nl)(*[arr_of(c, np.int32) for c in arr["S_colidx"]])
+    sv = (C.c_void_p * nl)(*[arr_of(v, np.float64) for v in arr["S"]])
+    a = h2_arrays(int(arr["n"]), q, arr_of(arr["level_rank"], np.int32), arr_of(arr["begin"], np.int64),
+                  arr_of(arr["end"], np.int64), arr_of(arr.get("U"), np.float64), arr_of(arr.get("V"), np.float64),
+                  arr_of(arr.get("E"), np.float64), arr_of(arr.get("F"), np.float64),
+                  C.cast(rp, C.c_void_p), C.cast(ci, C.c_void_p), C.cast(sv, C.c_void_p),
+                  arr_of(arr["D_rowptr"], np.int32), arr_of(arr["D_colidx"], np.int32),
+                  arr_of(arr["D"], np.float64))
+    h = C.c_void_p()
+    _check(lib().h2_build_from_arrays(C.byref(a), storage, C.c_void_p(stream), C.byref(h)))
     return h.value
 
 
@@ -226,6 +262,20 @@ class H2Matrix:
         self.handle = h2_build_from_points(points, dim, leaf_size, cheb_p, eta, corr_len, storage, flags, st)
         self.info = h2_get_info(self.handle)
         self.n = self.info.n
+
+    @classmethod
+    def from_arrays(cls, arr, storage=H2_FP64, stream=None):
+        """A matrix given by its arrays (h2_build_from_arrays); vectors are in
+        the order of arr's node ranges."""
+        import torch
+        self = cls.__new__(cls)
+        self._torch = torch
+        st = stream if stream is not None else (torch.cuda.current_stream().cuda_stream
+                                                if torch.cuda.is_available() else 0)
+        self.handle = h2_build_from_arrays(arr, storage, st)
+        self.info = h2_get_info(self.handle)
+        self.n = self.info.n
+        return self
 
     def close(self):
         if getattr(self, "handle", None):

@@ -75,3 +75,53 @@ def test_null_arguments():
         h2mv.h2_matvec(0, 8, 16)
     with pytest.raises(h2mv.H2Error):
         h2mv.h2_get_info(0)
+
+
+def _valid_arrays():
+    """A small, consistent H^2 given by arrays: 8 rows, q = 1, ranks (2, 3),
+    one coupling block per leaf pair, dense diagonal blocks."""
+    n = 8
+    b = np.array([0, 0, 4], dtype=np.int64)
+    e = np.array([8, 4, 8], dtype=np.int64)
+    return {"n": n, "q": 1, "level_rank": np.array([2, 3], dtype=np.int32), "begin": b, "end": e,
+            "U": np.ones(8 * 3), "V": np.ones(8 * 3), "E": np.ones(2 * 3 * 2), "F": np.ones(2 * 3 * 2),
+            "S_rowptr": [np.array([0, 0], dtype=np.int32), np.array([0, 1, 2], dtype=np.int32)],
+            "S_colidx": [np.zeros(0, dtype=np.int32), np.array([1, 0], dtype=np.int32)],
+            "S": [np.zeros(0), np.ones(2 * 9)],
+            "D_rowptr": np.array([0, 1, 2], dtype=np.int32), "D_colidx": np.array([0, 1], dtype=np.int32),
+            "D": np.ones(2 * 16)}
+
+
+def _bad(field, value):
+    a = _valid_arrays()
+    a[field] = value
+    return a
+
+
+@pytest.mark.parametrize("arr,storage,code", [
+    (_bad("n", 0), 0, h2mv.H2_ERR_INVALID_ARG),
+    (_bad("q", 30), 0, h2mv.H2_ERR_UNSUPPORTED),
+    (_bad("q", -1), 0, h2mv.H2_ERR_INVALID_ARG),
+    (_bad("level_rank", np.array([2, 0], dtype=np.int32)), 0, h2mv.H2_ERR_INVALID_ARG),
+    (_bad("level_rank", np.array([2, 65], dtype=np.int32)), 0, h2mv.H2_ERR_UNSUPPORTED),
+    (_bad("end", np.array([7, 4, 8], dtype=np.int64)), 0, h2mv.H2_ERR_INVALID_ARG),      # root not [0, n)
+    (_bad("begin", np.array([0, 0, 5], dtype=np.int64)), 0, h2mv.H2_ERR_INVALID_ARG),    # gap between children
+    (_bad("D_rowptr", np.array([0, 2, 1], dtype=np.int32)), 0, h2mv.H2_ERR_INVALID_ARG),  # decreasing
+    (_bad("D_colidx", np.array([0, 2], dtype=np.int32)), 0, h2mv.H2_ERR_INVALID_ARG),     # column out of range
+    (_bad("U", None), 0, h2mv.H2_ERR_INVALID_ARG),                                         # coupling without U
+    (_valid_arrays(), 5, h2mv.H2_ERR_INVALID_ARG),
+])
+def test_build_from_arrays_rejects(arr, storage, code):
+    with pytest.raises(h2mv.H2Error) as e:
+        h2mv.h2_build_from_arrays(arr, storage)
+    assert e.value.code == code
+    assert h2mv.h2_last_error()
+
+
+def test_build_from_arrays_rejects_wide_leaf():
+    a = _valid_arrays()
+    n = 130
+    a.update(n=n, begin=np.array([0, 0, 65], dtype=np.int64), end=np.array([n, 65, n], dtype=np.int64))
+    with pytest.raises(h2mv.H2Error) as e:
+        h2mv.h2_build_from_arrays(a, 0)
+    assert e.value.code == h2mv.H2_ERR_UNSUPPORTED
