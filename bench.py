@@ -160,13 +160,72 @@ def cpu_baseline(w, perm, xt, budget_s=20.0):
     t = time.perf_counter() - t0
     nbytes = touched_bytes(leaves)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {
         "value": round(nbytes / t / 1e9, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
         "sample": f"FP64 oracle, matrix-free (blocks regenerated from the kernel), full upsweep + rows of "
                   f"{nl} of {1 << q} leaves ({len(o.leaf_rows(leaves))} rows): {t:.1f} s for "
                   f"{nbytes / 1e9:.2f} GB of blocks, bases and transfers touched (at FP64 stored size); "
-                  f"oracle build {build_s:.1f} s",
+                  f"oracle build {build_s:.1f} s; {cores} threads of {os.cpu_count()} on {model}",
     }, o.leaf_rows(leaves), y_ref
+
+
+def small_case(reps=200):
+    """The 4096-point 2-D workload (rank 16, leaf 32), cache-resident, so a
+    latency figure: microseconds per product, eager and replayed from a HIP
+    graph, and its error against the FP64 oracle (the same H^2) and against
+    the exact kernel product (the approximation error)."""
+    import torch
+    from oracle import oracle as O
+    from paper_1902_01829_amd import h2mv
+    w = W.C1
+    A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=0)
+    perm = A.perm()
+    x_in = W.rhs(w, 1)
+    x = torch.from_numpy(x_in[perm]).cuda()
+    y = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(10):
+            A.matvec(x, out=y)
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            A.matvec(x, out=y)
+        s.synchronize()
+        eager_us = (time.perf_counter() - t0) * 1e6 / reps
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        A.matvec(x, out=y)
+    for _ in range(10):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_us = (time.perf_counter() - t0) * 1e6 / reps
+    yt = y.cpu().numpy()
+    del g
+    A.close()
+    o = O.OracleH2(W.points(w), w.leaf, w.cheb_p, w.eta, w.corr_len)
+    rel_oracle = float(np.linalg.norm(yt - o.matvec(x_in[perm])) / np.linalg.norm(o.matvec(x_in[perm])))
+    y_in = np.empty_like(yt)
+    y_in[perm] = yt
+    exact = O.kernel_matvec(W.points(w), x_in, w.corr_len)
+    rel_exact = float(np.linalg.norm(y_in - exact) / np.linalg.norm(exact))
+    log(f"{w.name}: {eager_us:.1f} us eager, {graph_us:.1f} us graph replay, rel err vs oracle {rel_oracle:.1e}, "
+        f"vs exact kernel product {rel_exact:.1e}")
+    return {"workload": w.name, "us_eager": round(eager_us, 2), "us_graph": round(graph_us, 2),
+            "rel_err_vs_fp64_oracle": rel_oracle, "rel_err_vs_exact_kernel_product": rel_exact,
+            "reps": reps}
 
 
 def storage_modes(steps, warmup, nleaves=16):
@@ -229,8 +288,14 @@ def matmat_modes(steps, warmup, fp64_matvec_ms, nleaves=8):
         for j in (0, 31):
             rows, ref = oracle_sample(w, perm, Xt[j], nleaves, seed=13)
             errs.append(float(np.linalg.norm(Yh[j][rows] - ref) / np.linalg.norm(ref)))
+        # roof = min(matrix-core peak, intensity x HBM peak); the useful products of BF16 blocks
+        # are issued as three exact BF16 MFMAs each, so their matrix-core roof is 1/3 of the BF16 peak
+        peak = 157.3 if name == "fp32" else 2500.0 / 3
+        roof = min(peak, flops / nbytes * HBM_PEAK_GBS / 1e3)
+        tflops = flops / (ms * 1e-3) / 1e12
         out[name] = {"ms": round(ms, 4), "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
-                     "TFLOP_per_s": round(flops / (ms * 1e-3) / 1e12, 2), "algorithmic_bytes": nbytes,
+                     "TFLOP_per_s": round(tflops, 2), "roof_TFLOP_per_s": round(roof, 1),
+                     "frac_of_roof": round(tflops / roof, 4), "algorithmic_bytes": nbytes,
                      "flops": flops, "stream_ms": round(float(phase_ms[1] / max(calls, 1)), 4),
                      "speedup_vs_32_fp64_matvecs": None if fp64_matvec_ms is None
                      else round(32 * fp64_matvec_ms / ms, 2),
@@ -346,7 +411,7 @@ def main():
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the storage-mode, many-right-hand-side and batch sections")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--only", choices=["modes", "matmat", "batch"], default=None,
+    ap.add_argument("--only", choices=["small", "modes", "matmat", "batch"], default=None,
                     help="run one section alone and print its JSON (for profiling runs); "
                          "the headline line is not printed")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
@@ -371,7 +436,9 @@ def main():
         del src, dst
 
     if args.only is not None:
-        if args.only == "modes":
+        if args.only == "small":
+            out = small_case()
+        elif args.only == "modes":
             out = storage_modes(args.steps, args.warmup)
         elif args.only == "matmat":
             out = matmat_modes(args.steps, args.warmup, None)
@@ -416,6 +483,7 @@ def main():
         result["cpu_baseline"] = cb
         result["rel_err_vs_oracle_sample"] = float(np.linalg.norm(r["y"][rows] - y_ref) / np.linalg.norm(y_ref))
     if not args.no_modes:
+        result["small"] = small_case()
         result["storage_modes"] = storage_modes(args.steps, args.warmup)
         fp64_ms = ms if (w.name == W.C2.name and args.storage == "fp64") else None
         if fp64_ms is not None:

@@ -24,6 +24,11 @@
  *  - Streams.  Every device operation is enqueued on the given hipStream_t
  *    (NULL = default stream) and is asynchronous.  A handle's workspace is shared
  *    by its calls: do not run two calls on one handle concurrently.
+ *  - Graphs.  h2_matvec, and h2_matmat after the first call on a handle (which
+ *    times its block loops and synchronizes), only enqueue kernels: they may
+ *    be captured into a HIP graph while profiling is off (h2_profile records
+ *    events).  A captured product reads x / X and writes y / Y at the
+ *    addresses given at capture.
  *  - Errors.  Every call returns an h2_status; no C++ exception crosses the ABI.
  *    On error *out is set to NULL, nothing is leaked, outputs are untouched,
  *    and h2_last_error() describes the failure (thread-local text).
