@@ -228,6 +228,43 @@ def small_case(reps=200):
             "reps": reps}
 
 
+_ONE_THREAD_SCRIPT = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from oracle import oracle as O
+from paper_1902_01829_amd import workloads as W
+out = {}
+w = W.C1
+o = O.OracleH2(W.points(w), w.leaf, w.cheb_p, w.eta, w.corr_len, keep_blocks=True)
+x = W.rhs(w, 1)[o.perm()]
+ts = []
+for _ in range(3):
+    t0 = time.perf_counter(); o.matvec(x); ts.append(time.perf_counter() - t0)
+out[w.name] = {"ms_per_product_median_of_3": round(1e3 * sorted(ts)[1], 3), "mode": "stored blocks, all rows"}
+w = W.C2
+o = O.OracleH2(W.points(w), w.leaf, w.cheb_p, w.eta, w.corr_len, keep_blocks=False)
+x = W.rhs(w, 1)[o.perm()]
+leaves = np.sort(np.random.Generator(np.random.PCG64(11)).permutation(o.leaf_nodes())[:64])
+t0 = time.perf_counter(); o.matvec_leaves(x, leaves); t = time.perf_counter() - t0
+out[w.name] = {"s_for_sample": round(t, 3), "mode": "matrix-free, full upsweep + rows of 64 seeded leaves"}
+print(json.dumps(out))
+"""
+
+
+def oracle_one_thread():
+    """The oracle on one host thread (a child process with OMP_NUM_THREADS=1):
+    the whole 4096-point product (median of 3), and the 2^20-point workload's
+    upsweep plus 64 sampled leaf rows."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ONE_THREAD_SCRIPT, ROOT], env=env, capture_output=True,
+                       text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def storage_modes(steps, warmup, nleaves=16):
     """The 3-D workload (2^19 points, rank 64) in FP64, FP32 and BF16 storage."""
     w = W.C3
@@ -480,6 +517,7 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         cb, rows, y_ref = cpu_baseline(w, r["perm"], r["xt"], args.cpu_budget)
+        cb["one_thread"] = oracle_one_thread()
         result["cpu_baseline"] = cb
         result["rel_err_vs_oracle_sample"] = float(np.linalg.norm(r["y"][rows] - y_ref) / np.linalg.norm(y_ref))
     if not args.no_modes:
