@@ -326,3 +326,71 @@ def rel_err(y, ref) -> float:
     """Relative 2-norm error |y - ref| / |ref| (the error measure of Sec. 4.6)."""
     ref = np.asarray(ref)
     return float(np.linalg.norm(np.asarray(y) - ref) / np.linalg.norm(ref))
+
+
+def _qr_positive(M):
+    """Thin QR with a non-negative diagonal of R (the unique factorization of
+    a full-column-rank M); numpy's Householder QR, signs normalized."""
+    Q, R = np.linalg.qr(M, mode="reduced")
+    d = np.where(np.diag(R) < 0.0, -1.0, 1.0)
+    return Q * d[None, :], R * d[:, None]
+
+
+def orthogonalize_arrays(arr):
+    """Basis orthogonalization and projection of the coupling blocks (Sec. 5.1,
+    Alg. 6 and Alg. 7) of a symmetric H^2 matrix given by its arrays (V = U,
+    F = E; see arrays_matvec for the layout).  Leaves: U_j = Q_j T_j (QR), Q_j
+    the new leaf basis.  Levels q .. l_min + 1, parent p with children c1, c2:
+    Z = [T_c1 E_c1; T_c2 E_c2] = Q T_p, the two k_l x k_(l-1) blocks of Q the
+    new transfers.  Every coupling block S_ij <- T_i S_ij T_j^T.  Transfers of
+    levels at or above l_min are not used by the product and are left as they
+    are.  Requires leaves with at least k_q rows and 2 k_l >= k_(l-1).
+    Returns (new arrays, {node: T})."""
+    q = int(arr["q"])
+    kr = [int(k) for k in arr["level_rank"]]
+    b, e = arr["begin"], arr["end"]
+    lf = (1 << q) - 1
+    lmin = next((l for l in range(q + 1) if int(arr["S_rowptr"][l][1 << l]) > 0), q + 1)
+    out = dict(arr)
+    T = {}
+    if lmin > q:
+        return out, T
+    U = np.array(arr["U"], dtype=np.float64, copy=True)
+    off = 0
+    for j in range(1 << q):
+        m = int(e[lf + j] - b[lf + j])
+        if m < kr[q]:
+            raise ValueError("a leaf holds fewer rows than the rank")
+        Uj = U[off:off + m * kr[q]].reshape(kr[q], m).T
+        Qj, T[lf + j] = _qr_positive(Uj)
+        U[off:off + m * kr[q]] = Qj.ravel(order="F")
+        off += m * kr[q]
+    E = np.array(arr["E"], dtype=np.float64, copy=True)
+    eo, off = {}, 0
+    for l in range(1, q + 1):
+        for c in range((1 << l) - 1, (2 << l) - 1):
+            eo[c] = off
+            off += kr[l] * kr[l - 1]
+    for l in range(q, lmin, -1):
+        kc, kp = kr[l], kr[l - 1]
+        if 2 * kc < kp:
+            raise ValueError("a level's rank exceeds twice its children's")
+        for p in range((1 << (l - 1)) - 1, (1 << l) - 1):
+            c1, c2 = 2 * p + 1, 2 * p + 2
+            E1 = E[eo[c1]:eo[c1] + kc * kp].reshape(kp, kc).T
+            E2 = E[eo[c2]:eo[c2] + kc * kp].reshape(kp, kc).T
+            Q, T[p] = _qr_positive(np.vstack([T[c1] @ E1, T[c2] @ E2]))
+            E[eo[c1]:eo[c1] + kc * kp] = Q[:kc].ravel(order="F")
+            E[eo[c2]:eo[c2] + kc * kp] = Q[kc:].ravel(order="F")
+    S = []
+    for l in range(q + 1):
+        Sl = np.array(arr["S"][l], dtype=np.float64, copy=True)
+        k, f = kr[l], (1 << l) - 1
+        rp, ci = arr["S_rowptr"][l], arr["S_colidx"][l]
+        for i in range(1 << l):
+            for t in range(rp[i], rp[i + 1]):
+                Sb = Sl[t * k * k:(t + 1) * k * k].reshape(k, k).T
+                Sl[t * k * k:(t + 1) * k * k] = (T[f + i] @ Sb @ T[f + int(ci[t])].T).ravel(order="F")
+        S.append(Sl)
+    out.update(U=U, V=U, E=E, F=E, S=S)
+    return out, T
