@@ -165,6 +165,29 @@ typedef struct {
  * q > 29; OOM; DEVICE. */
 h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *stream, h2_handle *out);
 
+/* The representation of A read back, in the layout h2_build_from_arrays
+ * takes (host buffers owned by the caller, column-major FP64 values; reduced storage is
+ * returned as stored: FP32 values, or BF16 code x block scale in FP32).  Any
+ * pointer may be NULL to skip that array, so a first call with level_rank,
+ * node_begin and node_end only gives the sizes: U and V hold sum_j m_j k_q
+ * values, E and F sum over levels l >= 1 of 2^l k_l k_(l-1), S[l] 2^l + 1
+ * offsets' last value times k_l^2, D the sum of m_i m_j over dense blocks.
+ * Transfers at or above the first level with a coupling block are not used
+ * by the product, not stored, and read back as zero.  For a matrix with no
+ * coupling block, U and V read back as zero.  Errors: INVALID_ARG for NULL
+ * A / out, or values asked of a structure-only handle; DEVICE. */
+typedef struct {
+    int32_t *level_rank;
+    int64_t *node_begin, *node_end;
+    double *U, *V, *E, *F;
+    int32_t *const *S_rowptr;
+    int32_t *const *S_colidx;
+    double *const *S;
+    int32_t *D_rowptr, *D_colidx;
+    double *D;
+} h2_arrays_out;
+h2_status h2_export_arrays(h2_handle A, const h2_arrays_out *out, void *stream);
+
 /* y = A x (Sec. 4, Fig. 4).
  *  x  device, n doubles, tree order.   y  device, n doubles, tree order.
  * x and y must not overlap.  Errors: INVALID_ARG for NULL pointers or a

@@ -157,6 +157,11 @@ struct h2_matrix_ {
     h2::MmConfig mm_cfg[2] = {{1, 0}, {1, 0}};
     bool mm_tuned[2] = {false, false};
     int64_t bytes_coupling = 0, bytes_dense = 0, bytes_leaf = 0, bytes_transfer = 0;
+    // layout: element offsets of U_j, V_j^T (per leaf), E_c, F_c^T (per node,
+    // -1 where not stored) in basis, and of every block in blocks (coupling
+    // blocks level by level in BSR order, then dense blocks)
+    std::vector<int64_t> off_U, off_VT, off_E, off_FT, off_blk;
+    int64_t basis_elems = 0, block_elems = 0;   // lengths of the two regions
     // profiling: PH_COUNT + 1 events per recorded call
     bool prof = false;
     std::vector<hipEvent_t> pending, spare;
@@ -300,9 +305,17 @@ void build_device(h2_matrix_ &A, const h2_arrays *src, hipStream_t stream) {
             ns += h2::block_elems(int(s.size(lf + i)), int(s.size(t)), sk);
         }
     const int64_t scale_bytes = sk == h2::ELEM_BF16 ? 4 : 0;
+    A.off_U = off_U;
+    A.off_VT = off_VT;
+    A.off_E = off_E;
+    A.off_FT = off_FT;
+    A.off_blk.resize(fill.size());
+    for (size_t i = 0; i < fill.size(); ++i) A.off_blk[i] = fill[i].a;
     A.bytes_coupling = coupling_elems * sb + scale_bytes * ncoupling;
     A.bytes_dense = (ns - coupling_elems) * sb + scale_bytes * (int64_t(fill.size()) - ncoupling);
 
+    A.basis_elems = nb;
+    A.block_elems = ns;
     A.basis = A.mem.alloc(nb * eb);
     A.blocks = A.mem.alloc(ns * sb);
     A.scales = static_cast<float *>(A.mem.alloc(std::max<int64_t>(1, int64_t(fill.size())) * 4));
@@ -1162,6 +1175,125 @@ void structure_from_arrays(const h2_arrays *a, h2::Structure &s) {
     for (int64_t i = 0; i < a->n; ++i) s.perm[i] = i;
 }
 
+// Reads blocks of a device region in offset order through a bounded host
+// window, converting each to column-major FP64 (the inverse of convert_block;
+// BF16 values are code x scale in FP32, as stored).
+struct Reader {
+    const char *dev;
+    int kind;
+    int64_t elem, total;   // element size, region length in elements
+    hipStream_t st;
+    std::vector<char> buf;
+    int64_t win = 0, len = 0;   // window [win, win + len) in elements
+    static constexpr int64_t kCap = int64_t(64) << 20;
+    Reader(const void *d, int k, int64_t n, hipStream_t s)
+        : dev(static_cast<const char *>(d)), kind(k), elem(h2::elem_bytes(k)), total(n), st(s) {}
+    const char *at(int64_t off, int64_t ne) {
+        if (off < 0 || off + ne > total) fail(H2_ERR_INTERNAL, "block outside its region");
+        if (off < win || off + ne > win + len) {
+            len = std::min<int64_t>(std::max<int64_t>(ne, kCap / elem), total - off);
+            buf.resize(size_t(len * elem));
+            check_hip(hipMemcpyAsync(buf.data(), dev + off * elem, size_t(len * elem), hipMemcpyDeviceToHost, st),
+                      "hipMemcpyAsync");
+            check_hip(hipStreamSynchronize(st), "export");
+            win = off;
+        }
+        return buf.data() + (off - win) * elem;
+    }
+    void block(int64_t off, int R, int C, bool transpose, float scale, double *dst) {
+        const int W = 16 / int(elem);
+        const int64_t ne = h2::block_elems(R, C, kind);
+        const char *p = at(off, ne);
+        for (int64_t e = 0; e < ne; ++e) {
+            const int w = int(e % W);
+            const int64_t t = e / W;
+            const int r = int(t % R), c = int(t / R) * W + w;
+            if (c >= C) continue;
+            double v;
+            if (kind == h2::ELEM_F64) v = reinterpret_cast<const double *>(p)[e];
+            else if (kind == h2::ELEM_F32) v = reinterpret_cast<const float *>(p)[e];
+            else {
+                const uint32_t u = uint32_t(reinterpret_cast<const uint16_t *>(p)[e]) << 16;
+                float f;
+                std::memcpy(&f, &u, 4);
+                v = double(f * scale);
+            }
+            if (transpose) dst[c + int64_t(r) * C] = v;   // stored R x C is the transpose of a C x R block
+            else dst[r + int64_t(c) * R] = v;
+        }
+    }
+};
+
+void export_arrays(h2_matrix_ &A, const h2_arrays_out *o, hipStream_t st) {
+    const Structure &s = A.st;
+    const int q = s.q;
+    const std::vector<int> &kl = s.lrank;
+    const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
+    if (o->level_rank)
+        for (int l = 0; l <= q; ++l) o->level_rank[l] = kl[l];
+    if (o->node_begin) std::copy(s.begin.begin(), s.begin.end(), o->node_begin);
+    if (o->node_end) std::copy(s.end.begin(), s.end.end(), o->node_end);
+    const bool lowrank = s.lmin <= q;
+    if (o->U || o->V || o->E || o->F) {
+        Reader rd(A.basis, A.basis_kind, A.basis_elems, st);
+        int64_t uoff = 0;
+        for (int64_t j = 0; j < nleaves; ++j) {
+            const int m = int(s.size(lf + j));
+            const int64_t len = int64_t(m) * kl[q];
+            if (!lowrank) {
+                if (o->U) std::fill(o->U + uoff, o->U + uoff + len, 0.0);
+                if (o->V) std::fill(o->V + uoff, o->V + uoff + len, 0.0);
+            } else {
+                if (o->U) rd.block(A.off_U[j], m, kl[q], false, 1.0f, o->U + uoff);
+                if (o->V) rd.block(A.off_VT[j], kl[q], m, true, 1.0f, o->V + uoff);
+            }
+            uoff += len;
+        }
+        int64_t eoff = 0;
+        for (int l = 1; l <= q; ++l)
+            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
+                const int64_t len = int64_t(kl[l]) * kl[l - 1];
+                if (A.off_E[c] < 0) {   // not stored: not used by the product
+                    if (o->E) std::fill(o->E + eoff, o->E + eoff + len, 0.0);
+                    if (o->F) std::fill(o->F + eoff, o->F + eoff + len, 0.0);
+                } else {
+                    if (o->E) rd.block(A.off_E[c], kl[l], kl[l - 1], false, 1.0f, o->E + eoff);
+                    if (o->F) rd.block(A.off_FT[c], kl[l - 1], kl[l], true, 1.0f, o->F + eoff);
+                }
+                eoff += len;
+            }
+    }
+    std::vector<float> scales;
+    if (A.block_kind == h2::ELEM_BF16 && A.nscales > 0) {
+        scales.resize(size_t(A.nscales));
+        check_hip(hipMemcpyAsync(scales.data(), A.scales, scales.size() * 4, hipMemcpyDeviceToHost, st),
+                  "hipMemcpyAsync");
+        check_hip(hipStreamSynchronize(st), "export scales");
+    }
+    auto scale_of = [&](int64_t i) { return scales.empty() ? 1.0f : scales[size_t(i)]; };
+    Reader rd(A.blocks, A.block_kind, A.block_elems, st);
+    int64_t fi = 0;
+    for (int l = 0; l <= q; ++l) {
+        const h2::Bsr &B = s.coupling[l];
+        if (o->S_rowptr && o->S_rowptr[l]) std::copy(B.rowptr.begin(), B.rowptr.end(), o->S_rowptr[l]);
+        if (o->S_colidx && o->S_colidx[l]) std::copy(B.colidx.begin(), B.colidx.end(), o->S_colidx[l]);
+        const int64_t kk = int64_t(kl[l]) * kl[l];
+        for (int64_t b = 0; b < B.blocks(); ++b, ++fi)
+            if (o->S && o->S[l]) rd.block(A.off_blk[fi], kl[l], kl[l], false, scale_of(fi), o->S[l] + b * kk);
+    }
+    if (o->D_rowptr) std::copy(s.dense.rowptr.begin(), s.dense.rowptr.end(), o->D_rowptr);
+    if (o->D_colidx) std::copy(s.dense.colidx.begin(), s.dense.colidx.end(), o->D_colidx);
+    if (o->D) {
+        int64_t doff = 0;
+        for (int64_t i = 0; i < nleaves; ++i)
+            for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++fi) {
+                const int R = int(s.size(lf + i)), C = int(s.size(lf + s.dense.colidx[b]));
+                rd.block(A.off_blk[fi], R, C, false, scale_of(fi), o->D + doff);
+                doff += int64_t(R) * C;
+            }
+    }
+}
+
 h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *stream, h2_handle *out) {
     if (out) *out = nullptr;
     h2_matrix_ *A = nullptr;
@@ -1188,6 +1320,25 @@ h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *strea
         return H2_ERR_OOM;
     } catch (...) {
         delete A;
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+h2_status h2_export_arrays(h2_handle A, const h2_arrays_out *out, void *stream) {
+    try {
+        if (!A || !out) fail(H2_ERR_INVALID_ARG, "NULL argument");
+        if (A->structure_only && (out->U || out->V || out->E || out->F || out->S || out->D))
+            fail(H2_ERR_INVALID_ARG, "structure-only handle holds no values");
+        export_arrays(*A, out, static_cast<hipStream_t>(stream));
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return H2_ERR_OOM;
+    } catch (...) {
         g_last_error = "internal error";
         return H2_ERR_INTERNAL;
     }

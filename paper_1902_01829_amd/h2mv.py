@@ -20,7 +20,7 @@ H2_FLAG_STRUCTURE_ONLY = 1
 STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
 
 # Every function declared in include/h2mv.h.
-EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
+EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
            "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_batch_create", "h2_batch_matmat",
            "h2_batch_tuning", "h2_batch_free", "h2_last_error")
 
@@ -34,6 +34,13 @@ class h2_arrays(C.Structure):
     _fields_ = [("n", C.c_int64), ("q", C.c_int), ("level_rank", C.c_void_p), ("node_begin", C.c_void_p),
                 ("node_end", C.c_void_p), ("U", C.c_void_p), ("V", C.c_void_p), ("E", C.c_void_p),
                 ("F", C.c_void_p), ("S_rowptr", C.c_void_p), ("S_colidx", C.c_void_p), ("S", C.c_void_p),
+                ("D_rowptr", C.c_void_p), ("D_colidx", C.c_void_p), ("D", C.c_void_p)]
+
+
+class h2_arrays_out(C.Structure):
+    _fields_ = [("level_rank", C.c_void_p), ("node_begin", C.c_void_p), ("node_end", C.c_void_p),
+                ("U", C.c_void_p), ("V", C.c_void_p), ("E", C.c_void_p), ("F", C.c_void_p),
+                ("S_rowptr", C.c_void_p), ("S_colidx", C.c_void_p), ("S", C.c_void_p),
                 ("D_rowptr", C.c_void_p), ("D_colidx", C.c_void_p), ("D", C.c_void_p)]
 
 
@@ -68,6 +75,7 @@ def lib():
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
         L.h2_build_from_points.argtypes = [vp, i64, C.POINTER(h2_params), vp, C.POINTER(vp)]
         L.h2_build_from_arrays.argtypes = [C.POINTER(h2_arrays), C.c_int, vp, C.POINTER(vp)]
+        L.h2_export_arrays.argtypes = [vp, C.POINTER(h2_arrays_out), vp]
         L.h2_matvec.argtypes = [vp, vp, vp, vp]
         L.h2_matmat.argtypes = [vp, vp, i64, vp, i64, C.c_int, vp]
         L.h2_free.argtypes = [vp]
@@ -138,6 +146,46 @@ def h2_build_from_arrays(arr, storage=H2_FP64, stream=0):
     h = C.c_void_p()
     _check(lib().h2_build_from_arrays(C.byref(a), storage, C.c_void_p(stream), C.byref(h)))
     return h.value
+
+
+def h2_export_arrays(h, stream=0):
+    """The representation read back as a dict in the layout h2_build_from_arrays
+    takes (numpy arrays)."""
+    info = h2_get_info(h)
+    q = info.levels_q
+    nn = (2 << q) - 1
+    lr = np.zeros(q + 1, dtype=np.int32)
+    b = np.zeros(nn, dtype=np.int64)
+    e = np.zeros(nn, dtype=np.int64)
+    _check(lib().h2_export_arrays(C.c_void_p(h), C.byref(h2_arrays_out(lr.ctypes.data, b.ctypes.data,
+                                                                         e.ctypes.data)), C.c_void_p(stream)))
+    lf = (1 << q) - 1
+    m = e[lf:] - b[lf:]
+    nU = int(m.sum()) * int(lr[q])
+    nE = sum(int(lr[l]) * int(lr[l - 1]) << l for l in range(1, q + 1))
+    U, V, E, F = (np.zeros(max(nU, 1)), np.zeros(max(nU, 1)), np.zeros(max(nE, 1)), np.zeros(max(nE, 1)))
+    S_rowptr, S_colidx, S = [], [], []
+    for l in range(q + 1):
+        rp, ci = h2_get_level_bsr(h, l, 1 << l)
+        S_rowptr.append(rp)
+        S_colidx.append(np.ascontiguousarray(ci))
+        S.append(np.zeros(max(len(ci), 1) * int(lr[l]) ** 2))
+    drp, dci = h2_get_level_bsr(h, -1, 1 << q)
+    dci = np.ascontiguousarray(dci)
+    nD = sum(int(m[i]) * int(m[dci[t]]) for i in range(1 << q) for t in range(drp[i], drp[i + 1]))
+    D = np.zeros(max(nD, 1))
+    P = C.c_void_p * (q + 1)
+    rpp = P(*[a.ctypes.data for a in S_rowptr])
+    cip = P(*[a.ctypes.data if a.size else None for a in S_colidx])
+    sp = P(*[a.ctypes.data for a in S])
+    out = h2_arrays_out(None, None, None, U.ctypes.data, V.ctypes.data, E.ctypes.data, F.ctypes.data,
+                        C.cast(rpp, C.c_void_p), C.cast(cip, C.c_void_p), C.cast(sp, C.c_void_p),
+                        None, None, D.ctypes.data)
+    _check(lib().h2_export_arrays(C.c_void_p(h), C.byref(out), C.c_void_p(stream)))
+    return {"n": info.n, "q": q, "level_rank": lr, "begin": b, "end": e, "U": U[:nU], "V": V[:nU],
+            "E": E[:nE], "F": F[:nE], "S_rowptr": S_rowptr, "S_colidx": S_colidx,
+            "S": [S[l][:len(S_colidx[l]) * int(lr[l]) ** 2] for l in range(q + 1)],
+            "D_rowptr": drp, "D_colidx": dci, "D": D[:nD]}
 
 
 def h2_matvec(h, x_ptr, y_ptr, stream=0):

@@ -147,3 +147,60 @@ def test_batch_with_array_members(oracle_mod):
     batch.close()
     for m in mats:
         m.close()
+
+
+def _lmin(arr):
+    q = int(arr["q"])
+    return next((l for l in range(q + 1) if len(arr["S_colidx"][l]) > 0), q + 1)
+
+
+def _transfer_mask(arr):
+    """Entries of E / F of nodes below the first coupling level (the stored ones)."""
+    q, kr = int(arr["q"]), [int(k) for k in arr["level_rank"]]
+    lmin = _lmin(arr)
+    mask = []
+    for l in range(1, q + 1):
+        mask.append(np.full((kr[l] * kr[l - 1]) << l, l > lmin))
+    return np.concatenate(mask) if mask else np.zeros(0, dtype=bool)
+
+
+def _assert_arrays_equal(a, b, tol, what):
+    m = _transfer_mask(a)
+    for key in ("U", "V"):
+        assert np.abs(a[key] - b[key]).max(initial=0.0) <= tol, (what, key)
+    for key in ("E", "F"):
+        assert np.abs(a[key][m] - b[key][m]).max(initial=0.0) <= tol, (what, key)
+        assert not np.any(b[key][~m]), (what, key, "unstored transfers read back as zero")
+    for l in range(int(a["q"]) + 1):
+        assert np.array_equal(a["S_rowptr"][l], b["S_rowptr"][l]) and np.array_equal(a["S_colidx"][l], b["S_colidx"][l])
+        assert np.abs(np.asarray(a["S"][l]) - b["S"][l]).max(initial=0.0) <= tol, (what, "S", l)
+    assert np.array_equal(a["D_rowptr"], b["D_rowptr"]) and np.array_equal(a["D_colidx"], b["D_colidx"])
+    assert np.abs(a["D"] - b["D"]).max(initial=0.0) <= tol, (what, "D")
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2], ids=["fp64", "fp32", "bf16"])
+def test_export_round_trip(oracle_mod, storage):
+    """Arrays in, arrays out: exactly the stored values (FP64 as given; FP32
+    rounded; BF16 code x scale), bitwise."""
+    h2mv = _h2mv()
+    arr = _structure_arrays(oracle_mod, 3000, 2, 32, 2, 8, 408, 40)
+    A = h2mv.H2Matrix.from_arrays(arr, storage)
+    got = h2mv.h2_export_arrays(A.handle)
+    assert np.array_equal(got["level_rank"], arr["level_rank"])
+    assert np.array_equal(got["begin"], arr["begin"]) and np.array_equal(got["end"], arr["end"])
+    _assert_arrays_equal(_stored(oracle_mod, arr, storage), got, 0.0, f"storage {storage}")
+    A.close()
+
+
+def test_export_of_points_build_matches_oracle(oracle_mod):
+    """A matrix built on the device from points reads back as the oracle's
+    arrays of the same H^2, to the rounding of the entries."""
+    h2mv = _h2mv()
+    w = W.C1
+    A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=0)
+    got = h2mv.h2_export_arrays(A.handle)
+    o = oracle_mod.OracleH2(W.points(w), w.leaf, w.cheb_p, w.eta, w.corr_len)
+    ref = o.export_arrays()
+    scale = max(np.abs(ref["U"]).max(), np.abs(ref["E"]).max(), 1.0)
+    _assert_arrays_equal(ref, got, 1e-13 * scale, "points build")
+    A.close()
