@@ -188,6 +188,20 @@ typedef struct {
 } h2_arrays_out;
 h2_status h2_export_arrays(h2_handle A, const h2_arrays_out *out, void *stream);
 
+/* Basis orthogonalization (Sec. 5.1, Alg. 6) and projection of the coupling
+ * blocks (Alg. 7), in place: every leaf basis becomes Q_j of U_j = Q_j T_j
+ * (thin QR), every transfer pair below the first level with a coupling block
+ * becomes the two blocks of Q in [T_c1 E_c1; T_c2 E_c2] = Q T_parent, and
+ * every coupling block S_ij becomes T_i S_ij T_j^T.  The diagonals of the T
+ * factors are made non-negative.  A (the product) is unchanged up to
+ * rounding; the nested bases of all nodes used by coupling blocks become
+ * orthonormal.  The call returns when the device work is done; a matrix
+ * without coupling blocks is left as it is.
+ * Errors: INVALID_ARG for NULL or structure-only handles; UNSUPPORTED for
+ * storage other than H2_FP64, V != U or F != E, a leaf with fewer rows than
+ * the leaf rank, or k_(l-1) > 2 k_l; DEVICE. */
+h2_status h2_orthogonalize(h2_handle A, void *stream);
+
 /* y = A x (Sec. 4, Fig. 4).
  *  x  device, n doubles, tree order.   y  device, n doubles, tree order.
  * x and y must not overlap.  Errors: INVALID_ARG for NULL pointers or a

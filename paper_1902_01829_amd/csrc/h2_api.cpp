@@ -162,6 +162,7 @@ struct h2_matrix_ {
     // blocks level by level in BSR order, then dense blocks)
     std::vector<int64_t> off_U, off_VT, off_E, off_FT, off_blk;
     int64_t basis_elems = 0, block_elems = 0;   // lengths of the two regions
+    bool symmetric = true;                      // V = U and F = E
     // profiling: PH_COUNT + 1 events per recorded call
     bool prof = false;
     std::vector<hipEvent_t> pending, spare;
@@ -1306,6 +1307,19 @@ h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *strea
         A->basis_kind = storage == H2_FP64 ? h2::ELEM_F64 : h2::ELEM_F32;
         A->block_kind = storage == H2_FP64 ? h2::ELEM_F64 : storage == H2_FP32 ? h2::ELEM_F32 : h2::ELEM_BF16;
         A->vec_f64 = storage == H2_FP64;
+        {
+            // V = U and F = E (value by value): the symmetric case orthogonalization handles
+            const h2::Structure &st = A->st;
+            const int64_t lf = h2::Structure::first(st.q);
+            int64_t nu = 0, ne = 0;
+            for (int64_t v = lf; v < st.nnodes; ++v) nu += st.size(v) * st.lrank[st.q];
+            for (int l = 1; l <= st.q; ++l) ne += (int64_t(st.lrank[l]) * st.lrank[l - 1]) << l;
+            const bool su = arrays->U == arrays->V || (arrays->U && arrays->V &&
+                                                         std::memcmp(arrays->U, arrays->V, size_t(nu) * 8) == 0);
+            const bool se = arrays->E == arrays->F || (arrays->E && arrays->F &&
+                                                         std::memcmp(arrays->E, arrays->F, size_t(ne) * 8) == 0);
+            A->symmetric = su && se;
+        }
         build_device(*A, arrays, static_cast<hipStream_t>(stream));
         *out = A;
         g_last_error.clear();
@@ -1320,6 +1334,69 @@ h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *strea
         return H2_ERR_OOM;
     } catch (...) {
         delete A;
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+// Basis orthogonalization and projection of the coupling blocks in place.
+void orthogonalize(h2_matrix_ &A, hipStream_t st) {
+    const Structure &s = A.st;
+    const int q = s.q;
+    if (A.storage != H2_FP64) fail(H2_ERR_UNSUPPORTED, "orthogonalization needs FP64 storage");
+    if (!A.symmetric) fail(H2_ERR_UNSUPPORTED, "orthogonalization needs V = U and F = E");
+    if (s.lmin > q) return;   // no coupling block: nothing to orthogonalize
+    const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
+    for (int64_t j = 0; j < nleaves; ++j)
+        if (s.size(lf + j) < s.lrank[q]) fail(H2_ERR_UNSUPPORTED, "a leaf holds fewer rows than the rank");
+    for (int l = q; l > s.lmin; --l)
+        if (2 * s.lrank[l] < s.lrank[l - 1]) fail(H2_ERR_UNSUPPORTED, "a level's rank exceeds twice its children's");
+    std::vector<h2::ProjDesc> proj;
+    int64_t fi = 0;
+    for (int l = 0; l <= q; ++l) {
+        const h2::Bsr &B = s.coupling[l];
+        const int64_t f = Structure::first(l);
+        for (int64_t i = 0; i < (int64_t(1) << l); ++i)
+            for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b, ++fi)
+                proj.push_back({A.off_blk[fi], f + i, f + B.colidx[b], s.lrank[l], 0});
+    }
+    DeviceArena scratch;
+    const int kmax = s.rank;
+    h2::OrthLaunch L;
+    L.basis = static_cast<double *>(A.basis);
+    L.blocks = static_cast<double *>(A.blocks);
+    L.T = static_cast<double *>(scratch.alloc(s.nnodes * int64_t(kmax) * kmax * 8));
+    L.off_U = scratch.upload(A.off_U, st);
+    L.off_VT = scratch.upload(A.off_VT, st);
+    L.off_E = scratch.upload(A.off_E, st);
+    L.off_FT = scratch.upload(A.off_FT, st);
+    L.leaf_begin = A.d_leaf_begin;
+    L.leaf_end = A.d_leaf_end;
+    L.proj = scratch.upload(proj, st);
+    L.nleaves = nleaves;
+    L.first_leaf = lf;
+    L.nproj = int64_t(proj.size());
+    L.level_rank = s.lrank.data();
+    L.q = q;
+    L.lmin = s.lmin;
+    L.kmax = kmax;
+    check_hip(h2::launch_orthogonalize(L, st), "orthogonalization launch");
+    check_hip(hipStreamSynchronize(st), "orthogonalization");
+}
+
+h2_status h2_orthogonalize(h2_handle A, void *stream) {
+    try {
+        if (!A) fail(H2_ERR_INVALID_ARG, "NULL handle");
+        if (A->structure_only) fail(H2_ERR_INVALID_ARG, "structure-only handle");
+        orthogonalize(*A, static_cast<hipStream_t>(stream));
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return H2_ERR_OOM;
+    } catch (...) {
         g_last_error = "internal error";
         return H2_ERR_INTERNAL;
     }

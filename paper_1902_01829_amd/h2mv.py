@@ -20,7 +20,7 @@ H2_FLAG_STRUCTURE_ONLY = 1
 STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
 
 # Every function declared in include/h2mv.h.
-EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
+EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_orthogonalize", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
            "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_batch_create", "h2_batch_matmat",
            "h2_batch_tuning", "h2_batch_free", "h2_last_error")
 
@@ -76,6 +76,7 @@ def lib():
         L.h2_build_from_points.argtypes = [vp, i64, C.POINTER(h2_params), vp, C.POINTER(vp)]
         L.h2_build_from_arrays.argtypes = [C.POINTER(h2_arrays), C.c_int, vp, C.POINTER(vp)]
         L.h2_export_arrays.argtypes = [vp, C.POINTER(h2_arrays_out), vp]
+        L.h2_orthogonalize.argtypes = [vp, vp]
         L.h2_matvec.argtypes = [vp, vp, vp, vp]
         L.h2_matmat.argtypes = [vp, vp, i64, vp, i64, C.c_int, vp]
         L.h2_free.argtypes = [vp]
@@ -186,6 +187,10 @@ def h2_export_arrays(h, stream=0):
             "E": E[:nE], "F": F[:nE], "S_rowptr": S_rowptr, "S_colidx": S_colidx,
             "S": [S[l][:len(S_colidx[l]) * int(lr[l]) ** 2] for l in range(q + 1)],
             "D_rowptr": drp, "D_colidx": dci, "D": D[:nD]}
+
+
+def h2_orthogonalize(h, stream=0):
+    _check(lib().h2_orthogonalize(C.c_void_p(h), C.c_void_p(stream)))
 
 
 def h2_matvec(h, x_ptr, y_ptr, stream=0):
