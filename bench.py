@@ -265,6 +265,46 @@ def oracle_one_thread():
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def orthogonalize_section(reps=3):
+    """Basis orthogonalization and projection of the coupling blocks (Sec. 5.1)
+    of the 2-D 2^20-point workload, FP64, on the GPU: time per call (a fresh
+    matrix each time), algorithmic flops (Householder QR with Q formed:
+    4 M N^2 - 4 N^3 / 3 per factorization; T_c E_c: k^3 per child; projection
+    with triangular T: 2 k^3 per coupling block), the bytes of the blocks,
+    bases and transfers read and written, and the change of A x."""
+    import torch
+    from paper_1902_01829_amd import h2mv
+    w = W.C2
+    ms = []
+    for rep in range(reps):
+        A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=0)
+        info = A.info
+        x = torch.from_numpy(W.rhs(w, 1)[A.perm()]).cuda()
+        y0 = A.matvec(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h2mv.h2_orthogonalize(A.handle)   # returns when the device work is done
+        ms.append((time.perf_counter() - t0) * 1e3)
+        y1 = A.matvec(x)
+        rel = float(((y1 - y0).norm() / y0.norm()).item())
+        A.close()
+        del x, y0, y1
+        torch.cuda.empty_cache()
+    k, q, lmin = info.rank, info.levels_q, info.lmin
+    nleaves, m = 1 << q, w.leaf
+    qr = lambda M, N: 4.0 * M * N * N - 4.0 * N ** 3 / 3.0
+    nparents = sum(1 << (l - 1) for l in range(lmin + 1, q + 1))
+    flops = nleaves * qr(m, k) + nparents * (2 * k ** 3 + qr(2 * k, k)) + info.coupling_blocks * 2.0 * k ** 3
+    nbytes = 2 * (info.bytes_coupling + info.bytes_leaf_bases + info.bytes_transfers)
+    best = min(ms)
+    log(f"orthogonalize {w.name}: {best:.1f} ms (of {[round(v, 1) for v in ms]}), {flops / best / 1e6:.0f} GFLOP/s, "
+        f"A x change {rel:.1e}")
+    return {"workload": w.name, "ms": round(best, 3), "ms_all": [round(v, 3) for v in ms],
+            "flops": flops, "GFLOP_per_s": round(flops / (best * 1e-3) / 1e9, 1),
+            "bytes_read_written": nbytes, "GB_per_s": round(nbytes / (best * 1e-3) / 1e9, 1),
+            "rel_change_of_Ax": rel, "fp64_vector_peak_TFLOP_per_s": 78.6}
+
+
 def storage_modes(steps, warmup, nleaves=16):
     """The 3-D workload (2^19 points, rank 64) in FP64, FP32 and BF16 storage."""
     w = W.C3
@@ -448,7 +488,7 @@ def main():
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the storage-mode, many-right-hand-side and batch sections")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--only", choices=["small", "modes", "matmat", "batch"], default=None,
+    ap.add_argument("--only", choices=["small", "modes", "matmat", "batch", "orthogonalize"], default=None,
                     help="run one section alone and print its JSON (for profiling runs); "
                          "the headline line is not printed")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
@@ -479,6 +519,8 @@ def main():
             out = storage_modes(args.steps, args.warmup)
         elif args.only == "matmat":
             out = matmat_modes(args.steps, args.warmup, None)
+        elif args.only == "orthogonalize":
+            out = orthogonalize_section()
         else:
             out = batch_modes(args.steps, args.warmup)
         print(json.dumps({"section": args.only, **out}), flush=True)
@@ -527,6 +569,7 @@ def main():
         if fp64_ms is not None:
             result["matmat"] = matmat_modes(max(3, args.steps // 4), 1, fp64_ms)
         result["batch"] = batch_modes(max(3, args.steps // 2), 1)
+        result["orthogonalize"] = orthogonalize_section()
     print(json.dumps(result), flush=True)
 
 

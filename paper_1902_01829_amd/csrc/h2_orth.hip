@@ -23,6 +23,12 @@ namespace h2 {
 namespace {
 
 constexpr int QR_MAXM = 128, QR_MAXN = 64;
+// Columns of the LDS matrices are QR_PAD doubles longer than their rows: the
+// threads of a wavefront read 16 columns at once, and a column stride of a
+// multiple of 64 doubles would put them all on the same LDS banks.
+constexpr int QR_PAD = 4;
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Element (r, c) of an R-row FP64 block in 16-byte column groups (2 columns).
 __device__ inline int64_t at2(int R, int r, int c) { return (int64_t(c >> 1) * R + r) * 2 + (c & 1); }
@@ -33,20 +39,20 @@ __device__ inline double sum4(double v) {   // over the 4 threads of a column (c
     return v;
 }
 
-// In-place Householder QR of the M x N matrix A (column-major, ld M, LDS),
-// M >= N: R in the upper triangle, v_c below the diagonal (v_c[c] = 1
-// implicit), tau[c].  Then Q (M x N, ld M) formed explicitly, and the signs of
-// R's rows and Q's columns flipped so that diag(R) >= 0.
-__device__ void householder_qr(double *A, double *Q, double *tau, double *scal, int M, int N) {
-    const int t = threadIdx.x, col = t >> 2, sub = t & 3;
+// In-place Householder QR of the M x N matrix A (column-major, ld M + QR_PAD, LDS),
+// M >= N.  R, with its rows' signs flipped so that diag(R) >= 0, goes to T
+// (ld ldt); then A is overwritten by the thin Q (M x N) with the matching
+// columns flipped.  Q is formed in place from the stored reflectors, the last
+// one first (column c of Q is final once reflectors c .. N-1 are applied).
+__device__ void householder_qr(double *A, double *tau, double *scal, double *sgn, int M, int N, double *T, int ldt) {
+    const int t = threadIdx.x, col = t >> 2, sub = t & 3, ld = M + QR_PAD;
     for (int c = 0; c < N; ++c) {
-        // norm of A[c:M, c] (column c's four threads), then the reflector
-        if (col == c) {
+        if (col == c) {   // norm of A[c:M, c] over the column's four threads, then the reflector
             double s = 0.0;
-            for (int r = c + sub; r < M; r += 4) s += A[c * M + r] * A[c * M + r];
+            for (int r = c + sub; r < M; r += 4) s += A[c * ld + r] * A[c * ld + r];
             s = sum4(s);
             if (sub == 0) {
-                const double alpha = A[c * M + c], nrm = sqrt(s);
+                const double alpha = A[c * ld + c], nrm = sqrt(s);
                 double tc = 0.0, beta = alpha, sc = 0.0;
                 if (nrm > 0.0) {
                     beta = alpha >= 0.0 ? -nrm : nrm;
@@ -60,139 +66,243 @@ __device__ void householder_qr(double *A, double *Q, double *tau, double *scal, 
         }
         __syncthreads();
         const double sc = scal[0], tc = tau[c];
-        if (col == c) {
-            for (int r = c + 1 + sub; r < M; r += 4) A[c * M + r] *= sc;
+        if (col == c) {   // v below the diagonal (v_c = 1 implicit), beta on it
+            for (int r = c + 1 + sub; r < M; r += 4) A[c * ld + r] *= sc;
+            if (sub == 0) A[c * ld + c] = scal[1];
         }
         __syncthreads();
-        if (col == c && sub == 0) A[c * M + c] = scal[1];
-        // apply H_c = I - tau v v^T to the columns to the right
-        if (col > c && col < N && tc != 0.0) {
-            double w = sub == 0 ? A[col * M + c] : 0.0;
-            for (int r = c + 1 + sub; r < M; r += 4) w += A[c * M + r] * A[col * M + r];
+        if (col > c && col < N && tc != 0.0) {   // H_c = I - tau v v^T on the columns to the right
+            double w = sub == 0 ? A[col * ld + c] : 0.0;
+            for (int r = c + 1 + sub; r < M; r += 4) w += A[c * ld + r] * A[col * ld + r];
             w = sum4(w) * tc;
-            if (sub == 0) A[col * M + c] -= w;
-            for (int r = c + 1 + sub; r < M; r += 4) A[col * M + r] -= w * A[c * M + r];
+            if (sub == 0) A[col * ld + c] -= w;
+            for (int r = c + 1 + sub; r < M; r += 4) A[col * ld + r] -= w * A[c * ld + r];
         }
         __syncthreads();
     }
-    // Q = H_0 ... H_(N-1) [I; 0], applied from the last reflector back
-    for (int i = t; i < M * N; i += blockDim.x) {
-        const int c = i / M, r = i - c * M;
-        Q[i] = r == c ? 1.0 : 0.0;
+    for (int i = t; i < N * N; i += blockDim.x) {   // R with diag(R) >= 0
+        const int c = i / N, r = i - c * N;
+        const double sr = A[r * ld + r] < 0.0 ? -1.0 : 1.0;
+        T[int64_t(c) * ldt + r] = r <= c ? sr * A[c * ld + r] : 0.0;
     }
+    for (int c = t; c < N; c += blockDim.x) sgn[c] = A[c * ld + c] < 0.0 ? -1.0 : 1.0;
     __syncthreads();
     for (int c = N - 1; c >= 0; --c) {
         const double tc = tau[c];
-        if (col >= c && col < N && tc != 0.0) {
-            double w = sub == 0 ? Q[col * M + c] : 0.0;
-            for (int r = c + 1 + sub; r < M; r += 4) w += A[c * M + r] * Q[col * M + r];
+        if (col > c && col < N) {   // apply H_c to the finished columns (their rows < col are zero)
+            double w = sub == 0 ? A[col * ld + c] : 0.0;
+            for (int r = c + 1 + sub; r < M; r += 4) w += A[c * ld + r] * A[col * ld + r];
             w = sum4(w) * tc;
-            if (sub == 0) Q[col * M + c] -= w;
-            for (int r = c + 1 + sub; r < M; r += 4) Q[col * M + r] -= w * A[c * M + r];
+            if (sub == 0) A[col * ld + c] -= w;
+            for (int r = c + 1 + sub; r < M; r += 4) A[col * ld + r] -= w * A[c * ld + r];
+        }
+        __syncthreads();
+        if (col == c) {   // column c of Q: H_c e_c
+            for (int r = c + 1 + sub; r < M; r += 4) A[c * ld + r] *= -tc;
+            for (int r = sub; r < c; r += 4) A[c * ld + r] = 0.0;
+            if (sub == 0) A[c * ld + c] = 1.0 - tc;
         }
         __syncthreads();
     }
-    // signs: diag(R) >= 0
     for (int i = t; i < M * N; i += blockDim.x) {
-        const int c = i / M;
-        if (A[c * M + c] < 0.0) Q[i] = -Q[i];
+        const int c = i / M, r = i - c * M;
+        A[c * ld + r] *= sgn[c];
     }
     __syncthreads();
-}
-
-// Writes R (N x N, upper triangle of A with the signs fixed) into T (ld ldt).
-__device__ void store_r(const double *A, int M, int N, double *T, int ldt) {
-    for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
-        const int c = i / N, r = i - c * N;
-        const double sgn = A[r * M + r] < 0.0 ? -1.0 : 1.0;
-        T[int64_t(c) * ldt + r] = r <= c ? sgn * A[c * M + r] : 0.0;
-    }
 }
 
 __global__ __launch_bounds__(256) void orth_leaf_kernel(double *basis, const int64_t *off_U, const int64_t *off_VT,
                                                         const int64_t *leaf_begin, const int64_t *leaf_end, int kq,
                                                         double *T, int kmax, int64_t first_leaf) {
-    __shared__ double A[QR_MAXM * QR_MAXN], Q[QR_MAXM * QR_MAXN], tau[QR_MAXN], scal[2];
+    __shared__ double A[(64 + QR_PAD) * QR_MAXN], tau[QR_MAXN], sgn[QR_MAXN], scal[2];
     const int64_t j = blockIdx.x;
     const int M = int(leaf_end[j] - leaf_begin[j]), N = kq;
-    const double *U = basis + off_U[j];
+    double *U = basis + off_U[j], *VT = basis + off_VT[j];
+    const int ld = M + QR_PAD;
     for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
         const int c = i / M, r = i - c * M;
-        A[i] = U[at2(M, r, c)];
+        A[c * ld + r] = U[at2(M, r, c)];
     }
     __syncthreads();
-    householder_qr(A, Q, tau, scal, M, N);
-    double *Uo = basis + off_U[j], *VT = basis + off_VT[j];
+    householder_qr(A, tau, scal, sgn, M, N, T + (first_leaf + j) * kmax * kmax, kmax);
     for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
         const int c = i / M, r = i - c * M;
-        Uo[at2(M, r, c)] = Q[i];      // U_j: M x N
-        VT[at2(N, c, r)] = Q[i];      // V_j^T: N x M
+        U[at2(M, r, c)] = A[c * ld + r];       // U_j: M x N
+        VT[at2(N, c, r)] = A[c * ld + r];      // V_j^T: N x M
     }
-    store_r(A, M, N, T + (first_leaf + j) * kmax * kmax, kmax);
 }
 
 // Parents of level l - 1 (2^(l-1) workgroups): Z = [T_c1 E_c1; T_c2 E_c2].
 __global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const int64_t *off_E, const int64_t *off_FT,
                                                          int kc, int kp, double *T, int kmax, int64_t first_parent) {
-    __shared__ double A[QR_MAXM * QR_MAXN], Q[QR_MAXM * QR_MAXN], tau[QR_MAXN], scal[2];
+    __shared__ double A[(QR_MAXM + QR_PAD) * QR_MAXN], tau[QR_MAXN], sgn[QR_MAXN], scal[2];
     const int64_t p = first_parent + blockIdx.x;
-    const int M = 2 * kc, N = kp;
-    for (int h = 0; h < 2; ++h) {
-        const int64_t ch = 2 * p + 1 + h;
-        const double *E = basis + off_E[ch];                    // kc x kp
-        const double *Tc = T + ch * kmax * kmax;                // kc x kc, upper triangular
-        for (int i = threadIdx.x; i < kc * kp; i += blockDim.x) {
-            const int c = i / kc, r = i - c * kc;
-            double s = 0.0;
-            for (int u = r; u < kc; ++u) s += Tc[int64_t(u) * kmax + r] * E[at2(kc, u, c)];
-            A[c * M + h * kc + r] = s;
+    const int M = 2 * kc, N = kp, ld = M + QR_PAD;
+    // Z = [T_c1 E_c1; T_c2 E_c2] on the FP64 matrix cores (the lane layout of
+    // the projection below): wavefront w computes rows 16 w .. 16 w + 15 of
+    // each half, its T_c operands loaded once, E's one column tile ahead.
+    {
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+        const int nrt = (kc + 15) >> 4, nct = (kp + 15) >> 4;
+        for (int h = 0; h < 2; ++h) {
+            const int64_t ch = 2 * p + 1 + h;
+            const double *E = basis + off_E[ch];                    // kc x kp
+            const double *Tc = T + ch * kmax * kmax;                // kc x kc, upper triangular
+            if (wv < nrt) {
+                const int r0 = 16 * wv;
+                double ta[16];
+#pragma unroll
+                for (int s4 = 0; s4 < 16; ++s4) {
+                    const int kk = 4 * s4 + lk, row = r0 + lr;
+                    ta[s4] = (row < kc && kk < kc) ? Tc[int64_t(kk) * kmax + row] : 0.0;   // T_c(row, kk)
+                }
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    if (ct >= nct) break;   // wave-uniform
+                    const int col = 16 * ct + lr;
+                    double eb[16];
+#pragma unroll
+                    for (int s4 = 0; s4 < 16; ++s4) {
+                        const int kk = 4 * s4 + lk;
+                        eb[s4] = (kk < kc && col < kp) ? E[at2(kc, kk, col)] : 0.0;          // E(kk, col)
+                    }
+                    // all 16 steps, with no early exit: the operand arrays keep static
+                    // register indices (steps past the rank multiply zeros)
+                    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int s4 = 0; s4 < 16; ++s4)
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[s4], eb[s4], acc, 0, 0, 0);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int row = r0 + lk + 4 * e;
+                        if (row < kc && col < kp) A[col * ld + h * kc + row] = acc[e];
+                    }
+                }
+            }
         }
     }
     __syncthreads();
-    householder_qr(A, Q, tau, scal, M, N);
+    householder_qr(A, tau, scal, sgn, M, N, T + p * kmax * kmax, kmax);
     for (int h = 0; h < 2; ++h) {
         const int64_t ch = 2 * p + 1 + h;
         double *E = basis + off_E[ch], *FT = basis + off_FT[ch];
         for (int i = threadIdx.x; i < kc * kp; i += blockDim.x) {
             const int c = i / kc, r = i - c * kc;
-            const double v = Q[c * M + h * kc + r];
+            const double v = A[c * ld + h * kc + r];
             E[at2(kc, r, c)] = v;       // E_c: kc x kp
             FT[at2(kp, c, r)] = v;      // F_c^T: kp x kc
         }
     }
-    store_r(A, M, N, T + p * kmax * kmax, kmax);
 }
 
-// Coupling block b: S <- T_i S T_j^T (k x k, in place).
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// Coupling block b: S <- T_i S T_j^T (k x k, in place), on the FP64 matrix
+// cores (v_mfma_f64_16x16x4_f64: lane l supplies A(l % 16, l / 16) and
+// B(l / 16, l % 16) and holds D(l / 16 + 4 e, l % 16), e = 0..3 -- the rows
+// of a lane's four results are 4 apart, unlike the FP32 16 x 16 forms).  Wavefront w owns
+// output rows 16 w .. 16 w + 15: first W_w = T_i(rows, :) S, staged in the
+// wave's own LDS slice, then S'(rows, :) = W_w T_j^T, staged back in the S
+// buffer and stored as whole 16-byte items.  S is loaded as 16-byte items
+// (two columns of a row), the next block's while this one's products run,
+// and zero-padded to a multiple of 16; T_i and T_j are read as operands from
+// memory (column-major, leading dimension kmax).  Each workgroup takes one
+// contiguous run of the list: the blocks of a block row share T_i, which
+// then stays in the caches.
+constexpr int PS_LD = 68;   // LDS leading dimension of S (spread over the banks)
+
+__device__ inline void proj_load(const double *blocks, const ProjDesc &d, f64x2 (&v)[8]) {
+    const int k = d.k, kp = (k + 15) & ~15, rows = kp, ng = kp >> 1;
+    const double *blk = blocks + d.off;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int i = threadIdx.x + 256 * j, g = i / rows, r = i - g * rows;
+        v[j] = (g < ng && r < k && 2 * g < k) ? __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(
+                                                     blk + (int64_t(g) * k + r) * 2))
+                                               : f64x2{0.0, 0.0};
+    }
+}
+
 __global__ __launch_bounds__(256) void orth_project_kernel(double *blocks, const ProjDesc *desc, int64_t nblocks,
                                                            const double *T, int kmax) {
-    __shared__ double S[64 * 64], W[64 * 64], Ti[64 * 64], Tj[64 * 64];
-    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    __shared__ double S[64 * PS_LD];     // column-major
+    __shared__ double Wl[4][16 * 64];    // per wave: 16 x 64, column-major, ld 16
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int64_t per = (nblocks + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = int64_t(blockIdx.x) * per, b1 = b0 + per < nblocks ? b0 + per : nblocks;
+    f64x2 nxt[8];
+    if (b0 < b1) proj_load(blocks, desc[b0], nxt);
+    for (int64_t b = b0; b < b1; ++b) {
         const ProjDesc d = desc[b];
-        const int k = d.k;
+        const int k = d.k, kp = (k + 15) & ~15, nt = kp >> 4;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {   // this block's items into LDS
+            const int i = threadIdx.x + 256 * j, g = i / kp, r = i - g * kp;
+            if (g < (kp >> 1)) {
+                S[(2 * g) * PS_LD + r] = nxt[j].x;
+                S[(2 * g + 1) * PS_LD + r] = nxt[j].y;
+            }
+        }
+        __syncthreads();
+        if (b + 1 < b1) proj_load(blocks, desc[b + 1], nxt);   // in flight during the products
+        const double *Ti = T + d.row * kmax * kmax, *Tj = T + d.col * kmax * kmax;
+        const int r0 = 16 * wv;
+        if (wv < nt) {
+            double ta[16];   // T_i(r0 + lr, 4 s + lk)
+#pragma unroll
+            for (int s4 = 0; s4 < 16; ++s4) {
+                const int kk = 4 * s4 + lk, row = r0 + lr;
+                ta[s4] = (row < k && kk < k) ? Ti[int64_t(kk) * kmax + row] : 0.0;
+            }
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                if (ct >= nt) break;   // wave-uniform
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s4 = 0; s4 < 16; ++s4) {
+                    if (4 * s4 >= kp) break;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[s4], S[(16 * ct + lr) * PS_LD + 4 * s4 + lk], acc, 0,
+                                                               0, 0);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Wl[wv][(16 * ct + lr) * 16 + lk + 4 * e] = acc[e];
+            }
+        }
+        __syncthreads();   // S is free from here on: S' goes into it
+        if (wv < nt) {
+            double tb[2][16];   // T_j(16 ct + lr, 4 s + lk), one column tile ahead
+            auto load_tb = [&](int ct, double (&o)[16]) {
+                const int col = 16 * ct + lr;
+#pragma unroll
+                for (int s4 = 0; s4 < 16; ++s4) {
+                    const int kk = 4 * s4 + lk;
+                    o[s4] = (col < k && kk < k) ? Tj[int64_t(kk) * kmax + col] : 0.0;
+                }
+            };
+            load_tb(0, tb[0]);
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                if (ct >= nt) break;   // unrolled, so the buffer indices are static
+                if (ct + 1 < nt) load_tb(ct + 1, tb[(ct + 1) & 1]);
+                const double(&cur)[16] = tb[ct & 1];
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s4 = 0; s4 < 16; ++s4) {
+                    if (4 * s4 >= kp) break;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wl[wv][(4 * s4 + lk) * 16 + lr], cur[s4], acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) S[(16 * ct + lr) * PS_LD + r0 + lk + 4 * e] = acc[e];
+            }
+        }
+        __syncthreads();
         double *blk = blocks + d.off;
-        const double *Ta = T + d.row * kmax * kmax, *Tb = T + d.col * kmax * kmax;
-        for (int i = threadIdx.x; i < k * k; i += blockDim.x) {
-            const int c = i / k, r = i - c * k;
-            S[i] = blk[at2(k, r, c)];
-            Ti[i] = Ta[int64_t(c) * kmax + r];
-            Tj[i] = Tb[int64_t(c) * kmax + r];
+        for (int i = threadIdx.x; i < k * ((k + 1) >> 1); i += 256) {   // S' as 16-byte items
+            const int g = i / k, r = i - g * k;
+            const double hi = 2 * g + 1 < k ? S[(2 * g + 1) * PS_LD + r] : 0.0;
+            *reinterpret_cast<f64x2 *>(blk + (int64_t(g) * k + r) * 2) = f64x2{S[(2 * g) * PS_LD + r], hi};
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < k * k; i += blockDim.x) {   // W = T_i S (T_i upper triangular)
-            const int c = i / k, r = i - c * k;
-            double s = 0.0;
-            for (int u = r; u < k; ++u) s += Ti[u * k + r] * S[c * k + u];
-            W[i] = s;
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < k * k; i += blockDim.x) {   // S' = W T_j^T: (W T_j^T)(r,c) = sum_u W(r,u) T_j(c,u)
-            const int c = i / k, r = i - c * k;
-            double s = 0.0;
-            for (int u = c; u < k; ++u) s += W[u * k + r] * Tj[u * k + c];
-            blk[at2(k, r, c)] = s;
-        }
-        __syncthreads();
+        __syncthreads();   // S is rewritten by the next block
     }
 }
 
