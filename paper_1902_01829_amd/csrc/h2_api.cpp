@@ -765,6 +765,11 @@ struct h2_batch_ {
     int64_t *d_ldx = nullptr, *d_ldy = nullptr;
     hipStream_t own = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // pinned host copy of the per-call tables (X, Y pointers, ldx, ldy), and
+    // the event after their upload: the next call waits for it before rewriting
+    int64_t *h_tables = nullptr;
+    hipEvent_t ev_tables = nullptr;
+    bool tables_pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     h2::MmConfig cfg{1, 0};
@@ -774,6 +779,11 @@ struct h2_batch_ {
     int64_t cu_count = 256;
 
     ~h2_batch_() {
+        if (ev_tables) {
+            if (tables_pending) (void)hipEventSynchronize(ev_tables);
+            (void)hipEventDestroy(ev_tables);
+        }
+        if (h_tables) (void)hipHostFree(h_tables);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (ev_in) (void)hipEventDestroy(ev_in);
@@ -1067,6 +1077,9 @@ void build_batch(h2_batch_ &B, hipStream_t stream) {
     check_hip(hipStreamCreateWithFlags(&B.own, hipStreamNonBlocking), "hipStreamCreate");
     check_hip(hipEventCreateWithFlags(&B.ev_in, hipEventDisableTiming), "hipEventCreate");
     check_hip(hipEventCreateWithFlags(&B.ev_out, hipEventDisableTiming), "hipEventCreate");
+    check_hip(hipEventCreateWithFlags(&B.ev_tables, hipEventDisableTiming), "hipEventCreate");
+    check_hip(hipHostMalloc(reinterpret_cast<void **>(&B.h_tables), size_t(4 * nm) * 8, hipHostMallocDefault),
+              "hipHostMalloc");
     check_hip(hipStreamSynchronize(stream), "batch build");
 }
 
@@ -1589,30 +1602,41 @@ h2_status h2_batch_matmat(h2_batch B, const double *const *X, const int64_t *ldx
     try {
         if (!B || !X || !ldx || !Y || !ldy) fail(H2_ERR_INVALID_ARG, "NULL argument");
         const int nm = int(B->mats.size());
-        std::vector<const double *> xt(nm);
-        std::vector<double *> yt(nm);
-        std::vector<int64_t> lx(nm), ly(nm);
         for (int b = 0; b < nm; ++b) {
             if (!X[b] || !Y[b]) fail(H2_ERR_INVALID_ARG, "NULL member matrix");
             if (ldx[b] < B->mats[b]->st.n || ldy[b] < B->mats[b]->st.n)
                 fail(H2_ERR_INVALID_ARG, "leading dimension below n");
-            xt[b] = X[b];
-            yt[b] = Y[b];
-            lx[b] = ldx[b];
-            ly[b] = ldy[b];
+        }
+        // pointer tables: written to pinned memory (after the previous call's upload
+        // of them has run) and uploaded outside the graph
+        if (B->tables_pending) check_hip(hipEventSynchronize(B->ev_tables), "hipEventSynchronize");
+        int64_t *tab = B->h_tables;
+        for (int b = 0; b < nm; ++b) {
+            tab[b] = int64_t(reinterpret_cast<uintptr_t>(X[b]));
+            tab[nm + b] = int64_t(reinterpret_cast<uintptr_t>(Y[b]));
+            tab[2 * nm + b] = ldx[b];
+            tab[3 * nm + b] = ldy[b];
         }
         const hipStream_t user = static_cast<hipStream_t>(stream);
         check_hip(hipEventRecord(B->ev_in, user), "hipEventRecord");
         check_hip(hipStreamWaitEvent(B->own, B->ev_in, 0), "hipStreamWaitEvent");
-        // pointer tables: outside the graph, copied from pageable memory (staged before return)
-        check_hip(hipMemcpyAsync(B->d_Xtab, xt.data(), nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
-        check_hip(hipMemcpyAsync(B->d_Ytab, yt.data(), nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
-        check_hip(hipMemcpyAsync(B->d_ldx, lx.data(), nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
-        check_hip(hipMemcpyAsync(B->d_ldy, ly.data(), nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
+        check_hip(hipMemcpyAsync(B->d_Xtab, tab, nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
+        check_hip(hipMemcpyAsync(B->d_Ytab, tab + nm, nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
+        check_hip(hipMemcpyAsync(B->d_ldx, tab + 2 * nm, nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
+        check_hip(hipMemcpyAsync(B->d_ldy, tab + 3 * nm, nm * 8, hipMemcpyHostToDevice, B->own), "copy tables");
+        check_hip(hipEventRecord(B->ev_tables, B->own), "hipEventRecord");
+        B->tables_pending = true;
         if (!B->tuned) batch_autotune(*B);
         if (!B->exec) {
             check_hip(hipStreamBeginCapture(B->own, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-            batch_enqueue(*B, B->cfg, B->own);
+            try {
+                batch_enqueue(*B, B->cfg, B->own);
+            } catch (...) {
+                hipGraph_t aborted = nullptr;   // leave the stream out of capture mode
+                (void)hipStreamEndCapture(B->own, &aborted);
+                if (aborted) (void)hipGraphDestroy(aborted);
+                throw;
+            }
             check_hip(hipStreamEndCapture(B->own, &B->graph), "hipStreamEndCapture");
             check_hip(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
         }
