@@ -394,3 +394,149 @@ def orthogonalize_arrays(arr):
         S.append(Sl)
     out.update(U=U, V=U, E=E, F=E, S=S)
     return out, T
+
+
+def _leaf_offsets(arr):
+    """Element offset of every leaf's m_j x k_q block in U (and V)."""
+    q, kq = int(arr["q"]), int(arr["level_rank"][int(arr["q"])])
+    b, e = arr["begin"], arr["end"]
+    lf = (1 << q) - 1
+    off, out = 0, {}
+    for j in range(1 << q):
+        m = int(e[lf + j] - b[lf + j])
+        out[lf + j] = (off, m)
+        off += m * kq
+    return out
+
+
+def _transfer_offsets(kr, q):
+    """Element offset of every node's k_l x k_(l-1) transfer in E (and F), levels 1 .. q."""
+    eo, off = {}, 0
+    for l in range(1, q + 1):
+        for c in range((1 << l) - 1, (2 << l) - 1):
+            eo[c] = off
+            off += kr[l] * kr[l - 1]
+    return eo, off
+
+
+def basis_generation(arr):
+    """The tree R of Sec. 5.2 (Alg. 8 and 9) for a symmetric H^2 matrix with
+    orthonormal nested bases, given by its arrays.  For node i of level l, with
+    parent i+ and coupling blocks S_ij1 .. S_ijb in its block row,
+        Sbar_i = [R_i+ E_i^T; S_ij1^T; ...; S_ijb^T]
+    and R_i is the triangular factor of the QR factorization of Sbar_i (Q is
+    not formed).  The parent term is absent on the coarsest level with blocks,
+    l_min (every level above it has an empty block row, so its R is 0).  R_i
+    is returned as a k_l x k_l matrix (rows past the number of rows of Sbar_i
+    are zero).  Returns {node: R_i} for the nodes of levels l_min .. q."""
+    q = int(arr["q"])
+    kr = [int(k) for k in arr["level_rank"]]
+    lmin = next((l for l in range(q + 1) if int(arr["S_rowptr"][l][1 << l]) > 0), q + 1)
+    eo, _ = _transfer_offsets(kr, q)
+    R = {}
+    for l in range(lmin, q + 1):
+        k, f = kr[l], (1 << l) - 1
+        rp, ci, S = arr["S_rowptr"][l], arr["S_colidx"][l], arr["S"][l]
+        for i in range(1 << l):
+            node = f + i
+            parts = []
+            if l > lmin:
+                kp = kr[l - 1]
+                Ei = arr["E"][eo[node]:eo[node] + k * kp].reshape(kp, k).T     # k_l x k_(l-1)
+                parts.append(R[(node - 1) // 2] @ Ei.T)
+            for t in range(int(rp[i]), int(rp[i + 1])):
+                parts.append(S[t * k * k:(t + 1) * k * k].reshape(k, k))      # S_ij^T (column-major S_ij read row-major)
+            Ri = np.zeros((k, k))
+            if parts:
+                r = np.linalg.qr(np.vstack(parts), mode="r")
+                Ri[:r.shape[0], :] = r
+            R[node] = Ri
+    return R
+
+
+def compress_arrays(arr, eps):
+    """Algebraic compression of a symmetric H^2 matrix given by its arrays
+    (Sec. 5): orthogonalization (Sec. 5.1), basis generation (Sec. 5.2), basis
+    truncation (Sec. 5.3, Alg. 10) with relative threshold eps, and projection
+    of the coupling blocks into the truncated bases.
+
+    Leaves: W_i = U_i R_i^T, SVD W_i = Q S Y^T; node i keeps the singular
+    vectors whose singular value is at least eps times its largest, and the
+    level keeps the largest such count over its nodes (at least 1): k~_q.  The
+    new leaf basis is the first k~_q columns of Q, T_i = Q^T U_i.  Levels q ..
+    l_min + 1, parent p with children c1, c2: Z_p = [T_c1 E_c1; T_c2 E_c2]
+    (2 k~_l x k_(l-1)), W_p = Z_p R_p^T, the same truncated SVD gives k~_(l-1)
+    and Q; its two k~_l x k~_(l-1) blocks are the new transfers of c1 and c2,
+    T_p = Q^T Z_p.  Every coupling block S_ij <- T_i S_ij T_j^T (k~_l x k~_l);
+    dense blocks are unchanged.  Levels above l_min take rank k~_(l_min) with
+    zero transfers (the product does not use them).
+
+    Returns (new arrays, info) with info = {"rank": k~ per level, "sigma":
+    {node: singular values of W}, "count": {node: kept count}, "R": R tree,
+    "T": {node: T}}."""
+    orth, _ = orthogonalize_arrays(arr)
+    q = int(arr["q"])
+    kr = [int(k) for k in orth["level_rank"]]
+    lmin = next((l for l in range(q + 1) if int(orth["S_rowptr"][l][1 << l]) > 0), q + 1)
+    if lmin > q:
+        return orth, {"rank": kr, "sigma": {}, "count": {}, "R": {}, "T": {}}
+    R = basis_generation(orth)
+    eo, _ = _transfer_offsets(kr, q)
+    lo = _leaf_offsets(orth)
+    lf = (1 << q) - 1
+
+    def kept(s):
+        return int(np.count_nonzero(s >= eps * s[0])) if s.size and s[0] > 0.0 else 0
+
+    sigma, count, T, kt = {}, {}, {}, list(kr)
+    Ul, left = {}, {}
+    for v in range(lf, 2 * lf + 1):   # leaves
+        off, m = lo[v]
+        Ul[v] = orth["U"][off:off + m * kr[q]].reshape(kr[q], m).T
+        Qv, s, _ = np.linalg.svd(Ul[v] @ R[v].T, full_matrices=False)
+        left[v], sigma[v], count[v] = Qv, s, kept(s)
+    kt[q] = max(1, max(count[v] for v in range(lf, 2 * lf + 1)))
+    newU = []
+    for v in range(lf, 2 * lf + 1):
+        Qv = left[v][:, :kt[q]]
+        T[v] = Qv.T @ Ul[v]
+        newU.append(Qv.ravel(order="F"))
+    newE = {}
+    for l in range(q, lmin, -1):
+        kc, kp = kr[l], kr[l - 1]
+        Z, left = {}, {}
+        for p in range((1 << (l - 1)) - 1, (1 << l) - 1):
+            halves = []
+            for c in (2 * p + 1, 2 * p + 2):
+                Ec = orth["E"][eo[c]:eo[c] + kc * kp].reshape(kp, kc).T
+                halves.append(T[c] @ Ec)
+            Z[p] = np.vstack(halves)
+            Qp, s, _ = np.linalg.svd(Z[p] @ R[p].T, full_matrices=False)
+            left[p], sigma[p], count[p] = Qp, s, kept(s)
+        kt[l - 1] = max(1, max(count[p] for p in Z))
+        for p in Z:
+            Qp = left[p][:, :kt[l - 1]]
+            newE[2 * p + 1] = Qp[:kt[l]]
+            newE[2 * p + 2] = Qp[kt[l]:]
+            T[p] = Qp.T @ Z[p]
+    for l in range(lmin):
+        kt[l] = kt[lmin]
+    E = []
+    for l in range(1, q + 1):
+        for c in range((1 << l) - 1, (2 << l) - 1):
+            E.append(newE[c].ravel(order="F") if c in newE else np.zeros(kt[l] * kt[l - 1]))
+    S = []
+    for l in range(q + 1):
+        k, kn, f = kr[l], kt[l], (1 << l) - 1
+        rp, ci, Sl = orth["S_rowptr"][l], orth["S_colidx"][l], orth["S"][l]
+        blocks = []
+        for i in range(1 << l):
+            for t in range(int(rp[i]), int(rp[i + 1])):
+                Sb = Sl[t * k * k:(t + 1) * k * k].reshape(k, k).T
+                blocks.append((T[f + i] @ Sb @ T[f + int(ci[t])].T).ravel(order="F"))
+        S.append(np.concatenate(blocks) if blocks else np.zeros(0))
+    out = dict(orth)
+    Uc = np.concatenate(newU)
+    Ec = np.concatenate(E) if E else np.zeros(0)
+    out.update(level_rank=np.array(kt, dtype=np.int32), U=Uc, V=Uc, E=Ec, F=Ec, S=S)
+    return out, {"rank": kt, "sigma": sigma, "count": count, "R": R, "T": T}

@@ -562,3 +562,180 @@ def test_orthogonalization_of_orthogonal_bases_is_identity(oracle_mod):
         assert np.abs(t - np.eye(t.shape[0])).max() <= 1e-12
     for key in ("U", "E"):
         assert np.abs(twice[key] - once[key]).max() <= 1e-12
+
+
+# ---- algebraic compression: basis generation (Sec. 5.2) and truncation (Sec. 5.3)
+
+def _far_columns(arr, v):
+    """Columns of the far field of node v: every coupling block of v or of an
+    ancestor of v (the part of block row v that the bases represent)."""
+    b, e = arr["begin"], arr["end"]
+    cols, a = [], v
+    while True:
+        l = int(np.floor(np.log2(a + 1)))
+        f = (1 << l) - 1
+        rp, ci = arr["S_rowptr"][l], arr["S_colidx"][l]
+        for t in range(int(rp[a - f]), int(rp[a - f + 1])):
+            c = f + int(ci[t])
+            cols.extend(range(int(b[c]), int(e[c])))
+        if a == 0:
+            break
+        a = (a - 1) // 2
+    return np.array(sorted(cols), dtype=np.int64)
+
+
+def _levels_with_blocks(arr):
+    q = int(arr["q"])
+    return [l for l in range(q + 1) if len(arr["S_colidx"][l]) > 0]
+
+
+@pytest.mark.parametrize("n,d,m,p", [(700, 2, 16, 3), (600, 3, 32, 2)])
+def test_leaf_singular_values_are_those_of_the_far_field(oracle_mod, n, d, m, p):
+    """W_i = U_i R_i^T has the singular values of leaf i's far-field block row
+    of the dense matrix (brute force): R_i^T R_i is the Gram matrix of that
+    block row in the orthonormal bases, parent levels included."""
+    o = oracle_mod.OracleH2(_pts(n, d, 23), m, p, 0.9, 0.2)
+    arr = o.export_arrays()
+    A = _dense_from_arrays(arr)
+    _, info = oracle_mod.compress_arrays(arr, 0.0)
+    b, e = arr["begin"], arr["end"]
+    lf = (1 << o.q) - 1
+    checked = 0
+    for v in range(lf, 2 * lf + 1):
+        cols = _far_columns(arr, v)
+        s = np.linalg.svd(A[b[v]:e[v]][:, cols], compute_uv=False) if len(cols) else np.zeros(0)
+        got = info["sigma"][v]
+        ref = np.zeros(len(got))
+        ref[:min(len(s), len(got))] = s[:len(got)]
+        assert np.abs(got - ref).max() <= 1e-12 * max(ref.max(), 1e-300)
+        checked += len(cols) > 0
+    assert checked > 0
+
+
+def test_inner_singular_values_are_those_of_the_projected_far_field(oracle_mod):
+    """W_p = Z_p R_p^T has the singular values of the far-field block row of p
+    projected onto its children's truncated bases (brute force on the dense
+    matrix with the children's new explicit bases)."""
+    o = oracle_mod.OracleH2(_pts(1400, 2, 29), 32, 4, 0.9, 0.2)
+    arr = o.export_arrays()
+    A = _dense_from_arrays(arr)
+    out, info = oracle_mod.compress_arrays(arr, 1e-5)
+    new = _explicit_bases(out)
+    b, e = arr["begin"], arr["end"]
+    lmin = _levels_with_blocks(arr)[0]
+    checked = 0
+    for p in range((1 << lmin) - 1, (1 << o.q) - 1):
+        cols = _far_columns(arr, p)
+        if not len(cols):
+            continue
+        c1, c2 = 2 * p + 1, 2 * p + 2
+        Pf = np.vstack([new[c1] @ (new[c1].T @ A[b[c1]:e[c1]][:, cols]),
+                        new[c2] @ (new[c2].T @ A[b[c2]:e[c2]][:, cols])])
+        s = np.linalg.svd(Pf, compute_uv=False)
+        got = info["sigma"][p]
+        assert np.abs(got - s[:len(got)]).max() <= 1e-12 * s[0]
+        checked += 1
+    assert checked > 0
+
+
+@pytest.mark.parametrize("n,d,m,p", [(1500, 2, 32, 4), (1000, 3, 32, 2)])
+def test_compression_at_zero_threshold_keeps_ranks_and_product(oracle_mod, n, d, m, p):
+    o = oracle_mod.OracleH2(_pts(n, d, 31), m, p, 0.9, 0.2)
+    arr = o.export_arrays()
+    out, info = oracle_mod.compress_arrays(arr, 0.0)
+    assert list(out["level_rank"]) == [o.k] * (o.q + 1)
+    x = _x(n, 32)
+    y0, y1 = oracle_mod.arrays_matvec(arr, x), oracle_mod.arrays_matvec(out, x)
+    assert np.linalg.norm(y1 - y0) <= 1e-12 * np.linalg.norm(y0)
+    new = _explicit_bases(out)
+    for v in range((1 << _levels_with_blocks(arr)[0]) - 1, o.nnodes):
+        assert np.abs(new[v].T @ new[v] - np.eye(new[v].shape[1])).max() <= 1e-12
+
+
+def _inflate(arr, extra, seed):
+    """The same matrix with `extra` more basis columns per level: bases
+    [U, N] with random N, transfers [[E, X], [0, Y]] (nested, since the
+    first k columns of the parent basis are still U_c E_c), coupling blocks
+    [[S, 0], [0, 0]].  The product is unchanged; every block row keeps the
+    rank of the original."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    q, kr = int(arr["q"]), [int(k) for k in arr["level_rank"]]
+    kn = [k + extra for k in kr]
+    b, e = arr["begin"], arr["end"]
+    lf = (1 << q) - 1
+    U, off = [], 0
+    for j in range(1 << q):
+        mj = int(e[lf + j] - b[lf + j])
+        Uj = arr["U"][off:off + mj * kr[q]].reshape(kr[q], mj).T
+        U.append(np.hstack([Uj, rng.standard_normal((mj, extra))]).ravel(order="F"))
+        off += mj * kr[q]
+    E, off = [], 0
+    for l in range(1, q + 1):
+        for c in range((1 << l) - 1, (2 << l) - 1):
+            Ec = arr["E"][off:off + kr[l] * kr[l - 1]].reshape(kr[l - 1], kr[l]).T
+            off += kr[l] * kr[l - 1]
+            En = np.zeros((kn[l], kn[l - 1]))
+            En[:kr[l], :kr[l - 1]] = Ec
+            En[:, kr[l - 1]:] = rng.standard_normal((kn[l], extra))
+            E.append(En.ravel(order="F"))
+    S = []
+    for l in range(q + 1):
+        k, nb = kr[l], len(arr["S_colidx"][l])
+        blocks = []
+        for t in range(nb):
+            Sn = np.zeros((kn[l], kn[l]))
+            Sn[:k, :k] = arr["S"][l][t * k * k:(t + 1) * k * k].reshape(k, k).T
+            blocks.append(Sn.ravel(order="F"))
+        S.append(np.concatenate(blocks) if blocks else np.zeros(0))
+    Uc, Ecat = np.concatenate(U), np.concatenate(E) if E else np.zeros(0)
+    return dict(arr, level_rank=np.array(kn, dtype=np.int32), U=Uc, V=Uc, E=Ecat, F=Ecat, S=S)
+
+
+@pytest.mark.parametrize("n,d,m,extra", [(1200, 2, 32, 6), (900, 3, 32, 5)])
+def test_compression_recovers_a_planted_rank(oracle_mod, n, d, m, extra):
+    """A rank-4 matrix (2-point Chebyshev bases in 2-D, rank 8 in 3-D) written
+    with `extra` redundant basis columns compresses back to its own rank on
+    every level with blocks, and the product does not change."""
+    o = oracle_mod.OracleH2(_pts(n, d, 37), m, 2, 0.9, 0.2)
+    arr = o.export_arrays()
+    big = _inflate(arr, extra, 38)
+    x = _x(n, 39)
+    y0 = oracle_mod.arrays_matvec(arr, x)
+    assert np.linalg.norm(oracle_mod.arrays_matvec(big, x) - y0) <= 1e-13 * np.linalg.norm(y0)
+    out, info = oracle_mod.compress_arrays(big, 1e-10)
+    for l in _levels_with_blocks(arr):
+        assert info["rank"][l] == o.k
+    assert np.linalg.norm(oracle_mod.arrays_matvec(out, x) - y0) <= 1e-12 * np.linalg.norm(y0)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6, 1e-9])
+def test_compression_error_is_below_the_threshold(oracle_mod, eps):
+    """||A~ - A||_F <= eps ||A||_F on the dense expansions, ranks below the
+    input's, and each level's rank is the largest count of kept singular
+    values over its nodes (Sec. 5.3)."""
+    o = oracle_mod.OracleH2(_pts(3000, 2, 41), 64, 6, 0.9, 0.2)
+    arr = o.export_arrays()
+    out, info = oracle_mod.compress_arrays(arr, eps)
+    A0, A1 = _dense_from_arrays(arr), _dense_from_arrays(out)
+    assert np.linalg.norm(A1 - A0) <= eps * np.linalg.norm(A0)
+    levels = _levels_with_blocks(arr)
+    assert all(info["rank"][l] < o.k for l in levels)
+    for l in levels:
+        nodes = range((1 << l) - 1, (2 << l) - 1)
+        assert info["rank"][l] == max(1, max(info["count"][v] for v in nodes))
+        for v in nodes:
+            s = info["sigma"][v]   # a node with an empty far field keeps nothing
+            assert info["count"][v] == (int(np.sum(s >= eps * s[0])) if s[0] > 0.0 else 0)
+
+
+def test_compression_to_rank_one(oracle_mod):
+    """Threshold 1: one singular vector per node; every level has rank 1 and
+    the arrays stay a valid H^2 matrix with orthonormal (unit) bases."""
+    o = oracle_mod.OracleH2(_pts(800, 2, 43), 32, 3, 0.9, 0.2)
+    out, info = oracle_mod.compress_arrays(o.export_arrays(), 1.0)
+    assert list(out["level_rank"]) == [1] * (o.q + 1)
+    new = _explicit_bases(out)
+    for v in range((1 << _levels_with_blocks(out)[0]) - 1, o.nnodes):
+        assert abs((new[v].T @ new[v]).item() - 1.0) <= 1e-12
+    x = _x(800, 44)
+    assert np.all(np.isfinite(oracle_mod.arrays_matvec(out, x)))
