@@ -202,6 +202,29 @@ h2_status h2_export_arrays(h2_handle A, const h2_arrays_out *out, void *stream);
  * the leaf rank, or k_(l-1) > 2 k_l; DEVICE. */
 h2_status h2_orthogonalize(h2_handle A, void *stream);
 
+/* Algebraic compression (Sec. 5), in place: orthogonalization as
+ * h2_orthogonalize; basis generation (Sec. 5.2): for every node i of the
+ * levels with coupling blocks, top-down, R_i = the triangular factor of the
+ * QR factorization of [R_parent E_i^T; S_ij1^T; ...; S_ijb^T] (its block
+ * row's coupling blocks under its parent's factor); truncation (Sec. 5.3),
+ * bottom-up: the left singular vectors of W_i = U_i R_i^T at the leaves and
+ * of W_p = [T_c1 E_c1; T_c2 E_c2] R_p^T above, a node keeping those whose
+ * singular value is at least eps times its largest, a level the largest such
+ * count over its nodes (at least 1, at most its rank); the kept vectors give
+ * the new leaf bases and transfers and T_i = Q_i^T (old basis); then every
+ * coupling block S_ij becomes T_i S_ij T_j^T.  Dense blocks are unchanged.
+ * The representation is rebuilt with the new per-level ranks (levels above
+ * the first with coupling blocks take that level's rank) and the old one is
+ * freed; products after the call use the new one.
+ *  eps         relative threshold, finite, >= 0 (0 keeps every rank).
+ *  level_rank  NULL, or host, q + 1 ints: the new rank of every level.
+ * The call returns when the device work is done; its scratch memory (about
+ * 3 nnodes k^2 + 2^q (64^2 + 128 x 64) doubles) is freed on return.
+ * Errors: INVALID_ARG for NULL or structure-only handles, eps < 0 or not
+ * finite, or a matrix that belongs to a live batch (free the batch first);
+ * the UNSUPPORTED cases of h2_orthogonalize; OOM; DEVICE. */
+h2_status h2_compress(h2_handle A, double eps, int *level_rank, void *stream);
+
 /* y = A x (Sec. 4, Fig. 4).
  *  x  device, n doubles, tree order.   y  device, n doubles, tree order.
  * x and y must not overlap.  Errors: INVALID_ARG for NULL pointers or a

@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <mutex>
 #include <string>
@@ -49,6 +50,11 @@ struct DeviceArena {
     DeviceArena &operator=(const DeviceArena &) = delete;
     ~DeviceArena() {
         for (void *p : ptrs) (void)hipFree(p);
+    }
+    void swap(DeviceArena &o) {
+        std::swap(ptrs, o.ptrs);
+        std::swap(bytes, o.bytes);
+        std::swap(cap, o.cap);
     }
     void *alloc(int64_t nbytes) {
         if (nbytes <= 0) nbytes = 16;
@@ -163,6 +169,7 @@ struct h2_matrix_ {
     std::vector<int64_t> off_U, off_VT, off_E, off_FT, off_blk;
     int64_t basis_elems = 0, block_elems = 0;   // lengths of the two regions
     bool symmetric = true;                      // V = U and F = E
+    int batch_refs = 0;                         // batches holding addresses into this matrix
     // profiling: PH_COUNT + 1 events per recorded call
     bool prof = false;
     std::vector<hipEvent_t> pending, spare;
@@ -252,21 +259,24 @@ struct Stager {
 // conversion of caller arrays (src), and the work lists of one product in
 // launch order.  Ranks may differ per level (k_l); vectors and tiles use the
 // largest rank as their node stride.
-void build_device(h2_matrix_ &A, const h2_arrays *src, hipStream_t stream) {
+// The device representation's layout for the structure's level ranks: sets
+// the offsets and byte counts of A, allocates its regions (basis, blocks,
+// scales) and returns the fill list (coupling blocks level by level in BSR
+// order, then dense blocks); ncoupling receives the number of coupling blocks.
+std::vector<h2::FillDesc> make_layout(h2_matrix_ &A, int64_t &ncoupling) {
     const Structure &s = A.st;
-    const int k = s.rank, q = s.q;   // k: largest level rank
+    const int q = s.q;
     const std::vector<int> &kl = s.lrank;
     const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
     const bool lowrank = s.lmin <= q;
     const int bk = A.basis_kind, sk = A.block_kind;
 
     // basis region: U_j, V_j^T per leaf; E_c, F_c^T per node of levels lmin+1..q
-    std::vector<int64_t> leaf_node(nleaves), off_U(nleaves), off_VT(nleaves);
+    std::vector<int64_t> off_U(nleaves), off_VT(nleaves);
     std::vector<int64_t> off_E(s.nnodes, -1), off_FT(s.nnodes, -1);
     int64_t nb = 0;
     for (int64_t j = 0; j < nleaves; ++j) {
         const int m = int(s.size(lf + j));
-        leaf_node[j] = lf + j;
         off_U[j] = nb;
         nb += h2::block_elems(m, kl[q], bk);
         off_VT[j] = nb;
@@ -298,7 +308,8 @@ void build_device(h2_matrix_ &A, const h2_arrays *src, hipStream_t stream) {
                 ns += h2::block_elems(kl[l], kl[l], sk);
             }
     }
-    const int64_t coupling_elems = ns, ncoupling = int64_t(fill.size());
+    const int64_t coupling_elems = ns;
+    ncoupling = int64_t(fill.size());
     for (int64_t i = 0; i < nleaves; ++i)
         for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b) {
             const int64_t t = lf + s.dense.colidx[b];
@@ -321,6 +332,23 @@ void build_device(h2_matrix_ &A, const h2_arrays *src, hipStream_t stream) {
     A.blocks = A.mem.alloc(ns * sb);
     A.scales = static_cast<float *>(A.mem.alloc(std::max<int64_t>(1, int64_t(fill.size())) * 4));
     A.nscales = int64_t(fill.size());
+    return fill;
+}
+
+void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t ncoupling, hipStream_t stream);
+
+void build_device(h2_matrix_ &A, const h2_arrays *src, hipStream_t stream) {
+    const Structure &s = A.st;
+    const int k = s.rank, q = s.q;   // k: largest level rank
+    const std::vector<int> &kl = s.lrank;
+    const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
+    const bool lowrank = s.lmin <= q;
+    const int bk = A.basis_kind, sk = A.block_kind;
+    int64_t ncoupling = 0;
+    const std::vector<h2::FillDesc> fill = make_layout(A, ncoupling);
+    const std::vector<int64_t> &off_U = A.off_U, &off_VT = A.off_VT, &off_E = A.off_E, &off_FT = A.off_FT;
+    std::vector<int64_t> leaf_node(nleaves);
+    for (int64_t j = 0; j < nleaves; ++j) leaf_node[j] = lf + j;
     if (!src) {
         // generation of the representation on the device (Sec. 4.6)
         std::vector<double> cheb(s.cheb_p);
@@ -404,6 +432,18 @@ void build_device(h2_matrix_ &A, const h2_arrays *src, hipStream_t stream) {
             }
         }
     }
+    build_lists(A, fill, ncoupling, stream);
+}
+
+// Vector workspace and work lists of the product for the layout of A.
+void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t ncoupling, hipStream_t stream) {
+    const Structure &s = A.st;
+    const int k = s.rank, q = s.q;
+    const std::vector<int> &kl = s.lrank;
+    const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
+    const bool lowrank = s.lmin <= q;
+    const int bk = A.basis_kind, sk = A.block_kind;
+    const std::vector<int64_t> &off_U = A.off_U, &off_VT = A.off_VT, &off_E = A.off_E, &off_FT = A.off_FT;
 
     // workspace: vector trees x^ and y^ (nnodes x k) and the near field (n)
     const int64_t vb = A.vec_f64 ? 8 : 4;
@@ -777,8 +817,11 @@ struct h2_batch_ {
     double tuned_ms = 0.0;
     std::string signature;
     int64_t cu_count = 256;
+    bool counted = false;   // the members' batch_refs include this batch
 
     ~h2_batch_() {
+        if (counted)
+            for (h2_matrix_ *m : mats) --m->batch_refs;
         if (ev_tables) {
             if (tables_pending) (void)hipEventSynchronize(ev_tables);
             (void)hipEventDestroy(ev_tables);
@@ -1127,6 +1170,10 @@ h2_status h2_build_from_points(const double *points, int64_t n, const h2_params 
 }
 
 // Checks the arrays and fills the host structure from them.
+}  // extern "C"
+
+namespace {
+
 void structure_from_arrays(const h2_arrays *a, h2::Structure &s) {
     if (!a) fail(H2_ERR_INVALID_ARG, "NULL arrays");
     if (a->n < 1 || a->n >= (int64_t(1) << 31)) fail(H2_ERR_INVALID_ARG, "n out of range");
@@ -1308,6 +1355,10 @@ void export_arrays(h2_matrix_ &A, const h2_arrays_out *o, hipStream_t st) {
     }
 }
 
+}  // namespace
+
+extern "C" {
+
 h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *stream, h2_handle *out) {
     if (out) *out = nullptr;
     h2_matrix_ *A = nullptr;
@@ -1352,6 +1403,10 @@ h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *strea
     }
 }
 
+}  // extern "C"
+
+namespace {
+
 // Basis orthogonalization and projection of the coupling blocks in place.
 void orthogonalize(h2_matrix_ &A, hipStream_t st) {
     const Structure &s = A.st;
@@ -1371,7 +1426,7 @@ void orthogonalize(h2_matrix_ &A, hipStream_t st) {
         const int64_t f = Structure::first(l);
         for (int64_t i = 0; i < (int64_t(1) << l); ++i)
             for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b, ++fi)
-                proj.push_back({A.off_blk[fi], f + i, f + B.colidx[b], s.lrank[l], 0});
+                proj.push_back({A.off_blk[fi], A.off_blk[fi], f + i, f + B.colidx[b], s.lrank[l], s.lrank[l]});
     }
     DeviceArena scratch;
     const int kmax = s.rank;
@@ -1395,6 +1450,192 @@ void orthogonalize(h2_matrix_ &A, hipStream_t st) {
     L.kmax = kmax;
     check_hip(h2::launch_orthogonalize(L, st), "orthogonalization launch");
     check_hip(hipStreamSynchronize(st), "orthogonalization");
+}
+
+// Moves the representation of B (structure, layout, device memory, work
+// lists) into A; B receives A's old one and frees it when destroyed.
+void adopt(h2_matrix_ &A, h2_matrix_ &B) {
+    std::swap(A.st, B.st);
+    A.mem.swap(B.mem);
+    std::swap(A.basis, B.basis);
+    std::swap(A.blocks, B.blocks);
+    std::swap(A.scales, B.scales);
+    std::swap(A.xh, B.xh);
+    std::swap(A.yh, B.yh);
+    std::swap(A.ynear, B.ynear);
+    std::swap(A.lists, B.lists);
+    std::swap(A.mm_lists, B.mm_lists);
+    std::swap(A.mm_host_rows, B.mm_host_rows);
+    std::swap(A.mm_host_blks, B.mm_host_blks);
+    std::swap(A.nscales, B.nscales);
+    std::swap(A.tile_slot, B.tile_slot);
+    std::swap(A.d_leaf_begin, B.d_leaf_begin);
+    std::swap(A.d_leaf_end, B.d_leaf_end);
+    std::swap(A.t_xh, B.t_xh);
+    std::swap(A.t_yh, B.t_yh);
+    std::swap(A.t_x, B.t_x);
+    std::swap(A.t_ynear, B.t_ynear);
+    for (int w = 0; w < 2; ++w) {
+        std::swap(A.mm_cfg[w], B.mm_cfg[w]);
+        std::swap(A.mm_tuned[w], B.mm_tuned[w]);
+    }
+    std::swap(A.bytes_coupling, B.bytes_coupling);
+    std::swap(A.bytes_dense, B.bytes_dense);
+    std::swap(A.bytes_leaf, B.bytes_leaf);
+    std::swap(A.bytes_transfer, B.bytes_transfer);
+    std::swap(A.off_U, B.off_U);
+    std::swap(A.off_VT, B.off_VT);
+    std::swap(A.off_E, B.off_E);
+    std::swap(A.off_FT, B.off_FT);
+    std::swap(A.off_blk, B.off_blk);
+    std::swap(A.basis_elems, B.basis_elems);
+    std::swap(A.block_elems, B.block_elems);
+}
+
+// Algebraic compression (Sec. 5): orthogonalization, basis generation,
+// truncation with relative threshold eps (rank of a level: the largest count
+// of kept singular values over its nodes), projection of the coupling blocks
+// into the truncated bases; the representation is rebuilt with the new ranks.
+void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
+    if (!(eps >= 0.0) || !std::isfinite(eps)) fail(H2_ERR_INVALID_ARG, "eps must be finite and >= 0");
+    if (A.batch_refs > 0) fail(H2_ERR_INVALID_ARG, "the matrix belongs to a batch (free the batch first)");
+    orthogonalize(A, st);
+    const Structure &s = A.st;
+    const int q = s.q, lmin = s.lmin, kmax = s.rank;
+    const std::vector<int> kr = s.lrank;
+    std::vector<int> kt = kr;
+    if (lmin <= q) {
+        const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
+        // coupling blocks in BSR order (all levels) and the first block of every node's row
+        std::vector<h2::ProjDesc> blk;
+        std::vector<int64_t> row_start(s.nnodes + 1);
+        {
+            int64_t fi = 0;
+            for (int l = 0; l <= q; ++l) {
+                const h2::Bsr &B = s.coupling[l];
+                const int64_t f = Structure::first(l);
+                for (int64_t i = 0; i < (int64_t(1) << l); ++i) {
+                    row_start[f + i] = int64_t(blk.size());
+                    for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b, ++fi)
+                        blk.push_back({A.off_blk[fi], 0, f + i, f + B.colidx[b], kr[l], 0});
+                }
+            }
+            row_start[s.nnodes] = int64_t(blk.size());
+        }
+        DeviceArena scratch;
+        const int64_t tree = s.nnodes * int64_t(kmax) * kmax;
+        const int64_t maxlevel = std::max<int64_t>(nleaves, 1);
+        h2::CompLaunch L{};
+        L.basis = static_cast<const double *>(A.basis);
+        L.blocks = static_cast<const double *>(A.blocks);
+        L.off_U = scratch.upload(A.off_U, st);
+        L.off_E = scratch.upload(A.off_E, st);
+        L.leaf_begin = A.d_leaf_begin;
+        L.leaf_end = A.d_leaf_end;
+        L.blk = scratch.upload(blk, st);
+        L.row_start = scratch.upload(row_start, st);
+        L.R = static_cast<double *>(scratch.alloc(tree * 8));
+        L.T = static_cast<double *>(scratch.alloc(tree * 8));
+        L.Enew = static_cast<double *>(scratch.alloc(tree * 8));
+        L.X = static_cast<double *>(scratch.alloc(maxlevel * h2::COMP_XSLOT * 8));
+        L.sigma = static_cast<double *>(scratch.alloc(maxlevel * 64 * 8));
+        L.count = static_cast<int32_t *>(scratch.alloc(maxlevel * 4));
+        L.Unew = static_cast<double *>(scratch.alloc(nleaves * h2::COMP_USLOT * 8));
+        L.first_leaf = lf;
+        L.nleaves = nleaves;
+        L.kmax = kmax;
+        // basis generation, top-down (Sec. 5.2)
+        for (int l = lmin; l <= q; ++l)
+            check_hip(h2::launch_basis_generation(L, l, kr[l], l > lmin ? kr[l - 1] : 0, l > lmin, st),
+                      "basis generation launch");
+        // truncation, bottom-up (Sec. 5.3); a level's rank is the largest kept count
+        std::vector<int32_t> cnt;
+        auto level_rank = [&](int64_t nodes, int bound) {
+            cnt.resize(size_t(nodes));
+            check_hip(hipMemcpyAsync(cnt.data(), L.count, size_t(nodes) * 4, hipMemcpyDeviceToHost, st),
+                      "hipMemcpyAsync");
+            check_hip(hipStreamSynchronize(st), "truncation");
+            int r = 1;
+            for (int32_t c : cnt) r = std::max(r, int(c));
+            return std::min(r, bound);
+        };
+        check_hip(h2::launch_truncate_leaves(L, kr[q], eps, st), "truncation launch");
+        kt[q] = level_rank(nleaves, kr[q]);
+        check_hip(h2::launch_truncate_leaves_apply(L, kr[q], kt[q], st), "truncation launch");
+        for (int l = q; l > lmin; --l) {
+            check_hip(h2::launch_truncate_level(L, l, kr[l], kt[l], kr[l - 1], eps, st), "truncation launch");
+            kt[l - 1] = level_rank(int64_t(1) << (l - 1), std::min(kr[l - 1], 2 * kt[l]));
+            check_hip(h2::launch_truncate_level_apply(L, l, kr[l], kt[l], kr[l - 1], kt[l - 1], st),
+                      "truncation launch");
+        }
+        for (int l = 0; l < lmin; ++l) kt[l] = kt[lmin];
+        // the representation with the new ranks
+        std::unique_ptr<h2_matrix_> B(new h2_matrix_());
+        B->st = s;
+        B->st.lrank = kt;
+        B->st.rank = *std::max_element(kt.begin(), kt.end());
+        B->storage = A.storage;
+        B->basis_kind = A.basis_kind;
+        B->block_kind = A.block_kind;
+        B->vec_f64 = A.vec_f64;
+        int64_t ncoupling = 0;
+        const std::vector<h2::FillDesc> fill = make_layout(*B, ncoupling);
+        std::vector<h2::PlaceDesc> pu, pe;
+        for (int64_t j = 0; j < nleaves; ++j) {
+            const int m = int(s.size(lf + j));
+            pu.push_back({j * h2::COMP_USLOT, B->off_U[j], m, kt[q], 64, 0});
+            pu.push_back({j * h2::COMP_USLOT, B->off_VT[j], kt[q], m, 64, 1});
+        }
+        for (int l = lmin + 1; l <= q; ++l)
+            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
+                pe.push_back({c * kmax * kmax, B->off_E[c], kt[l], kt[l - 1], kmax, 0});
+                pe.push_back({c * kmax * kmax, B->off_FT[c], kt[l - 1], kt[l], kmax, 1});
+            }
+        double *nbasis = static_cast<double *>(B->basis);
+        check_hip(h2::launch_place(L.Unew, nbasis, scratch.upload(pu, st), int64_t(pu.size()), st), "place launch");
+        check_hip(h2::launch_place(L.Enew, nbasis, scratch.upload(pe, st), int64_t(pe.size()), st), "place launch");
+        for (size_t i = 0; i < blk.size(); ++i) {
+            const int l = int(std::floor(std::log2(double(blk[i].row + 1))));
+            blk[i].out = B->off_blk[i];
+            blk[i].kout = kt[l];
+        }
+        check_hip(h2::launch_project(static_cast<const double *>(A.blocks), static_cast<double *>(B->blocks),
+                                     scratch.upload(blk, st), int64_t(blk.size()), L.T, kmax, st),
+                  "projection launch");
+        if (int64_t(fill.size()) > ncoupling) {   // dense blocks: same sizes and order
+            const int64_t from = A.off_blk[size_t(ncoupling)], to = B->off_blk[size_t(ncoupling)];
+            check_hip(hipMemcpyAsync(static_cast<double *>(B->blocks) + to, static_cast<const double *>(A.blocks) + from,
+                                     size_t(A.block_elems - from) * 8, hipMemcpyDeviceToDevice, st),
+                      "hipMemcpyAsync");
+        }
+        check_hip(hipStreamSynchronize(st), "compression");
+        build_lists(*B, fill, ncoupling, st);
+        adopt(A, *B);
+    }
+    if (ranks_out)
+        for (int l = 0; l <= q; ++l) ranks_out[l] = kt[l];
+}
+
+}  // namespace
+
+extern "C" {
+
+h2_status h2_compress(h2_handle A, double eps, int *level_rank, void *stream) {
+    try {
+        if (!A) fail(H2_ERR_INVALID_ARG, "NULL handle");
+        if (A->structure_only) fail(H2_ERR_INVALID_ARG, "structure-only handle");
+        compress(*A, eps, static_cast<hipStream_t>(stream), level_rank);
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return H2_ERR_OOM;
+    } catch (...) {
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
 }
 
 h2_status h2_orthogonalize(h2_handle A, void *stream) {
@@ -1580,6 +1821,8 @@ h2_status h2_batch_create(const h2_handle *mats, int count, int nrhs, void *stre
         }
         B->nrhs = nrhs;
         build_batch(*B, static_cast<hipStream_t>(stream));
+        for (h2_matrix_ *m : B->mats) ++m->batch_refs;
+        B->counted = true;
         *out = B;
         return H2_OK;
     } catch (const Failure &f) {

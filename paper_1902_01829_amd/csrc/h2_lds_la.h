@@ -1,0 +1,234 @@
+// Small dense FP64 factorizations of one workgroup (256 threads) on matrices
+// staged column-major in LDS: the Householder QR of the orthogonalization
+// (Sec. 5.1), the triangular factor of a stacked matrix for the basis
+// generation (Sec. 5.2), and the one-sided Jacobi SVD of the truncation
+// (Sec. 5.3).  Internal to libh2mv; included by its HIP sources only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace h2 {
+namespace lds {
+
+constexpr int QR_MAXM = 128, QR_MAXN = 64;
+// Columns of the LDS matrices are QR_PAD doubles longer than their rows: the
+// threads of a wavefront read 16 columns at once, and a column stride of a
+// multiple of 64 doubles would put them all on the same LDS banks.
+constexpr int QR_PAD = 4;
+
+// Element (r, c) of an R-row FP64 block in 16-byte column groups (2 columns).
+__device__ inline int64_t at2(int R, int r, int c) { return (int64_t(c >> 1) * R + r) * 2 + (c & 1); }
+
+__device__ inline double sum4(double v) {   // over the 4 threads of a column (consecutive lanes)
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    return v;
+}
+
+__device__ inline double sum8(double v) {   // over 8 consecutive lanes
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    return v;
+}
+
+// In-place Householder QR of the M x N matrix A (column-major, ld M + QR_PAD, LDS),
+// M >= N.  R, with its rows' signs flipped so that diag(R) >= 0, goes to T
+// (ld ldt); then A is overwritten by the thin Q (M x N) with the matching
+// columns flipped.  Q is formed in place from the stored reflectors, the last
+// one first (column c of Q is final once reflectors c .. N-1 are applied).
+// Four threads share a column: thread t owns column t / 4 and rows
+// (t % 4) + 4 i, combining partial dot products with lane shuffles.
+__device__ inline void householder_qr(double *A, double *tau, double *scal, double *sgn, int M, int N, double *T,
+                                      int ldt) {
+    const int t = threadIdx.x, col = t >> 2, sub = t & 3, ld = M + QR_PAD;
+    for (int c = 0; c < N; ++c) {
+        if (col == c) {   // norm of A[c:M, c] over the column's four threads, then the reflector
+            double s = 0.0;
+            for (int r = c + sub; r < M; r += 4) s += A[c * ld + r] * A[c * ld + r];
+            s = sum4(s);
+            if (sub == 0) {
+                const double alpha = A[c * ld + c], nrm = sqrt(s);
+                double tc = 0.0, beta = alpha, sc = 0.0;
+                if (nrm > 0.0) {
+                    beta = alpha >= 0.0 ? -nrm : nrm;
+                    tc = (beta - alpha) / beta;
+                    sc = 1.0 / (alpha - beta);
+                }
+                tau[c] = tc;
+                scal[0] = sc;
+                scal[1] = beta;
+            }
+        }
+        __syncthreads();
+        const double sc = scal[0], tc = tau[c];
+        if (col == c) {   // v below the diagonal (v_c = 1 implicit), beta on it
+            for (int r = c + 1 + sub; r < M; r += 4) A[c * ld + r] *= sc;
+            if (sub == 0) A[c * ld + c] = scal[1];
+        }
+        __syncthreads();
+        if (col > c && col < N && tc != 0.0) {   // H_c = I - tau v v^T on the columns to the right
+            double w = sub == 0 ? A[col * ld + c] : 0.0;
+            for (int r = c + 1 + sub; r < M; r += 4) w += A[c * ld + r] * A[col * ld + r];
+            w = sum4(w) * tc;
+            if (sub == 0) A[col * ld + c] -= w;
+            for (int r = c + 1 + sub; r < M; r += 4) A[col * ld + r] -= w * A[c * ld + r];
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < N * N; i += blockDim.x) {   // R with diag(R) >= 0
+        const int c = i / N, r = i - c * N;
+        const double sr = A[r * ld + r] < 0.0 ? -1.0 : 1.0;
+        T[int64_t(c) * ldt + r] = r <= c ? sr * A[c * ld + r] : 0.0;
+    }
+    for (int c = t; c < N; c += blockDim.x) sgn[c] = A[c * ld + c] < 0.0 ? -1.0 : 1.0;
+    __syncthreads();
+    for (int c = N - 1; c >= 0; --c) {
+        const double tc = tau[c];
+        if (col > c && col < N) {   // apply H_c to the finished columns (their rows < col are zero)
+            double w = sub == 0 ? A[col * ld + c] : 0.0;
+            for (int r = c + 1 + sub; r < M; r += 4) w += A[c * ld + r] * A[col * ld + r];
+            w = sum4(w) * tc;
+            if (sub == 0) A[col * ld + c] -= w;
+            for (int r = c + 1 + sub; r < M; r += 4) A[col * ld + r] -= w * A[c * ld + r];
+        }
+        __syncthreads();
+        if (col == c) {   // column c of Q: H_c e_c
+            for (int r = c + 1 + sub; r < M; r += 4) A[c * ld + r] *= -tc;
+            for (int r = sub; r < c; r += 4) A[c * ld + r] = 0.0;
+            if (sub == 0) A[c * ld + c] = 1.0 - tc;
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < M * N; i += blockDim.x) {
+        const int c = i / M, r = i - c * M;
+        A[c * ld + r] *= sgn[c];
+    }
+    __syncthreads();
+}
+
+// Triangular factor of the M x N matrix A (column-major, leading dimension
+// ld, LDS) whose first `top` rows are already upper triangular (top <= N):
+// Householder reflectors without Q, reflector c acting on row c and rows
+// max(top, c + 1) .. M - 1 only (the rows between are zero).  On return rows
+// 0 .. min(M, N) - 1 of A hold R (signs unnormalized) with zeros below its
+// diagonal; rows past min(M, N) are left undefined.  Same thread mapping as
+// householder_qr.
+__device__ inline void stacked_qr_r(double *A, int ld, double *tau, double *scal, int M, int N, int top) {
+    const int t = threadIdx.x, col = t >> 2, sub = t & 3;
+    const int nref = M < N ? M : N;
+    for (int c = 0; c < nref; ++c) {
+        const int r0 = top > c + 1 ? top : c + 1;   // first row of the reflector below row c
+        if (col == c) {
+            double s = 0.0;
+            for (int r = r0 + sub; r < M; r += 4) s += A[c * ld + r] * A[c * ld + r];
+            s = sum4(s);
+            if (sub == 0) {
+                const double alpha = A[c * ld + c], nrm = sqrt(s + alpha * alpha);
+                double tc = 0.0, beta = alpha, sc = 0.0;
+                if (nrm > 0.0 && s > 0.0) {
+                    beta = alpha >= 0.0 ? -nrm : nrm;
+                    tc = (beta - alpha) / beta;
+                    sc = 1.0 / (alpha - beta);
+                }
+                tau[c] = tc;
+                scal[0] = sc;
+                scal[1] = beta;
+            }
+        }
+        __syncthreads();
+        const double sc = scal[0], tc = tau[c];
+        if (col == c) {
+            for (int r = r0 + sub; r < M; r += 4) A[c * ld + r] *= sc;
+            if (sub == 0) A[c * ld + c] = scal[1];
+        }
+        __syncthreads();
+        if (col > c && col < N && tc != 0.0) {
+            double w = sub == 0 ? A[col * ld + c] : 0.0;
+            for (int r = r0 + sub; r < M; r += 4) w += A[c * ld + r] * A[col * ld + r];
+            w = sum4(w) * tc;
+            if (sub == 0) A[col * ld + c] -= w;
+            for (int r = r0 + sub; r < M; r += 4) A[col * ld + r] -= w * A[c * ld + r];
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < nref * N; i += blockDim.x) {   // clear the reflectors under the diagonal of R
+        const int c = i / nref, r = i - c * nref;
+        if (r > c) A[c * ld + r] = 0.0;
+    }
+    __syncthreads();
+}
+
+// One-sided (Hestenes) Jacobi SVD.  G is the L x n matrix (column-major,
+// leading dimension ldg, LDS) whose columns are the rows of the matrix B to
+// decompose (G = B^T); Y (n x n, leading dimension ldy, LDS) starts as the
+// identity.  Plane rotations applied to pairs of columns of G and Y make the
+// columns of G mutually orthogonal, so that G_0 Y = G and B = Y diag(s) V^T
+// with s_j = |column j of G|: the columns of Y are left singular vectors of
+// B, orthonormal to rounding also where s_j = 0.  Pairs are visited in the
+// round-robin order of the cyclic parallel Jacobi method (n/2 disjoint pairs
+// per step, 8 threads per pair); a pair is rotated when |g_p . g_q| exceeds
+// tol |g_p| |g_q|.  Sweeps stop after one without a rotation, or after
+// max_sweeps.  n <= 64, L <= 64 (8 elements per thread per column).
+// Returns the number of sweeps done.
+__device__ inline int jacobi_svd(double *G, int ldg, int L, double *Y, int ldy, int n, double tol, int max_sweeps,
+                                 int *flag) {
+    const int t = threadIdx.x, pr = t >> 3, sub = t & 7;
+    const int m = (n + 1) & ~1;   // even number of positions; an odd n pairs one column with nothing each step
+    int sweeps = 0;
+    for (; sweeps < max_sweeps; ++sweeps) {
+        if (t == 0) *flag = 0;
+        __syncthreads();
+        for (int step = 0; step + 1 < m; ++step) {
+            if (pr < (m >> 1)) {
+                // circle method: position 0 fixed, positions 1 .. m-1 rotate by one each step
+                const int a = pr, b = m - 1 - pr;
+                int p = a == 0 ? 0 : 1 + (a - 1 + step) % (m - 1);
+                int q = 1 + (b - 1 + step) % (m - 1);
+                if (p > q) {
+                    const int x = p;
+                    p = q;
+                    q = x;
+                }
+                if (q < n) {
+                    double al = 0.0, be = 0.0, ga = 0.0;
+                    for (int r = sub; r < L; r += 8) {
+                        const double gp = G[p * ldg + r], gq = G[q * ldg + r];
+                        al += gp * gp;
+                        be += gq * gq;
+                        ga += gp * gq;
+                    }
+                    al = sum8(al);
+                    be = sum8(be);
+                    ga = sum8(ga);
+                    if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+                        const double zeta = (be - al) / (2.0 * ga);
+                        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+                        for (int r = sub; r < L; r += 8) {
+                            const double gp = G[p * ldg + r], gq = G[q * ldg + r];
+                            G[p * ldg + r] = cs * gp - sn * gq;
+                            G[q * ldg + r] = sn * gp + cs * gq;
+                        }
+                        for (int r = sub; r < n; r += 8) {
+                            const double yp = Y[p * ldy + r], yq = Y[q * ldy + r];
+                            Y[p * ldy + r] = cs * yp - sn * yq;
+                            Y[q * ldy + r] = sn * yp + cs * yq;
+                        }
+                        if (sub == 0) *flag = 1;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const int rotated = *flag;
+        __syncthreads();
+        if (!rotated) break;
+    }
+    return sweeps;
+}
+
+}  // namespace lds
+}  // namespace h2

@@ -8,108 +8,22 @@
 // the factorization unique for full-column-rank inputs.
 //
 // One workgroup (256 threads) per factorization or per coupling block; the
-// matrices are staged column-major in LDS (up to 128 x 64 FP64 for Z).  In a
-// factorization four threads share a column: thread t owns column t / 4 and
-// rows (t % 4) + 4 i, and the four combine their partial dot products with
-// lane shuffles.
+// matrices are staged column-major in LDS (up to 128 x 64 FP64 for Z).
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "h2_device.h"
+#include "h2_lds_la.h"
 
 namespace h2 {
 namespace {
 
-constexpr int QR_MAXM = 128, QR_MAXN = 64;
-// Columns of the LDS matrices are QR_PAD doubles longer than their rows: the
-// threads of a wavefront read 16 columns at once, and a column stride of a
-// multiple of 64 doubles would put them all on the same LDS banks.
-constexpr int QR_PAD = 4;
+using namespace lds;
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-// Element (r, c) of an R-row FP64 block in 16-byte column groups (2 columns).
-__device__ inline int64_t at2(int R, int r, int c) { return (int64_t(c >> 1) * R + r) * 2 + (c & 1); }
-
-__device__ inline double sum4(double v) {   // over the 4 threads of a column (consecutive lanes)
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    return v;
-}
-
-// In-place Householder QR of the M x N matrix A (column-major, ld M + QR_PAD, LDS),
-// M >= N.  R, with its rows' signs flipped so that diag(R) >= 0, goes to T
-// (ld ldt); then A is overwritten by the thin Q (M x N) with the matching
-// columns flipped.  Q is formed in place from the stored reflectors, the last
-// one first (column c of Q is final once reflectors c .. N-1 are applied).
-__device__ void householder_qr(double *A, double *tau, double *scal, double *sgn, int M, int N, double *T, int ldt) {
-    const int t = threadIdx.x, col = t >> 2, sub = t & 3, ld = M + QR_PAD;
-    for (int c = 0; c < N; ++c) {
-        if (col == c) {   // norm of A[c:M, c] over the column's four threads, then the reflector
-            double s = 0.0;
-            for (int r = c + sub; r < M; r += 4) s += A[c * ld + r] * A[c * ld + r];
-            s = sum4(s);
-            if (sub == 0) {
-                const double alpha = A[c * ld + c], nrm = sqrt(s);
-                double tc = 0.0, beta = alpha, sc = 0.0;
-                if (nrm > 0.0) {
-                    beta = alpha >= 0.0 ? -nrm : nrm;
-                    tc = (beta - alpha) / beta;
-                    sc = 1.0 / (alpha - beta);
-                }
-                tau[c] = tc;
-                scal[0] = sc;
-                scal[1] = beta;
-            }
-        }
-        __syncthreads();
-        const double sc = scal[0], tc = tau[c];
-        if (col == c) {   // v below the diagonal (v_c = 1 implicit), beta on it
-            for (int r = c + 1 + sub; r < M; r += 4) A[c * ld + r] *= sc;
-            if (sub == 0) A[c * ld + c] = scal[1];
-        }
-        __syncthreads();
-        if (col > c && col < N && tc != 0.0) {   // H_c = I - tau v v^T on the columns to the right
-            double w = sub == 0 ? A[col * ld + c] : 0.0;
-            for (int r = c + 1 + sub; r < M; r += 4) w += A[c * ld + r] * A[col * ld + r];
-            w = sum4(w) * tc;
-            if (sub == 0) A[col * ld + c] -= w;
-            for (int r = c + 1 + sub; r < M; r += 4) A[col * ld + r] -= w * A[c * ld + r];
-        }
-        __syncthreads();
-    }
-    for (int i = t; i < N * N; i += blockDim.x) {   // R with diag(R) >= 0
-        const int c = i / N, r = i - c * N;
-        const double sr = A[r * ld + r] < 0.0 ? -1.0 : 1.0;
-        T[int64_t(c) * ldt + r] = r <= c ? sr * A[c * ld + r] : 0.0;
-    }
-    for (int c = t; c < N; c += blockDim.x) sgn[c] = A[c * ld + c] < 0.0 ? -1.0 : 1.0;
-    __syncthreads();
-    for (int c = N - 1; c >= 0; --c) {
-        const double tc = tau[c];
-        if (col > c && col < N) {   // apply H_c to the finished columns (their rows < col are zero)
-            double w = sub == 0 ? A[col * ld + c] : 0.0;
-            for (int r = c + 1 + sub; r < M; r += 4) w += A[c * ld + r] * A[col * ld + r];
-            w = sum4(w) * tc;
-            if (sub == 0) A[col * ld + c] -= w;
-            for (int r = c + 1 + sub; r < M; r += 4) A[col * ld + r] -= w * A[c * ld + r];
-        }
-        __syncthreads();
-        if (col == c) {   // column c of Q: H_c e_c
-            for (int r = c + 1 + sub; r < M; r += 4) A[c * ld + r] *= -tc;
-            for (int r = sub; r < c; r += 4) A[c * ld + r] = 0.0;
-            if (sub == 0) A[c * ld + c] = 1.0 - tc;
-        }
-        __syncthreads();
-    }
-    for (int i = t; i < M * N; i += blockDim.x) {
-        const int c = i / M, r = i - c * M;
-        A[c * ld + r] *= sgn[c];
-    }
-    __syncthreads();
-}
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 __global__ __launch_bounds__(256) void orth_leaf_kernel(double *basis, const int64_t *off_U, const int64_t *off_VT,
                                                         const int64_t *leaf_begin, const int64_t *leaf_end, int kq,
@@ -195,15 +109,14 @@ __global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const in
     }
 }
 
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-
-// Coupling block b: S <- T_i S T_j^T (k x k, in place), on the FP64 matrix
-// cores (v_mfma_f64_16x16x4_f64: lane l supplies A(l % 16, l / 16) and
-// B(l / 16, l % 16) and holds D(l / 16 + 4 e, l % 16), e = 0..3 -- the rows
-// of a lane's four results are 4 apart, unlike the FP32 16 x 16 forms).  Wavefront w owns
-// output rows 16 w .. 16 w + 15: first W_w = T_i(rows, :) S, staged in the
-// wave's own LDS slice, then S'(rows, :) = W_w T_j^T, staged back in the S
-// buffer and stored as whole 16-byte items.  S is loaded as 16-byte items
+// Coupling block b: S' = T_i S T_j^T with T_i, T_j cut to their first kout
+// rows (kout = k in the orthogonalization), on the FP64 matrix cores
+// (v_mfma_f64_16x16x4_f64: lane l supplies A(l % 16, l / 16) and B(l / 16,
+// l % 16) and holds D(l / 16 + 4 e, l % 16), e = 0..3 -- the rows of a lane's
+// four results are 4 apart, unlike the FP32 16 x 16 forms).  Wavefront w
+// owns output rows 16 w .. 16 w + 15: first W_w = T_i(rows, :) S, staged in
+// the wave's own LDS slice, then S'(rows, :) = W_w T_j^T, staged back in the
+// S buffer and stored as whole 16-byte items.  S is loaded as 16-byte items
 // (two columns of a row), the next block's while this one's products run,
 // and zero-padded to a multiple of 16; T_i and T_j are read as operands from
 // memory (column-major, leading dimension kmax).  Each workgroup takes one
@@ -223,18 +136,19 @@ __device__ inline void proj_load(const double *blocks, const ProjDesc &d, f64x2 
     }
 }
 
-__global__ __launch_bounds__(256) void orth_project_kernel(double *blocks, const ProjDesc *desc, int64_t nblocks,
-                                                           const double *T, int kmax) {
+__global__ __launch_bounds__(256) void project_kernel(const double *in, double *outp, const ProjDesc *desc,
+                                                      int64_t nblocks, const double *T, int kmax) {
     __shared__ double S[64 * PS_LD];     // column-major
     __shared__ double Wl[4][16 * 64];    // per wave: 16 x 64, column-major, ld 16
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
     const int64_t per = (nblocks + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = int64_t(blockIdx.x) * per, b1 = b0 + per < nblocks ? b0 + per : nblocks;
     f64x2 nxt[8];
-    if (b0 < b1) proj_load(blocks, desc[b0], nxt);
+    if (b0 < b1) proj_load(in, desc[b0], nxt);
     for (int64_t b = b0; b < b1; ++b) {
         const ProjDesc d = desc[b];
-        const int k = d.k, kp = (k + 15) & ~15, nt = kp >> 4;
+        const int k = d.k, kp = (k + 15) & ~15, nt = kp >> 4;   // input: k x k, nt column tiles
+        const int ko = d.kout, nto = (ko + 15) >> 4;             // output: ko x ko, nto row tiles
 #pragma unroll
         for (int j = 0; j < 8; ++j) {   // this block's items into LDS
             const int i = threadIdx.x + 256 * j, g = i / kp, r = i - g * kp;
@@ -244,15 +158,15 @@ __global__ __launch_bounds__(256) void orth_project_kernel(double *blocks, const
             }
         }
         __syncthreads();
-        if (b + 1 < b1) proj_load(blocks, desc[b + 1], nxt);   // in flight during the products
+        if (b + 1 < b1) proj_load(in, desc[b + 1], nxt);   // in flight during the products
         const double *Ti = T + d.row * kmax * kmax, *Tj = T + d.col * kmax * kmax;
         const int r0 = 16 * wv;
-        if (wv < nt) {
+        if (wv < nto) {
             double ta[16];   // T_i(r0 + lr, 4 s + lk)
 #pragma unroll
             for (int s4 = 0; s4 < 16; ++s4) {
                 const int kk = 4 * s4 + lk, row = r0 + lr;
-                ta[s4] = (row < k && kk < k) ? Ti[int64_t(kk) * kmax + row] : 0.0;
+                ta[s4] = (row < ko && kk < k) ? Ti[int64_t(kk) * kmax + row] : 0.0;
             }
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) {
@@ -269,21 +183,21 @@ __global__ __launch_bounds__(256) void orth_project_kernel(double *blocks, const
             }
         }
         __syncthreads();   // S is free from here on: S' goes into it
-        if (wv < nt) {
+        if (wv < nto) {
             double tb[2][16];   // T_j(16 ct + lr, 4 s + lk), one column tile ahead
             auto load_tb = [&](int ct, double (&o)[16]) {
                 const int col = 16 * ct + lr;
 #pragma unroll
                 for (int s4 = 0; s4 < 16; ++s4) {
                     const int kk = 4 * s4 + lk;
-                    o[s4] = (col < k && kk < k) ? Tj[int64_t(kk) * kmax + col] : 0.0;
+                    o[s4] = (col < ko && kk < k) ? Tj[int64_t(kk) * kmax + col] : 0.0;
                 }
             };
             load_tb(0, tb[0]);
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) {
-                if (ct >= nt) break;   // unrolled, so the buffer indices are static
-                if (ct + 1 < nt) load_tb(ct + 1, tb[(ct + 1) & 1]);
+                if (ct >= nto) break;   // unrolled, so the buffer indices are static
+                if (ct + 1 < nto) load_tb(ct + 1, tb[(ct + 1) & 1]);
                 const double(&cur)[16] = tb[ct & 1];
                 f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -296,11 +210,11 @@ __global__ __launch_bounds__(256) void orth_project_kernel(double *blocks, const
             }
         }
         __syncthreads();
-        double *blk = blocks + d.off;
-        for (int i = threadIdx.x; i < k * ((k + 1) >> 1); i += 256) {   // S' as 16-byte items
-            const int g = i / k, r = i - g * k;
-            const double hi = 2 * g + 1 < k ? S[(2 * g + 1) * PS_LD + r] : 0.0;
-            *reinterpret_cast<f64x2 *>(blk + (int64_t(g) * k + r) * 2) = f64x2{S[(2 * g) * PS_LD + r], hi};
+        double *blk = outp + d.out;
+        for (int i = threadIdx.x; i < ko * ((ko + 1) >> 1); i += 256) {   // S' as 16-byte items
+            const int g = i / ko, r = i - g * ko;
+            const double hi = 2 * g + 1 < ko ? S[(2 * g + 1) * PS_LD + r] : 0.0;
+            *reinterpret_cast<f64x2 *>(blk + (int64_t(g) * ko + r) * 2) = f64x2{S[(2 * g) * PS_LD + r], hi};
         }
         __syncthreads();   // S is rewritten by the next block
     }
@@ -322,13 +236,16 @@ hipError_t launch_orthogonalize(const OrthLaunch &L, hipStream_t st) {
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (L.nproj > 0) {
-        const int64_t grid = L.nproj < 65536 ? L.nproj : 65536;
-        hipLaunchKernelGGL(orth_project_kernel, dim3(unsigned(grid)), dim3(256), 0, st, L.blocks, L.proj, L.nproj, L.T,
-                           L.kmax);
-        e = hipGetLastError();
-    }
-    return e;
+    return launch_project(L.blocks, L.blocks, L.proj, L.nproj, L.T, L.kmax, st);
+}
+
+hipError_t launch_project(const double *in, double *out, const ProjDesc *desc, int64_t n, const double *T, int kmax,
+                          hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (kmax < 1 || kmax > QR_MAXN) return hipErrorInvalidValue;
+    const int64_t grid = n < 65536 ? n : 65536;
+    hipLaunchKernelGGL(project_kernel, dim3(unsigned(grid)), dim3(256), 0, st, in, out, desc, n, T, kmax);
+    return hipGetLastError();
 }
 
 }  // namespace h2

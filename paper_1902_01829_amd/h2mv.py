@@ -20,7 +20,7 @@ H2_FLAG_STRUCTURE_ONLY = 1
 STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
 
 # Every function declared in include/h2mv.h.
-EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_orthogonalize", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
+EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_orthogonalize", "h2_compress", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
            "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_batch_create", "h2_batch_matmat",
            "h2_batch_tuning", "h2_batch_free", "h2_last_error")
 
@@ -77,6 +77,7 @@ def lib():
         L.h2_build_from_arrays.argtypes = [C.POINTER(h2_arrays), C.c_int, vp, C.POINTER(vp)]
         L.h2_export_arrays.argtypes = [vp, C.POINTER(h2_arrays_out), vp]
         L.h2_orthogonalize.argtypes = [vp, vp]
+        L.h2_compress.argtypes = [vp, C.c_double, vp, vp]
         L.h2_matvec.argtypes = [vp, vp, vp, vp]
         L.h2_matmat.argtypes = [vp, vp, i64, vp, i64, C.c_int, vp]
         L.h2_free.argtypes = [vp]
@@ -191,6 +192,14 @@ def h2_export_arrays(h, stream=0):
 
 def h2_orthogonalize(h, stream=0):
     _check(lib().h2_orthogonalize(C.c_void_p(h), C.c_void_p(stream)))
+
+
+def h2_compress(h, eps, stream=0):
+    """Compresses in place; returns the new rank of every level (numpy int32)."""
+    q = h2_get_info(h).levels_q
+    ranks = np.zeros(q + 1, dtype=np.int32)
+    _check(lib().h2_compress(C.c_void_p(h), C.c_double(eps), C.c_void_p(ranks.ctypes.data), C.c_void_p(stream)))
+    return ranks
 
 
 def h2_matvec(h, x_ptr, y_ptr, stream=0):
@@ -350,6 +359,15 @@ class H2Matrix:
 
     def _stream(self):
         return self._torch.cuda.current_stream().cuda_stream
+
+    def orthogonalize(self):
+        h2_orthogonalize(self.handle, self._stream())
+
+    def compress(self, eps):
+        """Algebraic compression in place (h2_compress); returns the new rank of every level."""
+        ranks = h2_compress(self.handle, eps, self._stream())
+        self.info = h2_get_info(self.handle)
+        return ranks
 
     def matvec(self, x, out=None):
         """x: float64 CUDA tensor (n,), tree order."""
