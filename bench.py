@@ -305,6 +305,79 @@ def orthogonalize_section(reps=3):
             "rel_change_of_Ax": rel, "fp64_vector_peak_TFLOP_per_s": 78.6}
 
 
+def _time_matvec(A, x, y, steps):
+    import torch
+    from paper_1902_01829_amd import h2mv
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        h2mv.h2_matvec(A.handle, x.data_ptr(), y.data_ptr(), stream.cuda_stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h2mv.h2_matvec(A.handle, x.data_ptr(), y.data_ptr(), stream.cuda_stream)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def compress_section(steps=10, reps=2, nrows=256):
+    """Algebraic compression (Sec. 5) on the GPU, FP64: the 2-D 2^20-point
+    workload at the paper's 2-D threshold 1e-7 and the 3-D 2^19-point one at
+    its 3-D threshold 1e-3 (Tables 2 and 3).  Time per call (a fresh matrix
+    each time, orthogonalization included), the new rank of every level, the
+    bytes of the representation before and after, the change of A x, the
+    error against the exact kernel on sampled rows before and after (the
+    columns of Tables 2 and 3), and the time of the product before and after
+    (per-level ranks)."""
+    import torch
+    from oracle import oracle as O
+    from paper_1902_01829_amd import h2mv
+    out = {}
+    for w, eps in ((W.C2, 1e-7), (W.C3, 1e-3)):
+        ms = []
+        for rep in range(reps):
+            A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=0)
+            if rep == 0:
+                info0, perm = A.info, A.perm()
+                x_in = W.rhs(w, 1)
+                x = torch.from_numpy(x_in[perm]).cuda()
+                y = torch.empty_like(x)
+                mv0 = _time_matvec(A, x, y, steps)
+                y0 = y.cpu().numpy()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ranks = A.compress(eps)   # returns when the device work is done
+            ms.append((time.perf_counter() - t0) * 1e3)
+            if rep + 1 < reps:
+                A.close()
+                torch.cuda.empty_cache()
+        info1 = A.info
+        mv1 = _time_matvec(A, x, y, steps)
+        y1 = y.cpu().numpy()
+        A.close()
+        del x, y
+        torch.cuda.empty_cache()
+        rows = np.sort(np.random.Generator(np.random.PCG64(17)).choice(w.n, size=nrows, replace=False))
+        exact = O.kernel_matvec(W.points(w), x_in, w.corr_len, rows=perm[rows])
+        err = lambda yy: float(np.linalg.norm(yy[rows] - exact) / np.linalg.norm(exact))
+        lowrank = lambda i: i.bytes_coupling + i.bytes_leaf_bases + i.bytes_transfers
+        change = float(np.linalg.norm(y1 - y0) / np.linalg.norm(y0))
+        best = min(ms)
+        log(f"compress {w.name} eps {eps:g}: {best:.1f} ms (of {[round(v, 1) for v in ms]}), ranks "
+            f"{[int(r) for r in ranks]}, low-rank bytes {lowrank(info0) / 1e9:.2f} -> {lowrank(info1) / 1e9:.2f} GB, "
+            f"A x change {change:.1e}, matvec {mv0:.3f} -> {mv1:.3f} ms")
+        out[w.name] = {
+            "eps": eps, "ms": round(best, 2), "ms_all": [round(v, 2) for v in ms],
+            "level_rank_before": info0.rank, "level_rank_after": [int(r) for r in ranks],
+            "lowrank_bytes_before": int(lowrank(info0)), "lowrank_bytes_after": int(lowrank(info1)),
+            "dense_bytes": int(info0.bytes_dense),
+            "rel_change_of_Ax": change,
+            "rel_err_vs_exact_kernel_before": err(y0), "rel_err_vs_exact_kernel_after": err(y1),
+            "error_sample": f"{nrows} seeded rows against the dense kernel (brute force)",
+            "matvec_ms_before": round(mv0, 4), "matvec_ms_after": round(mv1, 4),
+            "matvec_speedup": round(mv0 / mv1, 3)}
+    return out
+
+
 def storage_modes(steps, warmup, nleaves=16):
     """The 3-D workload (2^19 points, rank 64) in FP64, FP32 and BF16 storage."""
     w = W.C3
@@ -488,7 +561,8 @@ def main():
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the storage-mode, many-right-hand-side and batch sections")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--only", choices=["small", "modes", "matmat", "batch", "orthogonalize"], default=None,
+    ap.add_argument("--only", choices=["small", "modes", "matmat", "batch", "orthogonalize", "compress"],
+                    default=None,
                     help="run one section alone and print its JSON (for profiling runs); "
                          "the headline line is not printed")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
@@ -521,6 +595,8 @@ def main():
             out = matmat_modes(args.steps, args.warmup, None)
         elif args.only == "orthogonalize":
             out = orthogonalize_section()
+        elif args.only == "compress":
+            out = compress_section()
         else:
             out = batch_modes(args.steps, args.warmup)
         print(json.dumps({"section": args.only, **out}), flush=True)
@@ -570,6 +646,7 @@ def main():
             result["matmat"] = matmat_modes(max(3, args.steps // 4), 1, fp64_ms)
         result["batch"] = batch_modes(max(3, args.steps // 2), 1)
         result["orthogonalize"] = orthogonalize_section()
+        result["compress"] = compress_section()
     print(json.dumps(result), flush=True)
 
 

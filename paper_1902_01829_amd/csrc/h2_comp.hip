@@ -5,7 +5,7 @@
 //     Sbar_i = [R_i+ E_i^T; S_ij1^T; ...; S_ijb^T]
 // (i+ its parent, S_ij the coupling blocks of its block row) and keeps the
 // triangular factor R_i of its QR factorization.  The stack is not formed
-// whole: a workgroup holds at most 128 x 64 in LDS, so blocks are appended
+// whole: a workgroup holds 128 x 64 in registers, so blocks are appended
 // under the current factor and folded into it with a QR of the stack
 // whenever the next block would not fit (the same R up to row signs, which
 // the truncation does not see: it uses R only through R^T R).
@@ -21,8 +21,9 @@
 // singular values at least eps times its largest; the host takes the
 // largest count of a level as its new rank.
 //
-// One workgroup (256 threads) per node; every matrix is staged column-major
-// in LDS.
+// One workgroup per node: 512 threads with the stack in registers for the
+// basis generation, 256 threads with every matrix staged column-major in LDS
+// for the truncation.
 
 #include <hip/hip_runtime.h>
 
@@ -38,55 +39,136 @@ using namespace lds;
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-constexpr int GEN_LD = QR_MAXM + QR_PAD;   // LDS stack: 128 rows (+ pad) x 64 columns
+constexpr int GEN_LD = QR_MAXM + QR_PAD;   // LDS matrices of up to 128 rows (+ pad) x 64 columns
 constexpr int SQ_LD = 64 + QR_PAD;         // LDS square matrices: 64 x 64 (+ pad)
 constexpr double JACOBI_TOL = 64 * 2.220446049250313e-16;
 constexpr int JACOBI_SWEEPS = 30;
 
 __device__ inline int64_t level_first(int l) { return (int64_t(1) << l) - 1; }
 
-__global__ __launch_bounds__(256) void basis_generation_kernel(CompLaunch L, int level, int k, int kp,
-                                                               int parent_term) {
-    __shared__ double A[GEN_LD * QR_MAXN], tau[QR_MAXN], scal[2];
-    const int t = threadIdx.x;
+// Basis generation of one node, a 256 x k stack held in registers of a
+// 1024-thread workgroup: wave w owns columns 4 w .. 4 w + 3, lanes
+// 16 h .. 16 h + 15 of it column 4 w + h, and lane j = l % 16 of those rows
+// j, j + 16, ..., j + 240 (a[i] = row j + 16 i; consecutive lanes touch
+// consecutive LDS words).  Rows 0 .. 63 (i < 4) hold the current triangular
+// factor (first: the parent term), rows 64 .. 255 the coupling blocks
+// appended since (as many k-row blocks as fit).  A fold is a Householder QR
+// without Q over all 256 rows: per column c the sixteen lanes of column c
+// form the reflector and publish it in LDS (double buffered, so one barrier
+// per column), and every lane of a later column applies it to its 16 rows;
+// entries below the diagonal are set to zero as they are eliminated, so
+// after a fold rows k .. 255 are zero.  The lanes of a column are one DPP
+// row, so their sums are four DPP moves.  Register arrays are indexed
+// statically only (the diagonal row is selected by comparison).
+constexpr int BG_THREADS = 1024, BG_ROWS = 16, BG_STACK = 256, BG_TLD = 65;
+
+__device__ inline void fold_r(double (&a)[BG_ROWS], int k, int col, int j, double (*vbuf)[BG_STACK],
+                              double *tbuf) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = 0; c < k; ++c) {
+        double *v = vbuf[c & 1];
+        if (wv == (c >> 2) && (lane >> 4) == (c & 3)) {   // the sixteen lanes of column c
+            double sq = 0.0, al = 0.0;
+#pragma unroll
+            for (int i = 0; i < BG_ROWS; ++i) {
+                const int r = j + 16 * i;
+                sq += r > c ? a[i] * a[i] : 0.0;
+                al += r == c ? a[i] : 0.0;
+            }
+            sq = dpp_sum16(sq);
+            al = dpp_sum16(al);
+            const double nrm = sqrt(sq + al * al);
+            double beta = al, tc = 0.0, sc = 0.0;
+            if (sq > 0.0) {
+                beta = al >= 0.0 ? -nrm : nrm;
+                tc = (beta - al) / beta;
+                sc = 1.0 / (al - beta);
+            }
+#pragma unroll
+            for (int i = 0; i < BG_ROWS; ++i) {
+                const int r = j + 16 * i;
+                v[r] = r > c ? a[i] * sc : (r == c ? 1.0 : 0.0);
+                a[i] = r > c ? 0.0 : (r == c ? beta : a[i]);
+            }
+            if (j == 0) tbuf[c & 1] = tc;
+        }
+        __syncthreads();
+        const double tc = tbuf[c & 1];
+        if (col > c && col < k && tc != 0.0) {   // uniform over the sixteen lanes of a column
+            double d = 0.0;
+#pragma unroll
+            for (int i = 0; i < BG_ROWS; ++i) d += v[j + 16 * i] * a[i];
+            d = dpp_sum16(d) * tc;
+#pragma unroll
+            for (int i = 0; i < BG_ROWS; ++i) a[i] -= d * v[j + 16 * i];
+        }
+    }
+    __syncthreads();   // the last reflector's readers are done before vbuf is reused
+}
+
+__global__ __launch_bounds__(BG_THREADS) void basis_generation_kernel(CompLaunch L, int level, int k, int kp,
+                                                                      int parent_term) {
+    __shared__ double vbuf[2][BG_STACK], tbuf[2];
+    __shared__ double tile[64 * BG_TLD];   // staging of R_parent (column-major) and of each coupling block (row-major)
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int col = 4 * wv + (lane >> 4), j = lane & 15;
     const int64_t node = level_first(level) + blockIdx.x;
-    int M = 0, top = 0;
-    if (parent_term) {   // P = R_parent E_i^T (kp x k); R_parent is upper triangular
-        const double *Rp = L.R + ((node - 1) >> 1) * L.kmax * L.kmax;
+    double a[BG_ROWS];
+#pragma unroll
+    for (int i = 0; i < BG_ROWS; ++i) a[i] = 0.0;
+    bool dirty = false;   // rows hold entries not yet folded into a triangular factor
+    if (parent_term) {    // rows 0 .. kp-1: P = R_parent E_i^T (kp x k), R_parent upper triangular
+        const double *Rp = L.R + ((node - 1) >> 1) * L.kmax * L.kmax;   // zero below its diagonal
+        for (int i = t; i < 64 * kp; i += BG_THREADS) {
+            const int c = i >> 6, r = i & 63;
+            tile[c * BG_TLD + r] = r < kp ? Rp[int64_t(c) * L.kmax + r] : 0.0;
+        }
+        __syncthreads();
         const double *E = L.basis + L.off_E[node];   // k x kp
-        for (int i = t; i < kp * k; i += 256) {
-            const int c = i / kp, r = i - c * kp;
-            double acc = 0.0;
-            for (int u = r; u < kp; ++u) acc += Rp[int64_t(u) * L.kmax + r] * E[at2(k, c, u)];
-            A[c * GEN_LD + r] = acc;
-        }
-        M = kp;
+        if (col < k)
+            for (int u = 0; u < kp; ++u) {
+                const double e = E[at2(k, col, u)];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] += tile[u * BG_TLD + j + 16 * i] * e;
+            }
+        dirty = true;
     }
-    const int64_t b0 = L.row_start[node], b1 = L.row_start[node + 1];
+    const int64_t b1 = L.row_start[node + 1];
     const int ng = (k + 1) >> 1;
-    for (int64_t b = b0; b < b1; ++b) {
-        if (M + k > QR_MAXM) {   // fold the stack into its triangular factor
+    int64_t b = L.row_start[node];
+    for (;;) {   // append as many blocks as fit under the factor, then fold (one call site)
+        for (int bot = 0; b < b1 && bot + k <= BG_STACK - 64; ++b, bot += k) {
+            __syncthreads();   // the tile's previous contents are consumed
+            const double *S = L.blocks + L.blk[b].off;   // S_b(r, 2g .. 2g+1) is one 16-byte item
+            for (int i = t; i < ng * k; i += BG_THREADS) {
+                const int g = i / k, r = i - g * k;
+                const f64x2 v = *reinterpret_cast<const f64x2 *>(S + (int64_t(g) * k + r) * 2);
+                tile[r * BG_TLD + 2 * g] = v.x;
+                tile[r * BG_TLD + 2 * g + 1] = v.y;   // column k when k is odd: padding, never read
+            }
             __syncthreads();
-            stacked_qr_r(A, GEN_LD, tau, scal, M, k, top);
-            M = top = M < k ? M : k;
+            // S_b^T into rows 64 + bot .. 64 + bot + k - 1: row rr of S_b^T, column col is S_b(col, rr)
+            if (col < k) {
+#pragma unroll
+                for (int i = 4; i < BG_ROWS; ++i) {
+                    const int rr = j + 16 * i - 64 - bot;
+                    if (rr >= 0 && rr < k) a[i] = tile[col * BG_TLD + rr];
+                }
+            }
+            dirty = true;
         }
-        // S_b^T below: S_b(c, 2g .. 2g+1) is one 16-byte item, rows 2g .. 2g+1 of S_b^T
-        const double *S = L.blocks + L.blk[b].off;
-        for (int i = t; i < ng * k; i += 256) {
-            const int g = i / k, c = i - g * k;
-            const f64x2 v = *reinterpret_cast<const f64x2 *>(S + (int64_t(g) * k + c) * 2);
-            A[c * GEN_LD + M + 2 * g] = v.x;
-            if (2 * g + 1 < k) A[c * GEN_LD + M + 2 * g + 1] = v.y;
-        }
-        M += k;
+        if (!dirty) break;
+        fold_r(a, k, col, j, vbuf, tbuf);
+        dirty = false;
+        if (b >= b1) break;
     }
-    __syncthreads();
-    if (M > top) stacked_qr_r(A, GEN_LD, tau, scal, M, k, top);
-    const int nr = M < k ? M : k;
-    double *R = L.R + node * L.kmax * L.kmax;
-    for (int i = t; i < k * k; i += 256) {
-        const int c = i / k, r = i - c * k;
-        R[int64_t(c) * L.kmax + r] = (r < nr && r <= c) ? A[c * GEN_LD + r] : 0.0;
+    double *R = L.R + node * L.kmax * L.kmax;   // rows 0 .. k-1 (zero below the diagonal)
+    if (col < k) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = j + 16 * i;
+            if (r < k) R[int64_t(col) * L.kmax + r] = a[i];
+        }
     }
 }
 
@@ -133,7 +215,7 @@ __global__ __launch_bounds__(256) void truncate_leaves_kernel(CompLaunch L, int 
         Y[c * SQ_LD + r] = r == c ? 1.0 : 0.0;
     }
     __syncthreads();
-    jacobi_svd(G, SQ_LD, k, Y, SQ_LD, k, JACOBI_TOL, JACOBI_SWEEPS, &flag);
+    jacobi_svd(G, SQ_LD, k, Y, SQ_LD, k, JACOBI_TOL, JACOBI_SWEEPS, &flag, s);
     sort_and_count(G, SQ_LD, k, k, eps, s, rank, L.sigma + j * 64, L.count + j);
     double *X = L.X + j * COMP_XSLOT;
     for (int i = t; i < k * k; i += 256) {
@@ -259,7 +341,7 @@ __global__ __launch_bounds__(256) void truncate_level_kernel(CompLaunch L, int l
         }
     }
     __syncthreads();
-    jacobi_svd(G, SQ_LD, Lrows, Y, SQ_LD, n, JACOBI_TOL, JACOBI_SWEEPS, &flag);
+    jacobi_svd(G, SQ_LD, Lrows, Y, SQ_LD, n, JACOBI_TOL, JACOBI_SWEEPS, &flag, s);
     sort_and_count(G, SQ_LD, Lrows, n, eps, s, rank, L.sigma + i0 * 64, L.count + i0);
     double *X = L.X + i0 * COMP_XSLOT;   // left singular vectors of W: M x n
     if (tall) {
@@ -320,8 +402,8 @@ __global__ __launch_bounds__(256) void place_kernel(const double *src, double *d
 
 hipError_t launch_basis_generation(const CompLaunch &L, int level, int k, int kp, bool parent_term, hipStream_t st) {
     if (k < 1 || k > QR_MAXN || kp > QR_MAXN || (parent_term && kp < 1)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(basis_generation_kernel, dim3(unsigned(int64_t(1) << level)), dim3(256), 0, st, L, level, k,
-                       kp, parent_term ? 1 : 0);
+    hipLaunchKernelGGL(basis_generation_kernel, dim3(unsigned(int64_t(1) << level)), dim3(BG_THREADS), 0, st, L,
+                       level, k, kp, parent_term ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -1,8 +1,7 @@
 // Small dense FP64 factorizations of one workgroup (256 threads) on matrices
 // staged column-major in LDS: the Householder QR of the orthogonalization
-// (Sec. 5.1), the triangular factor of a stacked matrix for the basis
-// generation (Sec. 5.2), and the one-sided Jacobi SVD of the truncation
-// (Sec. 5.3).  Internal to libh2mv; included by its HIP sources only.
+// (Sec. 5.1) and the one-sided Jacobi SVD of the truncation (Sec. 5.3).
+// Internal to libh2mv; included by its HIP sources only.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,13 +23,6 @@ __device__ inline int64_t at2(int R, int r, int c) { return (int64_t(c >> 1) * R
 __device__ inline double sum4(double v) {   // over the 4 threads of a column (consecutive lanes)
     v += __shfl_xor(v, 1);
     v += __shfl_xor(v, 2);
-    return v;
-}
-
-__device__ inline double sum8(double v) {   // over 8 consecutive lanes
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
     return v;
 }
 
@@ -109,56 +101,25 @@ __device__ inline void householder_qr(double *A, double *tau, double *scal, doub
     __syncthreads();
 }
 
-// Triangular factor of the M x N matrix A (column-major, leading dimension
-// ld, LDS) whose first `top` rows are already upper triangular (top <= N):
-// Householder reflectors without Q, reflector c acting on row c and rows
-// max(top, c + 1) .. M - 1 only (the rows between are zero).  On return rows
-// 0 .. min(M, N) - 1 of A hold R (signs unnormalized) with zeros below its
-// diagonal; rows past min(M, N) are left undefined.  Same thread mapping as
-// householder_qr.
-__device__ inline void stacked_qr_r(double *A, int ld, double *tau, double *scal, int M, int N, int top) {
-    const int t = threadIdx.x, col = t >> 2, sub = t & 3;
-    const int nref = M < N ? M : N;
-    for (int c = 0; c < nref; ++c) {
-        const int r0 = top > c + 1 ? top : c + 1;   // first row of the reflector below row c
-        if (col == c) {
-            double s = 0.0;
-            for (int r = r0 + sub; r < M; r += 4) s += A[c * ld + r] * A[c * ld + r];
-            s = sum4(s);
-            if (sub == 0) {
-                const double alpha = A[c * ld + c], nrm = sqrt(s + alpha * alpha);
-                double tc = 0.0, beta = alpha, sc = 0.0;
-                if (nrm > 0.0 && s > 0.0) {
-                    beta = alpha >= 0.0 ? -nrm : nrm;
-                    tc = (beta - alpha) / beta;
-                    sc = 1.0 / (alpha - beta);
-                }
-                tau[c] = tc;
-                scal[0] = sc;
-                scal[1] = beta;
-            }
-        }
-        __syncthreads();
-        const double sc = scal[0], tc = tau[c];
-        if (col == c) {
-            for (int r = r0 + sub; r < M; r += 4) A[c * ld + r] *= sc;
-            if (sub == 0) A[c * ld + c] = scal[1];
-        }
-        __syncthreads();
-        if (col > c && col < N && tc != 0.0) {
-            double w = sub == 0 ? A[col * ld + c] : 0.0;
-            for (int r = r0 + sub; r < M; r += 4) w += A[c * ld + r] * A[col * ld + r];
-            w = sum4(w) * tc;
-            if (sub == 0) A[col * ld + c] -= w;
-            for (int r = r0 + sub; r < M; r += 4) A[col * ld + r] -= w * A[c * ld + r];
-        }
-        __syncthreads();
-    }
-    for (int i = t; i < nref * N; i += blockDim.x) {   // clear the reflectors under the diagonal of R
-        const int c = i / nref, r = i - c * nref;
-        if (r > c) A[c * ld + r] = 0.0;
-    }
-    __syncthreads();
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {   // a DPP move of a double (two 32-bit halves)
+    const int64_t b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((int64_t(hi) << 32) | uint32_t(lo));
+}
+
+__device__ inline double dpp_sum8(double v) {   // over lanes 8 j .. 8 j + 7 (all active)
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp_f64<0x141>(v);   // row_half_mirror: i <-> 7 - i within 8, the other quad
+    return v;
+}
+
+__device__ inline double dpp_sum16(double v) {   // over the 16 lanes of a DPP row (all active)
+    v = dpp_sum8(v);
+    v += dpp_f64<0x140>(v);   // row_mirror: i <-> 15 - i, the other half
+    return v;
 }
 
 // One-sided (Hestenes) Jacobi SVD.  G is the L x n matrix (column-major,
@@ -169,14 +130,26 @@ __device__ inline void stacked_qr_r(double *A, int ld, double *tau, double *scal
 // with s_j = |column j of G|: the columns of Y are left singular vectors of
 // B, orthonormal to rounding also where s_j = 0.  Pairs are visited in the
 // round-robin order of the cyclic parallel Jacobi method (n/2 disjoint pairs
-// per step, 8 threads per pair); a pair is rotated when |g_p . g_q| exceeds
-// tol |g_p| |g_q|.  Sweeps stop after one without a rotation, or after
-// max_sweeps.  n <= 64, L <= 64 (8 elements per thread per column).
-// Returns the number of sweeps done.
+// per step, 8 adjacent threads per pair, sums by DPP); a pair is rotated when
+// |g_p . g_q| exceeds tol |g_p| |g_q| and neither column is negligible, i.e.
+// of norm at most 1e-15 |G|_F (rotations are norm preserving, so |G|_F is
+// fixed): such columns are rounding noise, and turning them changes a column
+// of norm s by at most 1e-15 |G|_F / s in direction.  Sweeps stop after one
+// without a rotation, or after max_sweeps.  n <= 64, L <= 64.  red is 64
+// doubles of LDS scratch.  Returns the number of sweeps done.
 __device__ inline int jacobi_svd(double *G, int ldg, int L, double *Y, int ldy, int n, double tol, int max_sweeps,
-                                 int *flag) {
+                                 int *flag, double *red) {
     const int t = threadIdx.x, pr = t >> 3, sub = t & 7;
     const int m = (n + 1) & ~1;   // even number of positions; an odd n pairs one column with nothing each step
+    if (t < n) {
+        double a = 0.0;
+        for (int r = 0; r < L; ++r) a += G[t * ldg + r] * G[t * ldg + r];
+        red[t] = a;
+    }
+    __syncthreads();
+    double f2 = 0.0;
+    for (int i = 0; i < n; ++i) f2 += red[i];
+    const double negligible = 1e-30 * f2;
     int sweeps = 0;
     for (; sweeps < max_sweeps; ++sweeps) {
         if (t == 0) *flag = 0;
@@ -200,10 +173,10 @@ __device__ inline int jacobi_svd(double *G, int ldg, int L, double *Y, int ldy, 
                         be += gq * gq;
                         ga += gp * gq;
                     }
-                    al = sum8(al);
-                    be = sum8(be);
-                    ga = sum8(ga);
-                    if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+                    al = dpp_sum8(al);
+                    be = dpp_sum8(be);
+                    ga = dpp_sum8(ga);
+                    if (ga != 0.0 && al > negligible && be > negligible && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
                         const double zeta = (be - al) / (2.0 * ga);
                         const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                         const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
