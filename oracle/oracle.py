@@ -540,3 +540,54 @@ def compress_arrays(arr, eps):
     Ec = np.concatenate(E) if E else np.zeros(0)
     out.update(level_rank=np.array(kt, dtype=np.int32), U=Uc, V=Uc, E=Ec, F=Ec, S=S)
     return out, {"rank": kt, "sigma": sigma, "count": count, "R": R, "T": T}
+
+
+def transpose_arrays(arr):
+    """The arrays of A^T for an H^2 matrix A = sum_l U S^l V^T + D given by
+    its arrays (Sec. 2.2): the row and column trees exchange roles (U <-> V,
+    E <-> F), every coupling block S_ij of level l becomes block (j, i) of
+    A^T with value S_ij^T, and every dense block D_ij becomes block (j, i)
+    with value D_ij^T.  Block rows of A^T list their columns in increasing
+    order."""
+    q = int(arr["q"])
+    kr = [int(k) for k in arr["level_rank"]]
+    b, e = arr["begin"], arr["end"]
+    lf = (1 << q) - 1
+
+    def transpose_bsr(nrows, rp, ci, blocks):
+        # blocks[t]: the t-th block as a dense matrix; returns rowptr, colidx, blocks of the transpose
+        rows = [[] for _ in range(nrows)]
+        for i in range(nrows):
+            for t in range(int(rp[i]), int(rp[i + 1])):
+                rows[int(ci[t])].append((i, blocks[t].T))
+        nrp = np.zeros(nrows + 1, dtype=np.int32)
+        nci, nbl = [], []
+        for jrow in range(nrows):
+            for i, blk in sorted(rows[jrow], key=lambda z: z[0]):
+                nci.append(i)
+                nbl.append(blk)
+            nrp[jrow + 1] = len(nci)
+        return nrp, np.array(nci, dtype=np.int32), nbl
+
+    S_rowptr, S_colidx, S = [], [], []
+    for l in range(q + 1):
+        k = kr[l]
+        rp, ci, Sl = arr["S_rowptr"][l], arr["S_colidx"][l], arr["S"][l]
+        blocks = [Sl[t * k * k:(t + 1) * k * k].reshape(k, k).T for t in range(len(ci))]
+        nrp, nci, nbl = transpose_bsr(1 << l, rp, ci, blocks)
+        S_rowptr.append(nrp)
+        S_colidx.append(nci)
+        S.append(np.concatenate([m.ravel(order="F") for m in nbl]) if nbl else np.zeros(0))
+    drp, dci = arr["D_rowptr"], arr["D_colidx"]
+    dblocks, off = [], 0
+    for i in range(1 << q):
+        for t in range(int(drp[i]), int(drp[i + 1])):
+            ms, mt = int(e[lf + i] - b[lf + i]), int(e[lf + int(dci[t])] - b[lf + int(dci[t])])
+            dblocks.append(arr["D"][off:off + ms * mt].reshape(mt, ms).T)
+            off += ms * mt
+    nrp, nci, nbl = transpose_bsr(1 << q, drp, dci, dblocks)
+    out = dict(arr)
+    out.update(U=arr["V"], V=arr["U"], E=arr["F"], F=arr["E"], S_rowptr=S_rowptr, S_colidx=S_colidx, S=S,
+               D_rowptr=nrp, D_colidx=nci,
+               D=np.concatenate([m.ravel(order="F") for m in nbl]) if nbl else np.zeros(0))
+    return out

@@ -739,3 +739,27 @@ def test_compression_to_rank_one(oracle_mod):
         assert abs((new[v].T @ new[v]).item() - 1.0) <= 1e-12
     x = _x(800, 44)
     assert np.all(np.isfinite(oracle_mod.arrays_matvec(out, x)))
+
+
+# ---- the transposed matrix (the arrays of A^T)
+
+@pytest.mark.parametrize("n,d,m,seed", [(600, 2, 16, 71), (700, 3, 16, 72)])
+def test_transposed_arrays_are_the_transpose(oracle_mod, n, d, m, seed):
+    """Random, non-symmetric values (U != V, E != F, S_ji != S_ij^T): the
+    dense expansion of the transposed arrays is the transpose of the dense
+    expansion (brute force), and transposing twice gives the arrays back."""
+    arr = _random_arrays(oracle_mod, n, d, m, seed, 200 + seed)
+    assert not np.array_equal(arr["U"], arr["V"])
+    A = _dense_from_arrays(arr)
+    At = _dense_from_arrays(oracle_mod.transpose_arrays(arr))
+    assert np.abs(At - A.T).max() <= 1e-13 * np.abs(A).max()
+    x = _x(n, 73)
+    assert np.linalg.norm(oracle_mod.arrays_matvec(oracle_mod.transpose_arrays(arr), x) - A.T @ x) \
+        <= 1e-12 * np.linalg.norm(A.T @ x)
+    back = oracle_mod.transpose_arrays(oracle_mod.transpose_arrays(arr))
+    for key in ("U", "V", "E", "F", "D"):
+        assert np.array_equal(back[key], arr[key])
+    for l in range(int(arr["q"]) + 1):
+        assert np.array_equal(back["S_rowptr"][l], arr["S_rowptr"][l])
+        assert np.array_equal(back["S_colidx"][l], arr["S_colidx"][l])
+        assert np.array_equal(back["S"][l], arr["S"][l])
