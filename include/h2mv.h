@@ -202,6 +202,19 @@ h2_status h2_export_arrays(h2_handle A, const h2_arrays_out *out, void *stream);
  * the leaf rank, or k_(l-1) > 2 k_l; DEVICE. */
 h2_status h2_orthogonalize(h2_handle A, void *stream);
 
+/* The transposed matrix A^T as a new handle (Sec. 2.2: A^T = sum over levels of
+ * V S^T U^T plus D^T): the same tree, ranks and permutation; the row and
+ * column trees exchange roles (U' = V, V' = U, E' = F, F' = E); block (i, j)
+ * of every level's block-sparse rows and of the dense part becomes block
+ * (j, i) with the transposed value.  Built on the device from A's stored
+ * values (no rounding: BF16 codes and scales are copied), with A's storage;
+ * A is unchanged and the two handles are independent (each is freed with
+ * h2_free).  For the symmetric matrices of h2_build_from_points, A^T = A.
+ *  out  receives the new handle (NULL on error).
+ * Errors: INVALID_ARG for NULL arguments or a structure-only handle; OOM;
+ * DEVICE. */
+h2_status h2_transpose(h2_handle A, void *stream, h2_handle *out);
+
 /* Algebraic compression (Sec. 5), in place: orthogonalization as
  * h2_orthogonalize; basis generation (Sec. 5.2): for every node i of the
  * levels with coupling blocks, top-down, R_i = the triangular factor of the

@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <new>
 #include <mutex>
@@ -1452,6 +1453,101 @@ void orthogonalize(h2_matrix_ &A, hipStream_t st) {
     check_hip(hipStreamSynchronize(st), "orthogonalization");
 }
 
+// The transposed matrix as a new handle: A^T = sum over levels of V S^T U^T
+// plus D^T (Sec. 2.2), i.e. the row and column trees exchange roles.  The
+// tree, ranks and permutation are A's; every level's block-sparse rows are
+// transposed (block (i, j) of A becomes block (j, i), rows listing their
+// columns in increasing order); blocks, bases and transfers are copied
+// transposed on the device (U'_j = V_j, V'_j = U_j, E'_c = F_c, F'_c = E_c),
+// values unchanged (BF16 codes and scales included).
+h2_matrix_ *transpose_matrix(h2_matrix_ &A, hipStream_t st) {
+    const Structure &s = A.st;
+    const int q = s.q;
+    const std::vector<int> &kl = s.lrank;
+    const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
+    std::unique_ptr<h2_matrix_> B(new h2_matrix_());
+    B->st = s;
+    B->storage = A.storage;
+    B->basis_kind = A.basis_kind;
+    B->block_kind = A.block_kind;
+    B->vec_f64 = A.vec_f64;
+    B->symmetric = A.symmetric;
+    // transposed rows; for block t of B (fill order): the block of A it copies and that block's size
+    std::vector<int64_t> src_fill;
+    std::vector<int32_t> src_R, src_C;
+    auto transpose_bsr = [&](const h2::Bsr &in, int64_t rows, int64_t fill0, h2::Bsr &out,
+                             const std::function<void(int64_t, int64_t)> &dims) {
+        out.rowptr.assign(size_t(rows + 1), 0);
+        for (int32_t c : in.colidx) ++out.rowptr[size_t(c) + 1];
+        for (int64_t i = 0; i < rows; ++i) out.rowptr[i + 1] += out.rowptr[i];
+        out.colidx.assign(in.colidx.size(), 0);
+        std::vector<int32_t> next(out.rowptr.begin(), out.rowptr.end() - 1);
+        std::vector<int64_t> from(in.colidx.size());
+        for (int64_t i = 0; i < rows; ++i)
+            for (int32_t t = in.rowptr[i]; t < in.rowptr[i + 1]; ++t) {
+                const int32_t pos = next[in.colidx[t]]++;
+                out.colidx[pos] = int32_t(i);
+                from[pos] = t;
+            }
+        for (size_t pos = 0; pos < from.size(); ++pos) {
+            src_fill.push_back(fill0 + from[pos]);
+            dims(from[pos], int64_t(pos));
+        }
+    };
+    int64_t fill0 = 0;
+    for (int l = 0; l <= q; ++l) {
+        transpose_bsr(s.coupling[l], int64_t(1) << l, fill0, B->st.coupling[l], [&](int64_t, int64_t) {
+            src_R.push_back(kl[l]);
+            src_C.push_back(kl[l]);
+        });
+        fill0 += s.coupling[l].blocks();
+    }
+    {
+        // dense block t of A: rows of leaf i (its BSR row), columns of leaf colidx[t]
+        std::vector<int32_t> row_of(s.dense.colidx.size());
+        for (int64_t i = 0; i < nleaves; ++i)
+            for (int32_t t = s.dense.rowptr[i]; t < s.dense.rowptr[i + 1]; ++t) row_of[t] = int32_t(i);
+        transpose_bsr(s.dense, nleaves, fill0, B->st.dense, [&](int64_t t, int64_t) {
+            src_R.push_back(int32_t(s.size(lf + row_of[t])));
+            src_C.push_back(int32_t(s.size(lf + s.dense.colidx[t])));
+        });
+    }
+    int64_t ncoupling = 0;
+    const std::vector<h2::FillDesc> fill = make_layout(*B, ncoupling);
+    DeviceArena scratch;
+    std::vector<h2::TransDesc> tb(fill.size()), tbas;
+    for (size_t fb = 0; fb < fill.size(); ++fb)
+        tb[fb] = {A.off_blk[size_t(src_fill[fb])], B->off_blk[fb], src_R[fb], src_C[fb]};
+    if (s.lmin <= q) {
+        for (int64_t j = 0; j < nleaves; ++j) {
+            const int m = int(s.size(lf + j));
+            tbas.push_back({A.off_VT[j], B->off_U[j], kl[q], m});   // U'_j = (V_j^T)^T
+            tbas.push_back({A.off_U[j], B->off_VT[j], m, kl[q]});   // V'_j^T = U_j^T
+        }
+        for (int l = s.lmin + 1; l <= q; ++l)
+            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
+                tbas.push_back({A.off_FT[c], B->off_E[c], kl[l - 1], kl[l]});   // E'_c = (F_c^T)^T
+                tbas.push_back({A.off_E[c], B->off_FT[c], kl[l], kl[l - 1]});   // F'_c^T = E_c^T
+            }
+    }
+    check_hip(h2::launch_transpose_blocks(A.block_kind, A.blocks, B->blocks, scratch.upload(tb, st),
+                                          int64_t(tb.size()), st),
+              "transpose launch");
+    check_hip(h2::launch_transpose_blocks(A.basis_kind, A.basis, B->basis, scratch.upload(tbas, st),
+                                          int64_t(tbas.size()), st),
+              "transpose launch");
+    if (A.block_kind == h2::ELEM_BF16 && A.nscales > 0) {
+        std::vector<float> sa(size_t(A.nscales)), sb(fill.size());
+        check_hip(hipMemcpyAsync(sa.data(), A.scales, sa.size() * 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+        check_hip(hipStreamSynchronize(st), "transpose scales");
+        for (size_t fb = 0; fb < fill.size(); ++fb) sb[fb] = sa[size_t(src_fill[fb])];
+        check_hip(hipMemcpyAsync(B->scales, sb.data(), sb.size() * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    }
+    check_hip(hipStreamSynchronize(st), "transpose");
+    build_lists(*B, fill, ncoupling, st);
+    return B.release();
+}
+
 // Moves the representation of B (structure, layout, device memory, work
 // lists) into A; B receives A's old one and frees it when destroyed.
 void adopt(h2_matrix_ &A, h2_matrix_ &B) {
@@ -1619,6 +1715,25 @@ void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
 }  // namespace
 
 extern "C" {
+
+h2_status h2_transpose(h2_handle A, void *stream, h2_handle *out) {
+    if (out) *out = nullptr;
+    try {
+        if (!A || !out) fail(H2_ERR_INVALID_ARG, "NULL argument");
+        if (A->structure_only) fail(H2_ERR_INVALID_ARG, "structure-only handle");
+        *out = transpose_matrix(*A, static_cast<hipStream_t>(stream));
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return H2_ERR_OOM;
+    } catch (...) {
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
 
 h2_status h2_compress(h2_handle A, double eps, int *level_rank, void *stream) {
     try {

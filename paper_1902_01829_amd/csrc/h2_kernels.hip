@@ -246,6 +246,29 @@ __global__ __launch_bounds__(256) void fill_blocks_bf16_kernel(Geometry g, uint1
     if (threadIdx.x == 0) scales[d.sidx] = s;
 }
 
+// ---------------------------------------------------------------- transposed copies
+// One workgroup per block (grid-strided over the list): destination element
+// e = ((r / W) * C + c) * W + r % W of the C x R transpose takes source element
+// (r, c) at ((c / W) * R + r) * W + c % W; padding columns of the destination's
+// last group are written as zero.
+template <typename T, int W>
+__global__ __launch_bounds__(256) void transpose_blocks_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                               const TransDesc *__restrict__ desc, int64_t n) {
+    for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+        const TransDesc d = desc[b];
+        const int R = d.R, C = d.C;                       // source R x C, destination C x R
+        const int64_t ne = int64_t((R + W - 1) / W) * C * W;
+        for (int64_t e = threadIdx.x; e < ne; e += blockDim.x) {
+            const int w = int(e % W);
+            const int64_t g = e / W;
+            const int c = int(g % C), r = int(g / C) * W + w;   // destination (c, r) = source (r, c)
+            T v = T(0);
+            if (r < R) v = src[d.src + (int64_t(c / W) * R + r) * W + c % W];
+            dst[d.dst + e] = v;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- block-row product
 // One wavefront per output segment.  For every block of the row, the input
 // segment (<= 64 values) is staged in the wave's LDS slot; each lane then
@@ -414,6 +437,22 @@ hipError_t launch_fill_blocks(const Geometry &g, int block_kind, void *blocks, f
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_transpose_blocks(int kind, const void *src, void *dst, const TransDesc *desc, int64_t n,
+                                   hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid(unsigned(n < 65536 ? n : 65536)), block(256);
+    if (kind == ELEM_F64)
+        hipLaunchKernelGGL((transpose_blocks_kernel<double, 2>), grid, block, 0, st, static_cast<const double *>(src),
+                           static_cast<double *>(dst), desc, n);
+    else if (kind == ELEM_F32)
+        hipLaunchKernelGGL((transpose_blocks_kernel<float, 4>), grid, block, 0, st, static_cast<const float *>(src),
+                           static_cast<float *>(dst), desc, n);
+    else
+        hipLaunchKernelGGL((transpose_blocks_kernel<uint16_t, 8>), grid, block, 0, st,
+                           static_cast<const uint16_t *>(src), static_cast<uint16_t *>(dst), desc, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_blockrow(const RowLaunch &L, int kind, bool vec_f64, int phase, hipStream_t st) {

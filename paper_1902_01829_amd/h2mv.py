@@ -20,7 +20,7 @@ H2_FLAG_STRUCTURE_ONLY = 1
 STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
 
 # Every function declared in include/h2mv.h.
-EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_orthogonalize", "h2_compress", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
+EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_orthogonalize", "h2_compress", "h2_transpose", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
            "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_batch_create", "h2_batch_matmat",
            "h2_batch_tuning", "h2_batch_free", "h2_last_error")
 
@@ -78,6 +78,7 @@ def lib():
         L.h2_export_arrays.argtypes = [vp, C.POINTER(h2_arrays_out), vp]
         L.h2_orthogonalize.argtypes = [vp, vp]
         L.h2_compress.argtypes = [vp, C.c_double, vp, vp]
+        L.h2_transpose.argtypes = [vp, vp, C.POINTER(vp)]
         L.h2_matvec.argtypes = [vp, vp, vp, vp]
         L.h2_matmat.argtypes = [vp, vp, i64, vp, i64, C.c_int, vp]
         L.h2_free.argtypes = [vp]
@@ -192,6 +193,13 @@ def h2_export_arrays(h, stream=0):
 
 def h2_orthogonalize(h, stream=0):
     _check(lib().h2_orthogonalize(C.c_void_p(h), C.c_void_p(stream)))
+
+
+def h2_transpose(h, stream=0):
+    """A new handle for the transposed matrix."""
+    out = C.c_void_p()
+    _check(lib().h2_transpose(C.c_void_p(h), C.c_void_p(stream), C.byref(out)))
+    return out.value
 
 
 def h2_compress(h, eps, stream=0):
@@ -362,6 +370,16 @@ class H2Matrix:
 
     def orthogonalize(self):
         h2_orthogonalize(self.handle, self._stream())
+
+    def transpose(self):
+        """A new H2Matrix for the transposed matrix (same tree order)."""
+        import torch
+        t = type(self).__new__(type(self))
+        t._torch = torch
+        t.handle = h2_transpose(self.handle, self._stream())
+        t.info = h2_get_info(t.handle)
+        t.n = t.info.n
+        return t
 
     def compress(self, eps):
         """Algebraic compression in place (h2_compress); returns the new rank of every level."""
