@@ -378,6 +378,38 @@ def compress_section(steps=10, reps=2, nrows=256):
     return out
 
 
+def transpose_section(reps=3):
+    """The transposed matrix (h2_transpose) of the 2-D 2^20-point FP64 matrix:
+    time per call (device transposition of every block, basis and transfer
+    plus the new work lists), the bytes read and written, and A^T x against
+    A x (the covariance matrix is symmetric)."""
+    import torch
+    from paper_1902_01829_amd import h2mv
+    w = W.C2
+    A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=0)
+    info = A.info
+    x = torch.from_numpy(W.rhs(w, 1)[A.perm()]).cuda()
+    y = A.matvec(x)
+    ms = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        At = A.transpose()   # returns when the device work is done
+        ms.append((time.perf_counter() - t0) * 1e3)
+        yt = At.matvec(x)
+        rel = float(((yt - y).norm() / y.norm()).item())
+        At.close()
+        torch.cuda.empty_cache()
+    A.close()
+    nbytes = 2 * (info.bytes_coupling + info.bytes_dense + info.bytes_leaf_bases + info.bytes_transfers)
+    best = min(ms)
+    log(f"transpose {w.name}: {best:.1f} ms (of {[round(v, 1) for v in ms]}), "
+        f"{nbytes / (best * 1e-3) / 1e9:.0f} GB/s read + written, A^T x vs A x {rel:.1e}")
+    return {"workload": w.name, "ms": round(best, 2), "ms_all": [round(v, 2) for v in ms],
+            "bytes_read_written": int(nbytes), "GB_per_s": round(nbytes / (best * 1e-3) / 1e9, 1),
+            "rel_diff_AT_x_vs_A_x": rel}
+
+
 def storage_modes(steps, warmup, nleaves=16):
     """The 3-D workload (2^19 points, rank 64) in FP64, FP32 and BF16 storage."""
     w = W.C3
@@ -561,7 +593,8 @@ def main():
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the storage-mode, many-right-hand-side and batch sections")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--only", choices=["small", "modes", "matmat", "batch", "orthogonalize", "compress"],
+    ap.add_argument("--only", choices=["small", "modes", "matmat", "batch", "orthogonalize", "compress",
+                                      "transpose"],
                     default=None,
                     help="run one section alone and print its JSON (for profiling runs); "
                          "the headline line is not printed")
@@ -597,6 +630,8 @@ def main():
             out = orthogonalize_section()
         elif args.only == "compress":
             out = compress_section()
+        elif args.only == "transpose":
+            out = transpose_section()
         else:
             out = batch_modes(args.steps, args.warmup)
         print(json.dumps({"section": args.only, **out}), flush=True)
@@ -647,6 +682,7 @@ def main():
         result["batch"] = batch_modes(max(3, args.steps // 2), 1)
         result["orthogonalize"] = orthogonalize_section()
         result["compress"] = compress_section()
+        result["transpose"] = transpose_section()
     print(json.dumps(result), flush=True)
 
 
