@@ -419,24 +419,57 @@ def _transfer_offsets(kr, q):
     return eo, off
 
 
-def basis_generation(arr):
-    """The tree R of Sec. 5.2 (Alg. 8 and 9) for a symmetric H^2 matrix with
-    orthonormal nested bases, given by its arrays.  For node i of level l, with
-    parent i+ and coupling blocks S_ij1 .. S_ijb in its block row,
+def coupling_is_symmetric(arr):
+    """Whether every coupling block has a mirror block with S_ji = S_ij^T
+    exactly (then A = A^T when V = U, F = E and D is symmetric)."""
+    q = int(arr["q"])
+    for l in range(q + 1):
+        k = int(arr["level_rank"][l])
+        rp, ci, Sl = arr["S_rowptr"][l], arr["S_colidx"][l], arr["S"][l]
+        where = {}
+        for i in range(1 << l):
+            for t in range(int(rp[i]), int(rp[i + 1])):
+                where[(i, int(ci[t]))] = t
+        for (i, j), t in where.items():
+            u = where.get((j, i))
+            if u is None:
+                return False
+            if not np.array_equal(Sl[t * k * k:(t + 1) * k * k].reshape(k, k),
+                                  Sl[u * k * k:(u + 1) * k * k].reshape(k, k).T):
+                return False
+    return True
+
+
+def basis_generation(arr, columns=None):
+    """The tree R of Sec. 5.2 (Alg. 8 and 9) for an H^2 matrix with one
+    orthonormal nested basis tree for rows and columns (V = U, F = E), given by
+    its arrays.  For node i of level l, with parent i+ and coupling blocks
+    S_ij1 .. S_ijb in its block row,
         Sbar_i = [R_i+ E_i^T; S_ij1^T; ...; S_ijb^T]
     and R_i is the triangular factor of the QR factorization of Sbar_i (Q is
-    not formed).  The parent term is absent on the coarsest level with blocks,
-    l_min (every level above it has an empty block row, so its R is 0).  R_i
-    is returned as a k_l x k_l matrix (rows past the number of rows of Sbar_i
-    are zero).  Returns {node: R_i} for the nodes of levels l_min .. q."""
+    not formed).  When the coupling blocks are not symmetric (S_ji != S_ij^T
+    for some block), the basis also carries block column i, so the blocks
+    S_j1i .. S_jci of that column are stacked below as well (the rows of the
+    column's blocks restricted to node i's columns).  The parent term is absent
+    on the coarsest level with blocks, l_min (every level above it has no
+    blocks, so its R is 0).  R_i is returned as a k_l x k_l matrix (rows past
+    the number of rows of Sbar_i are zero).  Returns {node: R_i} for the nodes
+    of levels l_min .. q.  columns: stack the block columns (None: when the
+    coupling blocks of arr are not exactly symmetric)."""
     q = int(arr["q"])
     kr = [int(k) for k in arr["level_rank"]]
     lmin = next((l for l in range(q + 1) if int(arr["S_rowptr"][l][1 << l]) > 0), q + 1)
     eo, _ = _transfer_offsets(kr, q)
+    if columns is None:
+        columns = not coupling_is_symmetric(arr)
     R = {}
     for l in range(lmin, q + 1):
         k, f = kr[l], (1 << l) - 1
         rp, ci, S = arr["S_rowptr"][l], arr["S_colidx"][l], arr["S"][l]
+        in_column = [[] for _ in range(1 << l)]   # blocks of each block column, by row
+        for i in range(1 << l):
+            for t in range(int(rp[i]), int(rp[i + 1])):
+                in_column[int(ci[t])].append(t)
         for i in range(1 << l):
             node = f + i
             parts = []
@@ -446,6 +479,9 @@ def basis_generation(arr):
                 parts.append(R[(node - 1) // 2] @ Ei.T)
             for t in range(int(rp[i]), int(rp[i + 1])):
                 parts.append(S[t * k * k:(t + 1) * k * k].reshape(k, k))      # S_ij^T (column-major S_ij read row-major)
+            if columns:
+                for t in in_column[i]:
+                    parts.append(S[t * k * k:(t + 1) * k * k].reshape(k, k).T)   # S_ji
             Ri = np.zeros((k, k))
             if parts:
                 r = np.linalg.qr(np.vstack(parts), mode="r")
@@ -455,8 +491,10 @@ def basis_generation(arr):
 
 
 def compress_arrays(arr, eps):
-    """Algebraic compression of a symmetric H^2 matrix given by its arrays
-    (Sec. 5): orthogonalization (Sec. 5.1), basis generation (Sec. 5.2), basis
+    """Algebraic compression of an H^2 matrix with one basis tree for rows and
+    columns (V = U, F = E) given by its arrays (Sec. 5): orthogonalization
+    (Sec. 5.1), basis generation (Sec. 5.2, block columns included when the
+    coupling blocks are not symmetric), basis
     truncation (Sec. 5.3, Alg. 10) with relative threshold eps, and projection
     of the coupling blocks into the truncated bases.
 
@@ -474,13 +512,16 @@ def compress_arrays(arr, eps):
     Returns (new arrays, info) with info = {"rank": k~ per level, "sigma":
     {node: singular values of W}, "count": {node: kept count}, "R": R tree,
     "T": {node: T}}."""
+    # symmetry is decided on the input: the projection keeps S_ji = S_ij^T in
+    # exact arithmetic but not bit for bit
+    columns = not coupling_is_symmetric(arr)
     orth, _ = orthogonalize_arrays(arr)
     q = int(arr["q"])
     kr = [int(k) for k in orth["level_rank"]]
     lmin = next((l for l in range(q + 1) if int(orth["S_rowptr"][l][1 << l]) > 0), q + 1)
     if lmin > q:
         return orth, {"rank": kr, "sigma": {}, "count": {}, "R": {}, "T": {}}
-    R = basis_generation(orth)
+    R = basis_generation(orth, columns)
     eo, _ = _transfer_offsets(kr, q)
     lo = _leaf_offsets(orth)
     lf = (1 << q) - 1

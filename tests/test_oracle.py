@@ -763,3 +763,65 @@ def test_transposed_arrays_are_the_transpose(oracle_mod, n, d, m, seed):
         assert np.array_equal(back["S_rowptr"][l], arr["S_rowptr"][l])
         assert np.array_equal(back["S_colidx"][l], arr["S_colidx"][l])
         assert np.array_equal(back["S"][l], arr["S"][l])
+
+
+def _nonsymmetric_coupling(arr):
+    """The same bases (V = U, F = E) with coupling blocks S_ij scaled by 1.5
+    above the diagonal of each level (i < j) and by 0.25 below it: S_ji !=
+    S_ij^T, and block rows and block columns differ."""
+    out = dict(arr)
+    S = []
+    for l in range(int(arr["q"]) + 1):
+        k = int(arr["level_rank"][l])
+        rp, ci = arr["S_rowptr"][l], arr["S_colidx"][l]
+        Sl = np.array(arr["S"][l], dtype=np.float64, copy=True)
+        for i in range(1 << l):
+            for t in range(int(rp[i]), int(rp[i + 1])):
+                Sl[t * k * k:(t + 1) * k * k] *= 1.5 if i < int(ci[t]) else 0.25
+        S.append(Sl)
+    out["S"] = S
+    return out
+
+
+def test_coupling_symmetry_check(oracle_mod):
+    o = oracle_mod.OracleH2(_pts(900, 2, 91), 32, 3, 0.9, 0.2)
+    arr = o.export_arrays()
+    assert oracle_mod.coupling_is_symmetric(arr)
+    assert not oracle_mod.coupling_is_symmetric(_nonsymmetric_coupling(arr))
+
+
+@pytest.mark.parametrize("n,d,m,p", [(700, 2, 16, 3), (600, 3, 32, 2)])
+def test_nonsymmetric_coupling_leaf_singular_values(oracle_mod, n, d, m, p):
+    """With one basis tree for rows and columns and non-symmetric coupling
+    blocks, W_i = U_i R_i^T has the singular values of [row far field of leaf
+    i, (column far field of leaf i)^T] of the dense matrix (brute force): the
+    basis must represent both."""
+    o = oracle_mod.OracleH2(_pts(n, d, 92), m, p, 0.9, 0.2)
+    arr = _nonsymmetric_coupling(o.export_arrays())
+    A = _dense_from_arrays(arr)
+    _, info = oracle_mod.compress_arrays(arr, 0.0)
+    b, e = arr["begin"], arr["end"]
+    lf = (1 << o.q) - 1
+    checked = 0
+    for v in range(lf, 2 * lf + 1):
+        cols = _far_columns(arr, v)   # the partners of v and its ancestors (the same sets for rows and columns)
+        if not len(cols):
+            continue
+        M = np.hstack([A[b[v]:e[v]][:, cols], A[cols][:, b[v]:e[v]].T])
+        s = np.linalg.svd(M, compute_uv=False)
+        got = info["sigma"][v]
+        ref = np.zeros(len(got))
+        ref[:min(len(s), len(got))] = s[:len(got)]
+        assert np.abs(got - ref).max() <= 1e-12 * ref.max()
+        checked += 1
+    assert checked > 0
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_nonsymmetric_coupling_compression_error(oracle_mod, eps):
+    o = oracle_mod.OracleH2(_pts(2500, 2, 93), 64, 5, 0.9, 0.2)
+    arr = _nonsymmetric_coupling(o.export_arrays())
+    out, info = oracle_mod.compress_arrays(arr, eps)
+    A0, A1 = _dense_from_arrays(arr), _dense_from_arrays(out)
+    assert np.linalg.norm(A1 - A0) <= eps * np.linalg.norm(A0)
+    assert all(info["rank"][l] < o.k for l in _levels_with_blocks(arr))
