@@ -219,7 +219,9 @@ h2_status h2_transpose(h2_handle A, void *stream, h2_handle *out);
  * h2_orthogonalize; basis generation (Sec. 5.2): for every node i of the
  * levels with coupling blocks, top-down, R_i = the triangular factor of the
  * QR factorization of [R_parent E_i^T; S_ij1^T; ...; S_ijb^T] (its block
- * row's coupling blocks under its parent's factor); truncation (Sec. 5.3),
+ * row's coupling blocks under its parent's factor; when some block has
+ * S_ji != S_ij^T bit for bit, the blocks S_ji of block column i are stacked
+ * too, as the one basis tree serves both); truncation (Sec. 5.3),
  * bottom-up: the left singular vectors of W_i = U_i R_i^T at the leaves and
  * of W_p = [T_c1 E_c1; T_c2 E_c2] R_p^T above, a node keeping those whose
  * singular value is at least eps times its largest, a level the largest such

@@ -1548,6 +1548,46 @@ h2_matrix_ *transpose_matrix(h2_matrix_ &A, hipStream_t st) {
     return B.release();
 }
 
+// S_ji = S_ij^T, bit for bit, for every coupling block (FP64 storage): the
+// mirror of each block is found by binary search in its mirror row (sorted
+// per row on the host), and the pairs are compared on the device.
+bool coupling_symmetric(h2_matrix_ &A, hipStream_t st) {
+    const Structure &s = A.st;
+    std::vector<h2::MirrorDesc> pairs;
+    int64_t fi = 0;
+    for (int l = 0; l <= s.q; ++l) {
+        const h2::Bsr &B = s.coupling[l];
+        const int64_t rows = int64_t(1) << l, f0 = fi;
+        // each row's (column, fill index) pairs sorted by column (rows are short)
+        std::vector<std::pair<int32_t, int64_t>> key(size_t(B.blocks()));
+        for (int64_t i = 0; i < rows; ++i) {
+            for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b) key[size_t(b)] = {B.colidx[b], f0 + b};
+            std::sort(key.begin() + B.rowptr[i], key.begin() + B.rowptr[i + 1]);
+        }
+        for (int64_t i = 0; i < rows; ++i)
+            for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b) {
+                const int64_t j = B.colidx[b];
+                if (j < i) continue;   // each pair once (i <= j)
+                const auto lo = key.begin() + B.rowptr[j], hi = key.begin() + B.rowptr[j + 1];
+                const auto it = std::lower_bound(lo, hi, std::make_pair(int32_t(i), int64_t(-1)));
+                if (it == hi || it->first != int32_t(i)) return false;   // no mirror block
+                pairs.push_back({A.off_blk[size_t(f0 + b)], A.off_blk[size_t(it->second)], s.lrank[l], 0});
+            }
+        fi += B.blocks();
+    }
+    if (pairs.empty()) return true;
+    DeviceArena scratch;
+    int32_t *flag = static_cast<int32_t *>(scratch.alloc(4));
+    check_hip(hipMemsetAsync(flag, 0, 4, st), "hipMemsetAsync");
+    check_hip(h2::launch_symmetry_check(static_cast<const double *>(A.blocks), scratch.upload(pairs, st),
+                                        int64_t(pairs.size()), flag, st),
+              "symmetry check launch");
+    int32_t h = 0;
+    check_hip(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    check_hip(hipStreamSynchronize(st), "symmetry check");
+    return h == 0;
+}
+
 // Moves the representation of B (structure, layout, device memory, work
 // lists) into A; B receives A's old one and frees it when destroyed.
 void adopt(h2_matrix_ &A, h2_matrix_ &B) {
@@ -1595,6 +1635,13 @@ void adopt(h2_matrix_ &A, h2_matrix_ &B) {
 void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
     if (!(eps >= 0.0) || !std::isfinite(eps)) fail(H2_ERR_INVALID_ARG, "eps must be finite and >= 0");
     if (A.batch_refs > 0) fail(H2_ERR_INVALID_ARG, "the matrix belongs to a batch (free the batch first)");
+    if (A.storage != H2_FP64) fail(H2_ERR_UNSUPPORTED, "compression needs FP64 storage");
+    if (!A.symmetric) fail(H2_ERR_UNSUPPORTED, "compression needs V = U and F = E");
+    // Whether S_ji = S_ij^T for every coupling block, decided before the
+    // orthogonalization (which keeps the symmetry only up to rounding): if
+    // not, the one basis tree also serves block columns that differ from the
+    // block rows, and the basis generation stacks both.
+    const bool sym = coupling_symmetric(A, st);
     orthogonalize(A, st);
     const Structure &s = A.st;
     const int q = s.q, lmin = s.lmin, kmax = s.rank;
@@ -1618,6 +1665,25 @@ void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
             }
             row_start[s.nnodes] = int64_t(blk.size());
         }
+        // blocks of every block column (by column, rows increasing), for the non-symmetric case
+        std::vector<int64_t> col_blk, col_start(s.nnodes + 1, 0);
+        if (!sym) {
+            int64_t fi = 0;
+            std::vector<std::vector<int64_t>> per_col;
+            for (int l = 0; l <= q; ++l) {
+                const h2::Bsr &B = s.coupling[l];
+                const int64_t f = Structure::first(l), rows = int64_t(1) << l;
+                per_col.assign(size_t(rows), {});
+                for (int64_t i = 0; i < rows; ++i)
+                    for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b, ++fi)
+                        per_col[size_t(B.colidx[b])].push_back(A.off_blk[size_t(fi)]);
+                for (int64_t jc = 0; jc < rows; ++jc) {
+                    col_start[f + jc] = int64_t(col_blk.size());
+                    col_blk.insert(col_blk.end(), per_col[size_t(jc)].begin(), per_col[size_t(jc)].end());
+                }
+            }
+            col_start[s.nnodes] = int64_t(col_blk.size());
+        }
         DeviceArena scratch;
         const int64_t tree = s.nnodes * int64_t(kmax) * kmax;
         const int64_t maxlevel = std::max<int64_t>(nleaves, 1);
@@ -1630,6 +1696,9 @@ void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
         L.leaf_end = A.d_leaf_end;
         L.blk = scratch.upload(blk, st);
         L.row_start = scratch.upload(row_start, st);
+        L.columns = sym ? 0 : 1;
+        L.col_blk = scratch.upload(col_blk, st);
+        L.col_start = scratch.upload(col_start, st);
         L.R = static_cast<double *>(scratch.alloc(tree * 8));
         L.T = static_cast<double *>(scratch.alloc(tree * 8));
         L.Enew = static_cast<double *>(scratch.alloc(tree * 8));

@@ -3,8 +3,10 @@
 //
 // Basis generation, top-down: node i of level l stacks
 //     Sbar_i = [R_i+ E_i^T; S_ij1^T; ...; S_ijb^T]
-// (i+ its parent, S_ij the coupling blocks of its block row) and keeps the
-// triangular factor R_i of its QR factorization.  The stack is not formed
+// (i+ its parent, S_ij the coupling blocks of its block row; when the blocks
+// are not symmetric, the blocks S_ji of its block column follow, since the
+// one basis tree serves the columns too) and keeps the triangular factor R_i
+// of its QR factorization.  The stack is not formed
 // whole: a workgroup holds 128 x 64 in registers, so blocks are appended
 // under the current factor and folded into it with a QR of the stack
 // whenever the next block would not fit (the same R up to row signs, which
@@ -133,26 +135,32 @@ __global__ __launch_bounds__(BG_THREADS) void basis_generation_kernel(CompLaunch
             }
         dirty = true;
     }
-    const int64_t b1 = L.row_start[node + 1];
+    // the stack's blocks: those of block row i, transposed, then (when the
+    // coupling blocks are not symmetric) those of block column i as they are
+    const int64_t nrow = L.row_start[node + 1] - L.row_start[node];
+    const int64_t nb = nrow + (L.columns ? L.col_start[node + 1] - L.col_start[node] : 0);
     const int ng = (k + 1) >> 1;
-    int64_t b = L.row_start[node];
+    int64_t b = 0;
     for (;;) {   // append as many blocks as fit under the factor, then fold (one call site)
-        for (int bot = 0; b < b1 && bot + k <= BG_STACK - 64; ++b, bot += k) {
+        for (int bot = 0; b < nb && bot + k <= BG_STACK - 64; ++b, bot += k) {
             __syncthreads();   // the tile's previous contents are consumed
-            const double *S = L.blocks + L.blk[b].off;   // S_b(r, 2g .. 2g+1) is one 16-byte item
-            for (int i = t; i < ng * k; i += BG_THREADS) {
+            const bool from_row = b < nrow;
+            const double *S = L.blocks + (from_row ? L.blk[L.row_start[node] + b].off
+                                                   : L.col_blk[L.col_start[node] + (b - nrow)]);
+            for (int i = t; i < ng * k; i += BG_THREADS) {   // S(r, 2g .. 2g+1) is one 16-byte item
                 const int g = i / k, r = i - g * k;
                 const f64x2 v = *reinterpret_cast<const f64x2 *>(S + (int64_t(g) * k + r) * 2);
                 tile[r * BG_TLD + 2 * g] = v.x;
                 tile[r * BG_TLD + 2 * g + 1] = v.y;   // column k when k is odd: padding, never read
             }
             __syncthreads();
-            // S_b^T into rows 64 + bot .. 64 + bot + k - 1: row rr of S_b^T, column col is S_b(col, rr)
+            // rows 64 + bot .. 64 + bot + k - 1: row rr, column col is S(col, rr) for a row block
+            // (S^T) and S(rr, col) for a column block
             if (col < k) {
 #pragma unroll
                 for (int i = 4; i < BG_ROWS; ++i) {
                     const int rr = j + 16 * i - 64 - bot;
-                    if (rr >= 0 && rr < k) a[i] = tile[col * BG_TLD + rr];
+                    if (rr >= 0 && rr < k) a[i] = from_row ? tile[col * BG_TLD + rr] : tile[rr * BG_TLD + col];
                 }
             }
             dirty = true;
@@ -160,7 +168,7 @@ __global__ __launch_bounds__(BG_THREADS) void basis_generation_kernel(CompLaunch
         if (!dirty) break;
         fold_r(a, k, col, j, vbuf, tbuf);
         dirty = false;
-        if (b >= b1) break;
+        if (b >= nb) break;
     }
     double *R = L.R + node * L.kmax * L.kmax;   // rows 0 .. k-1 (zero below the diagonal)
     if (col < k) {
@@ -383,6 +391,19 @@ __global__ __launch_bounds__(256) void truncate_level_apply_kernel(CompLaunch L,
     }
 }
 
+__global__ __launch_bounds__(256) void symmetry_check_kernel(const double *blocks, const MirrorDesc *desc, int64_t n,
+                                                             int32_t *flag) {
+    for (int64_t p = blockIdx.x; p < n; p += gridDim.x) {
+        const MirrorDesc d = desc[p];
+        int diff = 0;
+        for (int e = threadIdx.x; e < d.k * d.k; e += 256) {
+            const int c = e / d.k, r = e - c * d.k;
+            diff |= blocks[d.a + at2(d.k, r, c)] != blocks[d.b + at2(d.k, c, r)];
+        }
+        if (__syncthreads_or(diff) && threadIdx.x == 0) *flag = 1;
+    }
+}
+
 __global__ __launch_bounds__(256) void place_kernel(const double *src, double *dst, const PlaceDesc *desc, int64_t n) {
     for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
         const PlaceDesc d = desc[b];
@@ -433,6 +454,14 @@ hipError_t launch_truncate_level_apply(const CompLaunch &L, int l, int kc, int k
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(truncate_level_apply_kernel, dim3(unsigned(int64_t(1) << (l - 1))), dim3(256), 0, st, L, l, kc,
                        kt, kp, ktp);
+    return hipGetLastError();
+}
+
+hipError_t launch_symmetry_check(const double *blocks, const MirrorDesc *desc, int64_t n, int32_t *flag,
+                                 hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t grid = n < 65536 ? n : 65536;
+    hipLaunchKernelGGL(symmetry_check_kernel, dim3(unsigned(grid)), dim3(256), 0, st, blocks, desc, n, flag);
     return hipGetLastError();
 }
 

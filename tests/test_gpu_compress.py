@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from paper_1902_01829_amd import workloads as W
-from test_oracle import _explicit_bases, _inflate
+from test_oracle import _explicit_bases, _inflate, _nonsymmetric_coupling
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -116,6 +116,37 @@ def test_compress_matches_oracle(oracle_mod, w, epss):
         assert worst_o <= ORTHO_TOL
         assert worst_p <= 1.0
         A.close()
+
+
+@pytest.mark.parametrize("d,eps", [(2, 1e-6), (3, 1e-4)])
+def test_compress_nonsymmetric_coupling_matches_oracle(oracle_mod, d, eps):
+    """One basis tree for rows and columns (V = U, F = E) with coupling blocks
+    that are not symmetric: the basis generation stacks block rows and block
+    columns on both sides; ranks, products and orthonormality as above."""
+    h2mv = _h2mv()
+    n = 4000
+    pts = np.random.Generator(np.random.PCG64(670 + d)).random((n, d))
+    o = oracle_mod.OracleH2(pts, 64, 5 if d == 2 else 3, 0.9, 0.2)
+    arr = _nonsymmetric_coupling(o.export_arrays())
+    assert not oracle_mod.coupling_is_symmetric(arr)
+    ref, info = oracle_mod.compress_arrays(arr, eps)
+    _check_margin(info, eps)
+    A = h2mv.H2Matrix.from_arrays(arr, storage=0)
+    ranks = A.compress(eps)
+    assert list(ranks) == [int(r) for r in ref["level_rank"]], (list(ranks), list(ref["level_rank"]))
+    x = np.random.Generator(np.random.PCG64(671)).standard_normal(n)
+    y = A.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    par, err = _rel(y, oracle_mod.arrays_matvec(ref, x)), _rel(y, oracle_mod.arrays_matvec(arr, x))
+    got = h2mv.h2_export_arrays(A.handle)
+    new = _explicit_bases(got)
+    lmin = _lmin(got)
+    worst_o = max(float(np.abs(new[v].T @ new[v] - np.eye(new[v].shape[1])).max())
+                  for v in range((1 << lmin) - 1, o.nnodes))
+    print(f"d={d} eps={eps}: ranks {[int(r) for r in ranks]} vs oracle {par:.2e}, vs uncompressed {err:.2e}, "
+          f"orthonormality {worst_o:.1e}", flush=True)
+    assert par <= PARITY_TOL
+    assert err <= eps
+    assert worst_o <= ORTHO_TOL
 
 
 def test_compress_zero_threshold_keeps_ranks_and_product(oracle_mod):
