@@ -456,12 +456,19 @@ def basis_generation(arr, columns=None):
     the number of rows of Sbar_i are zero).  Returns {node: R_i} for the nodes
     of levels l_min .. q.  columns: stack the block columns (None: when the
     coupling blocks of arr are not exactly symmetric)."""
+    if columns is None:
+        columns = not coupling_is_symmetric(arr)
+    return _basis_generation_tree(arr, "E", True, columns)
+
+
+def _basis_generation_tree(arr, tkey, rows, cols):
+    """R tree of one basis tree (tkey "E": the row tree, "F": the column
+    tree): Sbar_i stacks R_i+ X_i^T (X = E or F), then the blocks of block row
+    i transposed (rows) and the blocks of block column i as they are (cols)."""
     q = int(arr["q"])
     kr = [int(k) for k in arr["level_rank"]]
     lmin = next((l for l in range(q + 1) if int(arr["S_rowptr"][l][1 << l]) > 0), q + 1)
     eo, _ = _transfer_offsets(kr, q)
-    if columns is None:
-        columns = not coupling_is_symmetric(arr)
     R = {}
     for l in range(lmin, q + 1):
         k, f = kr[l], (1 << l) - 1
@@ -475,11 +482,12 @@ def basis_generation(arr, columns=None):
             parts = []
             if l > lmin:
                 kp = kr[l - 1]
-                Ei = arr["E"][eo[node]:eo[node] + k * kp].reshape(kp, k).T     # k_l x k_(l-1)
-                parts.append(R[(node - 1) // 2] @ Ei.T)
-            for t in range(int(rp[i]), int(rp[i + 1])):
-                parts.append(S[t * k * k:(t + 1) * k * k].reshape(k, k))      # S_ij^T (column-major S_ij read row-major)
-            if columns:
+                Xi = arr[tkey][eo[node]:eo[node] + k * kp].reshape(kp, k).T     # k_l x k_(l-1)
+                parts.append(R[(node - 1) // 2] @ Xi.T)
+            if rows:
+                for t in range(int(rp[i]), int(rp[i + 1])):
+                    parts.append(S[t * k * k:(t + 1) * k * k].reshape(k, k))      # S_ij^T (column-major S_ij read row-major)
+            if cols:
                 for t in in_column[i]:
                     parts.append(S[t * k * k:(t + 1) * k * k].reshape(k, k).T)   # S_ji
             Ri = np.zeros((k, k))
@@ -491,8 +499,9 @@ def basis_generation(arr, columns=None):
 
 
 def compress_arrays(arr, eps):
-    """Algebraic compression of an H^2 matrix with one basis tree for rows and
-    columns (V = U, F = E) given by its arrays (Sec. 5): orthogonalization
+    """Algebraic compression of an H^2 matrix given by its arrays (Sec. 5);
+    matrices with different row and column trees go to compress_two_trees,
+    the rest (one basis tree, V = U, F = E) follow here: orthogonalization
     (Sec. 5.1), basis generation (Sec. 5.2, block columns included when the
     coupling blocks are not symmetric), basis
     truncation (Sec. 5.3, Alg. 10) with relative threshold eps, and projection
@@ -512,6 +521,8 @@ def compress_arrays(arr, eps):
     Returns (new arrays, info) with info = {"rank": k~ per level, "sigma":
     {node: singular values of W}, "count": {node: kept count}, "R": R tree,
     "T": {node: T}}."""
+    if not shares_one_tree(arr):
+        return compress_two_trees(arr, eps)
     # symmetry is decided on the input: the projection keeps S_ji = S_ij^T in
     # exact arithmetic but not bit for bit
     columns = not coupling_is_symmetric(arr)
@@ -632,3 +643,161 @@ def transpose_arrays(arr):
                D_rowptr=nrp, D_colidx=nci,
                D=np.concatenate([m.ravel(order="F") for m in nbl]) if nbl else np.zeros(0))
     return out
+
+
+def shares_one_tree(arr):
+    """V = U and F = E value by value: one basis tree for rows and columns."""
+    return np.array_equal(arr["U"], arr["V"]) and np.array_equal(arr["E"], arr["F"])
+
+
+def _orthogonalize_tree(arr, bkey, tkey):
+    """Sec. 5.1 up one basis tree (bkey "U" / tkey "E", or "V" / "F"):
+    returns the new leaf bases and transfers (flattened) and {node: T}."""
+    q = int(arr["q"])
+    kr = [int(k) for k in arr["level_rank"]]
+    b, e = arr["begin"], arr["end"]
+    lf = (1 << q) - 1
+    lmin = next((l for l in range(q + 1) if int(arr["S_rowptr"][l][1 << l]) > 0), q + 1)
+    B = np.array(arr[bkey], dtype=np.float64, copy=True)
+    X = np.array(arr[tkey], dtype=np.float64, copy=True)
+    T = {}
+    off = 0
+    for j in range(1 << q):
+        m = int(e[lf + j] - b[lf + j])
+        if m < kr[q]:
+            raise ValueError("a leaf holds fewer rows than the rank")
+        Q, T[lf + j] = _qr_positive(B[off:off + m * kr[q]].reshape(kr[q], m).T)
+        B[off:off + m * kr[q]] = Q.ravel(order="F")
+        off += m * kr[q]
+    eo, _ = _transfer_offsets(kr, q)
+    for l in range(q, lmin, -1):
+        kc, kp = kr[l], kr[l - 1]
+        if 2 * kc < kp:
+            raise ValueError("a level's rank exceeds twice its children's")
+        for p in range((1 << (l - 1)) - 1, (1 << l) - 1):
+            c1, c2 = 2 * p + 1, 2 * p + 2
+            X1 = X[eo[c1]:eo[c1] + kc * kp].reshape(kp, kc).T
+            X2 = X[eo[c2]:eo[c2] + kc * kp].reshape(kp, kc).T
+            Q, T[p] = _qr_positive(np.vstack([T[c1] @ X1, T[c2] @ X2]))
+            X[eo[c1]:eo[c1] + kc * kp] = Q[:kc].ravel(order="F")
+            X[eo[c2]:eo[c2] + kc * kp] = Q[kc:].ravel(order="F")
+    return B, X, T
+
+
+def orthogonalize_two_trees(arr):
+    """Basis orthogonalization (Sec. 5.1) of an H^2 matrix whose row and
+    column trees differ (V != U or F != E): each tree as in
+    orthogonalize_arrays (U = Q T up the row tree, V = Q' T' up the column
+    tree), then every coupling block S_ij <- T_i S_ij T'_j^T.  Returns (new
+    arrays, T of the row tree, T' of the column tree)."""
+    q = int(arr["q"])
+    kr = [int(k) for k in arr["level_rank"]]
+    lmin = next((l for l in range(q + 1) if int(arr["S_rowptr"][l][1 << l]) > 0), q + 1)
+    out = dict(arr)
+    if lmin > q:
+        return out, {}, {}
+    U, E, Tr = _orthogonalize_tree(arr, "U", "E")
+    V, F, Tc = _orthogonalize_tree(arr, "V", "F")
+    S = []
+    for l in range(q + 1):
+        Sl = np.array(arr["S"][l], dtype=np.float64, copy=True)
+        k, f = kr[l], (1 << l) - 1
+        rp, ci = arr["S_rowptr"][l], arr["S_colidx"][l]
+        for i in range(1 << l):
+            for t in range(int(rp[i]), int(rp[i + 1])):
+                Sb = Sl[t * k * k:(t + 1) * k * k].reshape(k, k).T
+                Sl[t * k * k:(t + 1) * k * k] = (Tr[f + i] @ Sb @ Tc[f + int(ci[t])].T).ravel(order="F")
+        S.append(Sl)
+    out.update(U=U, V=V, E=E, F=F, S=S)
+    return out, Tr, Tc
+
+
+def compress_two_trees(arr, eps):
+    """Algebraic compression (Sec. 5) with different row and column trees:
+    orthogonalize both (orthogonalize_two_trees); the row tree's R from the
+    block rows (S_ij^T) under R_i+ E_i^T, the column tree's R' from the block
+    columns (S_ji) under R'_i+ F_i^T (Sec. 5.2 for each tree); truncation
+    (Sec. 5.3) of each tree with its own R, the rank of a level being the
+    largest kept count over the nodes of both trees (the blocks stay square,
+    one rank per level); S_ij <- T_i S_ij T'_j^T.  Returns (new arrays, info)
+    with info["sigma"], info["count"] for the row tree and info["sigma_col"],
+    info["count_col"] for the column tree."""
+    orth, _, _ = orthogonalize_two_trees(arr)
+    q = int(arr["q"])
+    kr = [int(k) for k in orth["level_rank"]]
+    lmin = next((l for l in range(q + 1) if int(orth["S_rowptr"][l][1 << l]) > 0), q + 1)
+    if lmin > q:
+        return orth, {"rank": kr, "sigma": {}, "count": {}, "sigma_col": {}, "count_col": {}}
+    Rr = _basis_generation_tree(orth, "E", True, False)
+    Rc = _basis_generation_tree(orth, "F", False, True)
+    eo, _ = _transfer_offsets(kr, q)
+    lo = _leaf_offsets(orth)
+    lf = (1 << q) - 1
+
+    def kept(sv):
+        return int(np.count_nonzero(sv >= eps * sv[0])) if sv.size and sv[0] > 0.0 else 0
+
+    trees = {"row": ("U", "E", Rr), "col": ("V", "F", Rc)}
+    sigma = {"row": {}, "col": {}}
+    count = {"row": {}, "col": {}}
+    T = {"row": {}, "col": {}}
+    left = {"row": {}, "col": {}}
+    leafb = {"row": {}, "col": {}}
+    kt = list(kr)
+    for name, (bkey, _, R) in trees.items():
+        for v in range(lf, 2 * lf + 1):
+            off, m = lo[v]
+            leafb[name][v] = orth[bkey][off:off + m * kr[q]].reshape(kr[q], m).T
+            Qv, sv, _ = np.linalg.svd(leafb[name][v] @ R[v].T, full_matrices=False)
+            left[name][v], sigma[name][v], count[name][v] = Qv, sv, kept(sv)
+    kt[q] = max(1, max(max(count[t][v] for v in range(lf, 2 * lf + 1)) for t in trees))
+    newb = {"row": [], "col": []}
+    for name in trees:
+        for v in range(lf, 2 * lf + 1):
+            Qv = left[name][v][:, :kt[q]]
+            T[name][v] = Qv.T @ leafb[name][v]
+            newb[name].append(Qv.ravel(order="F"))
+    newx = {"row": {}, "col": {}}
+    for l in range(q, lmin, -1):
+        kc, kp = kr[l], kr[l - 1]
+        Z = {"row": {}, "col": {}}
+        for name, (_, tkey, R) in trees.items():
+            for p in range((1 << (l - 1)) - 1, (1 << l) - 1):
+                halves = []
+                for c in (2 * p + 1, 2 * p + 2):
+                    Xc = orth[tkey][eo[c]:eo[c] + kc * kp].reshape(kp, kc).T
+                    halves.append(T[name][c] @ Xc)
+                Z[name][p] = np.vstack(halves)
+                Qp, sv, _ = np.linalg.svd(Z[name][p] @ R[p].T, full_matrices=False)
+                left[name][p], sigma[name][p], count[name][p] = Qp, sv, kept(sv)
+        kt[l - 1] = max(1, max(max(count[t][p] for p in Z[t]) for t in trees))
+        for name in trees:
+            for p in Z[name]:
+                Qp = left[name][p][:, :kt[l - 1]]
+                newx[name][2 * p + 1] = Qp[:kt[l]]
+                newx[name][2 * p + 2] = Qp[kt[l]:]
+                T[name][p] = Qp.T @ Z[name][p]
+    for l in range(lmin):
+        kt[l] = kt[lmin]
+    flat = {}
+    for name in trees:
+        X = []
+        for l in range(1, q + 1):
+            for c in range((1 << l) - 1, (2 << l) - 1):
+                X.append(newx[name][c].ravel(order="F") if c in newx[name] else np.zeros(kt[l] * kt[l - 1]))
+        flat[name] = np.concatenate(X) if X else np.zeros(0)
+    S = []
+    for l in range(q + 1):
+        k, f = kr[l], (1 << l) - 1
+        rp, ci, Sl = orth["S_rowptr"][l], orth["S_colidx"][l], orth["S"][l]
+        blocks = []
+        for i in range(1 << l):
+            for t in range(int(rp[i]), int(rp[i + 1])):
+                Sb = Sl[t * k * k:(t + 1) * k * k].reshape(k, k).T
+                blocks.append((T["row"][f + i] @ Sb @ T["col"][f + int(ci[t])].T).ravel(order="F"))
+        S.append(np.concatenate(blocks) if blocks else np.zeros(0))
+    out = dict(orth)
+    out.update(level_rank=np.array(kt, dtype=np.int32), U=np.concatenate(newb["row"]), V=np.concatenate(newb["col"]),
+               E=flat["row"], F=flat["col"], S=S)
+    return out, {"rank": kt, "sigma": sigma["row"], "count": count["row"], "sigma_col": sigma["col"],
+                 "count_col": count["col"], "R": Rr, "R_col": Rc, "T": T["row"], "T_col": T["col"]}

@@ -825,3 +825,149 @@ def test_nonsymmetric_coupling_compression_error(oracle_mod, eps):
     A0, A1 = _dense_from_arrays(arr), _dense_from_arrays(out)
     assert np.linalg.norm(A1 - A0) <= eps * np.linalg.norm(A0)
     assert all(info["rank"][l] < o.k for l in _levels_with_blocks(arr))
+
+
+# ---- different row and column trees (V != U, F != E)
+
+def _two_trees(arr, seed):
+    """The same matrix written with a different column tree: V_j = U_j G_j
+    at the leaves, F_c = G_c^-1 E_c G_parent, S_ij <- S_ij G_j^-T, with a
+    random well-conditioned G_v per node (levels l_min .. q).  Then
+    [V_c1 F_c1; V_c2 F_c2] = U_p G_p and U_i S_ij V_j^T is unchanged."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    q, kr = int(arr["q"]), [int(k) for k in arr["level_rank"]]
+    lmin = _levels_with_blocks(arr)[0]
+    G = {}
+    for l in range(lmin, q + 1):
+        for v in range((1 << l) - 1, (2 << l) - 1):
+            G[v] = np.eye(kr[l]) + 0.3 * rng.standard_normal((kr[l], kr[l])) / np.sqrt(kr[l])
+    b, e = arr["begin"], arr["end"]
+    lf = (1 << q) - 1
+    V, off = [], 0
+    for j in range(1 << q):
+        m = int(e[lf + j] - b[lf + j])
+        Uj = arr["U"][off:off + m * kr[q]].reshape(kr[q], m).T
+        V.append((Uj @ G[lf + j]).ravel(order="F"))
+        off += m * kr[q]
+    F, off = [], 0
+    for l in range(1, q + 1):
+        for c in range((1 << l) - 1, (2 << l) - 1):
+            Ec = arr["E"][off:off + kr[l] * kr[l - 1]].reshape(kr[l - 1], kr[l]).T
+            off += kr[l] * kr[l - 1]
+            Fc = np.linalg.solve(G[c], Ec @ G[(c - 1) // 2]) if l > lmin else np.array(Ec)
+            F.append(Fc.ravel(order="F"))
+    S = []
+    for l in range(q + 1):
+        k, f = kr[l], (1 << l) - 1
+        rp, ci = arr["S_rowptr"][l], arr["S_colidx"][l]
+        Sl = np.array(arr["S"][l], dtype=np.float64, copy=True)
+        for i in range(1 << l):
+            for t in range(int(rp[i]), int(rp[i + 1])):
+                Sb = Sl[t * k * k:(t + 1) * k * k].reshape(k, k).T
+                Sl[t * k * k:(t + 1) * k * k] = np.linalg.solve(G[f + int(ci[t])], Sb.T).T.ravel(order="F")
+        S.append(Sl)
+    return dict(arr, V=np.concatenate(V), F=np.concatenate(F) if F else np.zeros(0), S=S)
+
+
+def _explicit_col_bases(arr):
+    return _explicit_bases(dict(arr, U=arr["V"], E=arr["F"]))
+
+
+@pytest.mark.parametrize("nonsym", [False, True], ids=["symmetric", "nonsymmetric"])
+def test_two_tree_representation_and_orthogonalization(oracle_mod, nonsym):
+    o = oracle_mod.OracleH2(_pts(1200, 2, 95), 32, 3, 0.9, 0.2)
+    arr = o.export_arrays()
+    if nonsym:
+        arr = _nonsymmetric_coupling(arr)
+    two = _two_trees(arr, 96)
+    assert not oracle_mod.shares_one_tree(two)
+    A = _dense_from_arrays(arr)
+    assert np.abs(_dense_from_arrays(two) - A).max() <= 1e-12 * np.abs(A).max()
+    orth, Tr, Tc = oracle_mod.orthogonalize_two_trees(two)
+    x = _x(1200, 97)
+    y0 = A @ x
+    assert np.linalg.norm(oracle_mod.arrays_matvec(orth, x) - y0) <= 1e-12 * np.linalg.norm(y0)
+    lmin = _levels_with_blocks(two)[0]
+    for expl, T, old in ((_explicit_bases(orth), Tr, _explicit_bases(two)),
+                         (_explicit_col_bases(orth), Tc, _explicit_col_bases(two))):
+        for v in range((1 << lmin) - 1, o.nnodes):
+            Q = expl[v]
+            assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() <= 1e-12
+            assert np.abs(Q @ T[v] - old[v]).max() <= 1e-10 * max(1.0, np.abs(old[v]).max())
+
+
+def test_two_tree_leaf_singular_values(oracle_mod):
+    """Row tree: W_i has the singular values of leaf i's row far field; column
+    tree: W'_i those of its column far field (brute force on the dense
+    matrix of a non-symmetric matrix written with two trees)."""
+    o = oracle_mod.OracleH2(_pts(700, 2, 98), 16, 3, 0.9, 0.2)
+    arr = _two_trees(_nonsymmetric_coupling(o.export_arrays()), 99)
+    A = _dense_from_arrays(arr)
+    _, info = oracle_mod.compress_arrays(arr, 0.0)
+    b, e = arr["begin"], arr["end"]
+    lf = (1 << o.q) - 1
+    checked = 0
+    for v in range(lf, 2 * lf + 1):
+        cols = _far_columns(arr, v)
+        if not len(cols):
+            continue
+        for M, got in ((A[b[v]:e[v]][:, cols], info["sigma"][v]), (A[cols][:, b[v]:e[v]].T, info["sigma_col"][v])):
+            s = np.linalg.svd(M, compute_uv=False)
+            ref = np.zeros(len(got))
+            ref[:min(len(s), len(got))] = s[:len(got)]
+            assert np.abs(got - ref).max() <= 1e-12 * ref.max()
+        checked += 1
+    assert checked > 0
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_two_tree_compression(oracle_mod, eps):
+    """Error below eps (Frobenius), ranks below the input's and equal to the
+    largest kept count over both trees; a symmetric matrix written with two
+    trees compresses to the same ranks and product as with one tree."""
+    o = oracle_mod.OracleH2(_pts(2500, 2, 100), 64, 5, 0.9, 0.2)
+    one = o.export_arrays()
+    for arr in (_two_trees(_nonsymmetric_coupling(one), 101), _two_trees(one, 102)):
+        out, info = oracle_mod.compress_arrays(arr, eps)
+        A0, A1 = _dense_from_arrays(arr), _dense_from_arrays(out)
+        assert np.linalg.norm(A1 - A0) <= eps * np.linalg.norm(A0)
+        for l in _levels_with_blocks(arr):
+            nodes = range((1 << l) - 1, (2 << l) - 1)
+            assert info["rank"][l] < o.k
+            assert info["rank"][l] == max(1, max(max(info["count"][v], info["count_col"][v]) for v in nodes))
+    ref, rinfo = oracle_mod.compress_arrays(one, eps)
+    assert list(out["level_rank"]) == list(ref["level_rank"])
+    x = _x(2500, 103)
+    y1, y2 = oracle_mod.arrays_matvec(out, x), oracle_mod.arrays_matvec(ref, x)
+    assert np.linalg.norm(y1 - y2) <= 1e-10 * np.linalg.norm(y2)
+
+
+def test_two_tree_rank_follows_the_column_tree(oracle_mod):
+    """Coupling blocks S_ij <- P_i P_i^T S_ij with a random rank-4 projector
+    P_i per row node: a leaf's block row needs 4 directions per level with
+    blocks (its own and its ancestors', through the transfers), its block
+    column many more.  The level's rank follows the column tree, and the
+    error stays below eps."""
+    o = oracle_mod.OracleH2(_pts(2500, 2, 104), 64, 5, 0.9, 0.2)
+    arr = o.export_arrays()
+    rng = np.random.Generator(np.random.PCG64(105))
+    S = []
+    for l in range(o.q + 1):
+        k, f = o.k, (1 << l) - 1
+        rp, ci = arr["S_rowptr"][l], arr["S_colidx"][l]
+        Sl = np.array(arr["S"][l], dtype=np.float64, copy=True)
+        for i in range(1 << l):
+            P = np.linalg.qr(rng.standard_normal((k, 4)))[0]
+            for t in range(int(rp[i]), int(rp[i + 1])):
+                Sb = Sl[t * k * k:(t + 1) * k * k].reshape(k, k).T
+                Sl[t * k * k:(t + 1) * k * k] = (P @ (P.T @ Sb)).ravel(order="F")
+        S.append(Sl)
+    arr = _two_trees(dict(arr, S=S), 106)
+    eps = 1e-8
+    out, info = oracle_mod.compress_arrays(arr, eps)
+    q = o.q
+    leaves = range((1 << q) - 1, (2 << q) - 1)
+    rows, cols = max(info["count"][v] for v in leaves), max(info["count_col"][v] for v in leaves)
+    assert rows <= 4 * len(_levels_with_blocks(arr)) and rows < cols == info["rank"][q]
+    A0, A1 = _dense_from_arrays(arr), _dense_from_arrays(out)
+    assert np.linalg.norm(A1 - A0) <= eps * np.linalg.norm(A0)
