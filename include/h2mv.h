@@ -192,14 +192,16 @@ h2_status h2_export_arrays(h2_handle A, const h2_arrays_out *out, void *stream);
  * blocks (Alg. 7), in place: every leaf basis becomes Q_j of U_j = Q_j T_j
  * (thin QR), every transfer pair below the first level with a coupling block
  * becomes the two blocks of Q in [T_c1 E_c1; T_c2 E_c2] = Q T_parent, and
- * every coupling block S_ij becomes T_i S_ij T_j^T.  The diagonals of the T
+ * every coupling block S_ij becomes T_i S_ij T'_j^T, where T' comes from the
+ * same steps on the column tree (V, F) when it differs from the row tree
+ * (T' = T when V = U and F = E).  The diagonals of the T
  * factors are made non-negative.  A (the product) is unchanged up to
  * rounding; the nested bases of all nodes used by coupling blocks become
  * orthonormal.  The call returns when the device work is done; a matrix
  * without coupling blocks is left as it is.
  * Errors: INVALID_ARG for NULL or structure-only handles; UNSUPPORTED for
- * storage other than H2_FP64, V != U or F != E, a leaf with fewer rows than
- * the leaf rank, or k_(l-1) > 2 k_l; DEVICE. */
+ * storage other than H2_FP64, a leaf with fewer rows than the leaf rank, or
+ * k_(l-1) > 2 k_l; DEVICE. */
 h2_status h2_orthogonalize(h2_handle A, void *stream);
 
 /* The transposed matrix A^T as a new handle (Sec. 2.2: A^T = sum over levels of
@@ -227,7 +229,11 @@ h2_status h2_transpose(h2_handle A, void *stream, h2_handle *out);
  * singular value is at least eps times its largest, a level the largest such
  * count over its nodes (at least 1, at most its rank); the kept vectors give
  * the new leaf bases and transfers and T_i = Q_i^T (old basis); then every
- * coupling block S_ij becomes T_i S_ij T_j^T.  Dense blocks are unchanged.
+ * coupling block S_ij becomes T_i S_ij T'_j^T.  A matrix whose column tree
+ * differs from its row tree (V != U or F != E) runs basis generation and
+ * truncation per tree (the column tree's R from the blocks S_ij of each block
+ * column under R'_parent F^T), a level's rank being the largest count over
+ * both trees, and T' from the column tree.  Dense blocks are unchanged.
  * The representation is rebuilt with the new per-level ranks (levels above
  * the first with coupling blocks take that level's rank) and the old one is
  * freed; products after the call use the new one.

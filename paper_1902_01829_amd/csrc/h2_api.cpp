@@ -1408,12 +1408,12 @@ h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *strea
 
 namespace {
 
-// Basis orthogonalization and projection of the coupling blocks in place.
+// Basis orthogonalization and projection of the coupling blocks in place
+// (one basis tree, or a row and a column tree of their own).
 void orthogonalize(h2_matrix_ &A, hipStream_t st) {
     const Structure &s = A.st;
     const int q = s.q;
     if (A.storage != H2_FP64) fail(H2_ERR_UNSUPPORTED, "orthogonalization needs FP64 storage");
-    if (!A.symmetric) fail(H2_ERR_UNSUPPORTED, "orthogonalization needs V = U and F = E");
     if (s.lmin > q) return;   // no coupling block: nothing to orthogonalize
     const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
     for (int64_t j = 0; j < nleaves; ++j)
@@ -1435,6 +1435,7 @@ void orthogonalize(h2_matrix_ &A, hipStream_t st) {
     L.basis = static_cast<double *>(A.basis);
     L.blocks = static_cast<double *>(A.blocks);
     L.T = static_cast<double *>(scratch.alloc(s.nnodes * int64_t(kmax) * kmax * 8));
+    if (!A.symmetric) L.T_col = static_cast<double *>(scratch.alloc(s.nnodes * int64_t(kmax) * kmax * 8));
     L.off_U = scratch.upload(A.off_U, st);
     L.off_VT = scratch.upload(A.off_VT, st);
     L.off_E = scratch.upload(A.off_E, st);
@@ -1630,18 +1631,20 @@ void adopt(h2_matrix_ &A, h2_matrix_ &B) {
 
 // Algebraic compression (Sec. 5): orthogonalization, basis generation,
 // truncation with relative threshold eps (rank of a level: the largest count
-// of kept singular values over its nodes), projection of the coupling blocks
-// into the truncated bases; the representation is rebuilt with the new ranks.
+// of kept singular values over its nodes, of both trees when rows and columns
+// have their own), projection of the coupling blocks into the truncated bases;
+// the representation is rebuilt with the new ranks.
 void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
     if (!(eps >= 0.0) || !std::isfinite(eps)) fail(H2_ERR_INVALID_ARG, "eps must be finite and >= 0");
     if (A.batch_refs > 0) fail(H2_ERR_INVALID_ARG, "the matrix belongs to a batch (free the batch first)");
     if (A.storage != H2_FP64) fail(H2_ERR_UNSUPPORTED, "compression needs FP64 storage");
-    if (!A.symmetric) fail(H2_ERR_UNSUPPORTED, "compression needs V = U and F = E");
-    // Whether S_ji = S_ij^T for every coupling block, decided before the
-    // orthogonalization (which keeps the symmetry only up to rounding): if
-    // not, the one basis tree also serves block columns that differ from the
-    // block rows, and the basis generation stacks both.
-    const bool sym = coupling_symmetric(A, st);
+    // One basis tree for rows and columns (V = U, F = E): whether S_ji = S_ij^T
+    // for every coupling block, decided before the orthogonalization (which
+    // keeps the symmetry only up to rounding); if not, the one tree also serves
+    // block columns that differ from the block rows, and the basis generation
+    // stacks both.  Two trees: each from its own blocks (rows / columns).
+    const bool two = !A.symmetric;
+    const bool sym = !two && coupling_symmetric(A, st);
     orthogonalize(A, st);
     const Structure &s = A.st;
     const int q = s.q, lmin = s.lmin, kmax = s.rank;
@@ -1665,7 +1668,7 @@ void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
             }
             row_start[s.nnodes] = int64_t(blk.size());
         }
-        // blocks of every block column (by column, rows increasing), for the non-symmetric case
+        // blocks of every block column (by column, rows increasing)
         std::vector<int64_t> col_blk, col_start(s.nnodes + 1, 0);
         if (!sym) {
             int64_t fi = 0;
@@ -1687,53 +1690,70 @@ void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
         DeviceArena scratch;
         const int64_t tree = s.nnodes * int64_t(kmax) * kmax;
         const int64_t maxlevel = std::max<int64_t>(nleaves, 1);
-        h2::CompLaunch L{};
-        L.basis = static_cast<const double *>(A.basis);
-        L.blocks = static_cast<const double *>(A.blocks);
-        L.off_U = scratch.upload(A.off_U, st);
-        L.off_E = scratch.upload(A.off_E, st);
-        L.leaf_begin = A.d_leaf_begin;
-        L.leaf_end = A.d_leaf_end;
-        L.blk = scratch.upload(blk, st);
-        L.row_start = scratch.upload(row_start, st);
-        L.columns = sym ? 0 : 1;
-        L.col_blk = scratch.upload(col_blk, st);
-        L.col_start = scratch.upload(col_start, st);
-        L.R = static_cast<double *>(scratch.alloc(tree * 8));
-        L.T = static_cast<double *>(scratch.alloc(tree * 8));
-        L.Enew = static_cast<double *>(scratch.alloc(tree * 8));
-        L.X = static_cast<double *>(scratch.alloc(maxlevel * h2::COMP_XSLOT * 8));
-        L.sigma = static_cast<double *>(scratch.alloc(maxlevel * 64 * 8));
-        L.count = static_cast<int32_t *>(scratch.alloc(maxlevel * 4));
-        L.Unew = static_cast<double *>(scratch.alloc(nleaves * h2::COMP_USLOT * 8));
-        L.first_leaf = lf;
-        L.nleaves = nleaves;
-        L.kmax = kmax;
+        // the launch of one tree: its bases, R, T, new bases and SVD buffers
+        auto tree_launch = [&](bool column_tree) {
+            h2::CompLaunch L{};
+            L.basis = static_cast<const double *>(A.basis);
+            L.blocks = static_cast<const double *>(A.blocks);
+            L.off_U = scratch.upload(column_tree ? A.off_VT : A.off_U, st);
+            L.off_E = scratch.upload(column_tree ? A.off_FT : A.off_E, st);
+            L.b_t = L.x_t = column_tree ? 1 : 0;
+            L.leaf_begin = A.d_leaf_begin;
+            L.leaf_end = A.d_leaf_end;
+            L.blk = scratch.upload(blk, st);
+            L.row_start = scratch.upload(row_start, st);
+            L.use_rows = column_tree ? 0 : 1;
+            L.columns = (column_tree || (!two && !sym)) ? 1 : 0;
+            L.col_blk = scratch.upload(col_blk, st);
+            L.col_start = scratch.upload(col_start, st);
+            L.R = static_cast<double *>(scratch.alloc(tree * 8));
+            L.T = static_cast<double *>(scratch.alloc(tree * 8));
+            L.Enew = static_cast<double *>(scratch.alloc(tree * 8));
+            L.X = static_cast<double *>(scratch.alloc(maxlevel * h2::COMP_XSLOT * 8));
+            L.sigma = static_cast<double *>(scratch.alloc(maxlevel * 64 * 8));
+            L.count = static_cast<int32_t *>(scratch.alloc(maxlevel * 4));
+            L.Unew = static_cast<double *>(scratch.alloc(nleaves * h2::COMP_USLOT * 8));
+            L.first_leaf = lf;
+            L.nleaves = nleaves;
+            L.kmax = kmax;
+            return L;
+        };
+        std::vector<h2::CompLaunch> trees{tree_launch(false)};
+        if (two) trees.push_back(tree_launch(true));
         // basis generation, top-down (Sec. 5.2)
-        for (int l = lmin; l <= q; ++l)
-            check_hip(h2::launch_basis_generation(L, l, kr[l], l > lmin ? kr[l - 1] : 0, l > lmin, st),
-                      "basis generation launch");
-        // truncation, bottom-up (Sec. 5.3); a level's rank is the largest kept count
+        for (const h2::CompLaunch &L : trees)
+            for (int l = lmin; l <= q; ++l)
+                check_hip(h2::launch_basis_generation(L, l, kr[l], l > lmin ? kr[l - 1] : 0, l > lmin, st),
+                          "basis generation launch");
+        // truncation, bottom-up (Sec. 5.3); a level's rank is the largest kept count over its nodes
+        // (of both trees)
         std::vector<int32_t> cnt;
         auto level_rank = [&](int64_t nodes, int bound) {
-            cnt.resize(size_t(nodes));
-            check_hip(hipMemcpyAsync(cnt.data(), L.count, size_t(nodes) * 4, hipMemcpyDeviceToHost, st),
-                      "hipMemcpyAsync");
-            check_hip(hipStreamSynchronize(st), "truncation");
             int r = 1;
-            for (int32_t c : cnt) r = std::max(r, int(c));
+            for (const h2::CompLaunch &L : trees) {
+                cnt.resize(size_t(nodes));
+                check_hip(hipMemcpyAsync(cnt.data(), L.count, size_t(nodes) * 4, hipMemcpyDeviceToHost, st),
+                          "hipMemcpyAsync");
+                check_hip(hipStreamSynchronize(st), "truncation");
+                for (int32_t c : cnt) r = std::max(r, int(c));
+            }
             return std::min(r, bound);
         };
-        check_hip(h2::launch_truncate_leaves(L, kr[q], eps, st), "truncation launch");
+        for (const h2::CompLaunch &L : trees)
+            check_hip(h2::launch_truncate_leaves(L, kr[q], eps, st), "truncation launch");
         kt[q] = level_rank(nleaves, kr[q]);
-        check_hip(h2::launch_truncate_leaves_apply(L, kr[q], kt[q], st), "truncation launch");
+        for (const h2::CompLaunch &L : trees)
+            check_hip(h2::launch_truncate_leaves_apply(L, kr[q], kt[q], st), "truncation launch");
         for (int l = q; l > lmin; --l) {
-            check_hip(h2::launch_truncate_level(L, l, kr[l], kt[l], kr[l - 1], eps, st), "truncation launch");
+            for (const h2::CompLaunch &L : trees)
+                check_hip(h2::launch_truncate_level(L, l, kr[l], kt[l], kr[l - 1], eps, st), "truncation launch");
             kt[l - 1] = level_rank(int64_t(1) << (l - 1), std::min(kr[l - 1], 2 * kt[l]));
-            check_hip(h2::launch_truncate_level_apply(L, l, kr[l], kt[l], kr[l - 1], kt[l - 1], st),
-                      "truncation launch");
+            for (const h2::CompLaunch &L : trees)
+                check_hip(h2::launch_truncate_level_apply(L, l, kr[l], kt[l], kr[l - 1], kt[l - 1], st),
+                          "truncation launch");
         }
         for (int l = 0; l < lmin; ++l) kt[l] = kt[lmin];
+        const h2::CompLaunch &Lr = trees.front(), &Lc = trees.back();
         // the representation with the new ranks
         std::unique_ptr<h2_matrix_> B(new h2_matrix_());
         B->st = s;
@@ -1743,29 +1763,32 @@ void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
         B->basis_kind = A.basis_kind;
         B->block_kind = A.block_kind;
         B->vec_f64 = A.vec_f64;
+        B->symmetric = A.symmetric;
         int64_t ncoupling = 0;
         const std::vector<h2::FillDesc> fill = make_layout(*B, ncoupling);
-        std::vector<h2::PlaceDesc> pu, pe;
+        std::vector<h2::PlaceDesc> pu, pv, pe, pf;
         for (int64_t j = 0; j < nleaves; ++j) {
             const int m = int(s.size(lf + j));
             pu.push_back({j * h2::COMP_USLOT, B->off_U[j], m, kt[q], 64, 0});
-            pu.push_back({j * h2::COMP_USLOT, B->off_VT[j], kt[q], m, 64, 1});
+            pv.push_back({j * h2::COMP_USLOT, B->off_VT[j], kt[q], m, 64, 1});
         }
         for (int l = lmin + 1; l <= q; ++l)
             for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
                 pe.push_back({c * kmax * kmax, B->off_E[c], kt[l], kt[l - 1], kmax, 0});
-                pe.push_back({c * kmax * kmax, B->off_FT[c], kt[l - 1], kt[l], kmax, 1});
+                pf.push_back({c * kmax * kmax, B->off_FT[c], kt[l - 1], kt[l], kmax, 1});
             }
         double *nbasis = static_cast<double *>(B->basis);
-        check_hip(h2::launch_place(L.Unew, nbasis, scratch.upload(pu, st), int64_t(pu.size()), st), "place launch");
-        check_hip(h2::launch_place(L.Enew, nbasis, scratch.upload(pe, st), int64_t(pe.size()), st), "place launch");
+        check_hip(h2::launch_place(Lr.Unew, nbasis, scratch.upload(pu, st), int64_t(pu.size()), st), "place launch");
+        check_hip(h2::launch_place(Lc.Unew, nbasis, scratch.upload(pv, st), int64_t(pv.size()), st), "place launch");
+        check_hip(h2::launch_place(Lr.Enew, nbasis, scratch.upload(pe, st), int64_t(pe.size()), st), "place launch");
+        check_hip(h2::launch_place(Lc.Enew, nbasis, scratch.upload(pf, st), int64_t(pf.size()), st), "place launch");
         for (size_t i = 0; i < blk.size(); ++i) {
             const int l = int(std::floor(std::log2(double(blk[i].row + 1))));
             blk[i].out = B->off_blk[i];
             blk[i].kout = kt[l];
         }
         check_hip(h2::launch_project(static_cast<const double *>(A.blocks), static_cast<double *>(B->blocks),
-                                     scratch.upload(blk, st), int64_t(blk.size()), L.T, kmax, st),
+                                     scratch.upload(blk, st), int64_t(blk.size()), Lr.T, Lc.T, kmax, st),
                   "projection launch");
         if (int64_t(fill.size()) > ncoupling) {   // dense blocks: same sizes and order
             const int64_t from = A.off_blk[size_t(ncoupling)], to = B->off_blk[size_t(ncoupling)];

@@ -12,6 +12,10 @@
 // whenever the next block would not fit (the same R up to row signs, which
 // the truncation does not see: it uses R only through R^T R).
 //
+// A matrix with a row and a column tree of their own runs basis generation
+// and truncation once per tree (the column tree from the block columns,
+// through V_j^T and F_c^T read transposed), a level taking the larger rank.
+//
 // Truncation, bottom-up: leaves decompose W_i = U_i R_i^T; as U_i has
 // orthonormal columns, the left singular vectors of W_i are U_i times those
 // of R_i^T, so the SVD runs on the k x k matrix R_i^T.  Parents decompose
@@ -126,10 +130,10 @@ __global__ __launch_bounds__(BG_THREADS) void basis_generation_kernel(CompLaunch
             tile[c * BG_TLD + r] = r < kp ? Rp[int64_t(c) * L.kmax + r] : 0.0;
         }
         __syncthreads();
-        const double *E = L.basis + L.off_E[node];   // k x kp
+        const double *E = L.basis + L.off_E[node];   // k x kp (or its transpose)
         if (col < k)
             for (int u = 0; u < kp; ++u) {
-                const double e = E[at2(k, col, u)];
+                const double e = L.x_t ? E[at2(kp, u, col)] : E[at2(k, col, u)];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) a[i] += tile[u * BG_TLD + j + 16 * i] * e;
             }
@@ -137,7 +141,7 @@ __global__ __launch_bounds__(BG_THREADS) void basis_generation_kernel(CompLaunch
     }
     // the stack's blocks: those of block row i, transposed, then (when the
     // coupling blocks are not symmetric) those of block column i as they are
-    const int64_t nrow = L.row_start[node + 1] - L.row_start[node];
+    const int64_t nrow = L.use_rows ? L.row_start[node + 1] - L.row_start[node] : 0;
     const int64_t nb = nrow + (L.columns ? L.col_start[node + 1] - L.col_start[node] : 0);
     const int ng = (k + 1) >> 1;
     int64_t b = 0;
@@ -237,11 +241,11 @@ __global__ __launch_bounds__(256) void truncate_leaves_apply_kernel(CompLaunch L
     const int t = threadIdx.x;
     const int64_t j = blockIdx.x, node = L.first_leaf + j;
     const int m = int(L.leaf_end[j] - L.leaf_begin[j]);
-    const double *U = L.basis + L.off_U[j];   // m x k
+    const double *U = L.basis + L.off_U[j];   // m x k (or its transpose)
     const double *X = L.X + j * COMP_XSLOT;
     for (int i = t; i < m * k; i += 256) {
         const int c = i / m, r = i - c * m;
-        Uo[c * SQ_LD + r] = U[at2(m, r, c)];
+        Uo[c * SQ_LD + r] = L.b_t ? U[at2(k, c, r)] : U[at2(m, r, c)];
     }
     for (int i = t; i < k * kt; i += 256) {
         const int c = i / k, r = i - c * k;
@@ -270,14 +274,14 @@ __device__ inline void form_z(const CompLaunch &L, int64_t p, int kc, int kt, in
     for (int h = 0; h < 2; ++h) {
         const int64_t ch = 2 * p + 1 + h;
         const double *Tc = L.T + ch * L.kmax * L.kmax;   // kt x kc
-        const double *E = L.basis + L.off_E[ch];        // kc x kp
+        const double *E = L.basis + L.off_E[ch];        // kc x kp (or its transpose)
         for (int i = t; i < kt * kc; i += 256) {
             const int c = i / kt, r = i - c * kt;
             Ts[c * SQ_LD + r] = Tc[int64_t(c) * L.kmax + r];
         }
         for (int i = t; i < kc * kp; i += 256) {
             const int c = i / kc, r = i - c * kc;
-            Es[c * SQ_LD + r] = E[at2(kc, r, c)];
+            Es[c * SQ_LD + r] = L.x_t ? E[at2(kp, c, r)] : E[at2(kc, r, c)];
         }
         __syncthreads();
         for (int i = t; i < kt * kp; i += 256) {

@@ -130,11 +130,12 @@ __device__ inline double dpp_sum16(double v) {   // over the 16 lanes of a DPP r
 // with s_j = |column j of G|: the columns of Y are left singular vectors of
 // B, orthonormal to rounding also where s_j = 0.  Pairs are visited in the
 // round-robin order of the cyclic parallel Jacobi method (n/2 disjoint pairs
-// per step, 8 adjacent threads per pair, sums by DPP); a pair is rotated when
-// |g_p . g_q| exceeds tol |g_p| |g_q| and neither column is negligible, i.e.
-// of norm at most 1e-15 |G|_F (rotations are norm preserving, so |G|_F is
-// fixed): such columns are rounding noise, and turning them changes a column
-// of norm s by at most 1e-15 |G|_F / s in direction.  Sweeps stop after one
+// per step, 8 adjacent threads per pair, 8 rows each held in registers, sums
+// by DPP); a pair is rotated when |g_p . g_q| exceeds tol |g_p| |g_q| and
+// neither column is negligible, i.e. of norm at most 1e-15 |G|_F (rotations
+// are norm preserving, so |G|_F is fixed): such columns are rounding noise,
+// and turning them changes a column of norm s by at most 1e-15 |G|_F / s in
+// direction.  Sweeps stop after one
 // without a rotation, or after max_sweeps.  n <= 64, L <= 64.  red is 64
 // doubles of LDS scratch.  Returns the number of sweeps done.
 __device__ inline int jacobi_svd(double *G, int ldg, int L, double *Y, int ldy, int n, double tol, int max_sweeps,
@@ -166,29 +167,45 @@ __device__ inline int jacobi_svd(double *G, int ldg, int L, double *Y, int ldy, 
                     q = x;
                 }
                 if (q < n) {
-                    double al = 0.0, be = 0.0, ga = 0.0;
-                    for (int r = sub; r < L; r += 8) {
-                        const double gp = G[p * ldg + r], gq = G[q * ldg + r];
-                        al += gp * gp;
-                        be += gq * gq;
-                        ga += gp * gq;
+                    // this thread's rows sub, sub + 8, ... of both columns, all loads issued at once
+                    double gp[8], gq[8], al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int r = sub + 8 * i;
+                        gp[i] = r < L ? G[p * ldg + r] : 0.0;
+                        gq[i] = r < L ? G[q * ldg + r] : 0.0;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        al += gp[i] * gp[i];
+                        be += gq[i] * gq[i];
+                        ga += gp[i] * gq[i];
                     }
                     al = dpp_sum8(al);
                     be = dpp_sum8(be);
                     ga = dpp_sum8(ga);
-                    if (ga != 0.0 && al > negligible && be > negligible && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+                    if (ga != 0.0 && al > negligible && be > negligible && ga * ga > tol * tol * al * be) {
                         const double zeta = (be - al) / (2.0 * ga);
                         const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                         const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-                        for (int r = sub; r < L; r += 8) {
-                            const double gp = G[p * ldg + r], gq = G[q * ldg + r];
-                            G[p * ldg + r] = cs * gp - sn * gq;
-                            G[q * ldg + r] = sn * gp + cs * gq;
+                        double yp[8], yq[8];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int r = sub + 8 * i;
+                            yp[i] = r < n ? Y[p * ldy + r] : 0.0;
+                            yq[i] = r < n ? Y[q * ldy + r] : 0.0;
                         }
-                        for (int r = sub; r < n; r += 8) {
-                            const double yp = Y[p * ldy + r], yq = Y[q * ldy + r];
-                            Y[p * ldy + r] = cs * yp - sn * yq;
-                            Y[q * ldy + r] = sn * yp + cs * yq;
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int r = sub + 8 * i;
+                            if (r < L) {
+                                G[p * ldg + r] = cs * gp[i] - sn * gq[i];
+                                G[q * ldg + r] = sn * gp[i] + cs * gq[i];
+                            }
+                            if (r < n) {
+                                Y[p * ldy + r] = cs * yp[i] - sn * yq[i];
+                                Y[q * ldy + r] = sn * yp[i] + cs * yq[i];
+                            }
                         }
                         if (sub == 0) *flag = 1;
                     }

@@ -1,10 +1,11 @@
 // Basis orthogonalization and projection of the coupling blocks (Sec. 5.1,
-// Alg. 6 and Alg. 7), FP64, for the symmetric case U = V, E = F.
+// Alg. 6 and Alg. 7), FP64, for one basis tree serving rows and columns
+// (U = V, E = F) or a row and a column tree of their own.
 //
 // Leaves: U_j = Q_j T_j (thin Householder QR), Q_j the new leaf basis.  Up the
 // tree, parent p with children c1, c2: Z = [T_c1 E_c1; T_c2 E_c2] = Q T_p, the
-// two blocks of Q the new transfers.  Then every coupling block S_ij becomes
-// T_i S_ij T_j^T.  The diagonal of every T is made non-negative, which makes
+// two blocks of Q the new transfers (the column tree likewise with V and F,
+// giving T').  Then every coupling block S_ij becomes T_i S_ij T'_j^T.  The diagonal of every T is made non-negative, which makes
 // the factorization unique for full-column-rank inputs.
 //
 // One workgroup (256 threads) per factorization or per coupling block; the
@@ -25,30 +26,38 @@ using namespace lds;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-__global__ __launch_bounds__(256) void orth_leaf_kernel(double *basis, const int64_t *off_U, const int64_t *off_VT,
+// A leaf basis is read from `in` (as stored: M x N, or its N x M transpose
+// when in_t) and Q is written to out_n (M x N) and/or out_t (N x M, the
+// transpose), either of which may be NULL: one tree for rows and columns
+// writes both U_j and V_j^T, a tree of its own only its own.
+__global__ __launch_bounds__(256) void orth_leaf_kernel(double *basis, const int64_t *in, int in_t,
+                                                        const int64_t *out_n, const int64_t *out_t,
                                                         const int64_t *leaf_begin, const int64_t *leaf_end, int kq,
                                                         double *T, int kmax, int64_t first_leaf) {
     __shared__ double A[(64 + QR_PAD) * QR_MAXN], tau[QR_MAXN], sgn[QR_MAXN], scal[2];
     const int64_t j = blockIdx.x;
     const int M = int(leaf_end[j] - leaf_begin[j]), N = kq;
-    double *U = basis + off_U[j], *VT = basis + off_VT[j];
+    const double *B = basis + in[j];
     const int ld = M + QR_PAD;
     for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
         const int c = i / M, r = i - c * M;
-        A[c * ld + r] = U[at2(M, r, c)];
+        A[c * ld + r] = in_t ? B[at2(N, c, r)] : B[at2(M, r, c)];
     }
     __syncthreads();
     householder_qr(A, tau, scal, sgn, M, N, T + (first_leaf + j) * kmax * kmax, kmax);
     for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
         const int c = i / M, r = i - c * M;
-        U[at2(M, r, c)] = A[c * ld + r];       // U_j: M x N
-        VT[at2(N, c, r)] = A[c * ld + r];      // V_j^T: N x M
+        if (out_n) basis[out_n[j] + at2(M, r, c)] = A[c * ld + r];   // M x N
+        if (out_t) basis[out_t[j] + at2(N, c, r)] = A[c * ld + r];   // N x M
     }
 }
 
 // Parents of level l - 1 (2^(l-1) workgroups): Z = [T_c1 E_c1; T_c2 E_c2].
-__global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const int64_t *off_E, const int64_t *off_FT,
-                                                         int kc, int kp, double *T, int kmax, int64_t first_parent) {
+// Transfers are read from `in` (kc x kp as stored, or its transpose when
+// in_t) and the new ones written to out_n (kc x kp) and/or out_t (kp x kc).
+__global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const int64_t *in, int in_t,
+                                                         const int64_t *out_n, const int64_t *out_t, int kc, int kp,
+                                                         double *T, int kmax, int64_t first_parent) {
     __shared__ double A[(QR_MAXM + QR_PAD) * QR_MAXN], tau[QR_MAXN], sgn[QR_MAXN], scal[2];
     const int64_t p = first_parent + blockIdx.x;
     const int M = 2 * kc, N = kp, ld = M + QR_PAD;
@@ -60,7 +69,7 @@ __global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const in
         const int nrt = (kc + 15) >> 4, nct = (kp + 15) >> 4;
         for (int h = 0; h < 2; ++h) {
             const int64_t ch = 2 * p + 1 + h;
-            const double *E = basis + off_E[ch];                    // kc x kp
+            const double *E = basis + in[ch];                       // kc x kp (or its transpose)
             const double *Tc = T + ch * kmax * kmax;                // kc x kc, upper triangular
             if (wv < nrt) {
                 const int r0 = 16 * wv;
@@ -78,7 +87,8 @@ __global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const in
 #pragma unroll
                     for (int s4 = 0; s4 < 16; ++s4) {
                         const int kk = 4 * s4 + lk;
-                        eb[s4] = (kk < kc && col < kp) ? E[at2(kc, kk, col)] : 0.0;          // E(kk, col)
+                        eb[s4] = (kk < kc && col < kp) ? (in_t ? E[at2(kp, col, kk)] : E[at2(kc, kk, col)])
+                                                        : 0.0;   // E(kk, col)
                     }
                     // all 16 steps, with no early exit: the operand arrays keep static
                     // register indices (steps past the rank multiply zeros)
@@ -99,12 +109,11 @@ __global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const in
     householder_qr(A, tau, scal, sgn, M, N, T + p * kmax * kmax, kmax);
     for (int h = 0; h < 2; ++h) {
         const int64_t ch = 2 * p + 1 + h;
-        double *E = basis + off_E[ch], *FT = basis + off_FT[ch];
         for (int i = threadIdx.x; i < kc * kp; i += blockDim.x) {
             const int c = i / kc, r = i - c * kc;
             const double v = A[c * ld + h * kc + r];
-            E[at2(kc, r, c)] = v;       // E_c: kc x kp
-            FT[at2(kp, c, r)] = v;      // F_c^T: kp x kc
+            if (out_n) basis[out_n[ch] + at2(kc, r, c)] = v;   // kc x kp
+            if (out_t) basis[out_t[ch] + at2(kp, c, r)] = v;   // kp x kc
         }
     }
 }
@@ -137,7 +146,7 @@ __device__ inline void proj_load(const double *blocks, const ProjDesc &d, f64x2 
 }
 
 __global__ __launch_bounds__(256) void project_kernel(const double *in, double *outp, const ProjDesc *desc,
-                                                      int64_t nblocks, const double *T, int kmax) {
+                                                      int64_t nblocks, const double *T, const double *Tcol, int kmax) {
     __shared__ double S[64 * PS_LD];     // column-major
     __shared__ double Wl[4][16 * 64];    // per wave: 16 x 64, column-major, ld 16
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
@@ -159,7 +168,7 @@ __global__ __launch_bounds__(256) void project_kernel(const double *in, double *
         }
         __syncthreads();
         if (b + 1 < b1) proj_load(in, desc[b + 1], nxt);   // in flight during the products
-        const double *Ti = T + d.row * kmax * kmax, *Tj = T + d.col * kmax * kmax;
+        const double *Ti = T + d.row * kmax * kmax, *Tj = Tcol + d.col * kmax * kmax;
         const int r0 = 16 * wv;
         if (wv < nto) {
             double ta[16];   // T_i(r0 + lr, 4 s + lk)
@@ -222,29 +231,46 @@ __global__ __launch_bounds__(256) void project_kernel(const double *in, double *
 
 }  // namespace
 
-hipError_t launch_orthogonalize(const OrthLaunch &L, hipStream_t st) {
-    if (L.nleaves <= 0) return hipSuccess;
-    if (L.kmax < 1 || L.kmax > QR_MAXN) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(orth_leaf_kernel, dim3(unsigned(L.nleaves)), dim3(256), 0, st, L.basis, L.off_U, L.off_VT,
-                       L.leaf_begin, L.leaf_end, L.level_rank[L.q], L.T, L.kmax, L.first_leaf);
+// One tree up: leaves, then levels q .. lmin+1.
+static hipError_t orthogonalize_tree(const OrthLaunch &L, const int64_t *leaf_in, int leaf_t, const int64_t *leaf_n,
+                              const int64_t *leaf_tr, const int64_t *xfer_in, int xfer_t, const int64_t *xfer_n,
+                              const int64_t *xfer_tr, double *T, hipStream_t st) {
+    hipLaunchKernelGGL(orth_leaf_kernel, dim3(unsigned(L.nleaves)), dim3(256), 0, st, L.basis, leaf_in, leaf_t, leaf_n,
+                       leaf_tr, L.leaf_begin, L.leaf_end, L.level_rank[L.q], T, L.kmax, L.first_leaf);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (int l = L.q; l > L.lmin; --l) {
         const int64_t nparents = int64_t(1) << (l - 1);
-        hipLaunchKernelGGL(orth_level_kernel, dim3(unsigned(nparents)), dim3(256), 0, st, L.basis, L.off_E, L.off_FT,
-                           L.level_rank[l], L.level_rank[l - 1], L.T, L.kmax, nparents - 1);
+        hipLaunchKernelGGL(orth_level_kernel, dim3(unsigned(nparents)), dim3(256), 0, st, L.basis, xfer_in, xfer_t,
+                           xfer_n, xfer_tr, L.level_rank[l], L.level_rank[l - 1], T, L.kmax, nparents - 1);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return launch_project(L.blocks, L.blocks, L.proj, L.nproj, L.T, L.kmax, st);
+    return hipSuccess;
 }
 
-hipError_t launch_project(const double *in, double *out, const ProjDesc *desc, int64_t n, const double *T, int kmax,
-                          hipStream_t st) {
+hipError_t launch_orthogonalize(const OrthLaunch &L, hipStream_t st) {
+    if (L.nleaves <= 0) return hipSuccess;
+    if (L.kmax < 1 || L.kmax > QR_MAXN) return hipErrorInvalidValue;
+    hipError_t e;
+    if (!L.T_col) {   // one tree: U_j and V_j^T, E_c and F_c^T written together
+        e = orthogonalize_tree(L, L.off_U, 0, L.off_U, L.off_VT, L.off_E, 0, L.off_E, L.off_FT, L.T, st);
+        if (e != hipSuccess) return e;
+        return launch_project(L.blocks, L.blocks, L.proj, L.nproj, L.T, L.T, L.kmax, st);
+    }
+    e = orthogonalize_tree(L, L.off_U, 0, L.off_U, nullptr, L.off_E, 0, L.off_E, nullptr, L.T, st);
+    if (e != hipSuccess) return e;
+    e = orthogonalize_tree(L, L.off_VT, 1, nullptr, L.off_VT, L.off_FT, 1, nullptr, L.off_FT, L.T_col, st);
+    if (e != hipSuccess) return e;
+    return launch_project(L.blocks, L.blocks, L.proj, L.nproj, L.T, L.T_col, L.kmax, st);
+}
+
+hipError_t launch_project(const double *in, double *out, const ProjDesc *desc, int64_t n, const double *T,
+                          const double *T_col, int kmax, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (kmax < 1 || kmax > QR_MAXN) return hipErrorInvalidValue;
     const int64_t grid = n < 65536 ? n : 65536;
-    hipLaunchKernelGGL(project_kernel, dim3(unsigned(grid)), dim3(256), 0, st, in, out, desc, n, T, kmax);
+    hipLaunchKernelGGL(project_kernel, dim3(unsigned(grid)), dim3(256), 0, st, in, out, desc, n, T, T_col, kmax);
     return hipGetLastError();
 }
 

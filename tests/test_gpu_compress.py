@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from paper_1902_01829_amd import workloads as W
-from test_oracle import _explicit_bases, _inflate, _nonsymmetric_coupling
+from test_oracle import _explicit_bases, _explicit_col_bases, _inflate, _nonsymmetric_coupling, _two_trees
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -144,6 +144,65 @@ def test_compress_nonsymmetric_coupling_matches_oracle(oracle_mod, d, eps):
                   for v in range((1 << lmin) - 1, o.nnodes))
     print(f"d={d} eps={eps}: ranks {[int(r) for r in ranks]} vs oracle {par:.2e}, vs uncompressed {err:.2e}, "
           f"orthonormality {worst_o:.1e}", flush=True)
+    assert par <= PARITY_TOL
+    assert err <= eps
+    assert worst_o <= ORTHO_TOL
+
+
+def _row_projected(arr, r, seed):
+    """Coupling blocks S_ij <- P_i P_i^T S_ij, P_i a random rank-r projector
+    per row node: block rows need few directions, block columns many."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    S = []
+    for l in range(int(arr["q"]) + 1):
+        k = int(arr["level_rank"][l])
+        rp = arr["S_rowptr"][l]
+        Sl = np.array(arr["S"][l], dtype=np.float64, copy=True)
+        for i in range(1 << l):
+            P = np.linalg.qr(rng.standard_normal((k, r)))[0]
+            for t in range(int(rp[i]), int(rp[i + 1])):
+                Sb = Sl[t * k * k:(t + 1) * k * k].reshape(k, k).T
+                Sl[t * k * k:(t + 1) * k * k] = (P @ (P.T @ Sb)).ravel(order="F")
+        S.append(Sl)
+    return dict(arr, S=S)
+
+
+@pytest.mark.parametrize("case,eps", [("nonsymmetric", 1e-6), ("nonsymmetric", 1e-4), ("row-projected", 1e-8)])
+def test_compress_two_trees_matches_oracle(oracle_mod, case, eps):
+    """Different row and column trees (V != U, F != E): each tree's R from its
+    own blocks, a level's rank the larger count of the two trees; ranks,
+    products and both trees' orthonormality against the oracle's
+    compress_two_trees.  The row-projected case has the column tree decide
+    the ranks."""
+    h2mv = _h2mv()
+    n = 4000
+    pts = np.random.Generator(np.random.PCG64(680)).random((n, 2))
+    o = oracle_mod.OracleH2(pts, 64, 5, 0.9, 0.2)
+    base = o.export_arrays()
+    base = _nonsymmetric_coupling(base) if case == "nonsymmetric" else _row_projected(base, 4, 681)
+    arr = _two_trees(base, 682)
+    ref, info = oracle_mod.compress_arrays(arr, eps)
+    _check_margin(info, eps)
+    _check_margin({"sigma": info["sigma_col"]}, eps)
+    A = h2mv.H2Matrix.from_arrays(arr, storage=0)
+    ranks = A.compress(eps)
+    assert list(ranks) == [int(r) for r in ref["level_rank"]], (list(ranks), list(ref["level_rank"]))
+    x = np.random.Generator(np.random.PCG64(683)).standard_normal(n)
+    y = A.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    par, err = _rel(y, oracle_mod.arrays_matvec(ref, x)), _rel(y, oracle_mod.arrays_matvec(arr, x))
+    got = h2mv.h2_export_arrays(A.handle)
+    lmin = _lmin(got)
+    worst_o = 0.0
+    for expl in (_explicit_bases(got), _explicit_col_bases(got)):
+        worst_o = max(worst_o, max(float(np.abs(expl[v].T @ expl[v] - np.eye(expl[v].shape[1])).max())
+                                   for v in range((1 << lmin) - 1, o.nnodes)))
+    q = o.q
+    leaves = range((1 << q) - 1, (2 << q) - 1)
+    rows, cols = max(info["count"][v] for v in leaves), max(info["count_col"][v] for v in leaves)
+    print(f"{case} eps={eps}: ranks {[int(r) for r in ranks]} (leaf counts rows {rows}, columns {cols}) vs oracle "
+          f"{par:.2e}, vs uncompressed {err:.2e}, orthonormality {worst_o:.1e}", flush=True)
+    if case == "row-projected":
+        assert rows < cols
     assert par <= PARITY_TOL
     assert err <= eps
     assert worst_o <= ORTHO_TOL

@@ -141,3 +141,32 @@ def test_orthogonalize_rejections():
             h2mv.h2_orthogonalize(A.handle)
         assert e.value.code == h2mv.H2_ERR_UNSUPPORTED
         A.close()
+
+
+def test_orthogonalize_two_trees_matches_oracle(oracle_mod):
+    """A non-symmetric matrix written with different row and column trees
+    (V != U, F != E): both trees orthogonalized, S <- T S T'^T; factors
+    against the oracle's orthogonalize_two_trees, product unchanged."""
+    from test_oracle import _nonsymmetric_coupling, _two_trees
+    h2mv = _h2mv()
+    n = 3000
+    pts = np.random.Generator(np.random.PCG64(508)).random((n, 2))
+    o = oracle_mod.OracleH2(pts, 32, 4, 0.9, 0.2)
+    arr = _two_trees(_nonsymmetric_coupling(o.export_arrays()), 509)
+    A = h2mv.H2Matrix.from_arrays(arr, 0)
+    x = np.random.Generator(np.random.PCG64(510)).standard_normal(n)
+    y0 = oracle_mod.arrays_matvec(arr, x)
+    h2mv.h2_orthogonalize(A.handle)
+    y = A.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    got = h2mv.h2_export_arrays(A.handle)
+    ref, _, _ = oracle_mod.orthogonalize_two_trees(arr)
+    q, lr = o.q, arr["level_rank"]
+    lmin = _lmin(ref)
+    mask = np.concatenate([np.full(int(lr[l]) * int(lr[l - 1]) << l, l > lmin) for l in range(1, q + 1)])
+    d = max(_max_rel(got["U"], ref["U"]), _max_rel(got["V"], ref["V"]), _max_rel(got["E"][mask], ref["E"][mask]),
+            _max_rel(got["F"][mask], ref["F"][mask]),
+            max(_max_rel(got["S"][l], ref["S"][l]) for l in range(q + 1) if len(ref["S_colidx"][l])))
+    print(f"  product change {np.linalg.norm(y - y0) / np.linalg.norm(y0):.2e}; vs oracle factors {d:.2e}", flush=True)
+    assert np.linalg.norm(y - y0) <= PRODUCT_TOL * np.linalg.norm(y0)
+    assert d <= FACTOR_TOL
+    A.close()
