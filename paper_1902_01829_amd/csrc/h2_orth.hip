@@ -27,10 +27,11 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // A leaf basis is read from `in` (as stored: M x N, or its N x M transpose
-// when in_t) and Q is written to out_n (M x N) and/or out_t (N x M, the
+// when IN_T) and Q is written to out_n (M x N) and/or out_t (N x M, the
 // transpose), either of which may be NULL: one tree for rows and columns
 // writes both U_j and V_j^T, a tree of its own only its own.
-__global__ __launch_bounds__(256) void orth_leaf_kernel(double *basis, const int64_t *in, int in_t,
+template <bool IN_T>
+__global__ __launch_bounds__(256) void orth_leaf_kernel(double *basis, const int64_t *in,
                                                         const int64_t *out_n, const int64_t *out_t,
                                                         const int64_t *leaf_begin, const int64_t *leaf_end, int kq,
                                                         double *T, int kmax, int64_t first_leaf) {
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(256) void orth_leaf_kernel(double *basis, const int
     const int ld = M + QR_PAD;
     for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
         const int c = i / M, r = i - c * M;
-        A[c * ld + r] = in_t ? B[at2(N, c, r)] : B[at2(M, r, c)];
+        A[c * ld + r] = IN_T ? B[at2(N, c, r)] : B[at2(M, r, c)];
     }
     __syncthreads();
     householder_qr(A, tau, scal, sgn, M, N, T + (first_leaf + j) * kmax * kmax, kmax);
@@ -54,8 +55,9 @@ __global__ __launch_bounds__(256) void orth_leaf_kernel(double *basis, const int
 
 // Parents of level l - 1 (2^(l-1) workgroups): Z = [T_c1 E_c1; T_c2 E_c2].
 // Transfers are read from `in` (kc x kp as stored, or its transpose when
-// in_t) and the new ones written to out_n (kc x kp) and/or out_t (kp x kc).
-__global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const int64_t *in, int in_t,
+// IN_T) and the new ones written to out_n (kc x kp) and/or out_t (kp x kc).
+template <bool IN_T>
+__global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const int64_t *in,
                                                          const int64_t *out_n, const int64_t *out_t, int kc, int kp,
                                                          double *T, int kmax, int64_t first_parent) {
     __shared__ double A[(QR_MAXM + QR_PAD) * QR_MAXN], tau[QR_MAXN], sgn[QR_MAXN], scal[2];
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const in
 #pragma unroll
                     for (int s4 = 0; s4 < 16; ++s4) {
                         const int kk = 4 * s4 + lk;
-                        eb[s4] = (kk < kc && col < kp) ? (in_t ? E[at2(kp, col, kk)] : E[at2(kc, kk, col)])
+                        eb[s4] = (kk < kc && col < kp) ? (IN_T ? E[at2(kp, col, kk)] : E[at2(kc, kk, col)])
                                                         : 0.0;   // E(kk, col)
                     }
                     // all 16 steps, with no early exit: the operand arrays keep static
@@ -232,16 +234,18 @@ __global__ __launch_bounds__(256) void project_kernel(const double *in, double *
 }  // namespace
 
 // One tree up: leaves, then levels q .. lmin+1.
-static hipError_t orthogonalize_tree(const OrthLaunch &L, const int64_t *leaf_in, int leaf_t, const int64_t *leaf_n,
-                              const int64_t *leaf_tr, const int64_t *xfer_in, int xfer_t, const int64_t *xfer_n,
-                              const int64_t *xfer_tr, double *T, hipStream_t st) {
-    hipLaunchKernelGGL(orth_leaf_kernel, dim3(unsigned(L.nleaves)), dim3(256), 0, st, L.basis, leaf_in, leaf_t, leaf_n,
+// (IN_T: the tree is stored transposed, V_j^T and F_c^T: the column tree.)
+template <bool IN_T>
+static hipError_t orthogonalize_tree(const OrthLaunch &L, const int64_t *leaf_in, const int64_t *leaf_n,
+                                     const int64_t *leaf_tr, const int64_t *xfer_in, const int64_t *xfer_n,
+                                     const int64_t *xfer_tr, double *T, hipStream_t st) {
+    hipLaunchKernelGGL(orth_leaf_kernel<IN_T>, dim3(unsigned(L.nleaves)), dim3(256), 0, st, L.basis, leaf_in, leaf_n,
                        leaf_tr, L.leaf_begin, L.leaf_end, L.level_rank[L.q], T, L.kmax, L.first_leaf);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (int l = L.q; l > L.lmin; --l) {
         const int64_t nparents = int64_t(1) << (l - 1);
-        hipLaunchKernelGGL(orth_level_kernel, dim3(unsigned(nparents)), dim3(256), 0, st, L.basis, xfer_in, xfer_t,
+        hipLaunchKernelGGL(orth_level_kernel<IN_T>, dim3(unsigned(nparents)), dim3(256), 0, st, L.basis, xfer_in,
                            xfer_n, xfer_tr, L.level_rank[l], L.level_rank[l - 1], T, L.kmax, nparents - 1);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -254,13 +258,13 @@ hipError_t launch_orthogonalize(const OrthLaunch &L, hipStream_t st) {
     if (L.kmax < 1 || L.kmax > QR_MAXN) return hipErrorInvalidValue;
     hipError_t e;
     if (!L.T_col) {   // one tree: U_j and V_j^T, E_c and F_c^T written together
-        e = orthogonalize_tree(L, L.off_U, 0, L.off_U, L.off_VT, L.off_E, 0, L.off_E, L.off_FT, L.T, st);
+        e = orthogonalize_tree<false>(L, L.off_U, L.off_U, L.off_VT, L.off_E, L.off_E, L.off_FT, L.T, st);
         if (e != hipSuccess) return e;
         return launch_project(L.blocks, L.blocks, L.proj, L.nproj, L.T, L.T, L.kmax, st);
     }
-    e = orthogonalize_tree(L, L.off_U, 0, L.off_U, nullptr, L.off_E, 0, L.off_E, nullptr, L.T, st);
+    e = orthogonalize_tree<false>(L, L.off_U, L.off_U, nullptr, L.off_E, L.off_E, nullptr, L.T, st);
     if (e != hipSuccess) return e;
-    e = orthogonalize_tree(L, L.off_VT, 1, nullptr, L.off_VT, L.off_FT, 1, nullptr, L.off_FT, L.T_col, st);
+    e = orthogonalize_tree<true>(L, L.off_VT, nullptr, L.off_VT, L.off_FT, nullptr, L.off_FT, L.T_col, st);
     if (e != hipSuccess) return e;
     return launch_project(L.blocks, L.blocks, L.proj, L.nproj, L.T, L.T_col, L.kmax, st);
 }
