@@ -306,3 +306,57 @@ def test_compress_full_size_2d(oracle_mod):
     assert err <= levels * 1e-7
     assert int(ranks[A.info.lmin:].max()) < 64
     assert bytes1 < bytes0
+
+
+def test_compress_without_coupling_blocks():
+    """A single leaf (only a dense block): nothing to compress; ranks and
+    product unchanged."""
+    h2mv = _h2mv()
+    rng = np.random.Generator(np.random.PCG64(690))
+    n = 40
+    D = rng.standard_normal((n, n))
+    arr = {"n": n, "q": 0, "level_rank": np.array([8], dtype=np.int32), "begin": np.array([0]),
+           "end": np.array([n]), "U": np.zeros(8 * n), "V": np.zeros(8 * n), "E": np.zeros(0), "F": np.zeros(0),
+           "S_rowptr": [np.array([0, 0], dtype=np.int32)], "S_colidx": [np.zeros(0, dtype=np.int32)],
+           "S": [np.zeros(0)], "D_rowptr": np.array([0, 1], dtype=np.int32),
+           "D_colidx": np.array([0], dtype=np.int32), "D": D.ravel(order="F")}
+    A = h2mv.H2Matrix.from_arrays(arr, storage=0)
+    x = rng.standard_normal(n)
+    ranks = A.compress(1e-3)
+    assert list(ranks) == [8]
+    y = A.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert _rel(y, D @ x) <= 1e-14
+
+
+def test_compress_twice_does_not_grow():
+    """Compressing a compressed matrix again at the same threshold keeps or
+    lowers every rank and changes the product by less than eps per level."""
+    h2mv = _h2mv()
+    w = W.C1.with_(name="2d-n8192-m64-p6", n=8192, leaf=64, cheb_p=6, seed=691)
+    A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=0)
+    x = torch.from_numpy(W.rhs(w)[A.perm()]).cuda()
+    r1 = A.compress(1e-6)
+    y1 = A.matvec(x).cpu().numpy()
+    r2 = A.compress(1e-6)
+    y2 = A.matvec(x).cpu().numpy()
+    print(f"ranks {[int(r) for r in r1]} -> {[int(r) for r in r2]}, product change {_rel(y2, y1):.2e}", flush=True)
+    assert all(int(b) <= int(a) for a, b in zip(r1, r2))
+    assert _rel(y2, y1) <= 1e-6 * (A.info.levels_q - A.info.lmin + 1)
+
+
+def test_transpose_of_a_compressed_nonsymmetric_matrix(oracle_mod):
+    """Per-level ranks after compression, then the transposed handle: its
+    product is the oracle's product of the transposed compressed arrays."""
+    h2mv = _h2mv()
+    n = 3000
+    pts = np.random.Generator(np.random.PCG64(692)).random((n, 2))
+    o = oracle_mod.OracleH2(pts, 64, 5, 0.9, 0.2)
+    arr = _two_trees(_nonsymmetric_coupling(o.export_arrays()), 693)
+    A = h2mv.H2Matrix.from_arrays(arr, storage=0)
+    A.compress(1e-5)
+    At = A.transpose()
+    got = h2mv.h2_export_arrays(A.handle)
+    ref = oracle_mod.transpose_arrays(got)
+    x = np.random.Generator(np.random.PCG64(694)).standard_normal(n)
+    y = At.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert _rel(y, oracle_mod.arrays_matvec(ref, x)) <= 1e-12
