@@ -97,7 +97,17 @@ struct WorkList {
     const h2::BlkDesc *blks;
     const int32_t *items = nullptr;   // tile lists: wavefront items in dispatch order
     int64_t nitems = 0;
+    // split stream list (single vector, small matrices): the rows are chunks
+    // writing FP64 partial sums, added up by a second launch
+    const h2::ReduceDesc *red = nullptr;
+    int64_t nred = 0;
+    double *partials = nullptr;
 };
+
+// A single-vector stream list with fewer block rows than this is split into
+// chunks: one wavefront per row would leave most of the machine idle.
+constexpr int64_t kSplitRows = 4096;
+constexpr int64_t kSplitWaves = 4096;   // target number of chunks (about 16 per CU)
 
 // Wavefront items of a tile list in dispatch order (see h2::MmLaunch): one
 // item per 32-row half of each row, the list cut into MM_XCDS contiguous
@@ -574,7 +584,46 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
         // Single right-hand side: the vector trees fit in the caches; longest
         // rows first, so the wavefronts that start last are the short ones.
         std::stable_sort(L.begin(), L.end(), [](const LRow &a, const LRow &b) { return a.b.size() > b.b.size(); });
-        emit_one(0, PH_STREAM, sk, A.blocks, L);
+        int64_t nblk = 0;
+        for (const LRow &r : L) nblk += int64_t(r.b.size());
+        if (int64_t(L.size()) < kSplitRows && nblk > int64_t(L.size())) {
+            // few rows: every row cut into chunks of `chunk` blocks, one wavefront
+            // each, writing FP64 partial sums that a second launch adds up per row
+            const int chunk = int(std::max<int64_t>(1, (nblk + kSplitWaves - 1) / kSplitWaves));
+            std::vector<RowDesc> rows;
+            std::vector<BlkDesc> blks;
+            std::vector<h2::ReduceDesc> red;
+            for (const LRow &r : L) {
+                const int nb = int(r.b.size()), nc = std::max(1, (nb + chunk - 1) / chunk);
+                red.push_back({mv_off(r.point, r.id), int32_t(rows.size()), int32_t(rows.size() + nc), r.R,
+                               r.point ? 1 : 0});
+                for (int c = 0; c < nc; ++c) {
+                    RowDesc d;
+                    d.out = int64_t(rows.size()) * 64;
+                    d.init = -1;
+                    d.R = r.R;
+                    d.sel = (r.sel & h2::ROW_IN_X) | h2::ROW_OUT_P;
+                    d.b0 = int32_t(blks.size());
+                    for (int b = c * chunk; b < std::min(nb, (c + 1) * chunk); ++b)
+                        blks.push_back({r.b[b].a, mv_off(r.b[b].point, r.b[b].id), r.b[b].C, r.b[b].sidx});
+                    d.b1 = int32_t(blks.size());
+                    rows.push_back(d);
+                }
+            }
+            WorkList w;
+            w.phase = PH_STREAM;
+            w.kind = sk;
+            w.data = A.blocks;
+            w.nrows = int64_t(rows.size());
+            w.rows = A.mem.upload(rows, stream);
+            w.blks = A.mem.upload(blks, stream);
+            w.red = A.mem.upload(red, stream);
+            w.nred = int64_t(red.size());
+            w.partials = static_cast<double *>(A.mem.alloc(w.nrows * 64 * 8));
+            A.lists.push_back(w);
+        } else {
+            emit_one(0, PH_STREAM, sk, A.blocks, L);
+        }
         L.clear();
     }
     if (lowrank) {
@@ -674,6 +723,13 @@ void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st) {
                 L.in0 = A.xh;
                 L.out0 = A.yh;
                 L.out1 = A.ynear;
+                if (w.red) {   // chunks of a split list: partial sums, then their sums per row
+                    L.out0 = L.out1 = w.partials;
+                    check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, int(w.phase), st, 1), "blockrow launch");
+                    check_hip(h2::launch_reduce_chunks(w.red, w.nred, w.partials, A.yh, A.ynear, A.vec_f64, st),
+                              "chunk sum launch");
+                    return;
+                }
                 break;
             case PH_DOWN:
                 L.in0 = A.yh;

@@ -246,6 +246,23 @@ __global__ __launch_bounds__(256) void fill_blocks_bf16_kernel(Geometry g, uint1
     if (threadIdx.x == 0) scales[d.sidx] = s;
 }
 
+// ---------------------------------------------------------------- chunk sums
+// One wavefront per split row: lane r adds partials[c * 64 + r] over the row's
+// chunks in order (FP64) and stores the row's output element r.
+template <typename TV>
+__global__ __launch_bounds__(256) void reduce_chunks_kernel(const ReduceDesc *__restrict__ desc, int64_t n,
+                                                            const double *__restrict__ partials, TV *__restrict__ out0,
+                                                            TV *__restrict__ out1) {
+    const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int r = threadIdx.x & 63;
+    if (i >= n) return;
+    const ReduceDesc d = desc[i];
+    if (r >= d.R) return;
+    double acc = 0.0;
+    for (int c = d.c0; c < d.c1; ++c) acc += partials[int64_t(c) * 64 + r];
+    (d.point ? out1 : out0)[d.out + r] = TV(acc);
+}
+
 // ---------------------------------------------------------------- transposed copies
 // One workgroup per block (grid-strided over the list): destination element
 // e = ((r / W) * C + c) * W + r % W of the C x R transpose takes source element
@@ -439,6 +456,19 @@ hipError_t launch_fill_blocks(const Geometry &g, int block_kind, void *blocks, f
     return hipSuccess;
 }
 
+hipError_t launch_reduce_chunks(const ReduceDesc *desc, int64_t n, const double *partials, void *out0, void *out1,
+                                bool vec_f64, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid(unsigned((n + 3) / 4)), block(256);
+    if (vec_f64)
+        hipLaunchKernelGGL(reduce_chunks_kernel<double>, grid, block, 0, st, desc, n, partials,
+                           static_cast<double *>(out0), static_cast<double *>(out1));
+    else
+        hipLaunchKernelGGL(reduce_chunks_kernel<float>, grid, block, 0, st, desc, n, partials,
+                           static_cast<float *>(out0), static_cast<float *>(out1));
+    return hipGetLastError();
+}
+
 hipError_t launch_transpose_blocks(int kind, const void *src, void *dst, const TransDesc *desc, int64_t n,
                                    hipStream_t st) {
     if (n <= 0) return hipSuccess;
@@ -455,8 +485,8 @@ hipError_t launch_transpose_blocks(int kind, const void *src, void *dst, const T
     return hipGetLastError();
 }
 
-hipError_t launch_blockrow(const RowLaunch &L, int kind, bool vec_f64, int phase, hipStream_t st) {
-    const bool out1_f64 = phase == PHASE_LEAF;
+hipError_t launch_blockrow(const RowLaunch &L, int kind, bool vec_f64, int phase, hipStream_t st, int out1_f64_in) {
+    const bool out1_f64 = out1_f64_in < 0 ? phase == PHASE_LEAF : out1_f64_in != 0;
     if (vec_f64) return run_blockrow<ELEM_F64, double, double>(L, phase, st);
     if (kind == ELEM_F32)
         return out1_f64 ? run_blockrow<ELEM_F32, float, double>(L, phase, st)
