@@ -1,0 +1,813 @@
+// Construction of the H^2 representation on the device (from points, or
+// from the arrays of an existing representation), its work lists, and the
+// export of its stored arrays.
+#include "h2_internal.h"
+
+namespace h2i {
+
+namespace {
+
+// Host conversion of a column-major FP64 block (R x C, leading dimension R)
+// into the device layout of its element kind: 16-byte column groups (see
+// block_elems), transposed on request, FP32 rounded to nearest even, BF16
+// with one FP32 scale (max |fp32(a)|) and codes rounded to nearest even --
+// the same rules as the device fill kernels.
+uint16_t host_bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+}  // namespace
+
+// Wavefront items of a tile list in dispatch order (see h2::MmLaunch): one
+// item per 32-row half of each row, the list cut into MM_XCDS contiguous
+// ranges of about equal work (per block: its columns rounded up to the
+// 16-column MFMA step, plus a fixed cost), each range padded to whole
+// workgroups, and range x's l-th workgroup placed at workgroup l * MM_XCDS + x.
+std::vector<int32_t> wave_items(const std::vector<h2::RowDesc> &rows, const std::vector<h2::BlkDesc> &blks) {
+    constexpr int X = h2::MM_XCDS;
+    if (rows.size() >= (size_t(1) << 30)) fail(H2_ERR_UNSUPPORTED, "too many rows in one tile list");
+    std::vector<int32_t> items;
+    std::vector<double> work;
+    double total = 0.0;
+    for (size_t r = 0; r < rows.size(); ++r) {
+        double w = 0.0;
+        for (int32_t b = rows[r].b0; b < rows[r].b1; ++b) w += double((blks[b].C + 15) / 16 * 16 + 8);
+        for (int mt = 0; mt * 32 < std::max(rows[r].R, 1); ++mt) {
+            items.push_back(int32_t(r << 1) | mt);
+            work.push_back(w);
+            total += w;
+        }
+    }
+    // cut points: range x = [cut[x], cut[x+1])
+    std::vector<size_t> cut(X + 1, items.size());
+    cut[0] = 0;
+    double acc = 0.0;
+    int x = 1;
+    for (size_t i = 0; i < items.size() && x < X; ++i) {
+        while (x < X && acc >= total * x / X) cut[x++] = i;
+        acc += work[i];
+    }
+    size_t per = 0;   // workgroups per XCD
+    for (int r = 0; r < X; ++r) per = std::max(per, (cut[r + 1] - cut[r] + 3) / 4);
+    std::vector<int32_t> out(per * X * 4, -1);
+    for (int r = 0; r < X; ++r)
+        for (size_t i = cut[r]; i < cut[r + 1]; ++i) {
+            const size_t l = (i - cut[r]) / 4, v = (i - cut[r]) % 4;
+            out[(l * X + r) * 4 + v] = items[i];
+        }
+    return out;
+}
+
+void convert_block(const double *src, int R, int C, bool transpose, int kind, void *dst, float *scale) {
+    // element (r, c) of the stored block: src[r + c * R] (or src[c + r * C] transposed)
+    auto val = [&](int r, int c) { return transpose ? src[c + int64_t(r) * C] : src[r + int64_t(c) * R]; };
+    const int W = 16 / h2::elem_bytes(kind);
+    const int64_t ne = h2::block_elems(R, C, kind);
+    float s = 0.0f;
+    if (kind == h2::ELEM_BF16)
+        for (int c = 0; c < C; ++c)
+            for (int r = 0; r < R; ++r) s = std::max(s, std::fabs(float(val(r, c))));
+    for (int64_t e = 0; e < ne; ++e) {
+        const int w = int(e % W);
+        const int64_t t = e / W;
+        const int r = int(t % R), c = int(t / R) * W + w;
+        const double v = c < C ? val(r, c) : 0.0;
+        if (kind == h2::ELEM_F64) static_cast<double *>(dst)[e] = v;
+        else if (kind == h2::ELEM_F32) static_cast<float *>(dst)[e] = float(v);
+        else static_cast<uint16_t *>(dst)[e] = s == 0.0f ? uint16_t(0) : host_bf16_rne(float(v) / s);
+    }
+    if (scale) *scale = s;
+}
+
+// Uploads converted blocks through a bounded host staging buffer.
+struct Stager {
+    char *dev;
+    int64_t elem;
+    hipStream_t st;
+    std::vector<char> buf;
+    int64_t buf_off = 0;   // element offset of buf[0] on the device
+    int64_t used = 0;      // bytes in buf
+    static constexpr int64_t kCap = int64_t(64) << 20;
+    Stager(void *d, int kind, hipStream_t s) : dev(static_cast<char *>(d)), elem(h2::elem_bytes(kind)), st(s) {
+        buf.resize(kCap);
+    }
+    void flush() {
+        if (used > 0) {
+            check_hip(hipMemcpyAsync(dev + buf_off * elem, buf.data(), size_t(used), hipMemcpyHostToDevice, st),
+                      "hipMemcpyAsync");
+            check_hip(hipStreamSynchronize(st), "upload blocks");
+        }
+        buf_off += used / elem;
+        used = 0;
+    }
+    // Room for a block of ne elements placed at element offset off (blocks arrive in offset order).
+    void *place(int64_t off, int64_t ne) {
+        const int64_t bytes = ne * elem;
+        if (off * elem != buf_off * elem + used || used + bytes > kCap) {
+            flush();
+            buf_off = off;
+        }
+        if (bytes > kCap) fail(H2_ERR_INTERNAL, "block larger than the staging buffer");
+        void *p = buf.data() + used;
+        used += bytes;
+        return p;
+    }
+};
+
+// Layout of the representation, generation on the device (from points) or
+// conversion of caller arrays (src), and the work lists of one product in
+// launch order.  Ranks may differ per level (k_l); vectors and tiles use the
+// largest rank as their node stride.
+// The device representation's layout for the structure's level ranks: sets
+// the offsets and byte counts of A, allocates its regions (basis, blocks,
+// scales) and returns the fill list (coupling blocks level by level in BSR
+// order, then dense blocks); ncoupling receives the number of coupling blocks.
+std::vector<h2::FillDesc> make_layout(h2_matrix_ &A, int64_t &ncoupling) {
+    const Structure &s = A.st;
+    const int q = s.q;
+    const std::vector<int> &kl = s.lrank;
+    const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
+    const bool lowrank = s.lmin <= q;
+    const int bk = A.basis_kind, sk = A.block_kind;
+
+    // basis region: U_j, V_j^T per leaf; E_c, F_c^T per node of levels lmin+1..q
+    std::vector<int64_t> off_U(nleaves), off_VT(nleaves);
+    std::vector<int64_t> off_E(s.nnodes, -1), off_FT(s.nnodes, -1);
+    int64_t nb = 0;
+    for (int64_t j = 0; j < nleaves; ++j) {
+        const int m = int(s.size(lf + j));
+        off_U[j] = nb;
+        nb += h2::block_elems(m, kl[q], bk);
+        off_VT[j] = nb;
+        nb += h2::block_elems(kl[q], m, bk);
+    }
+    const int64_t leaf_elems = nb;
+    if (lowrank)
+        for (int l = s.lmin + 1; l <= q; ++l)
+            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
+                off_E[c] = nb;
+                nb += h2::block_elems(kl[l], kl[l - 1], bk);
+                off_FT[c] = nb;
+                nb += h2::block_elems(kl[l - 1], kl[l], bk);
+            }
+    const int64_t eb = h2::elem_bytes(bk), sb = h2::elem_bytes(sk);
+    A.bytes_leaf = lowrank ? leaf_elems * eb : 0;
+    A.bytes_transfer = (nb - leaf_elems) * eb;
+
+    // block region: coupling blocks level by level in BSR order, then dense blocks
+    std::vector<h2::FillDesc> fill;
+    int64_t ns = 0;
+    for (int l = 0; l <= q; ++l) {
+        const h2::Bsr &B = s.coupling[l];
+        const int64_t f = Structure::first(l);
+        for (int64_t i = 0; i < (int64_t(1) << l); ++i)
+            for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b) {
+                fill.push_back({ns, int32_t(f + i), int32_t(f + B.colidx[b]), int32_t(fill.size()),
+                                h2::FILL_COUPLING});
+                ns += h2::block_elems(kl[l], kl[l], sk);
+            }
+    }
+    const int64_t coupling_elems = ns;
+    ncoupling = int64_t(fill.size());
+    for (int64_t i = 0; i < nleaves; ++i)
+        for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b) {
+            const int64_t t = lf + s.dense.colidx[b];
+            fill.push_back({ns, int32_t(lf + i), int32_t(t), int32_t(fill.size()), h2::FILL_DENSE});
+            ns += h2::block_elems(int(s.size(lf + i)), int(s.size(t)), sk);
+        }
+    const int64_t scale_bytes = sk == h2::ELEM_BF16 ? 4 : 0;
+    A.off_U = off_U;
+    A.off_VT = off_VT;
+    A.off_E = off_E;
+    A.off_FT = off_FT;
+    A.off_blk.resize(fill.size());
+    for (size_t i = 0; i < fill.size(); ++i) A.off_blk[i] = fill[i].a;
+    A.bytes_coupling = coupling_elems * sb + scale_bytes * ncoupling;
+    A.bytes_dense = (ns - coupling_elems) * sb + scale_bytes * (int64_t(fill.size()) - ncoupling);
+
+    A.basis_elems = nb;
+    A.block_elems = ns;
+    A.basis = A.mem.alloc(nb * eb);
+    A.blocks = A.mem.alloc(ns * sb);
+    A.scales = static_cast<float *>(A.mem.alloc(std::max<int64_t>(1, int64_t(fill.size())) * 4));
+    A.nscales = int64_t(fill.size());
+    return fill;
+}
+
+void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t ncoupling, hipStream_t stream);
+
+void build_device(h2_matrix_ &A, const h2_arrays *src, hipStream_t stream) {
+    const Structure &s = A.st;
+    const int k = s.rank, q = s.q;   // k: largest level rank
+    const std::vector<int> &kl = s.lrank;
+    const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
+    const bool lowrank = s.lmin <= q;
+    const int bk = A.basis_kind, sk = A.block_kind;
+    int64_t ncoupling = 0;
+    const std::vector<h2::FillDesc> fill = make_layout(A, ncoupling);
+    const std::vector<int64_t> &off_U = A.off_U, &off_VT = A.off_VT, &off_E = A.off_E, &off_FT = A.off_FT;
+    std::vector<int64_t> leaf_node(nleaves);
+    for (int64_t j = 0; j < nleaves; ++j) leaf_node[j] = lf + j;
+    if (!src) {
+        // generation of the representation on the device (Sec. 4.6)
+        std::vector<double> cheb(s.cheb_p);
+        for (int a = 0; a < s.cheb_p; ++a) cheb[a] = std::cos((2.0 * a + 1.0) * M_PI / (2.0 * s.cheb_p));
+        DeviceArena scratch;   // geometry and fill lists, freed after the build
+        if (A.mem.cap >= 0) scratch.cap = std::max<int64_t>(0, A.mem.cap - A.mem.bytes);
+        h2::Geometry g;
+        g.pts = scratch.upload(s.pts, stream);
+        g.lo = scratch.upload(s.lo, stream);
+        g.hi = scratch.upload(s.hi, stream);
+        g.begin = scratch.upload(s.begin, stream);
+        g.end = scratch.upload(s.end, stream);
+        g.cheb = scratch.upload(cheb, stream);
+        g.dim = s.dim;
+        g.cheb_p = s.cheb_p;
+        g.rank = k;
+        g.corr_len = s.corr_len;
+        const int64_t *d_leaf = scratch.upload(leaf_node, stream);
+        const int64_t *d_offU = scratch.upload(off_U, stream);
+        const int64_t *d_offVT = scratch.upload(off_VT, stream);
+        const int64_t *d_offE = scratch.upload(off_E, stream);
+        const int64_t *d_offFT = scratch.upload(off_FT, stream);
+        const h2::FillDesc *d_fill = scratch.upload(fill, stream);
+        check_hip(h2::launch_fill_bases(g, bk, A.basis, d_leaf, d_offU, d_offVT, nleaves, d_offE, d_offFT,
+                                        lowrank ? s.nnodes : 0, stream),
+                  "fill bases");
+        check_hip(h2::launch_fill_blocks(g, sk, A.blocks, A.scales, d_fill, int64_t(fill.size()), stream),
+                  "fill blocks");
+        check_hip(hipStreamSynchronize(stream), "fill");
+    } else {
+        // caller arrays (column-major FP64) converted to the device layout
+        {
+            Stager up(A.basis, bk, stream);
+            const int kq = kl[q];
+            int64_t uoff = 0;   // offset of leaf j's m_j x k_q block in U and V
+            for (int64_t j = 0; j < nleaves && lowrank; ++j) {
+                const int m = int(s.size(lf + j));
+                convert_block(src->U + uoff, m, kq, false, bk, up.place(off_U[j], h2::block_elems(m, kq, bk)),
+                              nullptr);
+                convert_block(src->V + uoff, kq, m, true, bk, up.place(off_VT[j], h2::block_elems(kq, m, bk)),
+                              nullptr);
+                uoff += int64_t(m) * kq;
+            }
+            int64_t eoff = 0;   // offset of node c's k_l x k_(l-1) block in E and F
+            for (int l = 1; l <= q; ++l)
+                for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
+                    if (off_E[c] >= 0) {
+                        convert_block(src->E + eoff, kl[l], kl[l - 1], false, bk,
+                                      up.place(off_E[c], h2::block_elems(kl[l], kl[l - 1], bk)), nullptr);
+                        convert_block(src->F + eoff, kl[l - 1], kl[l], true, bk,
+                                      up.place(off_FT[c], h2::block_elems(kl[l - 1], kl[l], bk)), nullptr);
+                    }
+                    eoff += int64_t(kl[l]) * kl[l - 1];
+                }
+            up.flush();
+        }
+        {
+            Stager up(A.blocks, sk, stream);
+            std::vector<float> scales(fill.size(), 1.0f);
+            int64_t fi = 0;
+            for (int l = 0; l <= q; ++l) {
+                const h2::Bsr &B = s.coupling[l];
+                const int64_t kk = int64_t(kl[l]) * kl[l];
+                for (int64_t b = 0; b < B.blocks(); ++b, ++fi)
+                    convert_block(src->S[l] + b * kk, kl[l], kl[l], false, sk,
+                                  up.place(fill[fi].a, h2::block_elems(kl[l], kl[l], sk)), &scales[fi]);
+            }
+            int64_t doff = 0;
+            for (int64_t i = 0; i < nleaves; ++i)
+                for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++fi) {
+                    const int R = int(s.size(lf + i)), C = int(s.size(lf + s.dense.colidx[b]));
+                    convert_block(src->D + doff, R, C, false, sk, up.place(fill[fi].a, h2::block_elems(R, C, sk)),
+                                  &scales[fi]);
+                    doff += int64_t(R) * C;
+                }
+            up.flush();
+            if (sk == h2::ELEM_BF16 && !scales.empty()) {
+                check_hip(hipMemcpyAsync(A.scales, scales.data(), scales.size() * 4, hipMemcpyHostToDevice, stream),
+                          "hipMemcpyAsync");
+                check_hip(hipStreamSynchronize(stream), "upload scales");
+            }
+        }
+    }
+    build_lists(A, fill, ncoupling, stream);
+}
+
+// Vector workspace and work lists of the product for the layout of A.
+void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t ncoupling, hipStream_t stream) {
+    const Structure &s = A.st;
+    const int k = s.rank, q = s.q;
+    const std::vector<int> &kl = s.lrank;
+    const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
+    const bool lowrank = s.lmin <= q;
+    const int bk = A.basis_kind, sk = A.block_kind;
+    const std::vector<int64_t> &off_U = A.off_U, &off_VT = A.off_VT, &off_E = A.off_E, &off_FT = A.off_FT;
+
+    // workspace: vector trees x^ and y^ (nnodes x k) and the near field (n)
+    const int64_t vb = A.vec_f64 ? 8 : 4;
+    A.xh = A.mem.alloc(s.nnodes * k * vb);
+    A.yh = A.mem.alloc(s.nnodes * k * vb);
+    A.ynear = A.mem.alloc(s.n * vb);
+
+    // Work lists in launch order.  Rows are first built logically: each
+    // operand names either a tree node's vector (x^ / y^) or a leaf's segment of
+    // the point vectors (x, y_near, y); they are then encoded twice, with
+    // single-vector offsets and with tile offsets for many right-hand sides.
+    struct LBlk {
+        int64_t a;
+        int32_t C, sidx;
+        bool point;
+        int64_t id;
+    };
+    struct LRow {
+        bool point;      // output is a leaf segment (else a tree node)
+        int64_t id;      // leaf index or node id
+        bool has_init;   // add the current value (downsweep: y^; leaf phase: y_near)
+        int R, sel;
+        std::vector<LBlk> b;
+    };
+    const int64_t kp = (k + 15) / 16 * 16;
+    int64_t mmax = 0;
+    for (int64_t j = 0; j < nleaves; ++j) mmax = std::max(mmax, s.size(lf + j));
+    A.tile_slot = (mmax + 15) / 16 * 16 * h2::MM_TILE;
+    auto mv_off = [&](bool point, int64_t id) { return point ? s.begin[lf + id] : id * k; };
+    auto mm_off = [&](bool point, int64_t id) { return point ? id * A.tile_slot : id * kp * h2::MM_TILE; };
+    // enc 0: single-vector offsets into A.lists; enc 1: tile offsets into A.mm_lists
+    auto emit_one = [&](int enc, Phase ph, int kind, const void *data, const std::vector<LRow> &L) {
+        std::vector<RowDesc> rows;
+        std::vector<BlkDesc> blks;
+        for (const LRow &r : L) {
+            RowDesc d;
+            if (ph == PH_LEAF) {   // out: rows of y; init: y_near
+                d.out = s.begin[lf + r.id];
+                d.init = enc == 0 ? mv_off(true, r.id) : mm_off(true, r.id);
+            } else {
+                d.out = enc == 0 ? mv_off(r.point, r.id) : mm_off(r.point, r.id);
+                d.init = !r.has_init ? -1 : enc == 0 ? mv_off(r.point, r.id) : mm_off(r.point, r.id);
+            }
+            d.b0 = int32_t(blks.size());
+            for (const LBlk &b : r.b)
+                blks.push_back({b.a, enc == 0 ? mv_off(b.point, b.id) : mm_off(b.point, b.id), b.C, b.sidx});
+            d.b1 = int32_t(blks.size());
+            d.R = r.R;
+            d.sel = r.sel;
+            rows.push_back(d);
+        }
+        WorkList w;
+        w.phase = ph;
+        w.kind = kind;
+        w.data = data;
+        w.nrows = int64_t(rows.size());
+        w.rows = A.mem.upload(rows, stream);
+        w.blks = A.mem.upload(blks, stream);
+        if (enc == 1) {
+            const std::vector<int32_t> it = wave_items(rows, blks);
+            w.items = A.mem.upload(it, stream);
+            w.nitems = int64_t(it.size());
+        }
+        (enc == 0 ? A.lists : A.mm_lists).push_back(w);
+        if (enc == 1) {
+            A.mm_host_rows.push_back(std::move(rows));
+            A.mm_host_blks.push_back(std::move(blks));
+        }
+    };
+    auto emit = [&](Phase ph, int kind, const void *data, std::vector<LRow> &L) {
+        emit_one(0, ph, kind, data, L);
+        emit_one(1, ph, kind, data, L);
+        L.clear();
+    };
+    std::vector<LRow> L;
+    if (lowrank) {
+        // leaf projection x^_j = V_j^T x(j)   (Sec. 4.2)
+        for (int64_t j = 0; j < nleaves; ++j) {
+            const int64_t v = lf + j;
+            L.push_back({false, v, false, kl[q], h2::ROW_IN_X, {{off_VT[j], int32_t(s.size(v)), 0, true, j}}});
+        }
+        emit(PH_UP, bk, A.basis, L);
+        // upsweep x^_p = F_c1^T x^_c1 + F_c2^T x^_c2 for levels q .. lmin+1   (Sec. 4.2)
+        for (int l = q; l > s.lmin; --l) {
+            for (int64_t p = Structure::first(l - 1); p < Structure::first(l); ++p)
+                L.push_back({false, p, false, kl[l - 1], 0,
+                             {{off_FT[2 * p + 1], kl[l], 0, false, 2 * p + 1},
+                              {off_FT[2 * p + 2], kl[l], 0, false, 2 * p + 2}}});
+            emit(PH_UP, bk, A.basis, L);
+        }
+    }
+    // tree multiplication y^_i = sum_j S_ij x^_j on all levels (Sec. 4.3) and the
+    // dense near field y_near(i) = sum_j D_ij x(j) (Sec. 4.1) in one launch
+    {
+        int64_t fi = 0;
+        if (lowrank)
+            for (int l = s.lmin; l <= q; ++l) {
+                const h2::Bsr &B = s.coupling[l];
+                const int64_t f = Structure::first(l);
+                for (int64_t i = 0; i < (int64_t(1) << l); ++i) {
+                    LRow r{false, f + i, false, kl[l], 0, {}};
+                    for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b, ++fi)
+                        r.b.push_back({fill[fi].a, kl[l], fill[fi].sidx, false, f + B.colidx[b]});
+                    L.push_back(std::move(r));
+                }
+            }
+        fi = ncoupling;
+        for (int64_t i = 0; i < nleaves; ++i) {
+            LRow r{true, i, false, int(s.size(lf + i)), h2::ROW_IN_X | h2::ROW_OUT_P, {}};
+            for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++fi) {
+                const int64_t t = s.dense.colidx[b];
+                r.b.push_back({fill[fi].a, int32_t(s.size(lf + t)), fill[fi].sidx, true, t});
+            }
+            L.push_back(std::move(r));
+        }
+        // Tile lists (many right-hand sides): the input tiles (k x 32 per node)
+        // outgrow the last-level cache, so rows stay in spatial order -- leaf rows
+        // (dense) first, then coupling rows from the finest level up, each by
+        // index -- and concurrently running rows share their input tiles.
+        std::vector<LRow> spatial;
+        for (const LRow &r : L)
+            if (r.point) spatial.push_back(r);
+        for (int l = q; l >= s.lmin && lowrank; --l)
+            for (const LRow &r : L)
+                if (!r.point && r.id >= Structure::first(l) && r.id < Structure::first(l + 1)) spatial.push_back(r);
+        emit_one(1, PH_STREAM, sk, A.blocks, spatial);
+        // Single right-hand side: the vector trees fit in the caches; longest
+        // rows first, so the wavefronts that start last are the short ones.
+        std::stable_sort(L.begin(), L.end(), [](const LRow &a, const LRow &b) { return a.b.size() > b.b.size(); });
+        int64_t nblk = 0;
+        for (const LRow &r : L) nblk += int64_t(r.b.size());
+        if (int64_t(L.size()) < kSplitRows && nblk > int64_t(L.size())) {
+            // few rows: every row cut into chunks of `chunk` blocks, one wavefront
+            // each, writing FP64 partial sums that a second launch adds up per row
+            const int chunk = int(std::max<int64_t>(1, (nblk + kSplitWaves - 1) / kSplitWaves));
+            std::vector<RowDesc> rows;
+            std::vector<BlkDesc> blks;
+            std::vector<h2::ReduceDesc> red;
+            for (const LRow &r : L) {
+                const int nb = int(r.b.size()), nc = std::max(1, (nb + chunk - 1) / chunk);
+                red.push_back({mv_off(r.point, r.id), int32_t(rows.size()), int32_t(rows.size() + nc), r.R,
+                               r.point ? 1 : 0});
+                for (int c = 0; c < nc; ++c) {
+                    RowDesc d;
+                    d.out = int64_t(rows.size()) * 64;
+                    d.init = -1;
+                    d.R = r.R;
+                    d.sel = (r.sel & h2::ROW_IN_X) | h2::ROW_OUT_P;
+                    d.b0 = int32_t(blks.size());
+                    for (int b = c * chunk; b < std::min(nb, (c + 1) * chunk); ++b)
+                        blks.push_back({r.b[b].a, mv_off(r.b[b].point, r.b[b].id), r.b[b].C, r.b[b].sidx});
+                    d.b1 = int32_t(blks.size());
+                    rows.push_back(d);
+                }
+            }
+            WorkList w;
+            w.phase = PH_STREAM;
+            w.kind = sk;
+            w.data = A.blocks;
+            w.nrows = int64_t(rows.size());
+            w.rows = A.mem.upload(rows, stream);
+            w.blks = A.mem.upload(blks, stream);
+            w.red = A.mem.upload(red, stream);
+            w.nred = int64_t(red.size());
+            w.partials = static_cast<double *>(A.mem.alloc(w.nrows * 64 * 8));
+            A.lists.push_back(w);
+        } else {
+            emit_one(0, PH_STREAM, sk, A.blocks, L);
+        }
+        L.clear();
+    }
+    if (lowrank) {
+        // downsweep y^_c += E_c y^_parent for levels lmin+1 .. q   (Sec. 4.4)
+        for (int l = s.lmin + 1; l <= q; ++l) {
+            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c)
+                L.push_back({false, c, true, kl[l], 0, {{off_E[c], kl[l - 1], 0, false, (c - 1) / 2}}});
+            emit(PH_DOWN, bk, A.basis, L);
+        }
+    }
+    // leaf expansion and sum: y(i) = y_near(i) + U_i y^_i   (Sec. 4.4, Sec. 4.1)
+    for (int64_t j = 0; j < nleaves; ++j) {
+        LRow r{true, j, true, int(s.size(lf + j)), h2::ROW_OUT_P, {}};
+        if (lowrank) r.b.push_back({off_U[j], kl[q], 0, false, lf + j});
+        L.push_back(std::move(r));
+    }
+    emit(PH_LEAF, bk, A.basis, L);
+    std::vector<int64_t> lb(nleaves), le(nleaves);
+    for (int64_t j = 0; j < nleaves; ++j) {
+        lb[j] = s.begin[lf + j];
+        le[j] = s.end[lf + j];
+    }
+    A.d_leaf_begin = A.mem.upload(lb, stream);
+    A.d_leaf_end = A.mem.upload(le, stream);
+    check_hip(hipStreamSynchronize(stream), "upload work lists");
+}
+
+void validate_params(const double *points, int64_t n, const h2_params *prm) {
+    if (!points || !prm) fail(H2_ERR_INVALID_ARG, "NULL points or params");
+    if (n < 1 || n >= (int64_t(1) << 31)) fail(H2_ERR_INVALID_ARG, "n must be in [1, 2^31)");
+    if (prm->dim != 2 && prm->dim != 3) fail(H2_ERR_INVALID_ARG, "dim must be 2 or 3");
+    if (prm->leaf_size < 2) fail(H2_ERR_INVALID_ARG, "leaf_size must be >= 2");
+    if (prm->cheb_p < 1) fail(H2_ERR_INVALID_ARG, "cheb_p must be >= 1");
+    if (!(prm->eta > 0.0) || !std::isfinite(prm->eta)) fail(H2_ERR_INVALID_ARG, "eta must be > 0");
+    if (!(prm->corr_len > 0.0) || !std::isfinite(prm->corr_len))
+        fail(H2_ERR_INVALID_ARG, "corr_len must be > 0");
+    if (prm->storage < H2_FP64 || prm->storage > H2_BF16_SCALED) fail(H2_ERR_INVALID_ARG, "bad storage");
+    if (prm->flags & ~unsigned(H2_FLAG_STRUCTURE_ONLY)) fail(H2_ERR_INVALID_ARG, "unknown flags");
+    for (int64_t i = 0; i < n * prm->dim; ++i)
+        if (!std::isfinite(points[i])) fail(H2_ERR_INVALID_ARG, "non-finite coordinate");
+    int64_t k = 1;
+    for (int a = 0; a < prm->dim; ++a) {
+        k *= prm->cheb_p;
+        if (k > 64) fail(H2_ERR_UNSUPPORTED, "rank cheb_p^dim above 64");
+    }
+    if (prm->leaf_size > 64) fail(H2_ERR_UNSUPPORTED, "leaf_size above 64");
+}
+
+// Checks the arrays and fills the host structure from them.
+void structure_from_arrays(const h2_arrays *a, h2::Structure &s) {
+    if (!a) fail(H2_ERR_INVALID_ARG, "NULL arrays");
+    if (a->n < 1 || a->n >= (int64_t(1) << 31)) fail(H2_ERR_INVALID_ARG, "n out of range");
+    if (a->q < 0) fail(H2_ERR_INVALID_ARG, "q < 0");
+    if (a->q > 29) fail(H2_ERR_UNSUPPORTED, "q above 29");
+    if ((int64_t(1) << a->q) > a->n) fail(H2_ERR_INVALID_ARG, "more leaves than rows");
+    if (!a->level_rank || !a->node_begin || !a->node_end || !a->S_rowptr || !a->S_colidx || !a->S ||
+        !a->D_rowptr || (!a->D_colidx && a->D_rowptr[int64_t(1) << a->q] > 0) ||
+        (!a->D && a->D_rowptr[int64_t(1) << a->q] > 0))
+        fail(H2_ERR_INVALID_ARG, "NULL array");
+    s = h2::Structure();
+    s.n = a->n;
+    s.q = a->q;
+    s.nnodes = (int64_t(2) << a->q) - 1;
+    s.lrank.resize(a->q + 1);
+    s.rank = 0;
+    for (int l = 0; l <= a->q; ++l) {
+        const int k = a->level_rank[l];
+        if (k < 1) fail(H2_ERR_INVALID_ARG, "level rank < 1");
+        if (k > 64) fail(H2_ERR_UNSUPPORTED, "level rank above 64");
+        s.lrank[l] = k;
+        s.rank = std::max(s.rank, k);
+    }
+    s.begin.assign(a->node_begin, a->node_begin + s.nnodes);
+    s.end.assign(a->node_end, a->node_end + s.nnodes);
+    if (s.begin[0] != 0 || s.end[0] != a->n) fail(H2_ERR_INVALID_ARG, "root must hold rows [0, n)");
+    for (int64_t v = 0; v < s.nnodes; ++v) {
+        if (s.end[v] <= s.begin[v]) fail(H2_ERR_INVALID_ARG, "empty node");
+        if (2 * v + 2 < s.nnodes) {
+            const int64_t c1 = 2 * v + 1, c2 = 2 * v + 2;
+            if (s.begin[c1] != s.begin[v] || s.end[c1] != s.begin[c2] || s.end[c2] != s.end[v])
+                fail(H2_ERR_INVALID_ARG, "children must split their parent into consecutive ranges");
+        } else {
+            s.leaf = int(std::max<int64_t>(s.leaf, s.size(v)));
+        }
+    }
+    if (s.leaf > 64) fail(H2_ERR_UNSUPPORTED, "leaf above 64 rows");
+    auto take_bsr = [&](int64_t rows, const int32_t *rp, const int32_t *ci, h2::Bsr &B) {
+        if (rp[0] != 0) fail(H2_ERR_INVALID_ARG, "BSR offsets must start at 0");
+        B.rowptr.assign(rp, rp + rows + 1);
+        for (int64_t i = 0; i < rows; ++i)
+            if (B.rowptr[i + 1] < B.rowptr[i]) fail(H2_ERR_INVALID_ARG, "BSR offsets must not decrease");
+        B.colidx.assign(ci, ci + B.rowptr[rows]);
+        for (int32_t c : B.colidx)
+            if (c < 0 || c >= rows) fail(H2_ERR_INVALID_ARG, "BSR column out of range");
+    };
+    s.coupling.resize(a->q + 1);
+    s.lmin = a->q + 1;
+    for (int l = a->q; l >= 0; --l) {
+        if (!a->S_rowptr[l]) fail(H2_ERR_INVALID_ARG, "NULL S_rowptr");
+        if (a->S_rowptr[l][int64_t(1) << l] > 0 && (!a->S_colidx[l] || !a->S[l]))
+            fail(H2_ERR_INVALID_ARG, "NULL S_colidx / S for a level with blocks");
+        take_bsr(int64_t(1) << l, a->S_rowptr[l], a->S_colidx[l], s.coupling[l]);
+        if (s.coupling[l].blocks() > 0) s.lmin = l;
+    }
+    take_bsr(int64_t(1) << a->q, a->D_rowptr, a->D_colidx, s.dense);
+    if (s.lmin <= a->q && (!a->U || !a->V)) fail(H2_ERR_INVALID_ARG, "NULL U / V with coupling blocks");
+    if (s.lmin < a->q && (!a->E || !a->F)) fail(H2_ERR_INVALID_ARG, "NULL E / F with coupling blocks above the leaves");
+    s.perm.resize(a->n);
+    for (int64_t i = 0; i < a->n; ++i) s.perm[i] = i;
+}
+
+// Reads blocks of a device region in offset order through a bounded host
+// window, converting each to column-major FP64 (the inverse of convert_block;
+// BF16 values are code x scale in FP32, as stored).
+struct Reader {
+    const char *dev;
+    int kind;
+    int64_t elem, total;   // element size, region length in elements
+    hipStream_t st;
+    std::vector<char> buf;
+    int64_t win = 0, len = 0;   // window [win, win + len) in elements
+    static constexpr int64_t kCap = int64_t(64) << 20;
+    Reader(const void *d, int k, int64_t n, hipStream_t s)
+        : dev(static_cast<const char *>(d)), kind(k), elem(h2::elem_bytes(k)), total(n), st(s) {}
+    const char *at(int64_t off, int64_t ne) {
+        if (off < 0 || off + ne > total) fail(H2_ERR_INTERNAL, "block outside its region");
+        if (off < win || off + ne > win + len) {
+            len = std::min<int64_t>(std::max<int64_t>(ne, kCap / elem), total - off);
+            buf.resize(size_t(len * elem));
+            check_hip(hipMemcpyAsync(buf.data(), dev + off * elem, size_t(len * elem), hipMemcpyDeviceToHost, st),
+                      "hipMemcpyAsync");
+            check_hip(hipStreamSynchronize(st), "export");
+            win = off;
+        }
+        return buf.data() + (off - win) * elem;
+    }
+    void block(int64_t off, int R, int C, bool transpose, float scale, double *dst) {
+        const int W = 16 / int(elem);
+        const int64_t ne = h2::block_elems(R, C, kind);
+        const char *p = at(off, ne);
+        for (int64_t e = 0; e < ne; ++e) {
+            const int w = int(e % W);
+            const int64_t t = e / W;
+            const int r = int(t % R), c = int(t / R) * W + w;
+            if (c >= C) continue;
+            double v;
+            if (kind == h2::ELEM_F64) v = reinterpret_cast<const double *>(p)[e];
+            else if (kind == h2::ELEM_F32) v = reinterpret_cast<const float *>(p)[e];
+            else {
+                const uint32_t u = uint32_t(reinterpret_cast<const uint16_t *>(p)[e]) << 16;
+                float f;
+                std::memcpy(&f, &u, 4);
+                v = double(f * scale);
+            }
+            if (transpose) dst[c + int64_t(r) * C] = v;   // stored R x C is the transpose of a C x R block
+            else dst[r + int64_t(c) * R] = v;
+        }
+    }
+};
+
+void export_arrays(h2_matrix_ &A, const h2_arrays_out *o, hipStream_t st) {
+    const Structure &s = A.st;
+    const int q = s.q;
+    const std::vector<int> &kl = s.lrank;
+    const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
+    if (o->level_rank)
+        for (int l = 0; l <= q; ++l) o->level_rank[l] = kl[l];
+    if (o->node_begin) std::copy(s.begin.begin(), s.begin.end(), o->node_begin);
+    if (o->node_end) std::copy(s.end.begin(), s.end.end(), o->node_end);
+    const bool lowrank = s.lmin <= q;
+    if (o->U || o->V || o->E || o->F) {
+        Reader rd(A.basis, A.basis_kind, A.basis_elems, st);
+        int64_t uoff = 0;
+        for (int64_t j = 0; j < nleaves; ++j) {
+            const int m = int(s.size(lf + j));
+            const int64_t len = int64_t(m) * kl[q];
+            if (!lowrank) {
+                if (o->U) std::fill(o->U + uoff, o->U + uoff + len, 0.0);
+                if (o->V) std::fill(o->V + uoff, o->V + uoff + len, 0.0);
+            } else {
+                if (o->U) rd.block(A.off_U[j], m, kl[q], false, 1.0f, o->U + uoff);
+                if (o->V) rd.block(A.off_VT[j], kl[q], m, true, 1.0f, o->V + uoff);
+            }
+            uoff += len;
+        }
+        int64_t eoff = 0;
+        for (int l = 1; l <= q; ++l)
+            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
+                const int64_t len = int64_t(kl[l]) * kl[l - 1];
+                if (A.off_E[c] < 0) {   // not stored: not used by the product
+                    if (o->E) std::fill(o->E + eoff, o->E + eoff + len, 0.0);
+                    if (o->F) std::fill(o->F + eoff, o->F + eoff + len, 0.0);
+                } else {
+                    if (o->E) rd.block(A.off_E[c], kl[l], kl[l - 1], false, 1.0f, o->E + eoff);
+                    if (o->F) rd.block(A.off_FT[c], kl[l - 1], kl[l], true, 1.0f, o->F + eoff);
+                }
+                eoff += len;
+            }
+    }
+    std::vector<float> scales;
+    if (A.block_kind == h2::ELEM_BF16 && A.nscales > 0) {
+        scales.resize(size_t(A.nscales));
+        check_hip(hipMemcpyAsync(scales.data(), A.scales, scales.size() * 4, hipMemcpyDeviceToHost, st),
+                  "hipMemcpyAsync");
+        check_hip(hipStreamSynchronize(st), "export scales");
+    }
+    auto scale_of = [&](int64_t i) { return scales.empty() ? 1.0f : scales[size_t(i)]; };
+    Reader rd(A.blocks, A.block_kind, A.block_elems, st);
+    int64_t fi = 0;
+    for (int l = 0; l <= q; ++l) {
+        const h2::Bsr &B = s.coupling[l];
+        if (o->S_rowptr && o->S_rowptr[l]) std::copy(B.rowptr.begin(), B.rowptr.end(), o->S_rowptr[l]);
+        if (o->S_colidx && o->S_colidx[l]) std::copy(B.colidx.begin(), B.colidx.end(), o->S_colidx[l]);
+        const int64_t kk = int64_t(kl[l]) * kl[l];
+        for (int64_t b = 0; b < B.blocks(); ++b, ++fi)
+            if (o->S && o->S[l]) rd.block(A.off_blk[fi], kl[l], kl[l], false, scale_of(fi), o->S[l] + b * kk);
+    }
+    if (o->D_rowptr) std::copy(s.dense.rowptr.begin(), s.dense.rowptr.end(), o->D_rowptr);
+    if (o->D_colidx) std::copy(s.dense.colidx.begin(), s.dense.colidx.end(), o->D_colidx);
+    if (o->D) {
+        int64_t doff = 0;
+        for (int64_t i = 0; i < nleaves; ++i)
+            for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++fi) {
+                const int R = int(s.size(lf + i)), C = int(s.size(lf + s.dense.colidx[b]));
+                rd.block(A.off_blk[fi], R, C, false, scale_of(fi), o->D + doff);
+                doff += int64_t(R) * C;
+            }
+    }
+}
+
+}  // namespace h2i
+
+using namespace h2i;
+
+extern "C" {
+
+h2_status h2_build_from_points(const double *points, int64_t n, const h2_params *prm, void *stream,
+                               h2_handle *out) {
+    if (out) *out = nullptr;
+    h2_matrix_ *A = nullptr;
+    try {
+        if (!out) fail(H2_ERR_INVALID_ARG, "NULL out");
+        validate_params(points, n, prm);
+        A = new h2_matrix_();
+        A->storage = prm->storage;
+        A->structure_only = (prm->flags & H2_FLAG_STRUCTURE_ONLY) != 0;
+        A->basis_kind = prm->storage == H2_FP64 ? h2::ELEM_F64 : h2::ELEM_F32;
+        A->block_kind = prm->storage == H2_FP64   ? h2::ELEM_F64
+                        : prm->storage == H2_FP32 ? h2::ELEM_F32
+                                                  : h2::ELEM_BF16;
+        A->vec_f64 = prm->storage == H2_FP64;
+        std::string err = h2::build_structure(points, n, prm->dim, prm->leaf_size, prm->cheb_p, prm->eta,
+                                              prm->corr_len, A->st);
+        if (!err.empty()) fail(H2_ERR_UNSUPPORTED, err);
+        if (!A->structure_only) build_device(*A, nullptr, static_cast<hipStream_t>(stream));
+        *out = A;
+        g_last_error.clear();
+        return H2_OK;
+    } catch (const Failure &f) {
+        delete A;
+        g_last_error = f.what;
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        delete A;
+        g_last_error = "host allocation failed";
+        return H2_ERR_OOM;
+    } catch (...) {
+        delete A;
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *stream, h2_handle *out) {
+    if (out) *out = nullptr;
+    h2_matrix_ *A = nullptr;
+    try {
+        if (!out) fail(H2_ERR_INVALID_ARG, "NULL out");
+        if (storage < H2_FP64 || storage > H2_BF16_SCALED) fail(H2_ERR_INVALID_ARG, "storage out of range");
+        A = new h2_matrix_();
+        structure_from_arrays(arrays, A->st);
+        A->storage = storage;
+        A->basis_kind = storage == H2_FP64 ? h2::ELEM_F64 : h2::ELEM_F32;
+        A->block_kind = storage == H2_FP64 ? h2::ELEM_F64 : storage == H2_FP32 ? h2::ELEM_F32 : h2::ELEM_BF16;
+        A->vec_f64 = storage == H2_FP64;
+        {
+            // V = U and F = E (value by value): the symmetric case orthogonalization handles
+            const h2::Structure &st = A->st;
+            const int64_t lf = h2::Structure::first(st.q);
+            int64_t nu = 0, ne = 0;
+            for (int64_t v = lf; v < st.nnodes; ++v) nu += st.size(v) * st.lrank[st.q];
+            for (int l = 1; l <= st.q; ++l) ne += (int64_t(st.lrank[l]) * st.lrank[l - 1]) << l;
+            const bool su = arrays->U == arrays->V || (arrays->U && arrays->V &&
+                                                         std::memcmp(arrays->U, arrays->V, size_t(nu) * 8) == 0);
+            const bool se = arrays->E == arrays->F || (arrays->E && arrays->F &&
+                                                         std::memcmp(arrays->E, arrays->F, size_t(ne) * 8) == 0);
+            A->symmetric = su && se;
+        }
+        build_device(*A, arrays, static_cast<hipStream_t>(stream));
+        *out = A;
+        g_last_error.clear();
+        return H2_OK;
+    } catch (const Failure &f) {
+        delete A;
+        g_last_error = f.what;
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        delete A;
+        g_last_error = "host allocation failed";
+        return H2_ERR_OOM;
+    } catch (...) {
+        delete A;
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+h2_status h2_export_arrays(h2_handle A, const h2_arrays_out *out, void *stream) {
+    try {
+        if (!A || !out) fail(H2_ERR_INVALID_ARG, "NULL argument");
+        if (A->structure_only && (out->U || out->V || out->E || out->F || out->S || out->D))
+            fail(H2_ERR_INVALID_ARG, "structure-only handle holds no values");
+        export_arrays(*A, out, static_cast<hipStream_t>(stream));
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return H2_ERR_OOM;
+    } catch (...) {
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+// The product: y = A x as a fixed sequence of block-row launches over the
+// work lists built at construction (the per-call marshaling of pointer
+// batches of Sec. 3.2 becomes static lists), and Y = A X in tiles of
+// right-hand sides on the matrix cores.
+#include "h2_internal.h"
+
+namespace h2i {
+
+namespace {
+
+hipEvent_t take_event(h2_matrix_ &A) {
+    if (!A.spare.empty()) {
+        hipEvent_t e = A.spare.back();
+        A.spare.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    check_hip(hipEventCreate(&e), "hipEventCreate");
+    return e;
+}
+
+// Enqueues the lists in order, with profiling events at phase boundaries
+// when enabled; launch(w) enqueues one list.
+template <class Launch>
+void run_lists(h2_matrix_ &A, const std::vector<WorkList> &lists, hipStream_t st, Launch launch) {
+    hipEvent_t ev[PH_COUNT + 1] = {};
+    if (A.prof)
+        for (auto &e : ev) e = take_event(A);
+    int next_phase = 0;   // lists are in phase order; each phase's event precedes its lists
+    for (const WorkList &w : lists) {
+        while (A.prof && next_phase <= int(w.phase))
+            check_hip(hipEventRecord(ev[next_phase++], st), "hipEventRecord");
+        launch(w);
+    }
+    if (A.prof) {
+        while (next_phase <= PH_COUNT) check_hip(hipEventRecord(ev[next_phase++], st), "hipEventRecord");
+        A.pending.insert(A.pending.end(), ev, ev + PH_COUNT + 1);
+    }
+}
+
+// Tile workspace of the many-right-hand-side product, allocated at first use.
+void ensure_tiles(h2_matrix_ &A) {
+    if (A.t_xh) return;
+    const int64_t kp = (A.st.rank + 15) / 16 * 16;
+    const int64_t tree = A.st.nnodes * kp * h2::MM_TILE, pts = (int64_t(1) << A.st.q) * A.tile_slot;
+    A.t_xh = static_cast<float *>(A.mem.alloc(tree * 4));
+    A.t_yh = static_cast<float *>(A.mem.alloc(tree * 4));
+    A.t_x = static_cast<float *>(A.mem.alloc(pts * 4));
+    A.t_ynear = static_cast<float *>(A.mem.alloc(pts * 4));
+}
+
+}  // namespace
+
+// Enqueues the whole single-vector product on st.
+void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st) {
+    run_lists(A, A.lists, st, [&](const WorkList &w) {
+        h2::RowLaunch L;
+        L.rows = w.rows;
+        L.nrows = w.nrows;
+        L.blks = w.blks;
+        L.data = w.data;
+        L.scales = A.scales;
+        L.in1 = x;
+        L.init = nullptr;
+        L.out1 = nullptr;
+        switch (w.phase) {
+            case PH_UP:
+                L.in0 = A.xh;
+                L.out0 = A.xh;
+                break;
+            case PH_STREAM:
+                L.in0 = A.xh;
+                L.out0 = A.yh;
+                L.out1 = A.ynear;
+                if (w.red) {   // chunks of a split list: partial sums, then their sums per row
+                    L.out0 = L.out1 = w.partials;
+                    check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, int(w.phase), st, 1), "blockrow launch");
+                    check_hip(h2::launch_reduce_chunks(w.red, w.nred, w.partials, A.yh, A.ynear, A.vec_f64, st),
+                              "chunk sum launch");
+                    return;
+                }
+                break;
+            case PH_DOWN:
+                L.in0 = A.yh;
+                L.init = A.yh;
+                L.out0 = A.yh;
+                break;
+            default:
+                L.in0 = A.yh;
+                L.init = A.ynear;
+                L.out0 = A.yh;
+                L.out1 = y;
+                break;
+        }
+        check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, int(w.phase), st), "blockrow launch");
+    });
+}
+
+// One pass of up to MM_TILE right-hand sides on the matrix cores.
+void run_tile_pass(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, int j0,
+                   const h2::MmConfig &cfg, hipStream_t st) {
+    const int64_t nleaves = int64_t(1) << A.st.q;
+    {
+        check_hip(h2::launch_pack(X, ldx, j0, nrhs, A.d_leaf_begin, A.d_leaf_end, nleaves, A.tile_slot, A.t_x, st),
+                  "pack launch");
+        run_lists(A, A.mm_lists, st, [&](const WorkList &w) {
+            h2::MmLaunch L;
+            L.rows = w.rows;
+            L.items = w.items;
+            L.nitems = w.nitems;
+            L.blks = w.blks;
+            L.data = w.data;
+            L.scales = A.scales;
+            L.in_tree = nullptr;
+            L.in_pts = A.t_x;
+            L.init = nullptr;
+            L.out_tree = nullptr;
+            L.out_pts = nullptr;
+            L.Y = Y + int64_t(j0) * ldy;
+            L.ldy = ldy;
+            L.ncols = std::min(h2::MM_TILE, nrhs - j0);
+            switch (w.phase) {
+                case PH_UP:
+                    L.in_tree = A.t_xh;
+                    L.out_tree = A.t_xh;
+                    break;
+                case PH_STREAM:
+                    L.in_tree = A.t_xh;
+                    L.out_tree = A.t_yh;
+                    L.out_pts = A.t_ynear;
+                    break;
+                case PH_DOWN:
+                    L.in_tree = A.t_yh;
+                    L.init = A.t_yh;
+                    L.out_tree = A.t_yh;
+                    break;
+                default:
+                    L.in_tree = A.t_yh;
+                    L.init = A.t_ynear;
+                    break;
+            }
+            check_hip(h2::launch_mm(L, w.kind, int(w.phase), cfg, st), "mfma launch");
+        });
+    }
+}
+
+// Y = A X on the matrix cores, MM_TILE right-hand sides per pass.
+void run_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, hipStream_t st) {
+    ensure_tiles(A);
+    for (int j0 = 0; j0 < nrhs; j0 += h2::MM_TILE) {
+        const int w = std::min(h2::MM_TILE, nrhs - j0) <= 16 ? 1 : 0;
+        if (!A.mm_tuned[w]) tune_tiles(A, X, ldx, Y, ldy, nrhs, j0, st);
+        run_tile_pass(A, X, ldx, Y, ldy, nrhs, j0, A.mm_cfg[w], st);
+    }
+}
+
+}  // namespace h2i
+
+using namespace h2i;
+
+extern "C" {
+
+h2_status h2_matvec(h2_handle A, const double *x, double *y, void *stream) {
+    try {
+        if (!A || !x || !y) fail(H2_ERR_INVALID_ARG, "NULL argument");
+        if (A->structure_only) fail(H2_ERR_INVALID_ARG, "structure-only handle");
+        run_product(*A, x, y, static_cast<hipStream_t>(stream));
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (...) {
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+h2_status h2_matmat(h2_handle A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs,
+                    void *stream) {
+    try {
+        if (!A || !X || !Y) fail(H2_ERR_INVALID_ARG, "NULL argument");
+        if (A->structure_only) fail(H2_ERR_INVALID_ARG, "structure-only handle");
+        if (nrhs < 1) fail(H2_ERR_INVALID_ARG, "nrhs must be >= 1");
+        if (ldx < A->st.n || ldy < A->st.n) fail(H2_ERR_INVALID_ARG, "leading dimension below n");
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        if (A->storage == H2_FP64) {
+            // FP64 storage: one single-vector product per column (FP64 arithmetic throughout)
+            for (int j = 0; j < nrhs; ++j) run_product(*A, X + int64_t(j) * ldx, Y + int64_t(j) * ldy, st);
+        } else {
+            run_tiles(*A, X, ldx, Y, ldy, nrhs, st);
+        }
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (...) {
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+h2_status h2_profile(h2_handle A, int enable) {
+    if (!A) {
+        g_last_error = "NULL handle";
+        return H2_ERR_INVALID_ARG;
+    }
+    A->prof = enable != 0;
+    if (A->prof) {
+        std::fill(A->prof_ms, A->prof_ms + 8, 0.0);
+        A->prof_calls = 0;
+    }
+    return H2_OK;
+}
+
+h2_status h2_profile_read(h2_handle A, double *ms, int64_t *calls) {
+    try {
+        if (!A || !ms || !calls) fail(H2_ERR_INVALID_ARG, "NULL argument");
+        for (size_t i = 0; i + PH_COUNT < A->pending.size(); i += PH_COUNT + 1) {
+            hipEvent_t *ev = &A->pending[i];
+            check_hip(hipEventSynchronize(ev[PH_COUNT]), "hipEventSynchronize");
+            for (int p = 0; p < PH_COUNT; ++p) {
+                float t = 0.0f;
+                // end of phase p = start of the next recorded phase
+                check_hip(hipEventElapsedTime(&t, ev[p], ev[p + 1]), "hipEventElapsedTime");
+                A->prof_ms[p] += t;
+            }
+            float tot = 0.0f;
+            check_hip(hipEventElapsedTime(&tot, ev[0], ev[PH_COUNT]), "hipEventElapsedTime");
+            A->prof_ms[PH_COUNT] += tot;
+            ++A->prof_calls;
+        }
+        A->spare.insert(A->spare.end(), A->pending.begin(), A->pending.end());
+        A->pending.clear();
+        std::copy(A->prof_ms, A->prof_ms + 8, ms);
+        *calls = A->prof_calls;
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    }
+}
+
+}  // extern "C"
