@@ -65,6 +65,21 @@ typedef enum {
  * fields are added in FP64. */
 typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16_SCALED = 2 } h2_storage;
 
+/* Storage modifier, OR-ed into an h2_storage value: blocks stored by halves
+ * (a use of the format that the symmetric case allows, Sec. 2.2: S_ji =
+ * S_ij^T and D_ji = D_ij^T with V = U and F = E).  Only the coupling and dense
+ * blocks with column >= row are held (diagonal dense blocks in full), which
+ * about halves the bytes a product streams; the product reads each stored
+ * block once for both S_ij x_j and S_ij^T x_i, and adds the transposed
+ * contributions of every segment (FP64 partial sums, 512 bytes per stored
+ * off-diagonal block) in a second launch.  Products match the full storage up
+ * to rounding order.  h2_get_info reports the modifier in storage and the
+ * stored bytes in bytes_coupling and bytes_dense.  Handles stored by halves
+ * are rejected with UNSUPPORTED by h2_orthogonalize, h2_compress,
+ * h2_transpose (such a matrix is its own transpose) and h2_batch_create;
+ * h2_matmat runs one single-vector product per column. */
+#define H2_HALF_STORAGE 16
+
 /* flags */
 #define H2_FLAG_STRUCTURE_ONLY 1u   /* build the host-side structure only: no device
                                        memory, matvec/matmat then return INVALID_ARG */
@@ -105,9 +120,10 @@ typedef struct {
  *  out     host; receives the handle (NULL on error).
  * The call returns after the device representation is complete.
  * Errors: INVALID_ARG for n < 1, dim not in {2,3}, leaf_size < 2, cheb_p < 1,
- * eta <= 0 or NaN, corr_len <= 0 or NaN, storage out of range, non-finite
- * coordinates or NULL pointers; UNSUPPORTED for rank or leaf_size > 64; OOM;
- * DEVICE. */
+ * eta <= 0 or NaN, corr_len <= 0 or NaN, storage out of range (an h2_storage,
+ * optionally | H2_HALF_STORAGE), non-finite coordinates or NULL pointers, and
+ * with H2_HALF_STORAGE a block pattern that is not symmetric; UNSUPPORTED for
+ * rank or leaf_size > 64; OOM; DEVICE. */
 h2_status h2_build_from_points(const double *points, int64_t n, const h2_params *prm,
                                void *stream, h2_handle *out);
 
@@ -156,7 +172,12 @@ typedef struct {
 
 /* Build a handle from arrays (values converted to the storage's layout and
  * element type on the host and uploaded in pieces of at most 64 MiB).
- *  storage  h2_storage; H2_FP32 / H2_BF16_SCALED round as described above.
+ *  storage  h2_storage, optionally | H2_HALF_STORAGE; H2_FP32 /
+ *           H2_BF16_SCALED round as described above.  With H2_HALF_STORAGE the
+ *           arrays must be symmetric bit for bit: V = U, F = E, every pair
+ *           (i, j) listed once per BSR list, its mirror (j, i) listed too, and
+ *           S_ji = S_ij^T, D_ji = D_ij^T (INVALID_ARG otherwise); the export
+ *           gives the full arrays back.
  *  stream   stream of the uploads; the call returns when they are done.
  * h2_get_info reports dim 0, cheb_p 0, leaf_size = the largest leaf and rank
  * = the largest level rank.  Errors: INVALID_ARG for NULL required pointers,
@@ -200,8 +221,8 @@ h2_status h2_export_arrays(h2_handle A, const h2_arrays_out *out, void *stream);
  * orthonormal.  The call returns when the device work is done; a matrix
  * without coupling blocks is left as it is.
  * Errors: INVALID_ARG for NULL or structure-only handles; UNSUPPORTED for
- * storage other than H2_FP64, a leaf with fewer rows than the leaf rank, or
- * k_(l-1) > 2 k_l; DEVICE. */
+ * storage other than H2_FP64, blocks stored by halves, a leaf with fewer rows
+ * than the leaf rank, or k_(l-1) > 2 k_l; DEVICE. */
 h2_status h2_orthogonalize(h2_handle A, void *stream);
 
 /* The transposed matrix A^T as a new handle (Sec. 2.2: A^T = sum over levels of
@@ -213,8 +234,8 @@ h2_status h2_orthogonalize(h2_handle A, void *stream);
  * A is unchanged and the two handles are independent (each is freed with
  * h2_free).  For the symmetric matrices of h2_build_from_points, A^T = A.
  *  out  receives the new handle (NULL on error).
- * Errors: INVALID_ARG for NULL arguments or a structure-only handle; OOM;
- * DEVICE. */
+ * Errors: INVALID_ARG for NULL arguments or a structure-only handle;
+ * UNSUPPORTED for blocks stored by halves; OOM; DEVICE. */
 h2_status h2_transpose(h2_handle A, void *stream, h2_handle *out);
 
 /* Algebraic compression (Sec. 5), in place: orthogonalization as
@@ -257,7 +278,8 @@ h2_status h2_matvec(h2_handle A, const double *x, double *y, void *stream);
  * dense contraction.
  *  X  device, column-major n x nrhs, leading dimension ldx >= n, tree order.
  *  Y  device, column-major n x nrhs, leading dimension ldy >= n.
- * H2_FP64 handles run nrhs FP64 products; H2_FP32 and H2_BF16_SCALED handles
+ * H2_FP64 handles, and handles stored by halves, run nrhs single-vector
+ * products; other H2_FP32 and H2_BF16_SCALED handles
  * run on the matrix cores (FP32 MFMA), 32 right-hand sides per pass.  The first
  * such call on a handle times the two block loops (pipelined or not) on its
  * first pass and keeps the faster (cached like a batch's choice, below).
@@ -306,7 +328,8 @@ h2_status h2_profile_read(h2_handle A, double *ms, int64_t *calls);
  *
  * h2_batch_create
  *  mats    host, count handles, all built with the same storage, H2_FP32 or
- *          H2_BF16_SCALED (H2_FP64 gives UNSUPPORTED); the handles must outlive
+ *          H2_BF16_SCALED (H2_FP64 or blocks stored by halves give
+ *          UNSUPPORTED); the handles must outlive
  *          the batch and must not be used by other calls while a batch product
  *          runs (the batch reads their representation).
  *  nrhs    1 <= nrhs <= 32 right-hand sides per member (UNSUPPORTED above).

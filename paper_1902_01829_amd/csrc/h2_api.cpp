@@ -33,7 +33,7 @@ h2_status h2_get_info(h2_handle A, h2_info *info) {
     r.rank = s.rank;
     r.levels_q = s.q;
     r.lmin = s.lmin;
-    r.storage = A->storage;
+    r.storage = A->storage | (A->half ? H2_HALF_STORAGE : 0);
     r.nnodes = s.nnodes;
     for (const auto &B : s.coupling) r.coupling_blocks += B.blocks();
     r.dense_blocks = s.dense.blocks();

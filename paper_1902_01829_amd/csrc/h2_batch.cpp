@@ -119,6 +119,7 @@ void build_batch(h2_batch_ &B, hipStream_t stream) {
     for (h2_matrix_ *M : B.mats) {
         if (M->structure_only) fail(H2_ERR_INVALID_ARG, "structure-only member");
         if (M->storage == H2_FP64) fail(H2_ERR_UNSUPPORTED, "batches need FP32 or BF16 storage");
+        if (M->half) fail(H2_ERR_UNSUPPORTED, "batch member stored by halves");
         if (M->basis_kind != kind_basis || M->block_kind != kind_block)
             fail(H2_ERR_UNSUPPORTED, "all batch members need the same storage");
     }

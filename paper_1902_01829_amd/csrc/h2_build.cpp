@@ -3,6 +3,9 @@
 // export of its stored arrays.
 #include "h2_internal.h"
 
+#include <unordered_map>
+#include <unordered_set>
+
 namespace h2i {
 
 namespace {
@@ -156,27 +159,68 @@ std::vector<h2::FillDesc> make_layout(h2_matrix_ &A, int64_t &ncoupling) {
     A.bytes_leaf = lowrank ? leaf_elems * eb : 0;
     A.bytes_transfer = (nb - leaf_elems) * eb;
 
-    // block region: coupling blocks level by level in BSR order, then dense blocks
+    // block region: coupling blocks level by level in BSR order, then dense
+    // blocks; stored by halves, only the blocks with column >= row
     std::vector<h2::FillDesc> fill;
+    std::vector<int64_t> store;   // per block of the lists: stored index, or -1 until linked
     int64_t ns = 0;
+    // Stored by halves: each block below the diagonal takes the index of its
+    // mirror; the pattern must be symmetric, with every pair listed once.
+    auto link_mirrors = [&](const h2::Bsr &B, int64_t nrows, size_t base) {
+        std::unordered_set<uint64_t> seen;
+        std::unordered_map<uint64_t, int64_t> upper;
+        for (int64_t i = 0; i < nrows; ++i)
+            for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b) {
+                const uint64_t key = (uint64_t(i) << 32) | uint32_t(B.colidx[b]);
+                if (!seen.insert(key).second) fail(H2_ERR_INVALID_ARG, "half storage: a block pair listed twice");
+                if (B.colidx[b] >= i) upper.emplace(key, store[base + size_t(b)]);
+            }
+        for (int64_t i = 0; i < nrows; ++i)
+            for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b)
+                if (B.colidx[b] < i) {
+                    const auto it = upper.find((uint64_t(uint32_t(B.colidx[b])) << 32) | uint64_t(i));
+                    if (it == upper.end()) fail(H2_ERR_INVALID_ARG, "half storage: block pattern not symmetric");
+                    store[base + size_t(b)] = -(it->second + 1);
+                }
+    };
     for (int l = 0; l <= q; ++l) {
         const h2::Bsr &B = s.coupling[l];
         const int64_t f = Structure::first(l);
+        const size_t base = store.size();
         for (int64_t i = 0; i < (int64_t(1) << l); ++i)
             for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b) {
+                if (A.half && B.colidx[b] < i) {
+                    store.push_back(-1);
+                    continue;
+                }
+                store.push_back(int64_t(fill.size()));
                 fill.push_back({ns, int32_t(f + i), int32_t(f + B.colidx[b]), int32_t(fill.size()),
                                 h2::FILL_COUPLING});
                 ns += h2::block_elems(kl[l], kl[l], sk);
             }
+        if (A.half) link_mirrors(B, int64_t(1) << l, base);
     }
     const int64_t coupling_elems = ns;
     ncoupling = int64_t(fill.size());
-    for (int64_t i = 0; i < nleaves; ++i)
-        for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b) {
-            const int64_t t = lf + s.dense.colidx[b];
-            fill.push_back({ns, int32_t(lf + i), int32_t(t), int32_t(fill.size()), h2::FILL_DENSE});
-            ns += h2::block_elems(int(s.size(lf + i)), int(s.size(t)), sk);
-        }
+    {
+        const size_t base = store.size();
+        for (int64_t i = 0; i < nleaves; ++i)
+            for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b) {
+                if (A.half && s.dense.colidx[b] < i) {
+                    store.push_back(-1);
+                    continue;
+                }
+                const int64_t t = lf + s.dense.colidx[b];
+                store.push_back(int64_t(fill.size()));
+                fill.push_back({ns, int32_t(lf + i), int32_t(t), int32_t(fill.size()), h2::FILL_DENSE});
+                ns += h2::block_elems(int(s.size(lf + i)), int(s.size(t)), sk);
+            }
+        if (A.half) link_mirrors(s.dense, nleaves, base);
+    }
+    if (A.half)
+        A.blk_store = std::move(store);
+    else
+        A.blk_store.clear();
     const int64_t scale_bytes = sk == h2::ELEM_BF16 ? 4 : 0;
     A.off_U = off_U;
     A.off_VT = off_VT;
@@ -267,24 +311,52 @@ void build_device(h2_matrix_ &A, const h2_arrays *src, hipStream_t stream) {
             up.flush();
         }
         {
-            Stager up(A.blocks, sk, stream);
-            std::vector<float> scales(fill.size(), 1.0f);
-            int64_t fi = 0;
+            // every block of the lists: its source values and shape
+            std::vector<const double *> bsrc;
+            std::vector<int> bR, bC;
             for (int l = 0; l <= q; ++l) {
-                const h2::Bsr &B = s.coupling[l];
                 const int64_t kk = int64_t(kl[l]) * kl[l];
-                for (int64_t b = 0; b < B.blocks(); ++b, ++fi)
-                    convert_block(src->S[l] + b * kk, kl[l], kl[l], false, sk,
-                                  up.place(fill[fi].a, h2::block_elems(kl[l], kl[l], sk)), &scales[fi]);
+                for (int64_t b = 0; b < s.coupling[l].blocks(); ++b) {
+                    bsrc.push_back(src->S[l] + b * kk);
+                    bR.push_back(kl[l]);
+                    bC.push_back(kl[l]);
+                }
             }
             int64_t doff = 0;
             for (int64_t i = 0; i < nleaves; ++i)
-                for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++fi) {
+                for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b) {
                     const int R = int(s.size(lf + i)), C = int(s.size(lf + s.dense.colidx[b]));
-                    convert_block(src->D + doff, R, C, false, sk, up.place(fill[fi].a, h2::block_elems(R, C, sk)),
-                                  &scales[fi]);
+                    bsrc.push_back(src->D + doff);
+                    bR.push_back(R);
+                    bC.push_back(C);
                     doff += int64_t(R) * C;
                 }
+            if (A.half) {
+                // stored by halves: V = U, F = E, and every block below the
+                // diagonal the transpose of its mirror, value by value
+                if (!A.symmetric) fail(H2_ERR_INVALID_ARG, "half storage needs V = U and F = E");
+                std::vector<size_t> stored_at(fill.size());
+                for (size_t b = 0; b < bsrc.size(); ++b)
+                    if (A.blk_store[b] >= 0) stored_at[size_t(A.blk_store[b])] = b;
+                for (size_t b = 0; b < bsrc.size(); ++b) {
+                    if (A.blk_store[b] >= 0) continue;
+                    const size_t m = stored_at[size_t(-A.blk_store[b] - 1)];
+                    const int R = bR[b], C = bC[b];
+                    bool same = bR[m] == C && bC[m] == R;
+                    for (int c = 0; c < C && same; ++c)
+                        for (int r = 0; r < R && same; ++r)
+                            same = std::memcmp(bsrc[b] + r + int64_t(c) * R, bsrc[m] + c + int64_t(r) * C, 8) == 0;
+                    if (!same) fail(H2_ERR_INVALID_ARG, "half storage: a block differs from its mirror's transpose");
+                }
+            }
+            Stager up(A.blocks, sk, stream);
+            std::vector<float> scales(fill.size(), 1.0f);
+            for (size_t b = 0; b < bsrc.size(); ++b) {
+                const int64_t fi = A.blk_store.empty() ? int64_t(b) : A.blk_store[b];
+                if (fi < 0) continue;   // mirror of a stored block
+                convert_block(bsrc[b], bR[b], bC[b], false, sk,
+                              up.place(fill[size_t(fi)].a, h2::block_elems(bR[b], bC[b], sk)), &scales[size_t(fi)]);
+            }
             up.flush();
             if (sk == h2::ELEM_BF16 && !scales.empty()) {
                 check_hip(hipMemcpyAsync(A.scales, scales.data(), scales.size() * 4, hipMemcpyHostToDevice, stream),
@@ -321,6 +393,7 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
         int32_t C, sidx;
         bool point;
         int64_t id;
+        int32_t slot = -1;   // stored by halves: partial slot of the transposed product
     };
     struct LRow {
         bool point;      // output is a leaf segment (else a tree node)
@@ -399,27 +472,95 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
     // tree multiplication y^_i = sum_j S_ij x^_j on all levels (Sec. 4.3) and the
     // dense near field y_near(i) = sum_j D_ij x(j) (Sec. 4.1) in one launch
     {
-        int64_t fi = 0;
+        // blocks by their index in the lists (coupling levels, then dense);
+        // stored by halves, the mirrors of stored blocks are left out
+        int64_t li = 0;
+        auto stored = [&](int64_t b) { return A.blk_store.empty() ? b : A.blk_store[size_t(b)]; };
+        for (int l = 0; l < s.lmin && lowrank; ++l) li += s.coupling[l].blocks();
         if (lowrank)
             for (int l = s.lmin; l <= q; ++l) {
                 const h2::Bsr &B = s.coupling[l];
                 const int64_t f = Structure::first(l);
                 for (int64_t i = 0; i < (int64_t(1) << l); ++i) {
                     LRow r{false, f + i, false, kl[l], 0, {}};
-                    for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b, ++fi)
-                        r.b.push_back({fill[fi].a, kl[l], fill[fi].sidx, false, f + B.colidx[b]});
+                    for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b, ++li) {
+                        const int64_t fi = stored(li);
+                        if (fi >= 0) r.b.push_back({fill[fi].a, kl[l], fill[fi].sidx, false, f + B.colidx[b]});
+                    }
                     L.push_back(std::move(r));
                 }
             }
-        fi = ncoupling;
+        li = 0;
+        for (int l = 0; l <= q; ++l) li += s.coupling[l].blocks();
         for (int64_t i = 0; i < nleaves; ++i) {
             LRow r{true, i, false, int(s.size(lf + i)), h2::ROW_IN_X | h2::ROW_OUT_P, {}};
-            for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++fi) {
-                const int64_t t = s.dense.colidx[b];
-                r.b.push_back({fill[fi].a, int32_t(s.size(lf + t)), fill[fi].sidx, true, t});
+            for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++li) {
+                const int64_t t = s.dense.colidx[b], fi = stored(li);
+                if (fi >= 0) r.b.push_back({fill[fi].a, int32_t(s.size(lf + t)), fill[fi].sidx, true, t});
             }
             L.push_back(std::move(r));
         }
+        if (A.half) {
+            // One launch reads every stored block once for both of its
+            // products; the transposed ones land in partial slots, grouped by
+            // the segment they belong to, and a second launch adds each
+            // segment's slots to its row sum.
+            struct Off {
+                bool point;
+                int64_t id;
+                size_t row, blk;
+            };
+            std::vector<Off> offd;
+            for (size_t r = 0; r < L.size(); ++r)
+                for (size_t b = 0; b < L[r].b.size(); ++b)
+                    if (L[r].b[b].point != L[r].point || L[r].b[b].id != L[r].id)
+                        offd.push_back({L[r].b[b].point, L[r].b[b].id, r, b});
+            std::stable_sort(offd.begin(), offd.end(), [](const Off &x, const Off &y) {
+                return x.point != y.point ? x.point < y.point : x.id < y.id;
+            });
+            if (offd.size() >= (size_t(1) << 31)) fail(H2_ERR_UNSUPPORTED, "too many blocks stored by halves");
+            std::vector<h2::ReduceDesc> red;
+            for (size_t k = 0; k < offd.size(); ++k) {
+                LBlk &lb = L[offd[k].row].b[offd[k].blk];
+                lb.slot = int32_t(k);
+                if (k == 0 || offd[k].point != offd[k - 1].point || offd[k].id != offd[k - 1].id)
+                    red.push_back({mv_off(lb.point, lb.id), int32_t(k), int32_t(k), lb.C, lb.point ? 1 : 0});
+                red.back().c1 = int32_t(k + 1);
+            }
+            std::stable_sort(L.begin(), L.end(), [](const LRow &a, const LRow &b) { return a.b.size() > b.b.size(); });
+            std::vector<RowDesc> rows;
+            std::vector<BlkDesc> blks;
+            std::vector<int32_t> slots;
+            for (const LRow &r : L) {
+                RowDesc d;
+                d.out = mv_off(r.point, r.id);
+                d.init = -1;
+                d.R = r.R;
+                d.sel = r.sel;
+                d.b0 = int32_t(blks.size());
+                for (const LBlk &b : r.b) {
+                    blks.push_back({b.a, mv_off(b.point, b.id), b.C, b.sidx});
+                    slots.push_back(b.slot);
+                }
+                d.b1 = int32_t(blks.size());
+                rows.push_back(d);
+            }
+            WorkList w;
+            w.phase = PH_STREAM;
+            w.kind = sk;
+            w.data = A.blocks;
+            w.nrows = int64_t(rows.size());
+            w.rows = A.mem.upload(rows, stream);
+            w.blks = A.mem.upload(blks, stream);
+            w.slot = A.mem.upload(slots, stream);
+            w.red = A.mem.upload(red, stream);
+            w.nred = int64_t(red.size());
+            w.partials = static_cast<double *>(A.mem.alloc(int64_t(offd.size()) * 64 * 8));
+            A.lists.push_back(w);
+            L.clear();
+        }
+    }
+    if (!A.half) {
         // Tile lists (many right-hand sides): the input tiles (k x 32 per node)
         // outgrow the last-level cache, so rows stay in spatial order -- leaf rows
         // (dense) first, then coupling rows from the finest level up, each by
@@ -510,7 +651,8 @@ void validate_params(const double *points, int64_t n, const h2_params *prm) {
     if (!(prm->eta > 0.0) || !std::isfinite(prm->eta)) fail(H2_ERR_INVALID_ARG, "eta must be > 0");
     if (!(prm->corr_len > 0.0) || !std::isfinite(prm->corr_len))
         fail(H2_ERR_INVALID_ARG, "corr_len must be > 0");
-    if (prm->storage < H2_FP64 || prm->storage > H2_BF16_SCALED) fail(H2_ERR_INVALID_ARG, "bad storage");
+    const int prec = prm->storage & ~H2_HALF_STORAGE;
+    if (prec < H2_FP64 || prec > H2_BF16_SCALED) fail(H2_ERR_INVALID_ARG, "bad storage");
     if (prm->flags & ~unsigned(H2_FLAG_STRUCTURE_ONLY)) fail(H2_ERR_INVALID_ARG, "unknown flags");
     for (int64_t i = 0; i < n * prm->dim; ++i)
         if (!std::isfinite(points[i])) fail(H2_ERR_INVALID_ARG, "non-finite coordinate");
@@ -682,6 +824,21 @@ void export_arrays(h2_matrix_ &A, const h2_arrays_out *o, hipStream_t st) {
     }
     auto scale_of = [&](int64_t i) { return scales.empty() ? 1.0f : scales[size_t(i)]; };
     Reader rd(A.blocks, A.block_kind, A.block_elems, st);
+    // Stored by halves, a block below the diagonal is its mirror transposed;
+    // those are read after the stored ones, in storage order.
+    struct Mirror {
+        int64_t m;
+        int R, C;
+        double *dst;
+    };
+    std::vector<Mirror> mirrors;
+    auto read_block = [&](int64_t li, int R, int C, double *dst) {
+        const int64_t si = A.blk_store.empty() ? li : A.blk_store[size_t(li)];
+        if (si >= 0)
+            rd.block(A.off_blk[size_t(si)], R, C, false, scale_of(si), dst);
+        else
+            mirrors.push_back({-si - 1, R, C, dst});
+    };
     int64_t fi = 0;
     for (int l = 0; l <= q; ++l) {
         const h2::Bsr &B = s.coupling[l];
@@ -689,7 +846,7 @@ void export_arrays(h2_matrix_ &A, const h2_arrays_out *o, hipStream_t st) {
         if (o->S_colidx && o->S_colidx[l]) std::copy(B.colidx.begin(), B.colidx.end(), o->S_colidx[l]);
         const int64_t kk = int64_t(kl[l]) * kl[l];
         for (int64_t b = 0; b < B.blocks(); ++b, ++fi)
-            if (o->S && o->S[l]) rd.block(A.off_blk[fi], kl[l], kl[l], false, scale_of(fi), o->S[l] + b * kk);
+            if (o->S && o->S[l]) read_block(fi, kl[l], kl[l], o->S[l] + b * kk);
     }
     if (o->D_rowptr) std::copy(s.dense.rowptr.begin(), s.dense.rowptr.end(), o->D_rowptr);
     if (o->D_colidx) std::copy(s.dense.colidx.begin(), s.dense.colidx.end(), o->D_colidx);
@@ -698,10 +855,13 @@ void export_arrays(h2_matrix_ &A, const h2_arrays_out *o, hipStream_t st) {
         for (int64_t i = 0; i < nleaves; ++i)
             for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++fi) {
                 const int R = int(s.size(lf + i)), C = int(s.size(lf + s.dense.colidx[b]));
-                rd.block(A.off_blk[fi], R, C, false, scale_of(fi), o->D + doff);
+                read_block(fi, R, C, o->D + doff);
                 doff += int64_t(R) * C;
             }
     }
+    std::stable_sort(mirrors.begin(), mirrors.end(), [](const Mirror &x, const Mirror &y) { return x.m < y.m; });
+    for (const Mirror &mi : mirrors)   // the stored block is C x R
+        rd.block(A.off_blk[size_t(mi.m)], mi.C, mi.R, true, scale_of(mi.m), mi.dst);
 }
 
 }  // namespace h2i
@@ -718,13 +878,13 @@ h2_status h2_build_from_points(const double *points, int64_t n, const h2_params 
         if (!out) fail(H2_ERR_INVALID_ARG, "NULL out");
         validate_params(points, n, prm);
         A = new h2_matrix_();
-        A->storage = prm->storage;
+        const int prec = prm->storage & ~H2_HALF_STORAGE;
+        A->storage = prec;
+        A->half = (prm->storage & H2_HALF_STORAGE) != 0;
         A->structure_only = (prm->flags & H2_FLAG_STRUCTURE_ONLY) != 0;
-        A->basis_kind = prm->storage == H2_FP64 ? h2::ELEM_F64 : h2::ELEM_F32;
-        A->block_kind = prm->storage == H2_FP64   ? h2::ELEM_F64
-                        : prm->storage == H2_FP32 ? h2::ELEM_F32
-                                                  : h2::ELEM_BF16;
-        A->vec_f64 = prm->storage == H2_FP64;
+        A->basis_kind = prec == H2_FP64 ? h2::ELEM_F64 : h2::ELEM_F32;
+        A->block_kind = prec == H2_FP64 ? h2::ELEM_F64 : prec == H2_FP32 ? h2::ELEM_F32 : h2::ELEM_BF16;
+        A->vec_f64 = prec == H2_FP64;
         std::string err = h2::build_structure(points, n, prm->dim, prm->leaf_size, prm->cheb_p, prm->eta,
                                               prm->corr_len, A->st);
         if (!err.empty()) fail(H2_ERR_UNSUPPORTED, err);
@@ -752,13 +912,15 @@ h2_status h2_build_from_arrays(const h2_arrays *arrays, int storage, void *strea
     h2_matrix_ *A = nullptr;
     try {
         if (!out) fail(H2_ERR_INVALID_ARG, "NULL out");
-        if (storage < H2_FP64 || storage > H2_BF16_SCALED) fail(H2_ERR_INVALID_ARG, "storage out of range");
+        const int prec = storage & ~H2_HALF_STORAGE;
+        if (prec < H2_FP64 || prec > H2_BF16_SCALED) fail(H2_ERR_INVALID_ARG, "storage out of range");
         A = new h2_matrix_();
         structure_from_arrays(arrays, A->st);
-        A->storage = storage;
-        A->basis_kind = storage == H2_FP64 ? h2::ELEM_F64 : h2::ELEM_F32;
-        A->block_kind = storage == H2_FP64 ? h2::ELEM_F64 : storage == H2_FP32 ? h2::ELEM_F32 : h2::ELEM_BF16;
-        A->vec_f64 = storage == H2_FP64;
+        A->storage = prec;
+        A->half = (storage & H2_HALF_STORAGE) != 0;
+        A->basis_kind = prec == H2_FP64 ? h2::ELEM_F64 : h2::ELEM_F32;
+        A->block_kind = prec == H2_FP64 ? h2::ELEM_F64 : prec == H2_FP32 ? h2::ELEM_F32 : h2::ELEM_BF16;
+        A->vec_f64 = prec == H2_FP64;
         {
             // V = U and F = E (value by value): the symmetric case orthogonalization handles
             const h2::Structure &st = A->st;

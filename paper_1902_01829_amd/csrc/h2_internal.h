@@ -7,7 +7,6 @@
 
 #include <hip/hip_runtime.h>
 
-#include <hip/hip_runtime.h>
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -109,6 +108,9 @@ struct WorkList {
     const h2::ReduceDesc *red = nullptr;
     int64_t nred = 0;
     double *partials = nullptr;
+    // stream list of a matrix stored by halves: partial slot of every block
+    // (-1: diagonal block); red then adds the slots to the row sums
+    const int32_t *slot = nullptr;
 };
 
 // A single-vector stream list with fewer block rows than this is split into
@@ -165,6 +167,11 @@ struct h2_matrix_ {
     std::vector<int64_t> off_U, off_VT, off_E, off_FT, off_blk;
     int64_t basis_elems = 0, block_elems = 0;   // lengths of the two regions
     bool symmetric = true;                      // V = U and F = E
+    // stored by halves (H2_HALF_STORAGE): only blocks with column >= row; for
+    // every block of the full BSR lists (coupling levels, then dense) its
+    // index in off_blk, or -(index + 1) of the stored block it mirrors
+    bool half = false;
+    std::vector<int64_t> blk_store;
     int batch_refs = 0;                         // batches holding addresses into this matrix
     // profiling: PH_COUNT + 1 events per recorded call
     bool prof = false;

@@ -247,9 +247,10 @@ __global__ __launch_bounds__(256) void fill_blocks_bf16_kernel(Geometry g, uint1
 }
 
 // ---------------------------------------------------------------- chunk sums
-// One wavefront per split row: lane r adds partials[c * 64 + r] over the row's
-// chunks in order (FP64) and stores the row's output element r.
-template <typename TV>
+// One wavefront per segment: lane r adds partials[c * 64 + r] over the
+// segment's chunks in order (FP64) and stores the segment's element r; with
+// ADD the sum starts from the element's current value.
+template <typename TV, bool ADD>
 __global__ __launch_bounds__(256) void reduce_chunks_kernel(const ReduceDesc *__restrict__ desc, int64_t n,
                                                             const double *__restrict__ partials, TV *__restrict__ out0,
                                                             TV *__restrict__ out1) {
@@ -258,9 +259,10 @@ __global__ __launch_bounds__(256) void reduce_chunks_kernel(const ReduceDesc *__
     if (i >= n) return;
     const ReduceDesc d = desc[i];
     if (r >= d.R) return;
-    double acc = 0.0;
+    TV *dst = (d.point ? out1 : out0) + d.out + r;
+    double acc = ADD ? double(*dst) : 0.0;
     for (int c = d.c0; c < d.c1; ++c) acc += partials[int64_t(c) * 64 + r];
-    (d.point ? out1 : out0)[d.out + r] = TV(acc);
+    *dst = TV(acc);
 }
 
 // ---------------------------------------------------------------- transposed copies
@@ -375,6 +377,98 @@ H2_BLOCKROW_KERNEL(downsweep_kernel)
 H2_BLOCKROW_KERNEL(leafexpand_kernel)
 #undef H2_BLOCKROW_KERNEL
 
+// ---------------------------------------------------------------- half storage
+// Column sums of a 32-column chunk held one row per lane (v[c] = row lane,
+// column c): each step pairs lanes across one lane bit, each partner keeps the
+// half of its live columns named by that bit and adds the other's copy of it,
+// so after five steps lane l holds column l % 32 summed over its 32-lane half;
+// the two halves are then added.
+template <typename P>
+__device__ __forceinline__ P column_sums32(P (&v)[32], int lane) {
+#pragma unroll
+    for (int h = 16; h >= 1; h >>= 1) {
+        const bool up = (lane & h) != 0;
+#pragma unroll
+        for (int k = 0; k < h; ++k) {
+            const P keep = up ? v[k + h] : v[k];
+            const P send = up ? v[k] : v[k + h];
+            v[k] = keep + __shfl_xor(send, h);
+        }
+    }
+    return v[0] + __shfl_xor(v[0], 32);
+}
+
+// Stream phase of a matrix stored by halves: block row i holds only its
+// blocks with j >= i (S_ji = S_ij^T, D_ji = D_ij^T).  One wavefront per block
+// row, lane r on row r; every stored block is read once, in 32-column chunks
+// kept in registers, and gives both of its products: S_ij x_j, summed over
+// the row as in the full product, and S_ij^T x_i, the contribution to
+// segment j, whose column sums are formed across the lanes (column_sums32)
+// and stored as FP64 in the block's partial slot (off-diagonal blocks only).
+// A second launch adds each segment's slots to its row sum.  The row's own
+// input segment has the offset of its output segment (x^ and y^ share the
+// node layout, x and y_near the point layout).
+template <int KIND, typename TV>
+__global__ __launch_bounds__(256) void stream_half_kernel(
+    const RowDesc *__restrict__ rows, int64_t nrows, const BlkDesc *__restrict__ blks,
+    const int32_t *__restrict__ slot, const typename Elem<KIND>::T *__restrict__ data,
+    const float *__restrict__ scales, const TV *__restrict__ in0, const double *__restrict__ in1,
+    TV *__restrict__ out0, TV *__restrict__ out1, double *__restrict__ partials) {
+    using E = Elem<KIND>;
+    using P = typename E::P;
+    using V = typename E::V;
+    constexpr int W = E::W;
+    constexpr int IPC = 32 / W;   // 16-byte items per row of a 32-column chunk
+    __shared__ __attribute__((aligned(16))) P xs[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t row = int64_t(blockIdx.x) * 4 + wv;
+    if (row >= nrows) return;
+    const RowDesc rd = rows[row];
+    const int R = rd.R;
+    const bool in_x = (rd.sel & ROW_IN_X) != 0, on = lane < R;
+    P xi = P(0);
+    if (on) xi = in_x ? P(in1[rd.out + lane]) : P(in0[rd.out + lane]);
+    double acc = 0.0;
+    for (int b = rd.b0; b < rd.b1; ++b) {
+        const BlkDesc bd = blks[b];
+        const int C = bd.C, CW = (C + W - 1) / W;
+        const int32_t sl = slot[b];
+        P xv = P(0);
+        if (lane < C) xv = in_x ? P(in1[bd.in + lane]) : P(in0[bd.in + lane]);
+        xs[wv][lane] = xv;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double scale = 1.0;
+        if constexpr (KIND == ELEM_BF16) scale = double(scales[bd.sidx]);
+        const V *p = reinterpret_cast<const V *>(data + bd.a) + lane;   // item (cw, r) at cw * R + r
+        P part = P(0);
+        for (int h = 0; h * 32 < C; ++h) {
+            P v[32];
+#pragma unroll
+            for (int i = 0; i < IPC; ++i) {
+                const int cw = h * IPC + i;
+                V raw = {};
+                if (on && cw < CW) raw = __builtin_nontemporal_load(p + cw * R);
+                E::unpack(raw, v + i * W);
+            }
+#pragma unroll
+            for (int c = 0; c < 32; ++c) part = fma(v[c], xs[wv][h * 32 + c], part);
+            if (sl >= 0) {
+#pragma unroll
+                for (int c = 0; c < 32; ++c) v[c] *= xi;
+                const P t = column_sums32(v, lane);
+                if ((lane >> 5) == h && lane < C) partials[int64_t(sl) * 64 + lane] = double(t) * scale;
+            }
+        }
+        acc += double(part) * scale;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (on) ((rd.sel & ROW_OUT_P) ? out1 : out0)[rd.out + lane] = TV(acc);
+}
+
 constexpr int kRowsPerBlock = 4;
 
 template <int KIND, typename TV, typename TO1>
@@ -457,15 +551,42 @@ hipError_t launch_fill_blocks(const Geometry &g, int block_kind, void *blocks, f
 }
 
 hipError_t launch_reduce_chunks(const ReduceDesc *desc, int64_t n, const double *partials, void *out0, void *out1,
-                                bool vec_f64, hipStream_t st) {
+                                bool vec_f64, hipStream_t st, bool add) {
     if (n <= 0) return hipSuccess;
     const dim3 grid(unsigned((n + 3) / 4)), block(256);
-    if (vec_f64)
-        hipLaunchKernelGGL(reduce_chunks_kernel<double>, grid, block, 0, st, desc, n, partials,
-                           static_cast<double *>(out0), static_cast<double *>(out1));
-    else
-        hipLaunchKernelGGL(reduce_chunks_kernel<float>, grid, block, 0, st, desc, n, partials,
-                           static_cast<float *>(out0), static_cast<float *>(out1));
+    if (vec_f64) {
+        auto *o0 = static_cast<double *>(out0), *o1 = static_cast<double *>(out1);
+        if (add)
+            hipLaunchKernelGGL((reduce_chunks_kernel<double, true>), grid, block, 0, st, desc, n, partials, o0, o1);
+        else
+            hipLaunchKernelGGL((reduce_chunks_kernel<double, false>), grid, block, 0, st, desc, n, partials, o0, o1);
+    } else {
+        auto *o0 = static_cast<float *>(out0), *o1 = static_cast<float *>(out1);
+        if (add)
+            hipLaunchKernelGGL((reduce_chunks_kernel<float, true>), grid, block, 0, st, desc, n, partials, o0, o1);
+        else
+            hipLaunchKernelGGL((reduce_chunks_kernel<float, false>), grid, block, 0, st, desc, n, partials, o0, o1);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_half(const RowLaunch &L, const int32_t *slot, double *partials, int kind, bool vec_f64,
+                              hipStream_t st) {
+    if (L.nrows <= 0) return hipSuccess;
+    const dim3 grid(unsigned((L.nrows + kRowsPerBlock - 1) / kRowsPerBlock)), block(256);
+    if (vec_f64) {
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_F64, double>), grid, block, 0, st, L.rows, L.nrows, L.blks, slot,
+                           static_cast<const double *>(L.data), L.scales, static_cast<const double *>(L.in0), L.in1,
+                           static_cast<double *>(L.out0), static_cast<double *>(L.out1), partials);
+    } else if (kind == ELEM_F32) {
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_F32, float>), grid, block, 0, st, L.rows, L.nrows, L.blks, slot,
+                           static_cast<const float *>(L.data), L.scales, static_cast<const float *>(L.in0), L.in1,
+                           static_cast<float *>(L.out0), static_cast<float *>(L.out1), partials);
+    } else {
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_BF16, float>), grid, block, 0, st, L.rows, L.nrows, L.blks, slot,
+                           static_cast<const uint16_t *>(L.data), L.scales, static_cast<const float *>(L.in0), L.in1,
+                           static_cast<float *>(L.out0), static_cast<float *>(L.out1), partials);
+    }
     return hipGetLastError();
 }
 

@@ -72,6 +72,13 @@ void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st) {
                 L.in0 = A.xh;
                 L.out0 = A.yh;
                 L.out1 = A.ynear;
+                if (w.slot) {   // stored by halves: row sums and transposed partials, then their sums
+                    check_hip(h2::launch_stream_half(L, w.slot, w.partials, w.kind, A.vec_f64, st),
+                              "half-storage stream launch");
+                    check_hip(h2::launch_reduce_chunks(w.red, w.nred, w.partials, A.yh, A.ynear, A.vec_f64, st, true),
+                              "partial sum launch");
+                    return;
+                }
                 if (w.red) {   // chunks of a split list: partial sums, then their sums per row
                     L.out0 = L.out1 = w.partials;
                     check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, int(w.phase), st, 1), "blockrow launch");
@@ -183,8 +190,9 @@ h2_status h2_matmat(h2_handle A, const double *X, int64_t ldx, double *Y, int64_
         if (nrhs < 1) fail(H2_ERR_INVALID_ARG, "nrhs must be >= 1");
         if (ldx < A->st.n || ldy < A->st.n) fail(H2_ERR_INVALID_ARG, "leading dimension below n");
         const hipStream_t st = static_cast<hipStream_t>(stream);
-        if (A->storage == H2_FP64) {
-            // FP64 storage: one single-vector product per column (FP64 arithmetic throughout)
+        if (A->storage == H2_FP64 || A->half) {
+            // FP64 storage, or blocks stored by halves: one single-vector
+            // product per column
             for (int j = 0; j < nrhs; ++j) run_product(*A, X + int64_t(j) * ldx, Y + int64_t(j) * ldy, st);
         } else {
             run_tiles(*A, X, ldx, Y, ldy, nrhs, st);

@@ -94,6 +94,7 @@ void orthogonalize(h2_matrix_ &A, hipStream_t st) {
     const Structure &s = A.st;
     const int q = s.q;
     if (A.storage != H2_FP64) fail(H2_ERR_UNSUPPORTED, "orthogonalization needs FP64 storage");
+    if (A.half) fail(H2_ERR_UNSUPPORTED, "orthogonalization of a matrix stored by halves");
     if (s.lmin > q) return;   // no coupling block: nothing to orthogonalize
     const int64_t nleaves = int64_t(1) << q, lf = Structure::first(q);
     for (int64_t j = 0; j < nleaves; ++j)
@@ -142,6 +143,7 @@ void orthogonalize(h2_matrix_ &A, hipStream_t st) {
 // transposed on the device (U'_j = V_j, V'_j = U_j, E'_c = F_c, F'_c = E_c),
 // values unchanged (BF16 codes and scales included).
 h2_matrix_ *transpose_matrix(h2_matrix_ &A, hipStream_t st) {
+    if (A.half) fail(H2_ERR_UNSUPPORTED, "a matrix stored by halves is symmetric: it is its own transpose");
     const Structure &s = A.st;
     const int q = s.q;
     const std::vector<int> &kl = s.lrank;
@@ -238,6 +240,7 @@ void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
     if (!(eps >= 0.0) || !std::isfinite(eps)) fail(H2_ERR_INVALID_ARG, "eps must be finite and >= 0");
     if (A.batch_refs > 0) fail(H2_ERR_INVALID_ARG, "the matrix belongs to a batch (free the batch first)");
     if (A.storage != H2_FP64) fail(H2_ERR_UNSUPPORTED, "compression needs FP64 storage");
+    if (A.half) fail(H2_ERR_UNSUPPORTED, "compression of a matrix stored by halves");
     // One basis tree for rows and columns (V = U, F = E): whether S_ji = S_ij^T
     // for every coupling block, decided before the orthogonalization (which
     // keeps the symmetry only up to rounding); if not, the one tree also serves

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libh2mv.so"
 H2_OK, H2_ERR_INVALID_ARG, H2_ERR_OOM, H2_ERR_DEVICE, H2_ERR_UNSUPPORTED, H2_ERR_INTERNAL = range(6)
 H2_FP64, H2_FP32, H2_BF16_SCALED = 0, 1, 2
 H2_FLAG_STRUCTURE_ONLY = 1
+H2_HALF_STORAGE = 16   # OR-ed into a storage value: blocks stored by halves (symmetric matrices)
 STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
 
 # Every function declared in include/h2mv.h.
