@@ -410,6 +410,57 @@ def transpose_section(reps=3):
             "rel_diff_AT_x_vs_A_x": rel}
 
 
+HALF = 16   # storage modifier: blocks stored by halves
+
+
+def half_partial_bytes(info, w):
+    """FP64 partial sums of the transposed products, written once and read
+    once: one per stored off-diagonal block, as long as its column segment."""
+    nleaves = 1 << info.levels_q
+    coupling_slots = info.coupling_blocks // 2
+    dense_slots = (info.dense_blocks - nleaves) // 2
+    return 2 * 8 * (coupling_slots * info.rank + dense_slots * w.leaf)
+
+
+def half_section(steps, warmup, full_ms=None, nleaves=16):
+    """Blocks stored by halves (symmetric matrices): the 2-D 2^20-point FP64
+    matrix and the 3-D 2^19-point matrix in its three storage modes.  Time per
+    product, stored bytes, the streaming phase (stored blocks read once for
+    both products, partial sums, their addition per segment) as GB/s of the
+    bytes it moves, the equivalent bandwidth (full-storage algorithmic bytes
+    over the product time), the speedup over full storage, and the error
+    against the FP64 oracle on sampled leaves.  full_ms: full-storage times
+    by (workload, storage) already measured; the others are measured here."""
+    full_ms = dict(full_ms or {})
+    out = {}
+    for w, name in ((W.C2, "fp64"), (W.C3, "fp64"), (W.C3, "fp32"), (W.C3, "bf16")):
+        r = run_matvec(w, STORAGE[name] | HALF, steps, warmup)
+        info = r["info"]
+        key = (w.name, name)
+        if key not in full_ms:
+            rf = run_matvec(w, STORAGE[name], steps, warmup)
+            full_ms[key] = (rf["ms"], algorithmic_bytes(rf["info"], w.n))
+        ms_full, bytes_full = full_ms[key]
+        rows, ref = oracle_sample(w, r["perm"], r["xt"], nleaves)
+        rel = float(np.linalg.norm(r["y"][rows] - ref) / np.linalg.norm(ref))
+        vb = 8 if name == "fp64" else 4
+        phase_bytes = info.bytes_coupling + info.bytes_dense + 8 * w.n + 2 * vb * w.n + half_partial_bytes(info, w)
+        stream_ms = float(r["phase_ms"][1])
+        out[f"{w.name}/{name}"] = {
+            "ms": round(r["ms"], 4), "ms_full_storage": round(ms_full, 4),
+            "speedup_vs_full_storage": round(ms_full / r["ms"], 3),
+            "stored_block_bytes": int(info.bytes_coupling + info.bytes_dense),
+            "algorithmic_bytes": int(algorithmic_bytes(info, w.n)),
+            "equivalent_GB_per_s": round(bytes_full / (r["ms"] * 1e-3) / 1e9, 1),
+            "stream_phase_ms": round(stream_ms, 4), "stream_phase_bytes": int(phase_bytes),
+            "stream_phase_GB_per_s": round(phase_bytes / (stream_ms * 1e-3) / 1e9, 1),
+            "rel_err_vs_fp64_oracle": rel}
+        log(f"half {w.name} {name}: {r['ms']:.3f} ms (full {ms_full:.3f} ms, x{ms_full / r['ms']:.2f}), stream "
+            f"phase {stream_ms:.3f} ms = {phase_bytes / (stream_ms * 1e-3) / 1e9:.0f} GB/s, rel err {rel:.2e}")
+    out["error_sample"] = f"all rows of {nleaves} seeded leaves vs the FP64 oracle"
+    return out
+
+
 def storage_modes(steps, warmup, nleaves=16):
     """The 3-D workload (2^19 points, rank 64) in FP64, FP32 and BF16 storage."""
     w = W.C3
@@ -594,7 +645,7 @@ def main():
                     help="skip the storage-mode, many-right-hand-side and batch sections")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--only", choices=["small", "modes", "matmat", "batch", "orthogonalize", "compress",
-                                      "transpose"],
+                                      "transpose", "half"],
                     default=None,
                     help="run one section alone and print its JSON (for profiling runs); "
                          "the headline line is not printed")
@@ -632,6 +683,8 @@ def main():
             out = compress_section()
         elif args.only == "transpose":
             out = transpose_section()
+        elif args.only == "half":
+            out = half_section(args.steps, args.warmup)
         else:
             out = batch_modes(args.steps, args.warmup)
         print(json.dumps({"section": args.only, **out}), flush=True)
@@ -675,7 +728,7 @@ def main():
         result["rel_err_vs_oracle_sample"] = float(np.linalg.norm(r["y"][rows] - y_ref) / np.linalg.norm(y_ref))
     if not args.no_modes:
         result["small"] = small_case()
-        result["storage_modes"] = storage_modes(args.steps, args.warmup)
+        result["storage_modes"] = modes = storage_modes(args.steps, args.warmup)
         fp64_ms = ms if (w.name == W.C2.name and args.storage == "fp64") else None
         if fp64_ms is not None:
             result["matmat"] = matmat_modes(max(3, args.steps // 4), 1, fp64_ms)
@@ -683,6 +736,10 @@ def main():
         result["orthogonalize"] = orthogonalize_section()
         result["compress"] = compress_section()
         result["transpose"] = transpose_section()
+        full = {(W.C3.name, m): (modes[m]["ms"], modes[m]["algorithmic_bytes"]) for m in ("fp64", "fp32", "bf16")}
+        if w.name == W.C2.name and args.storage == "fp64":
+            full[(w.name, "fp64")] = (ms, nbytes)
+        result["half_storage"] = half_section(args.steps, args.warmup, full)
     print(json.dumps(result), flush=True)
 
 

@@ -383,18 +383,23 @@ H2_BLOCKROW_KERNEL(leafexpand_kernel)
 // half of its live columns named by that bit and adds the other's copy of it,
 // so after five steps lane l holds column l % 32 summed over its 32-lane half;
 // the two halves are then added.
+template <int H, typename P>
+__device__ __forceinline__ void column_fold(P (&v)[32], int lane) {
+    const bool up = (lane & H) != 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const P keep = up ? v[k + H] : v[k];
+        const P send = up ? v[k] : v[k + H];
+        v[k] = keep + __shfl_xor(send, H);
+    }
+}
 template <typename P>
 __device__ __forceinline__ P column_sums32(P (&v)[32], int lane) {
-#pragma unroll
-    for (int h = 16; h >= 1; h >>= 1) {
-        const bool up = (lane & h) != 0;
-#pragma unroll
-        for (int k = 0; k < h; ++k) {
-            const P keep = up ? v[k + h] : v[k];
-            const P send = up ? v[k] : v[k + h];
-            v[k] = keep + __shfl_xor(send, h);
-        }
-    }
+    column_fold<16>(v, lane);
+    column_fold<8>(v, lane);
+    column_fold<4>(v, lane);
+    column_fold<2>(v, lane);
+    column_fold<1>(v, lane);
     return v[0] + __shfl_xor(v[0], 32);
 }
 
