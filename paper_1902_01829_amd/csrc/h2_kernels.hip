@@ -378,41 +378,43 @@ H2_BLOCKROW_KERNEL(leafexpand_kernel)
 #undef H2_BLOCKROW_KERNEL
 
 // ---------------------------------------------------------------- half storage
-// Column sums of a 32-column chunk held one row per lane (v[c] = row lane,
-// column c): each step pairs lanes across one lane bit, each partner keeps the
-// half of its live columns named by that bit and adds the other's copy of it,
-// so after five steps lane l holds column l % 32 summed over its 32-lane half;
-// the two halves are then added.
-template <int H, typename P>
-__device__ __forceinline__ void column_fold(P (&v)[32], int lane) {
-    const bool up = (lane & H) != 0;
+// Sums of 8 values per lane across the 8 lanes that differ in the lane bits
+// M1 > M2 > M3 (v[k] = lane's value number k): each fold pairs lanes across
+// one bit, each partner keeps the half of its live values named by that bit
+// and adds the other's copy of it; lane l ends with value number
+// (bit M1, bit M2, bit M3 of l) summed over its 8 lanes.
+template <int H, int MASK, typename P>
+__device__ __forceinline__ void fold_half(P (&v)[8], int lane) {
+    const bool up = (lane & MASK) != 0;
 #pragma unroll
     for (int k = 0; k < H; ++k) {
         const P keep = up ? v[k + H] : v[k];
         const P send = up ? v[k] : v[k + H];
-        v[k] = keep + __shfl_xor(send, H);
+        v[k] = keep + __shfl_xor(send, MASK);
     }
 }
-template <typename P>
-__device__ __forceinline__ P column_sums32(P (&v)[32], int lane) {
-    column_fold<16>(v, lane);
-    column_fold<8>(v, lane);
-    column_fold<4>(v, lane);
-    column_fold<2>(v, lane);
-    column_fold<1>(v, lane);
-    return v[0] + __shfl_xor(v[0], 32);
+template <int M1, int M2, int M3, typename P>
+__device__ __forceinline__ P fold8(P (&v)[8], int lane) {
+    fold_half<4, M1>(v, lane);
+    fold_half<2, M2>(v, lane);
+    fold_half<1, M3>(v, lane);
+    return v[0];
 }
 
 // Stream phase of a matrix stored by halves: block row i holds only its
 // blocks with j >= i (S_ji = S_ij^T, D_ji = D_ij^T).  One wavefront per block
-// row, lane r on row r; every stored block is read once, in 32-column chunks
-// kept in registers, and gives both of its products: S_ij x_j, summed over
-// the row as in the full product, and S_ij^T x_i, the contribution to
-// segment j, whose column sums are formed across the lanes (column_sums32)
-// and stored as FP64 in the block's partial slot (off-diagonal blocks only).
-// A second launch adds each segment's slots to its row sum.  The row's own
-// input segment has the offset of its output segment (x^ and y^ share the
-// node layout, x and y_near the point layout).
+// row; lane l = 8 g + a holds, of every block, the 8 x 8 tile of rows
+// a + 8 k and columns 8 g + c (k, c < 8), so each stored block is read once
+// (all of a lane's 16-byte items issued together, eight 128-byte runs per
+// load) and gives both of its products from registers: the lane's partial
+// sums of S_ij x_j for its rows, accumulated over the row's blocks (FP64
+// across blocks), and of S_ij^T x_i for its columns, summed over the 8 lanes
+// of its column group (three folds), after which lane l holds column l of the
+// transposed product: off-diagonal blocks store it as FP64 in their partial
+// slot.  At the end of the row the row sums are folded over the other three
+// lane bits (lane l: row l).  A second launch adds each segment's slots to
+// its row sum.  The row's own input segment has the offset of its output
+// segment (x^ and y^ share the node layout, x and y_near the point layout).
 template <int KIND, typename TV>
 __global__ __launch_bounds__(256) void stream_half_kernel(
     const RowDesc *__restrict__ rows, int64_t nrows, const BlkDesc *__restrict__ blks,
@@ -423,17 +425,23 @@ __global__ __launch_bounds__(256) void stream_half_kernel(
     using P = typename E::P;
     using V = typename E::V;
     constexpr int W = E::W;
-    constexpr int IPC = 32 / W;   // 16-byte items per row of a 32-column chunk
+    constexpr int IPR = 8 / W;   // 16-byte items per row of a lane's 8-column strip
     __shared__ __attribute__((aligned(16))) P xs[4][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int a = lane & 7, g = lane >> 3;
     const int64_t row = int64_t(blockIdx.x) * 4 + wv;
     if (row >= nrows) return;
     const RowDesc rd = rows[row];
     const int R = rd.R;
-    const bool in_x = (rd.sel & ROW_IN_X) != 0, on = lane < R;
-    P xi = P(0);
-    if (on) xi = in_x ? P(in1[rd.out + lane]) : P(in0[rd.out + lane]);
-    double acc = 0.0;
+    const bool in_x = (rd.sel & ROW_IN_X) != 0;
+    P xi[8];   // the row's own input at the lane's rows
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int r = a + 8 * k;
+        xi[k] = P(0);
+        if (r < R) xi[k] = in_x ? P(in1[rd.out + r]) : P(in0[rd.out + r]);
+    }
+    double rp[8] = {};   // partial sums of the lane's rows, over the row's blocks
     for (int b = rd.b0; b < rd.b1; ++b) {
         const BlkDesc bd = blks[b];
         const int C = bd.C, CW = (C + W - 1) / W;
@@ -444,34 +452,45 @@ __global__ __launch_bounds__(256) void stream_half_kernel(
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        P xj[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) xj[c] = xs[wv][8 * g + c];
+        const V *p = reinterpret_cast<const V *>(data + bd.a);   // item (cw, r) at cw * R + r
+        V raw[8][IPR];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int i = 0; i < IPR; ++i) {
+                const int r = a + 8 * k, cw = g * IPR + i;
+                raw[k][i] = V{};
+                if (r < R && cw < CW) raw[k][i] = __builtin_nontemporal_load(p + cw * R + r);
+            }
         double scale = 1.0;
         if constexpr (KIND == ELEM_BF16) scale = double(scales[bd.sidx]);
-        const V *p = reinterpret_cast<const V *>(data + bd.a) + lane;   // item (cw, r) at cw * R + r
-        P part = P(0);
-        for (int h = 0; h * 32 < C; ++h) {
-            P v[32];
+        P cp[8] = {};
 #pragma unroll
-            for (int i = 0; i < IPC; ++i) {
-                const int cw = h * IPC + i;
-                V raw = {};
-                if (on && cw < CW) raw = __builtin_nontemporal_load(p + cw * R);
-                E::unpack(raw, v + i * W);
+        for (int k = 0; k < 8; ++k) {
+            P v[8];
+#pragma unroll
+            for (int i = 0; i < IPR; ++i) E::unpack(raw[k][i], v + i * W);
+            P s = P(0);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                s = fma(v[c], xj[c], s);
+                cp[c] = fma(v[c], xi[k], cp[c]);
             }
-#pragma unroll
-            for (int c = 0; c < 32; ++c) part = fma(v[c], xs[wv][h * 32 + c], part);
-            if (sl >= 0) {
-#pragma unroll
-                for (int c = 0; c < 32; ++c) v[c] *= xi;
-                const P t = column_sums32(v, lane);
-                if ((lane >> 5) == h && lane < C) partials[int64_t(sl) * 64 + lane] = double(t) * scale;
-            }
+            rp[k] += double(s) * scale;
         }
-        acc += double(part) * scale;
+        if (sl >= 0) {
+            const P t = fold8<4, 2, 1>(cp, lane);   // column 8 g + a = lane
+            if (lane < C) partials[int64_t(sl) * 64 + lane] = double(t) * scale;
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (on) ((rd.sel & ROW_OUT_P) ? out1 : out0)[rd.out + lane] = TV(acc);
+    const double t = fold8<32, 16, 8>(rp, lane);   // row a + 8 g = lane
+    if (lane < R) ((rd.sel & ROW_OUT_P) ? out1 : out0)[rd.out + lane] = TV(t);
 }
 
 constexpr int kRowsPerBlock = 4;
