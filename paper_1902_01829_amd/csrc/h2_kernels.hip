@@ -254,14 +254,22 @@ template <typename TV, bool ADD>
 __global__ __launch_bounds__(256) void reduce_chunks_kernel(const ReduceDesc *__restrict__ desc, int64_t n,
                                                             const double *__restrict__ partials, TV *__restrict__ out0,
                                                             TV *__restrict__ out1) {
-    const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int64_t i = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = threadIdx.x & 63;
     if (i >= n) return;
     const ReduceDesc d = desc[i];
     if (r >= d.R) return;
     TV *dst = (d.point ? out1 : out0) + d.out + r;
     double acc = ADD ? double(*dst) : 0.0;
-    for (int c = d.c0; c < d.c1; ++c) acc += partials[int64_t(c) * 64 + r];
+    int c = d.c0;
+    for (; c + 8 <= d.c1; c += 8) {   // eight loads in flight, added in order
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = partials[int64_t(c + u) * 64 + r];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; c < d.c1; ++c) acc += partials[int64_t(c) * 64 + r];
     *dst = TV(acc);
 }
 
