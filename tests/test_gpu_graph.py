@@ -14,7 +14,7 @@ def _build(w, storage):
     return h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=storage)
 
 
-@pytest.mark.parametrize("storage", [0, 1, 2], ids=["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("storage", [0, 1, 2, 16, 18], ids=["fp64", "fp32", "bf16", "fp64-half", "bf16-half"])
 def test_matvec_graph_replays(storage):
     w = W.C1
     A = _build(w, storage)
