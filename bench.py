@@ -422,7 +422,10 @@ def half_partial_bytes(info, w):
     return 2 * 8 * (coupling_slots * info.rank + dense_slots * w.leaf)
 
 
-def half_section(steps, warmup, full_ms=None, nleaves=16):
+HALF_CASES = ((W.C2, "fp64"), (W.C3, "fp64"), (W.C3, "fp32"), (W.C3, "bf16"))
+
+
+def half_section(steps, warmup, full_ms=None, nleaves=16, cases=HALF_CASES):
     """Blocks stored by halves (symmetric matrices): the 2-D 2^20-point FP64
     matrix and the 3-D 2^19-point matrix in its three storage modes.  Time per
     product, stored bytes, the streaming phase (stored blocks read once for
@@ -430,10 +433,11 @@ def half_section(steps, warmup, full_ms=None, nleaves=16):
     bytes it moves, the equivalent bandwidth (full-storage algorithmic bytes
     over the product time), the speedup over full storage, and the error
     against the FP64 oracle on sampled leaves.  full_ms: full-storage times
-    by (workload, storage) already measured; the others are measured here."""
+    by (workload, storage) already measured; the others are measured here.
+    cases: the (workload, storage) pairs to run."""
     full_ms = dict(full_ms or {})
     out = {}
-    for w, name in ((W.C2, "fp64"), (W.C3, "fp64"), (W.C3, "fp32"), (W.C3, "bf16")):
+    for w, name in cases:
         r = run_matvec(w, STORAGE[name] | HALF, steps, warmup)
         info = r["info"]
         key = (w.name, name)
@@ -649,6 +653,8 @@ def main():
                     default=None,
                     help="run one section alone and print its JSON (for profiling runs); "
                          "the headline line is not printed")
+    ap.add_argument("--half-case", action="append", default=None, metavar="WORKLOAD/STORAGE",
+                    help="with --only half: run only these cases (e.g. 2d-n1048576-m64-k64/fp64)")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first run one device-to-device copy of this many GiB (a known-size "
                          "reference for hardware byte counters)")
@@ -684,7 +690,10 @@ def main():
         elif args.only == "transpose":
             out = transpose_section()
         elif args.only == "half":
-            out = half_section(args.steps, args.warmup)
+            cases = HALF_CASES
+            if args.half_case:
+                cases = tuple((W.WORKLOADS[c.split("/")[0]], c.split("/")[1]) for c in args.half_case)
+            out = half_section(args.steps, args.warmup, cases=cases)
         else:
             out = batch_modes(args.steps, args.warmup)
         print(json.dumps({"section": args.only, **out}), flush=True)
