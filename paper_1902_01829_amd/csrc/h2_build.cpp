@@ -119,14 +119,12 @@ struct Stager {
     }
 };
 
-// Layout of the representation, generation on the device (from points) or
-// conversion of caller arrays (src), and the work lists of one product in
-// launch order.  Ranks may differ per level (k_l); vectors and tiles use the
-// largest rank as their node stride.
 // The device representation's layout for the structure's level ranks: sets
 // the offsets and byte counts of A, allocates its regions (basis, blocks,
 // scales) and returns the fill list (coupling blocks level by level in BSR
-// order, then dense blocks); ncoupling receives the number of coupling blocks.
+// order, then dense blocks; stored by halves, only the blocks with column >=
+// row, A.blk_store mapping every block of the lists to its stored block);
+// ncoupling receives the number of stored coupling blocks.
 std::vector<h2::FillDesc> make_layout(h2_matrix_ &A, int64_t &ncoupling) {
     const Structure &s = A.st;
     const int q = s.q;
@@ -240,8 +238,10 @@ std::vector<h2::FillDesc> make_layout(h2_matrix_ &A, int64_t &ncoupling) {
     return fill;
 }
 
-void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t ncoupling, hipStream_t stream);
-
+// Layout of the representation, generation on the device (from points) or
+// conversion of caller arrays (src), and the work lists of one product in
+// launch order.  Ranks may differ per level (k_l); vectors and tiles use the
+// largest rank as their node stride.
 void build_device(h2_matrix_ &A, const h2_arrays *src, hipStream_t stream) {
     const Structure &s = A.st;
     const int k = s.rank, q = s.q;   // k: largest level rank
