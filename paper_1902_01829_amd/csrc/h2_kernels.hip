@@ -386,13 +386,13 @@ H2_BLOCKROW_KERNEL(leafexpand_kernel)
 #undef H2_BLOCKROW_KERNEL
 
 // ---------------------------------------------------------------- half storage
-// Sums of 8 values per lane across the 8 lanes that differ in the lane bits
-// M1 > M2 > M3 (v[k] = lane's value number k): each fold pairs lanes across
-// one bit, each partner keeps the half of its live values named by that bit
-// and adds the other's copy of it; lane l ends with value number
-// (bit M1, bit M2, bit M3 of l) summed over its 8 lanes.
-template <int H, int MASK, typename P>
-__device__ __forceinline__ void fold_half(P (&v)[8], int lane) {
+// Sums of N values per lane across the N lanes that differ in the lane bits
+// MASK, MASK / 2, ..., MASK / (N / 2) (v[k] = the lane's value number k): each
+// fold pairs lanes across one bit, each partner keeps the half of its live
+// values named by that bit and adds the other's copy of it; lane l ends with
+// value number (those bits of l, highest first) summed over its N lanes.
+template <int H, int MASK, int N, typename P>
+__device__ __forceinline__ void fold_half(P (&v)[N], int lane) {
     const bool up = (lane & MASK) != 0;
 #pragma unroll
     for (int k = 0; k < H; ++k) {
@@ -401,29 +401,32 @@ __device__ __forceinline__ void fold_half(P (&v)[8], int lane) {
         v[k] = keep + __shfl_xor(send, MASK);
     }
 }
-template <int M1, int M2, int M3, typename P>
-__device__ __forceinline__ P fold8(P (&v)[8], int lane) {
-    fold_half<4, M1>(v, lane);
-    fold_half<2, M2>(v, lane);
-    fold_half<1, M3>(v, lane);
-    return v[0];
+template <int N, int MASK, int LIVE = N, typename P>
+__device__ __forceinline__ P fold_lanes(P (&v)[N], int lane) {
+    if constexpr (LIVE == 1) {
+        return v[0];
+    } else {
+        fold_half<LIVE / 2, MASK>(v, lane);
+        return fold_lanes<N, MASK / 2, LIVE / 2>(v, lane);
+    }
 }
 
 // Stream phase of a matrix stored by halves: block row i holds only its
 // blocks with j >= i (S_ji = S_ij^T, D_ji = D_ij^T).  One wavefront per block
-// row; lane l = 8 g + a holds, of every block, the 8 x 8 tile of rows
-// a + 8 k and columns 8 g + c (k, c < 8), so each stored block is read once
-// (all of a lane's 16-byte items issued together, eight 128-byte runs per
-// load) and gives both of its products from registers: the lane's partial
-// sums of S_ij x_j for its rows, accumulated over the row's blocks (FP64
-// across blocks), and of S_ij^T x_i for its columns, summed over the 8 lanes
-// of its column group (three folds), after which lane l holds column l of the
-// transposed product: off-diagonal blocks store it as FP64 in their partial
-// slot.  At the end of the row the row sums are folded over the other three
-// lane bits (lane l: row l).  A second launch adds each segment's slots to
-// its row sum.  The row's own input segment has the offset of its output
-// segment (x^ and y^ share the node layout, x and y_near the point layout).
-template <int KIND, typename TV>
+// row; with TR lanes per column strip, lane l = TR g + a holds, of every
+// block, the tile of rows a + TR k (k < 64 / TR) and columns TR g + c
+// (c < TR), so each stored block is read once (all of a lane's 16-byte items
+// issued together; each load reads 64 / TR runs of TR consecutive rows) and
+// gives both of its products from registers: the lane's partial sums of
+// S_ij x_j for its rows, accumulated over the row's blocks (FP64 across
+// blocks), and of S_ij^T x_i for its columns, summed over the TR lanes of its
+// strip (log2 TR folds), after which lane l holds column l of the transposed
+// product: off-diagonal blocks store it as FP64 in their partial slot.  At the
+// end of the row the row sums are folded over the strip bits (lane l: row l).
+// A second launch adds each segment's slots to its row sum.  The row's own
+// input segment has the offset of its output segment (x^ and y^ share the node
+// layout, x and y_near the point layout).
+template <int KIND, typename TV, int TR>
 __global__ __launch_bounds__(256) void stream_half_kernel(
     const RowDesc *__restrict__ rows, int64_t nrows, const BlkDesc *__restrict__ blks,
     const int32_t *__restrict__ slot, const typename Elem<KIND>::T *__restrict__ data,
@@ -433,23 +436,25 @@ __global__ __launch_bounds__(256) void stream_half_kernel(
     using P = typename E::P;
     using V = typename E::V;
     constexpr int W = E::W;
-    constexpr int IPR = 8 / W;   // 16-byte items per row of a lane's 8-column strip
+    constexpr int NS = 64 / TR;    // strips, and rows per lane
+    constexpr int IPR = TR / W;    // 16-byte items per row of a strip
+    static_assert(IPR >= 1 && TR * NS == 64, "strip of whole 16-byte items");
     __shared__ __attribute__((aligned(16))) P xs[4][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int a = lane & 7, g = lane >> 3;
+    const int a = lane % TR, g = lane / TR;
     const int64_t row = int64_t(blockIdx.x) * 4 + wv;
     if (row >= nrows) return;
     const RowDesc rd = rows[row];
     const int R = rd.R;
     const bool in_x = (rd.sel & ROW_IN_X) != 0;
-    P xi[8];   // the row's own input at the lane's rows
+    P xi[NS];   // the row's own input at the lane's rows
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int r = a + 8 * k;
+    for (int k = 0; k < NS; ++k) {
+        const int r = a + TR * k;
         xi[k] = P(0);
         if (r < R) xi[k] = in_x ? P(in1[rd.out + r]) : P(in0[rd.out + r]);
     }
-    double rp[8] = {};   // partial sums of the lane's rows, over the row's blocks
+    double rp[NS] = {};   // partial sums of the lane's rows, over the row's blocks
     for (int b = rd.b0; b < rd.b1; ++b) {
         const BlkDesc bd = blks[b];
         const int C = bd.C, CW = (C + W - 1) / W;
@@ -460,44 +465,44 @@ __global__ __launch_bounds__(256) void stream_half_kernel(
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        P xj[8];
+        P xj[TR];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) xj[c] = xs[wv][8 * g + c];
+        for (int c = 0; c < TR; ++c) xj[c] = xs[wv][TR * g + c];
         const V *p = reinterpret_cast<const V *>(data + bd.a);   // item (cw, r) at cw * R + r
-        V raw[8][IPR];
+        V raw[NS][IPR];
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
+        for (int k = 0; k < NS; ++k)
 #pragma unroll
             for (int i = 0; i < IPR; ++i) {
-                const int r = a + 8 * k, cw = g * IPR + i;
+                const int r = a + TR * k, cw = g * IPR + i;
                 raw[k][i] = V{};
                 if (r < R && cw < CW) raw[k][i] = __builtin_nontemporal_load(p + cw * R + r);
             }
         double scale = 1.0;
         if constexpr (KIND == ELEM_BF16) scale = double(scales[bd.sidx]);
-        P cp[8] = {};
+        P cp[TR] = {};
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            P v[8];
+        for (int k = 0; k < NS; ++k) {
+            P v[TR];
 #pragma unroll
             for (int i = 0; i < IPR; ++i) E::unpack(raw[k][i], v + i * W);
             P s = P(0);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
+            for (int c = 0; c < TR; ++c) {
                 s = fma(v[c], xj[c], s);
                 cp[c] = fma(v[c], xi[k], cp[c]);
             }
             rp[k] += double(s) * scale;
         }
         if (sl >= 0) {
-            const P t = fold8<4, 2, 1>(cp, lane);   // column 8 g + a = lane
+            const P t = fold_lanes<TR, TR / 2>(cp, lane);   // column TR g + a = lane
             if (lane < C) partials[int64_t(sl) * 64 + lane] = double(t) * scale;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    const double t = fold8<32, 16, 8>(rp, lane);   // row a + 8 g = lane
+    const double t = fold_lanes<NS, 32>(rp, lane);   // row a + TR g = lane
     if (lane < R) ((rd.sel & ROW_OUT_P) ? out1 : out0)[rd.out + lane] = TV(t);
 }
 
@@ -602,22 +607,29 @@ hipError_t launch_reduce_chunks(const ReduceDesc *desc, int64_t n, const double 
     return hipGetLastError();
 }
 
+// Lanes per column strip of the half-storage kernel, per element kind (16 and
+// 32 measured no faster: 8 x 8 tiles in every storage mode).
+constexpr int kHalfStripF64 = 8, kHalfStripF32 = 8, kHalfStripBF16 = 8;
+
 hipError_t launch_stream_half(const RowLaunch &L, const int32_t *slot, double *partials, int kind, bool vec_f64,
                               hipStream_t st) {
     if (L.nrows <= 0) return hipSuccess;
     const dim3 grid(unsigned((L.nrows + kRowsPerBlock - 1) / kRowsPerBlock)), block(256);
     if (vec_f64) {
-        hipLaunchKernelGGL((stream_half_kernel<ELEM_F64, double>), grid, block, 0, st, L.rows, L.nrows, L.blks, slot,
-                           static_cast<const double *>(L.data), L.scales, static_cast<const double *>(L.in0), L.in1,
-                           static_cast<double *>(L.out0), static_cast<double *>(L.out1), partials);
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_F64, double, kHalfStripF64>), grid, block, 0, st, L.rows, L.nrows,
+                           L.blks, slot, static_cast<const double *>(L.data), L.scales,
+                           static_cast<const double *>(L.in0), L.in1, static_cast<double *>(L.out0),
+                           static_cast<double *>(L.out1), partials);
     } else if (kind == ELEM_F32) {
-        hipLaunchKernelGGL((stream_half_kernel<ELEM_F32, float>), grid, block, 0, st, L.rows, L.nrows, L.blks, slot,
-                           static_cast<const float *>(L.data), L.scales, static_cast<const float *>(L.in0), L.in1,
-                           static_cast<float *>(L.out0), static_cast<float *>(L.out1), partials);
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_F32, float, kHalfStripF32>), grid, block, 0, st, L.rows, L.nrows,
+                           L.blks, slot, static_cast<const float *>(L.data), L.scales,
+                           static_cast<const float *>(L.in0), L.in1, static_cast<float *>(L.out0),
+                           static_cast<float *>(L.out1), partials);
     } else {
-        hipLaunchKernelGGL((stream_half_kernel<ELEM_BF16, float>), grid, block, 0, st, L.rows, L.nrows, L.blks, slot,
-                           static_cast<const uint16_t *>(L.data), L.scales, static_cast<const float *>(L.in0), L.in1,
-                           static_cast<float *>(L.out0), static_cast<float *>(L.out1), partials);
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_BF16, float, kHalfStripBF16>), grid, block, 0, st, L.rows,
+                           L.nrows, L.blks, slot, static_cast<const uint16_t *>(L.data), L.scales,
+                           static_cast<const float *>(L.in0), L.in1, static_cast<float *>(L.out0),
+                           static_cast<float *>(L.out1), partials);
     }
     return hipGetLastError();
 }
