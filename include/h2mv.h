@@ -71,8 +71,9 @@ typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16_SCALED = 2 } h2_storage;
  * blocks with column >= row are held (diagonal dense blocks in full), which
  * about halves the bytes a product streams; the product reads each stored
  * block once for both S_ij x_j and S_ij^T x_i, and adds the transposed
- * contributions of every segment (FP64 partial sums, 512 bytes per stored
- * off-diagonal block) in a second launch.  Products match the full storage up
+ * contributions of every segment (partial sums per stored off-diagonal block:
+ * 64 FP64 values, or FP32 in the reduced modes, summed in FP64) in a second
+ * launch.  Products match the full storage up
  * to rounding order.  h2_get_info reports the modifier in storage and the
  * stored bytes in bytes_coupling and bytes_dense.  Handles stored by halves
  * are rejected with UNSUPPORTED by h2_orthogonalize, h2_compress,

@@ -107,7 +107,7 @@ struct WorkList {
     // writing FP64 partial sums, added up by a second launch
     const h2::ReduceDesc *red = nullptr;
     int64_t nred = 0;
-    double *partials = nullptr;
+    void *partials = nullptr;   // FP64 (FP32 for the half-storage list of a reduced-storage matrix)
     // stream list of a matrix stored by halves: partial slot of every block
     // (-1: diagonal block); red then adds the slots to the row sums
     const int32_t *slot = nullptr;

@@ -247,12 +247,12 @@ __global__ __launch_bounds__(256) void fill_blocks_bf16_kernel(Geometry g, uint1
 }
 
 // ---------------------------------------------------------------- chunk sums
-// One wavefront per segment: lane r adds partials[c * 64 + r] over the
-// segment's chunks in order (FP64) and stores the segment's element r; with
-// ADD the sum starts from the element's current value.
-template <typename TV, bool ADD>
+// One wavefront per segment: lane r adds partials[c * 64 + r] (FP64 or FP32)
+// over the segment's chunks in order, in FP64, and stores the segment's
+// element r; with ADD the sum starts from the element's current value.
+template <typename TV, typename TP, bool ADD>
 __global__ __launch_bounds__(256) void reduce_chunks_kernel(const ReduceDesc *__restrict__ desc, int64_t n,
-                                                            const double *__restrict__ partials, TV *__restrict__ out0,
+                                                            const TP *__restrict__ partials, TV *__restrict__ out0,
                                                             TV *__restrict__ out1) {
     const int64_t i = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = threadIdx.x & 63;
@@ -265,11 +265,11 @@ __global__ __launch_bounds__(256) void reduce_chunks_kernel(const ReduceDesc *__
     for (; c + 8 <= d.c1; c += 8) {   // eight loads in flight, added in order
         double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = partials[int64_t(c + u) * 64 + r];
+        for (int u = 0; u < 8; ++u) v[u] = double(partials[int64_t(c + u) * 64 + r]);
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc += v[u];
     }
-    for (; c < d.c1; ++c) acc += partials[int64_t(c) * 64 + r];
+    for (; c < d.c1; ++c) acc += double(partials[int64_t(c) * 64 + r]);
     *dst = TV(acc);
 }
 
@@ -421,8 +421,10 @@ __device__ __forceinline__ P fold_lanes(P (&v)[N], int lane) {
 // S_ij x_j for its rows, accumulated over the row's blocks (FP64 across
 // blocks), and of S_ij^T x_i for its columns, summed over the TR lanes of its
 // strip (log2 TR folds), after which lane l holds column l of the transposed
-// product: off-diagonal blocks store it as FP64 in their partial slot.  At the
-// end of the row the row sums are folded over the strip bits (lane l: row l).
+// product: off-diagonal blocks store it in their partial slot, in the vector
+// type (FP64, or FP32 in the reduced modes: half the partial writes, whose
+// cost on the read stream exceeds their share of the bytes).  At the end of
+// the row the row sums are folded over the strip bits (lane l: row l).
 // A second launch adds each segment's slots to its row sum.  The row's own
 // input segment has the offset of its output segment (x^ and y^ share the node
 // layout, x and y_near the point layout).
@@ -431,7 +433,7 @@ __global__ __launch_bounds__(256) void stream_half_kernel(
     const RowDesc *__restrict__ rows, int64_t nrows, const BlkDesc *__restrict__ blks,
     const int32_t *__restrict__ slot, const typename Elem<KIND>::T *__restrict__ data,
     const float *__restrict__ scales, const TV *__restrict__ in0, const double *__restrict__ in1,
-    TV *__restrict__ out0, TV *__restrict__ out1, double *__restrict__ partials) {
+    TV *__restrict__ out0, TV *__restrict__ out1, TV *__restrict__ partials) {
     using E = Elem<KIND>;
     using P = typename E::P;
     using V = typename E::V;
@@ -496,7 +498,7 @@ __global__ __launch_bounds__(256) void stream_half_kernel(
         }
         if (sl >= 0) {
             const P t = fold_lanes<TR, TR / 2>(cp, lane);   // column TR g + a = lane
-            if (lane < C) partials[int64_t(sl) * 64 + lane] = double(t) * scale;
+            if (lane < C) partials[int64_t(sl) * 64 + lane] = TV(double(t) * scale);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -587,22 +589,26 @@ hipError_t launch_fill_blocks(const Geometry &g, int block_kind, void *blocks, f
     return hipSuccess;
 }
 
-hipError_t launch_reduce_chunks(const ReduceDesc *desc, int64_t n, const double *partials, void *out0, void *out1,
-                                bool vec_f64, hipStream_t st, bool add) {
+hipError_t launch_reduce_chunks(const ReduceDesc *desc, int64_t n, const void *partials, bool partials_f32, void *out0,
+                                void *out1, bool vec_f64, hipStream_t st, bool add) {
     if (n <= 0) return hipSuccess;
     const dim3 grid(unsigned((n + 3) / 4)), block(256);
+    auto go = [&](auto tv, auto tp) {   // vector and partial types
+        using TV = decltype(tv);
+        using TP = decltype(tp);
+        auto *o0 = static_cast<TV *>(out0), *o1 = static_cast<TV *>(out1);
+        const TP *pp = static_cast<const TP *>(partials);
+        if (add)
+            hipLaunchKernelGGL((reduce_chunks_kernel<TV, TP, true>), grid, block, 0, st, desc, n, pp, o0, o1);
+        else
+            hipLaunchKernelGGL((reduce_chunks_kernel<TV, TP, false>), grid, block, 0, st, desc, n, pp, o0, o1);
+    };
     if (vec_f64) {
-        auto *o0 = static_cast<double *>(out0), *o1 = static_cast<double *>(out1);
-        if (add)
-            hipLaunchKernelGGL((reduce_chunks_kernel<double, true>), grid, block, 0, st, desc, n, partials, o0, o1);
-        else
-            hipLaunchKernelGGL((reduce_chunks_kernel<double, false>), grid, block, 0, st, desc, n, partials, o0, o1);
+        if (partials_f32) go(double(), float());
+        else go(double(), double());
     } else {
-        auto *o0 = static_cast<float *>(out0), *o1 = static_cast<float *>(out1);
-        if (add)
-            hipLaunchKernelGGL((reduce_chunks_kernel<float, true>), grid, block, 0, st, desc, n, partials, o0, o1);
-        else
-            hipLaunchKernelGGL((reduce_chunks_kernel<float, false>), grid, block, 0, st, desc, n, partials, o0, o1);
+        if (partials_f32) go(float(), float());
+        else go(float(), double());
     }
     return hipGetLastError();
 }
@@ -611,7 +617,7 @@ hipError_t launch_reduce_chunks(const ReduceDesc *desc, int64_t n, const double 
 // 32 measured no faster: 8 x 8 tiles in every storage mode).
 constexpr int kHalfStripF64 = 8, kHalfStripF32 = 8, kHalfStripBF16 = 8;
 
-hipError_t launch_stream_half(const RowLaunch &L, const int32_t *slot, double *partials, int kind, bool vec_f64,
+hipError_t launch_stream_half(const RowLaunch &L, const int32_t *slot, void *partials, int kind, bool vec_f64,
                               hipStream_t st) {
     if (L.nrows <= 0) return hipSuccess;
     const dim3 grid(unsigned((L.nrows + kRowsPerBlock - 1) / kRowsPerBlock)), block(256);
@@ -619,17 +625,17 @@ hipError_t launch_stream_half(const RowLaunch &L, const int32_t *slot, double *p
         hipLaunchKernelGGL((stream_half_kernel<ELEM_F64, double, kHalfStripF64>), grid, block, 0, st, L.rows, L.nrows,
                            L.blks, slot, static_cast<const double *>(L.data), L.scales,
                            static_cast<const double *>(L.in0), L.in1, static_cast<double *>(L.out0),
-                           static_cast<double *>(L.out1), partials);
+                           static_cast<double *>(L.out1), static_cast<double *>(partials));
     } else if (kind == ELEM_F32) {
         hipLaunchKernelGGL((stream_half_kernel<ELEM_F32, float, kHalfStripF32>), grid, block, 0, st, L.rows, L.nrows,
                            L.blks, slot, static_cast<const float *>(L.data), L.scales,
                            static_cast<const float *>(L.in0), L.in1, static_cast<float *>(L.out0),
-                           static_cast<float *>(L.out1), partials);
+                           static_cast<float *>(L.out1), static_cast<float *>(partials));
     } else {
         hipLaunchKernelGGL((stream_half_kernel<ELEM_BF16, float, kHalfStripBF16>), grid, block, 0, st, L.rows,
                            L.nrows, L.blks, slot, static_cast<const uint16_t *>(L.data), L.scales,
                            static_cast<const float *>(L.in0), L.in1, static_cast<float *>(L.out0),
-                           static_cast<float *>(L.out1), partials);
+                           static_cast<float *>(L.out1), static_cast<float *>(partials));
     }
     return hipGetLastError();
 }

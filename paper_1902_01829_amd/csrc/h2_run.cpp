@@ -75,14 +75,15 @@ void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st) {
                 if (w.slot) {   // stored by halves: row sums and transposed partials, then their sums
                     check_hip(h2::launch_stream_half(L, w.slot, w.partials, w.kind, A.vec_f64, st),
                               "half-storage stream launch");
-                    check_hip(h2::launch_reduce_chunks(w.red, w.nred, w.partials, A.yh, A.ynear, A.vec_f64, st, true),
+                    check_hip(h2::launch_reduce_chunks(w.red, w.nred, w.partials, !A.vec_f64, A.yh, A.ynear, A.vec_f64,
+                                                       st, true),
                               "partial sum launch");
                     return;
                 }
                 if (w.red) {   // chunks of a split list: partial sums, then their sums per row
                     L.out0 = L.out1 = w.partials;
                     check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, int(w.phase), st, 1), "blockrow launch");
-                    check_hip(h2::launch_reduce_chunks(w.red, w.nred, w.partials, A.yh, A.ynear, A.vec_f64, st),
+                    check_hip(h2::launch_reduce_chunks(w.red, w.nred, w.partials, false, A.yh, A.ynear, A.vec_f64, st),
                               "chunk sum launch");
                     return;
                 }
