@@ -660,7 +660,7 @@ def main():
                          "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the per-GPU kernel at its real shape is what one GPU shows).", file=sys.stderr)
         sys.exit(2)
 
