@@ -429,7 +429,7 @@ __device__ __forceinline__ P fold_lanes(P (&v)[N], int lane) {
 // A second launch adds each segment's slots to its row sum.  The row's own
 // input segment has the offset of its output segment (x^ and y^ share the node
 // layout, x and y_near the point layout).
-template <int KIND, typename TV, int TR, bool PIPE>
+template <int KIND, typename TV, int TR>
 __global__ __launch_bounds__(256) void stream_half_kernel(
     const RowDesc *__restrict__ rows, int64_t nrows, const BlkDesc *__restrict__ blks,
     const int32_t *__restrict__ slot, const typename Elem<KIND>::T *__restrict__ data,
@@ -443,151 +443,93 @@ __global__ __launch_bounds__(256) void stream_half_kernel(
     constexpr int IPR = TR / W;    // 16-byte items per row of a strip
     static_assert(IPR >= 1 && TR * NS == 64, "strip of whole 16-byte items");
     __shared__ __attribute__((aligned(16))) P xs[4][64];
-    // pipelined: the wave index made uniform (row and block descriptors through scalar loads)
-    const int wv = PIPE ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index made uniform: row and block descriptors come through scalar loads
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int a = lane % TR, g = lane / TR;
     const int64_t row = int64_t(blockIdx.x) * 4 + wv;
     if (row >= nrows) return;
     const RowDesc rd = rows[row];
     const int R = rd.R;
     double rp[NS] = {};   // partial sums of the lane's rows, over the row's blocks
-    if constexpr (PIPE) {
-        // Pipelined form: block b + 1's descriptor, slot and input are loaded
-        // while block b's items are in flight, the next block's input is staged
-        // before block b's partial store (so no wait covers that store), LDS-only
-        // fences, and the input vector chosen once per row (the row is uniform, so
-        // one of two instantiations runs).
-        auto blocks = [&](auto input_is_x) {
-            constexpr bool IN_X = decltype(input_is_x)::value;
-            // element e of the input segment at off, zero from element n on (the
-            // load is clamped into the segment, so the loads issue back to back)
-            auto input = [&](int64_t off, int e, int n) {
-                const int ec = e < n ? e : n - 1;
-                P v;
-                if constexpr (IN_X) v = P(in1[off + ec]);
-                else v = P(in0[off + ec]);
-                return e < n ? v : P(0);
-            };
-            P xi[NS];   // the row's own input at the lane's rows
-    #pragma unroll
-            for (int k = 0; k < NS; ++k) xi[k] = input(rd.out, a + TR * k, R);
-            if (rd.b0 >= rd.b1) return;
-            P xj[TR];   // the input at the lane's columns of the current block
-            auto stage = [&](const P xv) {
-                xs[wv][lane] = xv;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-    #pragma unroll
-                for (int c = 0; c < TR; ++c) xj[c] = xs[wv][TR * g + c];
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-            };
-            BlkDesc bd = blks[rd.b0];
-            int32_t sl = slot[rd.b0];
-            stage(input(bd.in, lane, bd.C));
-            for (int b = rd.b0; b < rd.b1; ++b) {
-                const int C = bd.C, CW = (C + W - 1) / W;
-                const V *p = reinterpret_cast<const V *>(data + bd.a);   // item (cw, r) at cw * R + r
-                V raw[NS][IPR];
-    #pragma unroll
-                for (int k = 0; k < NS; ++k)
-    #pragma unroll
-                    for (int i = 0; i < IPR; ++i) {
-                        const int r = a + TR * k, cw = g * IPR + i;
-                        raw[k][i] = V{};
-                        if (r < R && cw < CW) raw[k][i] = __builtin_nontemporal_load(p + cw * R + r);
-                    }
-                const bool more = b + 1 < rd.b1;
-                const BlkDesc nbd = blks[more ? b + 1 : b];
-                const int32_t nsl = slot[more ? b + 1 : b];
-                const P nxv = input(nbd.in, lane, nbd.C);   // unused after the last block
-                double scale = 1.0;
-                if constexpr (KIND == ELEM_BF16) scale = double(scales[bd.sidx]);
-                P cp[TR] = {};
-    #pragma unroll
-                for (int k = 0; k < NS; ++k) {
-                    P v[TR];
-    #pragma unroll
-                    for (int i = 0; i < IPR; ++i) E::unpack(raw[k][i], v + i * W);
-                    P s = P(0);
-    #pragma unroll
-                    for (int c = 0; c < TR; ++c) {
-                        s = fma(v[c], xj[c], s);
-                        cp[c] = fma(v[c], xi[k], cp[c]);
-                    }
-                    rp[k] += double(s) * scale;
-                }
-                P t = P(0);
-                if (sl >= 0) t = fold_lanes<TR, TR / 2>(cp, lane);   // column TR g + a = lane
-                if (more) stage(nxv);
-                if (sl >= 0 && lane < C) partials[int64_t(sl) * 64 + lane] = TV(double(t) * scale);
-                bd = nbd;
-                sl = nsl;
-            }
+    // The block loop is pipelined: block b + 1's descriptor, slot and input
+    // are loaded while block b's items are in flight, the next block's input
+    // is staged before block b's partial store (so no wait covers that
+    // store), the LDS fences order LDS only, and the input vector is chosen
+    // once per row (the row is uniform, so one of two instantiations runs).
+    auto blocks = [&](auto input_is_x) {
+        constexpr bool IN_X = decltype(input_is_x)::value;
+        // element e of the input segment at off, zero from element n on (the
+        // load is clamped into the segment, so the loads issue back to back)
+        auto input = [&](int64_t off, int e, int n) {
+            const int ec = e < n ? e : n - 1;
+            P v;
+            if constexpr (IN_X) v = P(in1[off + ec]);
+            else v = P(in0[off + ec]);
+            return e < n ? v : P(0);
         };
-        if (rd.sel & ROW_IN_X)
-            blocks(std::true_type{});
-        else
-            blocks(std::false_type{});
-    } else {
-        const bool in_x = (rd.sel & ROW_IN_X) != 0;
         P xi[NS];   // the row's own input at the lane's rows
-    #pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            const int r = a + TR * k;
-            xi[k] = P(0);
-            if (r < R) xi[k] = in_x ? P(in1[rd.out + r]) : P(in0[rd.out + r]);
-        }
-        for (int b = rd.b0; b < rd.b1; ++b) {
-            const BlkDesc bd = blks[b];
-            const int C = bd.C, CW = (C + W - 1) / W;
-            const int32_t sl = slot[b];
-            P xv = P(0);
-            if (lane < C) xv = in_x ? P(in1[bd.in + lane]) : P(in0[bd.in + lane]);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) xi[k] = input(rd.out, a + TR * k, R);
+        if (rd.b0 >= rd.b1) return;
+        P xj[TR];   // the input at the lane's columns of the current block
+        auto stage = [&](const P xv) {
             xs[wv][lane] = xv;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
             __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            P xj[TR];
-    #pragma unroll
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+#pragma unroll
             for (int c = 0; c < TR; ++c) xj[c] = xs[wv][TR * g + c];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        };
+        BlkDesc bd = blks[rd.b0];
+        int32_t sl = slot[rd.b0];
+        stage(input(bd.in, lane, bd.C));
+        for (int b = rd.b0; b < rd.b1; ++b) {
+            const int C = bd.C, CW = (C + W - 1) / W;
             const V *p = reinterpret_cast<const V *>(data + bd.a);   // item (cw, r) at cw * R + r
             V raw[NS][IPR];
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < NS; ++k)
-    #pragma unroll
+#pragma unroll
                 for (int i = 0; i < IPR; ++i) {
                     const int r = a + TR * k, cw = g * IPR + i;
                     raw[k][i] = V{};
                     if (r < R && cw < CW) raw[k][i] = __builtin_nontemporal_load(p + cw * R + r);
                 }
+            const bool more = b + 1 < rd.b1;
+            const BlkDesc nbd = blks[more ? b + 1 : b];
+            const int32_t nsl = slot[more ? b + 1 : b];
+            const P nxv = input(nbd.in, lane, nbd.C);   // unused after the last block
             double scale = 1.0;
             if constexpr (KIND == ELEM_BF16) scale = double(scales[bd.sidx]);
             P cp[TR] = {};
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < NS; ++k) {
                 P v[TR];
-    #pragma unroll
+#pragma unroll
                 for (int i = 0; i < IPR; ++i) E::unpack(raw[k][i], v + i * W);
                 P s = P(0);
-    #pragma unroll
+#pragma unroll
                 for (int c = 0; c < TR; ++c) {
                     s = fma(v[c], xj[c], s);
                     cp[c] = fma(v[c], xi[k], cp[c]);
                 }
                 rp[k] += double(s) * scale;
             }
-            if (sl >= 0) {
-                const P t = fold_lanes<TR, TR / 2>(cp, lane);   // column TR g + a = lane
-                if (lane < C) partials[int64_t(sl) * 64 + lane] = TV(double(t) * scale);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            P t = P(0);
+            if (sl >= 0) t = fold_lanes<TR, TR / 2>(cp, lane);   // column TR g + a = lane
+            if (more) stage(nxv);
+            if (sl >= 0 && lane < C) partials[int64_t(sl) * 64 + lane] = TV(double(t) * scale);
+            bd = nbd;
+            sl = nsl;
         }
-    }
+    };
+    if (rd.sel & ROW_IN_X)
+        blocks(std::true_type{});
+    else
+        blocks(std::false_type{});
     const double t = fold_lanes<NS, 32>(rp, lane);   // row a + TR g = lane
     if (lane < R) ((rd.sel & ROW_OUT_P) ? out1 : out0)[rd.out + lane] = TV(t);
 }
@@ -698,8 +640,7 @@ hipError_t launch_reduce_chunks(const ReduceDesc *desc, int64_t n, const void *p
 }
 
 // Lanes per column strip of the half-storage kernel, per element kind (16 and
-// 32 measured no faster: 8 x 8 tiles in every storage mode); the pipelined
-// block loop is faster in FP64 and BF16 and slower in FP32 (measured).
+// 32 measured no faster: 8 x 8 tiles in every storage mode).
 constexpr int kHalfStripF64 = 8, kHalfStripF32 = 8, kHalfStripBF16 = 8;
 
 hipError_t launch_stream_half(const RowLaunch &L, const int32_t *slot, void *partials, int kind, bool vec_f64,
@@ -707,17 +648,17 @@ hipError_t launch_stream_half(const RowLaunch &L, const int32_t *slot, void *par
     if (L.nrows <= 0) return hipSuccess;
     const dim3 grid(unsigned((L.nrows + kRowsPerBlock - 1) / kRowsPerBlock)), block(256);
     if (vec_f64) {
-        hipLaunchKernelGGL((stream_half_kernel<ELEM_F64, double, kHalfStripF64, true>), grid, block, 0, st, L.rows, L.nrows,
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_F64, double, kHalfStripF64>), grid, block, 0, st, L.rows, L.nrows,
                            L.blks, slot, static_cast<const double *>(L.data), L.scales,
                            static_cast<const double *>(L.in0), L.in1, static_cast<double *>(L.out0),
                            static_cast<double *>(L.out1), static_cast<double *>(partials));
     } else if (kind == ELEM_F32) {
-        hipLaunchKernelGGL((stream_half_kernel<ELEM_F32, float, kHalfStripF32, false>), grid, block, 0, st, L.rows, L.nrows,
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_F32, float, kHalfStripF32>), grid, block, 0, st, L.rows, L.nrows,
                            L.blks, slot, static_cast<const float *>(L.data), L.scales,
                            static_cast<const float *>(L.in0), L.in1, static_cast<float *>(L.out0),
                            static_cast<float *>(L.out1), static_cast<float *>(partials));
     } else {
-        hipLaunchKernelGGL((stream_half_kernel<ELEM_BF16, float, kHalfStripBF16, true>), grid, block, 0, st, L.rows,
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_BF16, float, kHalfStripBF16>), grid, block, 0, st, L.rows,
                            L.nrows, L.blks, slot, static_cast<const uint16_t *>(L.data), L.scales,
                            static_cast<const float *>(L.in0), L.in1, static_cast<float *>(L.out0),
                            static_cast<float *>(L.out1), static_cast<float *>(partials));
