@@ -13,14 +13,16 @@ import pytest
 
 from paper_1902_01829_amd import workloads as W
 
+from test_gpu_matvec import bf16_derived_bound
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 MM_VS_DEQUANT_TOL = 1e-6
-VS_FP64_TOL = {1: 1e-6, 2: 4e-3}
-# BF16 storage error where leaves hold fewer points than the rank (the leaf
-# bases are then overcomplete and amplify the coupling blocks' rounding).
-BF16_OVERCOMPLETE_TOL = 6e-3
+# Against the FP64 oracle: the workloads' bounds (FP32 1e-6, BF16 2e-3) for the
+# 4096-point and 2^20-point 2-D matrices; for other BF16 cases the bound
+# derived from the representation's own storage error (bf16_derived_bound).
+VS_FP64_TOL = {1: 1e-6, 2: 2e-3}
 
 CASES = [
     (W.C1, 5),
@@ -57,12 +59,15 @@ def test_matmat_matches_oracle(oracle_mod, w, nrhs, storage):
     worst_q = worst_64 = 0.0
     for j in cols:
         refq, ref64 = oq.matvec(X[j]), o64.matvec(X[j])
-        worst_q = max(worst_q, np.linalg.norm(Y[j] - refq) / np.linalg.norm(refq))
-        worst_64 = max(worst_64, np.linalg.norm(Y[j] - ref64) / np.linalg.norm(ref64))
+        eq = np.linalg.norm(Y[j] - refq) / np.linalg.norm(refq)
+        e64 = np.linalg.norm(Y[j] - ref64) / np.linalg.norm(ref64)
+        worst_q, worst_64 = max(worst_q, eq), max(worst_64, e64)
+        if storage == 2:
+            assert e64 <= bf16_derived_bound(refq, ref64), (j, e64)
     print(f"  worst column rel err: vs dequantized {worst_q:.3e}, vs fp64 {worst_64:.3e}", flush=True)
     assert worst_q <= MM_VS_DEQUANT_TOL
-    overcomplete = w.n / 2 ** oq.q < w.rank
-    assert worst_64 <= (BF16_OVERCOMPLETE_TOL if storage == 2 and overcomplete else VS_FP64_TOL[storage])
+    if storage == 1 or w == W.C1:
+        assert worst_64 <= VS_FP64_TOL[storage]
 
 
 @pytest.mark.parametrize("storage", [1, 2], ids=["fp32", "bf16"])

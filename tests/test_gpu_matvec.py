@@ -22,16 +22,23 @@ FP64_TOL = 1e-12
 # FP32 input and vector trees (u_32 = 6e-8 each), FP64 sums over blocks.
 REDUCED_VS_DEQUANT_TOL = 1e-6
 FP32_VS_FP64_TOL = 1e-6
-# BF16 keeps 8 significant bits: each stored entry carries a relative rounding
-# error up to 2^-9 (RMS ~1.1e-3 over a block's mantissas).  Dense blocks pass it
-# to y unchanged; coupling errors reach y through the interpolation bases,
-# whose Lebesgue constant (~1.7 per axis for 4 first-kind Chebyshev points,
-# ~2.2 for 8) amplifies them, and more where leaves hold fewer points than the
-# rank (overcomplete leaf bases).  Bounds: 4e-3, 6e-3 with overcomplete leaves;
-# the 2^19-point 3-D workload (64-point leaves, rank 64) must meet 2e-3.
-BF16_VS_FP64_TOL = 4e-3
-BF16_OVERCOMPLETE_TOL = 6e-3
-BF16_VS_FP64_TOL_3D_512K = 2e-3
+# BF16 storage against the FP64 oracle.  The workloads state their bound,
+# 2e-3 (the 4096-point 2-D matrix, the 2^19-point 3-D matrix, the 2^20-point
+# 2-D matrix with 32 right-hand sides).  For any other case the bound is
+# derived rather than chosen: the GPU result differs from the FP64 product by
+# the storage error of the representation itself, e_store = |y_q - y_64| /
+# |y_64| with y_q the oracle's exact product on the dequantized values (a
+# property of the BF16 matrix, computed by the oracle alone), plus the
+# arithmetic error, at most REDUCED_VS_DEQUANT_TOL relative to |y_q| (triangle
+# inequality).  Where leaves hold fewer points than the rank, e_store exceeds
+# 2e-3 (rounding reaches y through overcomplete leaf bases).
+BF16_VS_FP64_TOL = 2e-3
+
+
+def bf16_derived_bound(y_q, y_64):
+    """Storage error of the BF16 representation plus the arithmetic bound."""
+    n64 = np.linalg.norm(y_64)
+    return np.linalg.norm(y_q - y_64) / n64 + REDUCED_VS_DEQUANT_TOL * np.linalg.norm(y_q) / n64
 
 
 def _h2mv():
@@ -125,12 +132,30 @@ def _sampled_parity(oracle_mod, w, storage, nleaves, tol, quant_ref_tol=None):
     return rel
 
 
-def test_fp64_full_2d_1m(oracle_mod):
-    _sampled_parity(oracle_mod, W.C2, 0, 48, FP64_TOL)
+def _all_rows_fp64(oracle_mod, w):
+    """Full-size workload, FP64: every row against the matrix-free oracle,
+    elementwise and in the 2-norm."""
+    print(f"case {w.name} fp64 all rows", flush=True)
+    A = _build(w, 0)
+    perm = A.perm()
+    xt = W.rhs(w)[perm]
+    y = _gpu_matvec(A, xt)
+    A.close()
+    o = oracle_mod.OracleH2(W.points(w), w.leaf, w.cheb_p, w.eta, w.corr_len, keep_blocks=False)
+    assert np.array_equal(perm, o.perm())
+    ref = o.matvec(xt)
+    rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    print(f"  rel err vs fp64 oracle on all {w.n} rows: {rel:.3e}, "
+          f"max abs err / max |y|: {np.abs(y - ref).max() / np.abs(ref).max():.3e}", flush=True)
+    _check_fp64(y, ref)
 
 
-def test_fp64_full_3d_512k(oracle_mod):
-    _sampled_parity(oracle_mod, W.C3, 0, 24, FP64_TOL)
+def test_fp64_full_2d_1m_all_rows(oracle_mod):
+    _all_rows_fp64(oracle_mod, W.C2)
+
+
+def test_fp64_full_3d_512k_all_rows(oracle_mod):
+    _all_rows_fp64(oracle_mod, W.C3)
 
 
 @pytest.mark.parametrize("w", [W.C1, SMALL[2], SMALL[4], SMALL[5]], ids=lambda w: w.name)
@@ -150,14 +175,17 @@ def test_reduced_storage_small(oracle_mod, w, storage):
     rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
     print(f"  vs dequantized {relq:.3e}  vs fp64 {rel:.3e}", flush=True)
     assert relq <= REDUCED_VS_DEQUANT_TOL
-    overcomplete = w.n / 2 ** o64.q < w.rank
-    bf16_tol = BF16_OVERCOMPLETE_TOL if overcomplete else BF16_VS_FP64_TOL
-    assert rel <= (FP32_VS_FP64_TOL if storage == 1 else bf16_tol)
+    if storage == 1:
+        assert rel <= FP32_VS_FP64_TOL
+    else:
+        assert rel <= bf16_derived_bound(refq, ref)
+        if w == W.C1:
+            assert rel <= BF16_VS_FP64_TOL
 
 
 @pytest.mark.parametrize("storage", [1, 2], ids=["fp32", "bf16"])
 def test_reduced_storage_full_3d_512k(oracle_mod, storage):
-    _sampled_parity(oracle_mod, W.C3, storage, 16, FP32_VS_FP64_TOL if storage == 1 else BF16_VS_FP64_TOL_3D_512K,
+    _sampled_parity(oracle_mod, W.C3, storage, 16, FP32_VS_FP64_TOL if storage == 1 else BF16_VS_FP64_TOL,
                     quant_ref_tol=REDUCED_VS_DEQUANT_TOL)
 
 
