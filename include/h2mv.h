@@ -274,6 +274,24 @@ h2_status h2_compress(h2_handle A, double eps, int *level_rank, void *stream);
  * structure-only handle; DEVICE. */
 h2_status h2_matvec(h2_handle A, const double *x, double *y, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = A x as
+ * h2_matvec computes it (same kernels, same order, bitwise the same result),
+ * with the product's intermediate vectors -- x^ and y^ (nnodes x rank each),
+ * the near field (n) and, for small or half-stored matrices, the partial sums
+ * of the stream phase -- in a static device array of H2_NOALLOC_SCRATCH_BYTES
+ * per GPU instead of the handle's workspace.  The call allocates nothing,
+ * records no profiling events and never synchronizes.  The array belongs to
+ * the library, one copy on every GPU the process uses, held until the
+ * process ends; all calls on one GPU share it, so two calls that overlap on
+ * one GPU (on different streams or host threads) race.  The current device
+ * must be the one A was built on.  Errors: INVALID_ARG as h2_matvec;
+ * UNSUPPORTED when the product needs more scratch than the array holds (the
+ * message gives both sizes: FP64 matrices need 16 bytes per node and rank
+ * unit plus 8 per point, e.g. 42 MB for 2^20 points of rank 64); DEVICE. */
+#define H2_NOALLOC_SCRATCH_BYTES (64ll << 20)
+h2_status h2_matvec_noalloc(h2_handle A, const double *x, double *y, void *stream);
+
 /* Y = A X for nrhs right-hand sides at once: the same phases with every
  * per-node vector replaced by a k x nrhs tile, so each block product becomes a
  * dense contraction.

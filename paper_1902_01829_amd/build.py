@@ -21,7 +21,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["h2_structure.cpp", "h2_build.cpp", "h2_run.cpp", "h2_batch.cpp", "h2_transform.cpp", "h2_api.cpp"]
-HIP_SOURCES = ["h2_kernels.hip", "h2_mm.hip", "h2_orth.hip", "h2_comp.hip"]
+HIP_SOURCES = ["h2_kernels.hip", "h2_mm.hip", "h2_orth.hip", "h2_comp.hip", "h2_noalloc.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 # Packed FP32 instructions stay off: hipcc must not form them from float code.

@@ -555,7 +555,8 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
             w.slot = A.mem.upload(slots, stream);
             w.red = A.mem.upload(red, stream);
             w.nred = int64_t(red.size());
-            w.partials = A.mem.alloc(int64_t(offd.size()) * 64 * (A.vec_f64 ? 8 : 4));
+            w.partials_bytes = int64_t(offd.size()) * 64 * (A.vec_f64 ? 8 : 4);
+            w.partials = A.mem.alloc(w.partials_bytes);
             A.lists.push_back(w);
             L.clear();
         }
@@ -610,7 +611,8 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
             w.blks = A.mem.upload(blks, stream);
             w.red = A.mem.upload(red, stream);
             w.nred = int64_t(red.size());
-            w.partials = A.mem.alloc(w.nrows * 64 * 8);
+            w.partials_bytes = w.nrows * 64 * 8;
+            w.partials = A.mem.alloc(w.partials_bytes);
             A.lists.push_back(w);
         } else {
             emit_one(0, PH_STREAM, sk, A.blocks, L);

@@ -108,6 +108,7 @@ struct WorkList {
     const h2::ReduceDesc *red = nullptr;
     int64_t nred = 0;
     void *partials = nullptr;   // FP64 (FP32 for the half-storage list of a reduced-storage matrix)
+    int64_t partials_bytes = 0;
     // stream list of a matrix stored by halves: partial slot of every block
     // (-1: diagonal block); red then adds the slots to the row sums
     const int32_t *slot = nullptr;
@@ -242,7 +243,17 @@ void structure_from_arrays(const h2_arrays *a, h2::Structure &s);
 void export_arrays(h2_matrix_ &A, const h2_arrays_out *o, hipStream_t st);
 
 // h2_run.cpp
-void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st);
+// Intermediate vectors of one single-vector product: the trees x^ and y^, the
+// near field, and the partial sums of a split or half-storage stream list.
+struct Workspace {
+    void *xh, *yh, *ynear, *partials;
+};
+// Bytes of each part (rounded up to 256), in the order above; the sum is the
+// whole.
+void workspace_bytes(const h2_matrix_ &A, int64_t part[4]);
+// Enqueues the whole single-vector product on st, in the handle's own
+// workspace, or in ws (then without profiling events).
+void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st, const Workspace *ws = nullptr);
 void run_tile_pass(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, int j0,
                    const h2::MmConfig &cfg, hipStream_t st);
 void run_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, hipStream_t st);

@@ -22,17 +22,19 @@ hipEvent_t take_event(h2_matrix_ &A) {
 // Enqueues the lists in order, with profiling events at phase boundaries
 // when enabled; launch(w) enqueues one list.
 template <class Launch>
-void run_lists(h2_matrix_ &A, const std::vector<WorkList> &lists, hipStream_t st, Launch launch) {
+void run_lists(h2_matrix_ &A, const std::vector<WorkList> &lists, hipStream_t st, Launch launch,
+               bool allow_prof = true) {
+    const bool prof = A.prof && allow_prof;
     hipEvent_t ev[PH_COUNT + 1] = {};
-    if (A.prof)
+    if (prof)
         for (auto &e : ev) e = take_event(A);
     int next_phase = 0;   // lists are in phase order; each phase's event precedes its lists
     for (const WorkList &w : lists) {
-        while (A.prof && next_phase <= int(w.phase))
+        while (prof && next_phase <= int(w.phase))
             check_hip(hipEventRecord(ev[next_phase++], st), "hipEventRecord");
         launch(w);
     }
-    if (A.prof) {
+    if (prof) {
         while (next_phase <= PH_COUNT) check_hip(hipEventRecord(ev[next_phase++], st), "hipEventRecord");
         A.pending.insert(A.pending.end(), ev, ev + PH_COUNT + 1);
     }
@@ -51,9 +53,20 @@ void ensure_tiles(h2_matrix_ &A) {
 
 }  // namespace
 
-// Enqueues the whole single-vector product on st.
-void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st) {
+void workspace_bytes(const h2_matrix_ &A, int64_t part[4]) {
+    auto r256 = [](int64_t b) { return (b + 255) / 256 * 256; };
+    const int64_t vb = A.vec_f64 ? 8 : 4;
+    part[0] = part[1] = r256(A.st.nnodes * A.st.rank * vb);
+    part[2] = r256(A.st.n * vb);
+    part[3] = 0;
+    for (const WorkList &w : A.lists) part[3] = std::max(part[3], r256(w.partials_bytes));
+}
+
+void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st, const Workspace *ws) {
+    const Workspace own{A.xh, A.yh, A.ynear, nullptr};
+    const Workspace &W = ws ? *ws : own;
     run_lists(A, A.lists, st, [&](const WorkList &w) {
+        void *partials = ws ? ws->partials : w.partials;
         h2::RowLaunch L;
         L.rows = w.rows;
         L.nrows = w.nrows;
@@ -65,43 +78,43 @@ void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st) {
         L.out1 = nullptr;
         switch (w.phase) {
             case PH_UP:
-                L.in0 = A.xh;
-                L.out0 = A.xh;
+                L.in0 = W.xh;
+                L.out0 = W.xh;
                 break;
             case PH_STREAM:
-                L.in0 = A.xh;
-                L.out0 = A.yh;
-                L.out1 = A.ynear;
+                L.in0 = W.xh;
+                L.out0 = W.yh;
+                L.out1 = W.ynear;
                 if (w.slot) {   // stored by halves: row sums and transposed partials, then their sums
-                    check_hip(h2::launch_stream_half(L, w.slot, w.partials, w.kind, A.vec_f64, st),
+                    check_hip(h2::launch_stream_half(L, w.slot, partials, w.kind, A.vec_f64, st),
                               "half-storage stream launch");
-                    check_hip(h2::launch_reduce_chunks(w.red, w.nred, w.partials, !A.vec_f64, A.yh, A.ynear, A.vec_f64,
+                    check_hip(h2::launch_reduce_chunks(w.red, w.nred, partials, !A.vec_f64, W.yh, W.ynear, A.vec_f64,
                                                        st, true),
                               "partial sum launch");
                     return;
                 }
                 if (w.red) {   // chunks of a split list: partial sums, then their sums per row
-                    L.out0 = L.out1 = w.partials;
+                    L.out0 = L.out1 = partials;
                     check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, int(w.phase), st, 1), "blockrow launch");
-                    check_hip(h2::launch_reduce_chunks(w.red, w.nred, w.partials, false, A.yh, A.ynear, A.vec_f64, st),
+                    check_hip(h2::launch_reduce_chunks(w.red, w.nred, partials, false, W.yh, W.ynear, A.vec_f64, st),
                               "chunk sum launch");
                     return;
                 }
                 break;
             case PH_DOWN:
-                L.in0 = A.yh;
-                L.init = A.yh;
-                L.out0 = A.yh;
+                L.in0 = W.yh;
+                L.init = W.yh;
+                L.out0 = W.yh;
                 break;
             default:
-                L.in0 = A.yh;
-                L.init = A.ynear;
-                L.out0 = A.yh;
+                L.in0 = W.yh;
+                L.init = W.ynear;
+                L.out0 = W.yh;
                 L.out1 = y;
                 break;
         }
         check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, int(w.phase), st), "blockrow launch");
-    });
+    }, ws == nullptr);
 }
 
 // One pass of up to MM_TILE right-hand sides on the matrix cores.

@@ -21,7 +21,7 @@ H2_HALF_STORAGE = 16   # OR-ed into a storage value: blocks stored by halves (sy
 STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
 
 # Every function declared in include/h2mv.h.
-EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_orthogonalize", "h2_compress", "h2_transpose", "h2_matvec", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
+EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_orthogonalize", "h2_compress", "h2_transpose", "h2_matvec", "h2_matvec_noalloc", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
            "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_batch_create", "h2_batch_matmat",
            "h2_batch_tuning", "h2_batch_free", "h2_last_error")
 
@@ -81,6 +81,7 @@ def lib():
         L.h2_compress.argtypes = [vp, C.c_double, vp, vp]
         L.h2_transpose.argtypes = [vp, vp, C.POINTER(vp)]
         L.h2_matvec.argtypes = [vp, vp, vp, vp]
+        L.h2_matvec_noalloc.argtypes = [vp, vp, vp, vp]
         L.h2_matmat.argtypes = [vp, vp, i64, vp, i64, C.c_int, vp]
         L.h2_free.argtypes = [vp]
         L.h2_free.restype = None
@@ -213,6 +214,10 @@ def h2_compress(h, eps, stream=0):
 
 def h2_matvec(h, x_ptr, y_ptr, stream=0):
     _check(lib().h2_matvec(C.c_void_p(h), C.c_void_p(x_ptr), C.c_void_p(y_ptr), C.c_void_p(stream)))
+
+
+def h2_matvec_noalloc(h, x_ptr, y_ptr, stream=0):
+    _check(lib().h2_matvec_noalloc(C.c_void_p(h), C.c_void_p(x_ptr), C.c_void_p(y_ptr), C.c_void_p(stream)))
 
 
 def h2_matmat(h, X_ptr, ldx, Y_ptr, ldy, nrhs, stream=0):
