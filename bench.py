@@ -510,6 +510,7 @@ def matmat_modes(steps, warmup, fp64_matvec_ms, nleaves=8):
         ms = (time.perf_counter() - t0) * 1e3 / steps
         phase_ms, calls = h2mv.h2_profile_read(A.handle)
         h2mv.h2_profile(A.handle, False)
+        tuning = A.matmat_tuning(0)
         Yh = Y.cpu().numpy()
         A.close()
         del X, Y
@@ -536,9 +537,9 @@ def matmat_modes(steps, warmup, fp64_matvec_ms, nleaves=8):
                      "flops": flops, "stream_ms": round(float(phase_ms[1] / max(calls, 1)), 4),
                      "speedup_vs_32_fp64_matvecs": None if fp64_matvec_ms is None
                      else round(32 * fp64_matvec_ms / ms, 2),
-                     "rel_err_vs_fp64_oracle_max": max(errs)}
+                     "rel_err_vs_fp64_oracle_max": max(errs), "tuning": tuning}
         log(f"{w.name} matmat {name}: {ms:.3f} ms, {out[name]['GB_per_s']} GB/s, "
-            f"{out[name]['TFLOP_per_s']} TFLOP/s, rel err {max(errs):.2e}")
+            f"{out[name]['TFLOP_per_s']} TFLOP/s, rel err {max(errs):.2e}, tuning {tuning}")
     out["error_sample"] = f"columns 0 and 31, all rows of {nleaves} seeded leaves vs the FP64 oracle"
     return out
 

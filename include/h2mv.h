@@ -300,12 +300,26 @@ h2_status h2_matvec_noalloc(h2_handle A, const double *x, double *y, void *strea
  * H2_FP64 handles, and handles stored by halves, run nrhs single-vector
  * products; other H2_FP32 and H2_BF16_SCALED handles
  * run on the matrix cores (FP32 MFMA), 32 right-hand sides per pass.  The first
- * such call on a handle times the two block loops (pipelined or not) on its
- * first pass and keeps the faster (cached like a batch's choice, below).
+ * such call on a handle times the candidate launch shapes (the block loop's
+ * prefetch depth 0..3, one workgroup per two rows or a persistent grid of 1
+ * or 2 workgroups per compute unit, and the MFMA tile width 16 or 32 for
+ * passes of at most 16 right-hand sides) on its first pass and keeps the
+ * fastest (cached like a batch's choice, below; h2_matmat_tuning reports it).
  * Errors: INVALID_ARG for nrhs < 1, ldx < n, ldy < n, NULL pointers or a
  * structure-only handle; DEVICE. */
 h2_status h2_matmat(h2_handle A, const double *X, int64_t ldx, double *Y, int64_t ldy,
                     int nrhs, void *stream);
+
+/* Launch shape h2_matmat chose on A for passes of more than 16 right-hand
+ * sides (narrow = 0) or of at most 16 (narrow = 1): pipelined, grid and
+ * tile_width as for batches (h2_batch_tuning), and the timed pass in ms (-1
+ * before the first such pass; 0 when the choice came from the cache). */
+h2_status h2_matmat_tuning(h2_handle A, int narrow, int *pipelined, int64_t *grid, int *tile_width,
+                           double *tuned_ms);
+/* Fixes that shape instead of timing the candidates (pipelined 0..3; grid >=
+ * 0; tile_width 32, or 16 for narrow passes).  Every shape gives the same
+ * products to rounding.  Errors: INVALID_ARG. */
+h2_status h2_matmat_set_tuning(h2_handle A, int narrow, int pipelined, int64_t grid, int tile_width);
 
 /* Release every device and host resource of A.  NULL is a no-op.  The caller
  * must make sure no enqueued work on A is still running. */
@@ -340,10 +354,10 @@ h2_status h2_profile_read(h2_handle A, double *ms, int64_t *calls);
  * rank and leaf size run together, one launch per level slot (upsweep slots
  * aligned at the leaves, downsweep slots aligned at the leaves, one streaming
  * and one leaf slot), the whole sequence captured once in a HIP graph and
- * replayed.  The launch configuration (pipelined block loop or not, persistent
- * grid size) is chosen by timing the candidates at the first product; the
- * choice is cached per process and, when the environment variable
- * H2MV_AUTOTUNE_CACHE names a file, in that file.
+ * replayed.  The launch configuration (the block loop's prefetch depth, the
+ * persistent grid size and the MFMA tile width) is chosen by timing the
+ * candidates at the first product; the choice is cached per process and, when
+ * the environment variable H2MV_AUTOTUNE_CACHE names a file, in that file.
  *
  * h2_batch_create
  *  mats    host, count handles, all built with the same storage, H2_FP32 or
@@ -367,10 +381,20 @@ h2_status h2_profile_read(h2_handle A, double *ms, int64_t *calls);
 h2_status h2_batch_create(const h2_handle *mats, int count, int nrhs, void *stream, h2_batch *out);
 h2_status h2_batch_matmat(h2_batch B, const double *const *X, const int64_t *ldx, double *const *Y,
                           const int64_t *ldy, void *stream);
-/* Chosen configuration: pipelined (0/1), grid (workgroups; 0 = one per two
- * rows) and the tuned time in ms of one product (-1 before the first product;
- * 0 when the choice came from the cache). */
-h2_status h2_batch_tuning(h2_batch B, int *pipelined, int64_t *grid, double *tuned_ms);
+/* Chosen configuration: pipelined (the block loop's prefetch depth: 0 none,
+ * 1 the next block, 2 or 3 a ring of that many blocks refilled chunk by
+ * chunk), grid (workgroups; 0 = one per two rows), tile_width (16: 16x16
+ * MFMAs; 32: 32x32 MFMAs) and the tuned time in ms of one product (-1 before
+ * the first product; 0 when the choice came from the cache or
+ * h2_batch_set_tuning). */
+h2_status h2_batch_tuning(h2_batch B, int *pipelined, int64_t *grid, int *tile_width, double *tuned_ms);
+/* Fixes the configuration instead of timing the candidates: pipelined 0..3,
+ * grid >= 0, tile_width 16 (at most 16 right-hand sides) or 32; every choice
+ * gives the members' products to rounding (the tile width changes the order
+ * of a block's FP32 sums).  Waits for the batch's running products and drops
+ * its captured graph (the next product captures again).  Errors:
+ * INVALID_ARG; DEVICE. */
+h2_status h2_batch_set_tuning(h2_batch B, int pipelined, int64_t grid, int tile_width);
 void h2_batch_free(h2_batch B);   /* NULL is a no-op; wait for running products first */
 
 /* Text of the last failure on this thread ("" if none). */

@@ -13,7 +13,8 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# H2_ORACLE_LIBRARY names another build of h2oracle.c (the sanitizer test's)
+LIB_PATH = os.environ.get("H2_ORACLE_LIBRARY") or os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "h2oracle.c")
 
 KERNEL_EXP, KERNEL_POLY2 = 0, 1
@@ -41,6 +42,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
+            if os.environ.get("H2_ORACLE_LIBRARY"):
+                raise RuntimeError(f"H2_ORACLE_LIBRARY={LIB_PATH} does not exist")
             build()
         L = C.CDLL(LIB_PATH)
         L.or_cheb_nodes.argtypes = [C.c_int, _f64p]

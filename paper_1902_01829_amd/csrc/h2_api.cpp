@@ -52,7 +52,7 @@ h2_status h2_get_perm(h2_handle A, int64_t *perm) {
         g_last_error = "NULL argument";
         return H2_ERR_INVALID_ARG;
     }
-    std::memcpy(perm, A->st.perm.data(), A->st.perm.size() * sizeof(int64_t));
+    if (!A->st.perm.empty()) std::memcpy(perm, A->st.perm.data(), A->st.perm.size() * sizeof(int64_t));
     return H2_OK;
 }
 
@@ -63,8 +63,9 @@ h2_status h2_get_level_bsr(h2_handle A, int level, int64_t *count, int32_t *rowp
     }
     const h2::Bsr &B = level < 0 ? A->st.dense : A->st.coupling[level];
     *count = B.blocks();
-    if (rowptr) std::memcpy(rowptr, B.rowptr.data(), B.rowptr.size() * sizeof(int32_t));
-    if (colidx) std::memcpy(colidx, B.colidx.data(), B.colidx.size() * sizeof(int32_t));
+    // (empty vectors may hand out a null data(), which memcpy must not get)
+    if (rowptr && !B.rowptr.empty()) std::memcpy(rowptr, B.rowptr.data(), B.rowptr.size() * sizeof(int32_t));
+    if (colidx && !B.colidx.empty()) std::memcpy(colidx, B.colidx.data(), B.colidx.size() * sizeof(int32_t));
     return H2_OK;
 }
 

@@ -21,7 +21,8 @@ void batch_enqueue(h2_batch_ &B, const h2::MmConfig &cfg, hipStream_t st) {
                                     cfg.grid > 0 ? cfg.grid : 0, st),
               "batch pack");
     for (const BatchSlot &sl : B.slots) {
-        h2::MmBatchLaunch L{sl.rows, sl.items, sl.nitems, sl.blks, B.scales, B.pool, B.d_Ytab, B.d_ldy, B.nrhs};
+        h2::MmBatchLaunch L{sl.rows, sl.items, sl.nitems, sl.pitems, sl.npitems, sl.blks, B.scales, B.pool,
+                            B.d_Ytab, B.d_ldy, B.nrhs};
         check_hip(h2::launch_mm_batch(L, sl.kind, int(sl.phase), cfg, st), "batch launch");
     }
 }
@@ -31,7 +32,8 @@ std::string config_file() {
     return p ? std::string(p) : std::string();
 }
 
-// The cache file holds one "signature pipelined grid" line per entry.
+// The cache file holds one "signature pipelined grid tile_width" line per
+// entry (a line without the tile width means 0: chosen by the pass width).
 bool cached_config(const std::string &sig, h2::MmConfig &cfg) {
     std::lock_guard<std::mutex> lock(config_cache().mu);
     for (auto &e : config_cache().entries)
@@ -47,10 +49,12 @@ bool cached_config(const std::string &sig, h2::MmConfig &cfg) {
     bool found = false;
     while (std::fgets(line, sizeof line, fp)) {
         char key[400];
-        int pipe = 0;
+        int pipe = 0, nt = 0;
         long long grid = 0;
-        if (std::sscanf(line, "%399s %d %lld", key, &pipe, &grid) == 3 && sig == key) {
-            cfg = {pipe, grid};
+        const int got = std::sscanf(line, "%399s %d %lld %d", key, &pipe, &grid, &nt);
+        if (got >= 3 && sig == key && pipe >= 0 && pipe <= 5 && grid >= 0 && (nt == 0 || nt == 16 || nt == 32) &&
+            (pipe < 4 || nt == 32)) {
+            cfg = {pipe, grid, got == 4 ? nt : 0};
             found = true;
         }
     }
@@ -65,16 +69,27 @@ void store_config(const std::string &sig, const h2::MmConfig &cfg) {
     const std::string f = config_file();
     if (f.empty()) return;
     if (FILE *fp = std::fopen(f.c_str(), "a")) {
-        std::fprintf(fp, "%s %d %lld\n", sig.c_str(), cfg.pipelined, static_cast<long long>(cfg.grid));
+        std::fprintf(fp, "%s %d %lld %d\n", sig.c_str(), cfg.pipelined, static_cast<long long>(cfg.grid), cfg.nt);
         std::fclose(fp);
     }
 }
 
+// Launch shapes the tuners try: the block loop's prefetch depth (0 plain, 1
+// the next block, 2 and 3 rings of block slots), and for passes of at most 16
+// right-hand sides the MFMA tile width (16: 16x16 MFMAs, half the matrix-core
+// work and registers of 32, but every tile pads 8 right-hand sides to 16;
+// 32: 32x32 MFMAs).  Depth 3 with 32-wide tiles runs one wavefront per SIMD.
+constexpr int kDepths = 6;   // 4 and 5 (tiles shared by a row's halves) only with 32-wide tiles
+
+std::vector<int> tile_widths(int ncols) {
+    return ncols <= 16 ? std::vector<int>{16, 32} : std::vector<int>{32};
+}
+
 // Times every candidate configuration on the batch (tables set) and keeps the
-// fastest: pipelined block loop or not, times persistent grids of 2, 4 and 8
-// workgroups per compute unit or one workgroup per two rows.
+// fastest: prefetch depth x tile width x grid (persistent grids of 1, 2 and 4
+// workgroups per compute unit, or one workgroup per two rows).
 void batch_autotune(h2_batch_ &B) {
-    h2::MmConfig best{1, 0};
+    h2::MmConfig best{1, 0, 0};
     if (cached_config(B.signature, best)) {
         B.cfg = best;
         B.tuned = true;
@@ -85,26 +100,28 @@ void batch_autotune(h2_batch_ &B) {
     check_hip(hipEventCreate(&t1), "hipEventCreate");
     double best_ms = 1e30;
     const int64_t cu = (B.cu_count + h2::MM_XCDS - 1) / h2::MM_XCDS * h2::MM_XCDS;
-    const int64_t grids[4] = {0, 2 * cu, 4 * cu, 8 * cu};
-    for (int pipe = 0; pipe < 2; ++pipe)
-        for (int64_t grid : grids) {
-            const h2::MmConfig c{pipe, grid};
-            batch_enqueue(B, c, B.own);   // warm-up
-            float ms_best = 1e30f;
-            for (int rep = 0; rep < 2; ++rep) {
-                check_hip(hipEventRecord(t0, B.own), "hipEventRecord");
-                batch_enqueue(B, c, B.own);
-                check_hip(hipEventRecord(t1, B.own), "hipEventRecord");
-                check_hip(hipEventSynchronize(t1), "hipEventSynchronize");
-                float ms = 0.0f;
-                check_hip(hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
-                ms_best = std::min(ms_best, ms);
+    const int64_t grids[4] = {0, cu, 2 * cu, 4 * cu};
+    for (int nt : tile_widths(B.nrhs))
+        for (int pipe = 0; pipe < kDepths; ++pipe)
+            for (int64_t grid : grids) {
+                if (pipe >= 4 && nt != 32) continue;
+                const h2::MmConfig c{pipe, grid, nt};
+                batch_enqueue(B, c, B.own);   // warm-up
+                float ms_best = 1e30f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    check_hip(hipEventRecord(t0, B.own), "hipEventRecord");
+                    batch_enqueue(B, c, B.own);
+                    check_hip(hipEventRecord(t1, B.own), "hipEventRecord");
+                    check_hip(hipEventSynchronize(t1), "hipEventSynchronize");
+                    float ms = 0.0f;
+                    check_hip(hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
+                    ms_best = std::min(ms_best, ms);
+                }
+                if (ms_best < best_ms) {
+                    best_ms = ms_best;
+                    best = c;
+                }
             }
-            if (ms_best < best_ms) {
-                best_ms = ms_best;
-                best = c;
-            }
-        }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     B.cfg = best;
@@ -205,9 +222,10 @@ void build_batch(h2_batch_ &B, hipStream_t stream) {
     };
     auto add_slot = [&](Phase ph, int kind, std::vector<h2::RowDesc> &rows, std::vector<h2::BlkDesc> &blks) {
         if (rows.empty()) return;
-        const std::vector<int32_t> it = wave_items(rows, blks);
+        const std::vector<int32_t> it = wave_items(rows, blks), pit = pair_items(rows, blks);
         BatchSlot sl{ph, kind, B.mem.upload(rows, stream), int64_t(rows.size()), B.mem.upload(blks, stream),
-                     B.mem.upload(it, stream), int64_t(it.size())};
+                     B.mem.upload(it, stream), int64_t(it.size()), B.mem.upload(pit, stream),
+                     int64_t(pit.size())};
         B.slots.push_back(sl);
     };
     std::vector<h2::RowDesc> rows;
@@ -270,41 +288,52 @@ void build_batch(h2_batch_ &B, hipStream_t stream) {
 
 void tune_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t ldy, int nrhs, int j0,
                 hipStream_t st) {
-    const int w = std::min(h2::MM_TILE, nrhs - j0) <= 16 ? 1 : 0;
+    const int ncols = std::min(h2::MM_TILE, nrhs - j0);
+    const int w = ncols <= 16 ? 1 : 0;
     int64_t nblocks = 0;
     for (const auto &hb : A.mm_host_blks) nblocks += int64_t(hb.size());
     const std::string sig = "single-k" + std::to_string(A.block_kind) + "-n" + std::to_string(A.st.n) + "-r" +
                             std::to_string(A.st.rank) + "-blocks" + std::to_string(nblocks) + "-nt" +
                             std::to_string(w ? 16 : 32);
-    h2::MmConfig best{1, 0};
+    h2::MmConfig best{1, 0, 0};
+    double best_ms = 0.0;
     if (!cached_config(sig, best)) {
         const bool prof = A.prof;   // tuning runs stay out of the profile
         A.prof = false;
         hipEvent_t t0, t1;
         check_hip(hipEventCreate(&t0), "hipEventCreate");
         check_hip(hipEventCreate(&t1), "hipEventCreate");
-        float best_ms = 1e30f;
-        for (int pipe = 0; pipe < 2; ++pipe) {
-            const h2::MmConfig c{pipe, 0};
-            run_tile_pass(A, X, ldx, Y, ldy, nrhs, j0, c, st);   // warm-up
-            check_hip(hipEventRecord(t0, st), "hipEventRecord");
-            run_tile_pass(A, X, ldx, Y, ldy, nrhs, j0, c, st);
-            check_hip(hipEventRecord(t1, st), "hipEventRecord");
-            check_hip(hipEventSynchronize(t1), "hipEventSynchronize");
-            float ms = 0.0f;
-            check_hip(hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = c;
-            }
-        }
+        float bms = 1e30f;
+        int dev = 0, cus = 256;
+        check_hip(hipGetDevice(&dev), "hipGetDevice");
+        check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+        const int64_t cu = (cus + h2::MM_XCDS - 1) / h2::MM_XCDS * h2::MM_XCDS;
+        for (int nt : tile_widths(ncols))
+            for (int pipe = 0; pipe < kDepths; ++pipe)
+                for (int64_t grid : {int64_t(0), cu, 2 * cu}) {
+                    if (pipe >= 4 && nt != 32) continue;
+                    const h2::MmConfig c{pipe, grid, nt};
+                    run_tile_pass(A, X, ldx, Y, ldy, nrhs, j0, c, st);   // warm-up
+                    check_hip(hipEventRecord(t0, st), "hipEventRecord");
+                    run_tile_pass(A, X, ldx, Y, ldy, nrhs, j0, c, st);
+                    check_hip(hipEventRecord(t1, st), "hipEventRecord");
+                    check_hip(hipEventSynchronize(t1), "hipEventSynchronize");
+                    float ms = 0.0f;
+                    check_hip(hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
+                    if (ms < bms) {
+                        bms = ms;
+                        best = c;
+                    }
+                }
         (void)hipEventDestroy(t0);
         (void)hipEventDestroy(t1);
         A.prof = prof;
+        best_ms = bms;
         store_config(sig, best);
     }
     A.mm_cfg[w] = best;
     A.mm_tuned[w] = true;
+    A.mm_tuned_ms[w] = best_ms;
 }
 
 }  // namespace h2i
@@ -402,14 +431,71 @@ h2_status h2_batch_matmat(h2_batch B, const double *const *X, const int64_t *ldx
     }
 }
 
-h2_status h2_batch_tuning(h2_batch B, int *pipelined, int64_t *grid, double *tuned_ms) {
-    if (!B || !pipelined || !grid || !tuned_ms) {
+h2_status h2_batch_tuning(h2_batch B, int *pipelined, int64_t *grid, int *tile_width, double *tuned_ms) {
+    if (!B || !pipelined || !grid || !tile_width || !tuned_ms) {
         g_last_error = "NULL argument";
         return H2_ERR_INVALID_ARG;
     }
     *pipelined = B->cfg.pipelined;
     *grid = B->cfg.grid;
+    *tile_width = B->cfg.nt ? B->cfg.nt : (B->nrhs <= 16 ? 16 : 32);
     *tuned_ms = B->tuned ? B->tuned_ms : -1.0;
+    return H2_OK;
+}
+
+h2_status h2_batch_set_tuning(h2_batch B, int pipelined, int64_t grid, int tile_width) {
+    try {
+        if (!B) fail(H2_ERR_INVALID_ARG, "NULL batch");
+        if (pipelined < 0 || pipelined > 5) fail(H2_ERR_INVALID_ARG, "pipelined must be 0 .. 5");
+        if (pipelined >= 4 && tile_width != 32) fail(H2_ERR_INVALID_ARG, "tile sharing (4, 5) needs 32-wide tiles");
+        if (grid < 0) fail(H2_ERR_INVALID_ARG, "grid must be >= 0");
+        if (tile_width != 16 && tile_width != 32) fail(H2_ERR_INVALID_ARG, "tile_width must be 16 or 32");
+        if (tile_width == 16 && B->nrhs > 16) fail(H2_ERR_INVALID_ARG, "16-wide tiles take at most 16 right-hand sides");
+        // the captured graph holds the old launches: drop it (the next
+        // product captures again); wait for products that may still replay it
+        check_hip(hipStreamSynchronize(B->own), "hipStreamSynchronize");
+        if (B->exec) (void)hipGraphExecDestroy(B->exec);
+        if (B->graph) (void)hipGraphDestroy(B->graph);
+        B->exec = nullptr;
+        B->graph = nullptr;
+        B->cfg = {pipelined, grid, tile_width};
+        B->tuned = true;
+        B->tuned_ms = 0.0;
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (...) {
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+h2_status h2_matmat_tuning(h2_handle A, int narrow, int *pipelined, int64_t *grid, int *tile_width,
+                           double *tuned_ms) {
+    if (!A || !pipelined || !grid || !tile_width || !tuned_ms || (narrow != 0 && narrow != 1)) {
+        g_last_error = "NULL argument or narrow not 0 / 1";
+        return H2_ERR_INVALID_ARG;
+    }
+    const h2::MmConfig &c = A->mm_cfg[narrow];
+    *pipelined = c.pipelined;
+    *grid = c.grid;
+    *tile_width = c.nt ? c.nt : (narrow ? 16 : 32);
+    *tuned_ms = A->mm_tuned[narrow] ? A->mm_tuned_ms[narrow] : -1.0;
+    return H2_OK;
+}
+
+h2_status h2_matmat_set_tuning(h2_handle A, int narrow, int pipelined, int64_t grid, int tile_width) {
+    if (!A || (narrow != 0 && narrow != 1) || pipelined < 0 || pipelined > 5 || grid < 0 ||
+        (tile_width != 16 && tile_width != 32) || (tile_width == 16 && narrow == 0) ||
+        (pipelined >= 4 && tile_width != 32)) {
+        g_last_error = "bad argument (narrow 0/1, pipelined 0..5 (4, 5 with 32-wide tiles), grid >= 0, "
+                       "tile_width 16 or 32, 16 only for narrow passes)";
+        return H2_ERR_INVALID_ARG;
+    }
+    A->mm_cfg[narrow] = {pipelined, grid, tile_width};
+    A->mm_tuned[narrow] = true;
+    A->mm_tuned_ms[narrow] = 0.0;
     return H2_OK;
 }
 

@@ -28,39 +28,89 @@ uint16_t host_bf16_rne(float f) {
 // ranges of about equal work (per block: its columns rounded up to the
 // 16-column MFMA step, plus a fixed cost), each range padded to whole
 // workgroups, and range x's l-th workgroup placed at workgroup l * MM_XCDS + x.
-std::vector<int32_t> wave_items(const std::vector<h2::RowDesc> &rows, const std::vector<h2::BlkDesc> &blks) {
+namespace {
+
+// Cost of a row's block loop (columns rounded to the MFMA step, plus a
+// constant per block).
+double row_work(const h2::RowDesc &r, const std::vector<h2::BlkDesc> &blks) {
+    double w = 0.0;
+    for (int32_t b = r.b0; b < r.b1; ++b) w += double((blks[b].C + 15) / 16 * 16 + 8);
+    return w;
+}
+
+// Dispatch order of work units (usize items each, in list order): the list
+// is cut into MM_XCDS contiguous ranges of about equal work, and range x's
+// units fill workgroups wg = l * MM_XCDS + x (per_wg items each) in order, so
+// that the workgroups of XCD x (wg % MM_XCDS == x) walk range x.
+std::vector<int32_t> layout_units(const std::vector<int32_t> &units, int usize, const std::vector<double> &work,
+                                  int per_wg) {
     constexpr int X = h2::MM_XCDS;
-    if (rows.size() >= (size_t(1) << 30)) fail(H2_ERR_UNSUPPORTED, "too many rows in one tile list");
-    std::vector<int32_t> items;
-    std::vector<double> work;
+    const size_t n = work.size(), upw = size_t(per_wg / usize);
     double total = 0.0;
-    for (size_t r = 0; r < rows.size(); ++r) {
-        double w = 0.0;
-        for (int32_t b = rows[r].b0; b < rows[r].b1; ++b) w += double((blks[b].C + 15) / 16 * 16 + 8);
-        for (int mt = 0; mt * 32 < std::max(rows[r].R, 1); ++mt) {
-            items.push_back(int32_t(r << 1) | mt);
-            work.push_back(w);
-            total += w;
-        }
-    }
-    // cut points: range x = [cut[x], cut[x+1])
-    std::vector<size_t> cut(X + 1, items.size());
+    for (double w : work) total += w;
+    std::vector<size_t> cut(X + 1, n);   // range x = units [cut[x], cut[x+1])
     cut[0] = 0;
     double acc = 0.0;
     int x = 1;
-    for (size_t i = 0; i < items.size() && x < X; ++i) {
+    for (size_t i = 0; i < n && x < X; ++i) {
         while (x < X && acc >= total * x / X) cut[x++] = i;
         acc += work[i];
     }
     size_t per = 0;   // workgroups per XCD
-    for (int r = 0; r < X; ++r) per = std::max(per, (cut[r + 1] - cut[r] + 3) / 4);
-    std::vector<int32_t> out(per * X * 4, -1);
+    for (int r = 0; r < X; ++r) per = std::max(per, (cut[r + 1] - cut[r] + upw - 1) / upw);
+    std::vector<int32_t> out(per * X * size_t(per_wg), -1);
     for (int r = 0; r < X; ++r)
         for (size_t i = cut[r]; i < cut[r + 1]; ++i) {
-            const size_t l = (i - cut[r]) / 4, v = (i - cut[r]) % 4;
-            out[(l * X + r) * 4 + v] = items[i];
+            const size_t l = (i - cut[r]) / upw, v = (i - cut[r]) % upw;
+            for (int e = 0; e < usize; ++e) out[(l * X + r) * size_t(per_wg) + v * usize + e] = units[i * usize + e];
         }
     return out;
+}
+
+}  // namespace
+
+std::vector<int32_t> wave_items(const std::vector<h2::RowDesc> &rows, const std::vector<h2::BlkDesc> &blks) {
+    if (rows.size() >= (size_t(1) << 30)) fail(H2_ERR_UNSUPPORTED, "too many rows in one tile list");
+    std::vector<int32_t> items;
+    std::vector<double> work;
+    for (size_t r = 0; r < rows.size(); ++r) {
+        const double w = row_work(rows[r], blks);
+        for (int mt = 0; mt * 32 < std::max(rows[r].R, 1); ++mt) {
+            items.push_back(int32_t(r << 1) | mt);
+            work.push_back(w);
+        }
+    }
+    return layout_units(items, 1, work, 4);
+}
+
+std::vector<int32_t> pair_items(const std::vector<h2::RowDesc> &rows, const std::vector<h2::BlkDesc> &blks) {
+    if (rows.size() >= (size_t(1) << 30)) fail(H2_ERR_UNSUPPORTED, "too many rows in one tile list");
+    std::vector<int32_t> units;
+    std::vector<double> work;
+    int32_t single = -1;   // a row of at most 32 rows waiting for a partner
+    double single_w = 0.0;
+    for (size_t r = 0; r < rows.size(); ++r) {
+        const double w = row_work(rows[r], blks);
+        if (rows[r].R > 32) {
+            units.push_back(int32_t(r << 1));
+            units.push_back(int32_t(r << 1) | 1);
+            work.push_back(2 * w);
+        } else if (single < 0) {
+            single = int32_t(r << 1);
+            single_w = w;
+        } else {
+            units.push_back(single);
+            units.push_back(int32_t(r << 1));
+            work.push_back(single_w + w);
+            single = -1;
+        }
+    }
+    if (single >= 0) {
+        units.push_back(single);
+        units.push_back(-1);
+        work.push_back(single_w);
+    }
+    return layout_units(units, 2, work, 2);
 }
 
 void convert_block(const double *src, int R, int C, bool transpose, int kind, void *dst, float *scale) {
@@ -437,9 +487,11 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
         w.rows = A.mem.upload(rows, stream);
         w.blks = A.mem.upload(blks, stream);
         if (enc == 1) {
-            const std::vector<int32_t> it = wave_items(rows, blks);
+            const std::vector<int32_t> it = wave_items(rows, blks), pit = pair_items(rows, blks);
             w.items = A.mem.upload(it, stream);
             w.nitems = int64_t(it.size());
+            w.pitems = A.mem.upload(pit, stream);
+            w.npitems = int64_t(pit.size());
         }
         (enc == 0 ? A.lists : A.mm_lists).push_back(w);
         if (enc == 1) {

@@ -103,6 +103,8 @@ struct WorkList {
     const h2::BlkDesc *blks;
     const int32_t *items = nullptr;   // tile lists: wavefront items in dispatch order
     int64_t nitems = 0;
+    const int32_t *pitems = nullptr;  // tile lists: pair items (two per workgroup) in dispatch order
+    int64_t npitems = 0;
     // split stream list (single vector, small matrices): the rows are chunks
     // writing FP64 partial sums, added up by a second launch
     const h2::ReduceDesc *red = nullptr;
@@ -134,6 +136,8 @@ struct BatchSlot {
     h2::BlkDesc *blks;
     int32_t *items;
     int64_t nitems;
+    int32_t *pitems;
+    int64_t npitems;
 };
 
 }  // namespace h2i
@@ -159,8 +163,9 @@ struct h2_matrix_ {
     float *t_xh = nullptr, *t_yh = nullptr, *t_x = nullptr, *t_ynear = nullptr;   // tile workspace (lazy)
     // block loop chosen at the first pass of each tile width (32, or 16 for
     // passes of at most 16 right-hand sides)
-    h2::MmConfig mm_cfg[2] = {{1, 0}, {1, 0}};
+    h2::MmConfig mm_cfg[2] = {{1, 0, 0}, {1, 0, 0}};
     bool mm_tuned[2] = {false, false};
+    double mm_tuned_ms[2] = {0.0, 0.0};   // timed choice's pass time (0: from the cache)
     int64_t bytes_coupling = 0, bytes_dense = 0, bytes_leaf = 0, bytes_transfer = 0;
     // layout: element offsets of U_j, V_j^T (per leaf), E_c, F_c^T (per node,
     // -1 where not stored) in basis, and of every block in blocks (coupling
@@ -207,7 +212,7 @@ struct h2_batch_ {
     bool tables_pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    h2::MmConfig cfg{1, 0};
+    h2::MmConfig cfg{1, 0, 0};
     bool tuned = false;
     double tuned_ms = 0.0;
     std::string signature;
@@ -234,6 +239,7 @@ namespace h2i {
 
 // h2_build.cpp
 std::vector<int32_t> wave_items(const std::vector<h2::RowDesc> &rows, const std::vector<h2::BlkDesc> &blks);
+std::vector<int32_t> pair_items(const std::vector<h2::RowDesc> &rows, const std::vector<h2::BlkDesc> &blks);
 void convert_block(const double *src, int R, int C, bool transpose, int kind, void *dst, float *scale);
 std::vector<h2::FillDesc> make_layout(h2_matrix_ &A, int64_t &ncoupling);
 void build_device(h2_matrix_ &A, const h2_arrays *src, hipStream_t stream);

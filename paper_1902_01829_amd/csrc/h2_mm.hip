@@ -38,6 +38,15 @@ constexpr int NT = MM_TILE;   // right-hand sides per tile
 
 __device__ inline int round16(int v) { return (v + 15) & ~15; }
 
+// Non-temporal 16-byte load of block data through a global-address-space
+// pointer: batches hold block addresses as integers, and a generic pointer
+// made from one would be read with FLAT loads, which the compiler counts
+// against both memory counters (it then waits for every load in flight).
+template <typename T>
+__device__ inline T load_block_item(const T *p) {
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) T *)(p));
+}
+
 // Block operand of one wavefront and the matching input-tile operand.
 // FP32 blocks: 8 column steps of 4 values (lane group g holds columns
 // 8p + 4g + t of step p, one per K = 2 MFMA).  BF16 blocks: 4 steps of 16
@@ -68,7 +77,7 @@ __device__ inline void load_a(const BlkDesc &bd, const void *blk, int R, int ic,
         for (int p = 0; p < 8; ++p) {
             if (p >= NP) break;   // wave-uniform
             const int cg = 2 * p + lg, cgc = cg < CW ? cg : CW - 1;
-            o.v[p] = __builtin_nontemporal_load(
+            o.v[p] = load_block_item(
                 reinterpret_cast<const f32x4 *>(static_cast<const float *>(blk) + (int64_t(cgc) * R + ic) * 4));
         }
     } else {
@@ -77,7 +86,7 @@ __device__ inline void load_a(const BlkDesc &bd, const void *blk, int R, int ic,
         for (int s = 0; s < 4; ++s) {
             if (s >= NS) break;
             const int cg = 2 * s + lg, cgc = cg < CW ? cg : CW - 1;
-            o.v[s] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(
+            o.v[s] = load_block_item(reinterpret_cast<const u32x4 *>(
                 static_cast<const uint16_t *>(blk) + (int64_t(cgc) * R + ic) * 8));
         }
     }
@@ -259,6 +268,176 @@ __device__ inline void mm_row(const MmArgs &g, int64_t row, int mt, int lane) {
     }
 }
 
+// Chunks of the 32-wide loop: FP32 blocks have 8 (8 columns, four K = 2
+// MFMAs each), BF16 blocks 4 (16 columns, one K = 16 step as three MFMAs).
+template <int KIND> constexpr int chunks32() { return KIND == ELEM_F32 ? 8 : 4; }
+template <int KIND> __device__ inline int used_chunks32(int C) {
+    return KIND == ELEM_F32 ? round16(C) >> 3 : round16(C) >> 4;
+}
+
+// Chunk p of the block operand and of the input-tile operand (the loads of
+// load_a / load_b restricted to one chunk).  Issued for every chunk, with no
+// branch around them, so that the compiler's count of loads in flight stays
+// exact (a conditional load makes it wait for all of them): chunks past the
+// block's width re-read its last column group and the tile's last columns
+// (cache hits; their products are skipped), and with live == false (no block
+// left for this slot) the block operand's load reads the first item of the
+// input tile instead (a different address from the tile operand's, so the
+// compiler cannot fold the two loads into one on that path and branch).
+template <int KIND>
+__device__ inline void load_chunk32(const BlkDesc &bd, const void *blk, const float *xbase, int R, int ic, int li,
+                                    int lg, int p, bool live, BlockA<KIND> &a, TileB &b) {
+    const int C = bd.C, Cp = round16(C);
+    const float *xb = xbase + bd.in + li * Cp;
+    if constexpr (KIND == ELEM_F32) {
+        const int CW = (C + 3) >> 2, cg = 2 * p + lg, cgc = cg < CW ? cg : CW - 1;
+        const int col = 8 * p + 4 * lg, colc = col < Cp ? col : Cp - 4;
+        const f32x4 *bp = reinterpret_cast<const f32x4 *>(xb + colc);
+        const f32x4 *ap = live ? reinterpret_cast<const f32x4 *>(static_cast<const float *>(blk) +
+                                                                 (int64_t(cgc) * R + ic) * 4)
+                               : reinterpret_cast<const f32x4 *>(xbase + bd.in);
+        a.v[p] = load_block_item(ap);
+        b.v[p] = *bp;
+    } else {
+        const int CW = (C + 7) >> 3, cg = 2 * p + lg, cgc = cg < CW ? cg : CW - 1;
+        const int col = 16 * p + 8 * lg, colc = col < Cp ? col : Cp - 8;
+        const f32x4 *bp = reinterpret_cast<const f32x4 *>(xb + colc);
+        const u32x4 *ap = live ? reinterpret_cast<const u32x4 *>(static_cast<const uint16_t *>(blk) +
+                                                                 (int64_t(cgc) * R + ic) * 8)
+                               : reinterpret_cast<const u32x4 *>(xbase + bd.in);
+        a.v[p] = load_block_item(ap);
+        b.v[2 * p] = bp[0];
+        b.v[2 * p + 1] = bp[1];
+    }
+}
+
+// Products of chunk p accumulated into acc (the steps of block_products).
+template <int KIND>
+__device__ inline f32x16 chunk_products32(const BlockA<KIND> &a_op, const TileB &b_op, int p, f32x16 acc) {
+    if constexpr (KIND == ELEM_F32) {
+        const f32x4 a = a_op.v[p];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b_op.v[p].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b_op.v[p].y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b_op.v[p].z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b_op.v[p].w, acc, 0, 0, 0);
+    } else {
+        const bf16x8 a = __builtin_bit_cast(bf16x8, a_op.v[p]);
+        bf16x8 hi, mid, lo;
+        split3(b_op.v[2 * p], b_op.v[2 * p + 1], hi, mid, lo);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, lo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, mid, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hi, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Epilogue shared by the 32-wide block loops: lane l holds rows
+// 32*mt + 8*q + 4*(l/32) + e (e = 0..3) of right-hand side l % 32 in tot.
+template <bool LEAF, bool BATCH>
+__device__ inline void mm_store32(const MmArgs &g, const RowDesc &rd, int mt, int li, int lg, const double (&tot)[16]) {
+    const int R = rd.R, Rp = round16(R);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i0 = 32 * mt + 8 * q + 4 * lg;
+        if (i0 >= Rp) continue;
+        if constexpr (LEAF) {
+            if (li >= g.ncols) continue;
+            const f32x4 yn = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(li) * Rp + i0);
+            const double ynv[4] = {yn.x, yn.y, yn.z, yn.w};
+            double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
+            const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
+            double *yc = Yb + int64_t(li) * ldy + rd.out;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (i0 + e < R) yc[i0 + e] = ynv[e] + tot[4 * q + e];
+        } else {
+            double v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = i0 + e < R ? tot[4 * q + e] : 0.0;
+            if (rd.init >= 0) {
+                const f32x4 t = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(li) * Rp + i0);
+                v[0] += t.x; v[1] += t.y; v[2] += t.z; v[3] += t.w;
+            }
+            float *o = ((rd.sel & ROW_OUT_P) ? g.out_pts : g.out_tree) + rd.out + int64_t(li) * Rp + i0;
+            *reinterpret_cast<f32x4 *>(o) = f32x4{float(v[0]), float(v[1]), float(v[2]), float(v[3])};
+        }
+    }
+}
+
+// The 32-wide block loop with a ring of D block slots: slot s holds block
+// b = s (mod D).  As each chunk of block b is consumed, the same registers
+// are refilled with that chunk of block b + D, so about D blocks of loads
+// stay in flight through the row instead of one.  The arithmetic and its
+// order are those of mm_row (bitwise the same results).
+template <int KIND, bool LEAF, bool BATCH, int D>
+__device__ inline void mm_row_ring(const MmArgs &g, int64_t row, int mt, int lane) {
+    const RowDesc rd = g.rows[row];
+    const int R = rd.R;
+    if (32 * mt >= R) return;
+    const int li = lane & 31, lg = lane >> 5;
+    const int i = 32 * mt + li;
+    const int ic = i < R ? i : R - 1;
+    const float *xbase = (rd.sel & ROW_IN_X) ? g.in_pts : g.in_tree;
+    auto block_ptr = [&](const BlkDesc &bd) -> const void * {
+        if constexpr (BATCH) return reinterpret_cast<const void *>(bd.a);
+        else return static_cast<const char *>(g.data) + bd.a * (KIND == ELEM_F32 ? 4 : 2);
+    };
+    constexpr int NCH = chunks32<KIND>();
+
+    double tot[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) tot[r] = 0.0;
+
+    BlockA<KIND> a[D];
+    TileB b[D];
+    BlkDesc bd[D];
+    const int nb = rd.b1 - rd.b0;
+    if (nb > 0) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+            const bool live = s < nb;   // wave-uniform
+            bd[s] = g.blks[rd.b0 + (live ? s : 0)];
+            const void *blk = block_ptr(bd[s]);
+#pragma unroll
+            for (int p = 0; p < NCH; ++p) load_chunk32<KIND>(bd[s], blk, xbase, R, ic, li, lg, p, live, a[s], b[s]);
+        }
+    }
+    // block k from slot s, whose registers then receive block k + D
+    auto step = [&](const int s, const int k) {
+        const bool refill = k + D < nb;
+        const BlkDesc nx = g.blks[rd.b0 + (refill ? k + D : k)];
+        const int np = used_chunks32<KIND>(bd[s].C);
+        const void *nblk = block_ptr(nx);
+        f32x16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+        for (int p = 0; p < NCH; ++p) {
+            if (p < np) acc = chunk_products32<KIND>(a[s], b[s], p, acc);
+            load_chunk32<KIND>(nx, nblk, xbase, R, ic, li, lg, p, refill, a[s], b[s]);
+        }
+        const double sc = KIND == ELEM_BF16 ? double(g.scales[bd[s].sidx]) : 1.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tot[r] += sc * double(acc[r]);
+        bd[s] = nx;
+    };
+    // Whole rounds of D blocks, then the last < D: no branch inside a round
+    // reaches the loop's back edge, which keeps the compiler's waits exact.
+    int base = 0;
+    for (; base + D <= nb; base += D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) step(s, base + s);
+    }
+#pragma unroll
+    for (int s = 0; s < D - 1; ++s)
+        if (base + s < nb) step(s, base + s);   // wave-uniform
+    // The refills of the last D blocks were dead loads: let them land here,
+    // so that no load of this row is in flight when a persistent workgroup's
+    // loop starts its next row (the compiler's counts stay exact there too).
+    __builtin_amdgcn_s_waitcnt(0);
+    mm_store32<LEAF, BATCH>(g, rd, mt, li, lg, tot);
+}
+
 // ---- 16 right-hand sides (passes of at most 16 columns, batches of <= 16)
 // The tiles keep their layout; only their first 16 right-hand sides are
 // used.  A wavefront still owns a 32-row half of an output segment, as two
@@ -293,7 +472,7 @@ __device__ inline void load_a16(const BlkDesc &bd, const void *blk, int R, const
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 if (h >= nh) break;
-                o.v[h][c] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(
+                o.v[h][c] = load_block_item(reinterpret_cast<const f32x4 *>(
                     static_cast<const float *>(blk) + (int64_t(cgc) * R + ic[h]) * 4));
             }
         }
@@ -306,7 +485,7 @@ __device__ inline void load_a16(const BlkDesc &bd, const void *blk, int R, const
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 if (h >= nh) break;
-                o.v[h][c] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(
+                o.v[h][c] = load_block_item(reinterpret_cast<const u32x4 *>(
                     static_cast<const uint16_t *>(blk) + (int64_t(cgc) * R + ic[h]) * 8));
             }
         }
@@ -479,22 +658,427 @@ __device__ inline void mm_row16(const MmArgs &g, int64_t row, int mt, int lane) 
     }
 }
 
+// Chunks of the 16-wide loop: FP32 blocks have 4 (16 columns), BF16 blocks 2
+// (32 columns).
+template <int KIND> constexpr int chunks16() { return KIND == ELEM_F32 ? 4 : 2; }
+template <int KIND> __device__ inline int used_chunks16(int C) {
+    return KIND == ELEM_F32 ? round16(C) >> 4 : (C + 31) >> 5;
+}
+
+// Chunk c of both operands of the 16-wide loop (load_a16 / load_b16 restricted
+// to one chunk), issued unconditionally like load_chunk32: a missing second
+// row tile re-reads the first's rows (clamped), chunks past the width re-read
+// the last column group, and live == false reads the tile's first items (one
+// per row tile, at different addresses, as in load_chunk32).
+template <int KIND>
+__device__ inline void load_chunk16(const BlkDesc &bd, const void *blk, const float *xbase, int R, const int (&ic)[2],
+                                    int n, int kq, int c, bool live, BlockA16<KIND> &a, TileB16 &b) {
+    const int C = bd.C, Cp = round16(C);
+    const float *xb = xbase + bd.in + n * Cp;
+    if constexpr (KIND == ELEM_F32) {
+        const int CW = (C + 3) >> 2, cg = 4 * c + kq, cgc = cg < CW ? cg : CW - 1;
+        const int col = 16 * c + 4 * kq, colc = col < Cp ? col : Cp - 4;
+        const f32x4 *bp = reinterpret_cast<const f32x4 *>(xb + colc);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const f32x4 *ap = live ? reinterpret_cast<const f32x4 *>(static_cast<const float *>(blk) +
+                                                                     (int64_t(cgc) * R + ic[h]) * 4)
+                                   : reinterpret_cast<const f32x4 *>(xbase + bd.in + 4 * h);
+            a.v[h][c] = load_block_item(ap);
+        }
+        b.v[c] = *bp;
+    } else {
+        const int CW = (C + 7) >> 3, cg = 4 * c + kq, cgc = cg < CW ? cg : CW - 1;
+        const int col = 32 * c + 8 * kq, colc = col < Cp ? col : Cp - 8;
+        const f32x4 *bp = reinterpret_cast<const f32x4 *>(xb + colc);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const u32x4 *ap = live ? reinterpret_cast<const u32x4 *>(static_cast<const uint16_t *>(blk) +
+                                                                     (int64_t(cgc) * R + ic[h]) * 8)
+                                   : reinterpret_cast<const u32x4 *>(xbase + bd.in + 4 * h);
+            a.v[h][c] = load_block_item(ap);
+        }
+        b.v[2 * c] = bp[0];
+        b.v[2 * c + 1] = bp[1];
+    }
+}
+
+// Products of chunk c accumulated into acc (the steps of block_products16).
+template <int KIND>
+__device__ inline void chunk_products16(const BlockA16<KIND> &a_op, const TileB16 &b_op, int c, int Cp, int nh,
+                                        int kq, f32x4 (&acc)[2]) {
+    if constexpr (KIND == ELEM_F32) {
+        const f32x4 b = b_op.v[c];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h >= nh) break;
+            const f32x4 a = a_op.v[h][c];
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[h], 0, 0, 0);
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[h], 0, 0, 0);
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[h], 0, 0, 0);
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[h], 0, 0, 0);
+        }
+    } else {
+        bf16x8 hi, mid, lo;
+        split3(b_op.v[2 * c], b_op.v[2 * c + 1], hi, mid, lo);
+        if (32 * c + 8 * kq >= Cp) {   // past the tile: zero (see load_b16)
+            const u32x4 z = {0u, 0u, 0u, 0u};
+            hi = mid = lo = __builtin_bit_cast(bf16x8, z);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h >= nh) break;
+            const bf16x8 a = __builtin_bit_cast(bf16x8, a_op.v[h][c]);
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, lo, acc[h], 0, 0, 0);
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, mid, acc[h], 0, 0, 0);
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hi, acc[h], 0, 0, 0);
+        }
+    }
+}
+
+// Epilogue shared by the 16-wide block loops: accumulator element e of row
+// tile h holds row 32*mt + 16*h + 4*(l/16) + e of right-hand side l % 16.
+template <bool LEAF, bool BATCH>
+__device__ inline void mm_store16(const MmArgs &g, const RowDesc &rd, int mt, int nh, int n, int kq,
+                                  const double (&tot)[2][4]) {
+    const int R = rd.R, Rp = round16(R);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h >= nh) break;
+        const int i0 = 32 * mt + 16 * h + 4 * kq;
+        if (i0 >= Rp) continue;
+        if constexpr (LEAF) {
+            if (n >= g.ncols) continue;
+            const f32x4 yn = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(n) * Rp + i0);
+            const double ynv[4] = {yn.x, yn.y, yn.z, yn.w};
+            double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
+            const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
+            double *yc = Yb + int64_t(n) * ldy + rd.out;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (i0 + e < R) yc[i0 + e] = ynv[e] + tot[h][e];
+        } else {
+            double v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = i0 + e < R ? tot[h][e] : 0.0;
+            if (rd.init >= 0) {
+                const f32x4 t = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(n) * Rp + i0);
+                v[0] += t.x; v[1] += t.y; v[2] += t.z; v[3] += t.w;
+            }
+            float *o = ((rd.sel & ROW_OUT_P) ? g.out_pts : g.out_tree) + rd.out + int64_t(n) * Rp + i0;
+            *reinterpret_cast<f32x4 *>(o) = f32x4{float(v[0]), float(v[1]), float(v[2]), float(v[3])};
+        }
+    }
+}
+
+// The 16-wide block loop with a ring of D block slots (as mm_row_ring).
+template <int KIND, bool LEAF, bool BATCH, int D>
+__device__ inline void mm_row16_ring(const MmArgs &g, int64_t row, int mt, int lane) {
+    const RowDesc rd = g.rows[row];
+    const int R = rd.R;
+    if (32 * mt >= R) return;
+    const int n = lane & 15, kq = lane >> 4;
+    const int nh = 32 * mt + 16 < R ? 2 : 1;   // wave-uniform
+    int ic[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = 32 * mt + 16 * h + n;
+        ic[h] = i < R ? i : R - 1;
+    }
+    const float *xbase = (rd.sel & ROW_IN_X) ? g.in_pts : g.in_tree;
+    auto block_ptr = [&](const BlkDesc &bd) -> const void * {
+        if constexpr (BATCH) return reinterpret_cast<const void *>(bd.a);
+        else return static_cast<const char *>(g.data) + bd.a * (KIND == ELEM_F32 ? 4 : 2);
+    };
+    constexpr int NCH = chunks16<KIND>();
+
+    double tot[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tot[h][e] = 0.0;
+
+    BlockA16<KIND> a[D];
+    TileB16 b[D];
+    BlkDesc bd[D];
+    const int nb = rd.b1 - rd.b0;
+    if (nb > 0) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+            const bool live = s < nb;   // wave-uniform
+            bd[s] = g.blks[rd.b0 + (live ? s : 0)];
+            const void *blk = block_ptr(bd[s]);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) load_chunk16<KIND>(bd[s], blk, xbase, R, ic, n, kq, c, live, a[s], b[s]);
+        }
+    }
+    auto step = [&](const int s, const int k) {
+        const bool refill = k + D < nb;
+        const BlkDesc nx = g.blks[rd.b0 + (refill ? k + D : k)];
+        const int np = used_chunks16<KIND>(bd[s].C);
+        const int Cp = round16(bd[s].C);
+        const void *nblk = block_ptr(nx);
+        f32x4 acc[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c < np) chunk_products16<KIND>(a[s], b[s], c, Cp, nh, kq, acc);
+            load_chunk16<KIND>(nx, nblk, xbase, R, ic, n, kq, c, refill, a[s], b[s]);
+        }
+        const double sc = KIND == ELEM_BF16 ? double(g.scales[bd[s].sidx]) : 1.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            tot[h][0] += sc * double(acc[h].x);
+            tot[h][1] += sc * double(acc[h].y);
+            tot[h][2] += sc * double(acc[h].z);
+            tot[h][3] += sc * double(acc[h].w);
+        }
+        bd[s] = nx;
+    };
+    int base = 0;
+    for (; base + D <= nb; base += D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) step(s, base + s);
+    }
+#pragma unroll
+    for (int s = 0; s < D - 1; ++s)
+        if (base + s < nb) step(s, base + s);   // wave-uniform
+    __builtin_amdgcn_s_waitcnt(0);   // the dead refills land (see mm_row_ring)
+    mm_store16<LEAF, BATCH>(g, rd, mt, nh, n, kq, tot);
+}
+
+// ---- both halves of a row in one workgroup of two wavefronts, sharing each
+// block's input tile through LDS (32-wide tiles)
+// Each wavefront loads half of the tile (right-hand sides 16*mt .. 16*mt+15)
+// and writes it to the workgroup's LDS buffer; both read the whole tile from
+// there, so the tile crosses the memory pipeline once per block instead of
+// once per wavefront.  LDS rows are padded to kPairLd floats so that the
+// 16-byte reads of consecutive right-hand sides fall in distinct banks.
+constexpr int kPairLd = 68;
+constexpr int kPairBuf = MM_TILE * kPairLd;   // floats per buffer
+
+// Barrier of the two wavefronts ordering only their LDS accesses: a full
+// __syncthreads would also wait for every global load in flight, which would
+// drain the block prefetch at every block.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// This wavefront's half of the tile of block bd: float4 item t*64 + lane of
+// the half's 16 x Cp/4 items (right-hand side 16*mt + q / (Cp/4), columns
+// 4*(q % (Cp/4)) ..), wrapped into range for narrow tiles (duplicates of
+// valid items).  With live == false the loads re-read the first items.
+struct TileHalf {
+    f32x4 v[4];
+};
+__device__ inline void half_index(int Cp, int mt, int lane, int t, int &r, int &c) {
+    const int q4 = Cp >> 2, nq = 16 * q4;
+    int q = lane + 64 * t;
+    q = q < nq ? q : q % nq;
+    r = 16 * mt + q / q4;
+    c = 4 * (q % q4);
+}
+__device__ inline void load_half(const BlkDesc &bd, const float *xbase, int mt, int lane, bool live, TileHalf &h) {
+    const int Cp = round16(bd.C);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        int r, c;
+        half_index(Cp, mt, lane, t, r, c);
+        const float *p = xbase + bd.in + (live ? r * Cp + c : 4 * t);
+        h.v[t] = *reinterpret_cast<const f32x4 *>(p);
+    }
+}
+__device__ inline void store_half(const BlkDesc &bd, int mt, int lane, const TileHalf &h, float *buf) {
+    const int Cp = round16(bd.C);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        int r, c;
+        half_index(Cp, mt, lane, t, r, c);
+        *reinterpret_cast<f32x4 *>(buf + r * kPairLd + c) = h.v[t];
+    }
+}
+
+// Chunk p of the block operand (the block half's part of load_chunk32).
+template <int KIND>
+__device__ inline void load_a_chunk(const BlkDesc &bd, const void *blk, const float *xbase, int R, int ic, int lg,
+                                    int p, bool live, BlockA<KIND> &a) {
+    const int C = bd.C;
+    if constexpr (KIND == ELEM_F32) {
+        const int CW = (C + 3) >> 2, cg = 2 * p + lg, cgc = cg < CW ? cg : CW - 1;
+        const f32x4 *ap = live ? reinterpret_cast<const f32x4 *>(static_cast<const float *>(blk) +
+                                                                 (int64_t(cgc) * R + ic) * 4)
+                               : reinterpret_cast<const f32x4 *>(xbase + bd.in + 4 * p);
+        a.v[p] = load_block_item(ap);
+    } else {
+        const int CW = (C + 7) >> 3, cg = 2 * p + lg, cgc = cg < CW ? cg : CW - 1;
+        const u32x4 *ap = live ? reinterpret_cast<const u32x4 *>(static_cast<const uint16_t *>(blk) +
+                                                                 (int64_t(cgc) * R + ic) * 8)
+                               : reinterpret_cast<const u32x4 *>(xbase + bd.in + 4 * p);
+        a.v[p] = load_block_item(ap);
+    }
+}
+
+// Products of chunk p with the tile operand read from LDS: lane l supplies
+// right-hand side l % 32, columns 8p + 4(l/32) .. + 3 (FP32) or 16p + 8(l/32)
+// .. + 7 (BF16).
+template <int KIND>
+__device__ inline f32x16 chunk_products_lds(const BlockA<KIND> &a_op, const float *buf, int li, int lg, int p,
+                                            f32x16 acc) {
+    if constexpr (KIND == ELEM_F32) {
+        const f32x4 b = *reinterpret_cast<const f32x4 *>(buf + li * kPairLd + 8 * p + 4 * lg);
+        const f32x4 a = a_op.v[p];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
+    } else {
+        const f32x4 *bp = reinterpret_cast<const f32x4 *>(buf + li * kPairLd + 16 * p + 8 * lg);
+        const bf16x8 a = __builtin_bit_cast(bf16x8, a_op.v[p]);
+        bf16x8 hi, mid, lo;
+        split3(bp[0], bp[1], hi, mid, lo);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, lo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, mid, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hi, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Half mt of a row whose other half runs on the partner wavefront of the
+// workgroup (R > 32).  The block operand uses the ring of mm_row_ring (D
+// slots, refilled chunk by chunk); the tile half of block k + D is loaded at
+// iteration k into th[k % D] and written to LDS buffer (k + D) % 2 at the end
+// of iteration k + D - 1, before the barrier that ends it.  The summation
+// order is that of mm_row (bitwise the same results).
+template <int KIND, bool LEAF, bool BATCH, int D>
+__device__ inline void mm_row_pair(const MmArgs &g, int64_t row, int mt, int lane, float *lds) {
+    const RowDesc rd = g.rows[row];
+    const int R = rd.R;
+    const int li = lane & 31, lg = lane >> 5;
+    const int i = 32 * mt + li;
+    const int ic = i < R ? i : R - 1;
+    const float *xbase = (rd.sel & ROW_IN_X) ? g.in_pts : g.in_tree;
+    auto block_ptr = [&](const BlkDesc &bd) -> const void * {
+        if constexpr (BATCH) return reinterpret_cast<const void *>(bd.a);
+        else return static_cast<const char *>(g.data) + bd.a * (KIND == ELEM_F32 ? 4 : 2);
+    };
+    constexpr int NCH = chunks32<KIND>();
+
+    double tot[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) tot[r] = 0.0;
+
+    BlockA<KIND> a[D];
+    TileHalf th[D];
+    BlkDesc bd[D];
+    const int nb = rd.b1 - rd.b0;
+    if (nb > 0) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+            const bool live = s < nb;   // wave-uniform
+            bd[s] = g.blks[rd.b0 + (live ? s : 0)];
+            load_half(bd[s], xbase, mt, lane, live, th[s]);
+            const void *blk = block_ptr(bd[s]);
+#pragma unroll
+            for (int p = 0; p < NCH; ++p) load_a_chunk<KIND>(bd[s], blk, xbase, R, ic, lg, p, live, a[s]);
+        }
+        store_half(bd[0], mt, lane, th[0], lds);
+    }
+    lds_barrier();
+    // block k from slot s and LDS buffer k % 2; then the tile half of block
+    // k + 1 goes to the other buffer
+    auto step = [&](const int s, const int k) {
+        const bool refill = k + D < nb;
+        const BlkDesc nx = g.blks[rd.b0 + (refill ? k + D : k)];
+        load_half(nx, xbase, mt, lane, refill, th[s]);
+        const int np = used_chunks32<KIND>(bd[s].C);
+        const void *nblk = block_ptr(nx);
+        const float *buf = lds + (k & 1) * kPairBuf;
+        f32x16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+        for (int p = 0; p < NCH; ++p) {
+            if (p < np) acc = chunk_products_lds<KIND>(a[s], buf, li, lg, p, acc);
+            load_a_chunk<KIND>(nx, nblk, xbase, R, ic, lg, p, refill, a[s]);
+        }
+        const double sc = KIND == ELEM_BF16 ? double(g.scales[bd[s].sidx]) : 1.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tot[r] += sc * double(acc[r]);
+        bd[s] = nx;
+        if (k + 1 < nb) {   // wave-uniform: the tile half of block k + 1 (slot (s + 1) % D)
+            const int s1 = (s + 1) % D;
+            store_half(bd[s1], mt, lane, th[s1], lds + ((k + 1) & 1) * kPairBuf);
+        }
+        lds_barrier();
+    };
+    int base = 0;
+    for (; base + D <= nb; base += D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) step(s, base + s);
+    }
+#pragma unroll
+    for (int s = 0; s < D - 1; ++s)
+        if (base + s < nb) step(s, base + s);   // wave-uniform (the same on both wavefronts)
+    __builtin_amdgcn_s_waitcnt(0);   // the dead refills land (see mm_row_ring)
+    mm_store32<LEAF, BATCH>(g, rd, mt, li, lg, tot);
+}
+
+// Two wavefronts per workgroup, one work unit (two items) each: both halves
+// of one row (R > 32) share their tiles through LDS; otherwise the items are
+// independent and each wavefront runs mm_row_ring alone.  The choice is the
+// same on both wavefronts (they read the same two items), so the barriers of
+// mm_row_pair are met by both.
+template <int KIND, bool LEAF, bool BATCH, int D, bool PERSIST>
+__device__ inline void mm_pair_body(const MmArgs &g) {
+    __shared__ float lds[2 * kPairBuf];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t nwg = g.nitems >> 1;
+    auto unit = [&](int64_t wg) {
+        const int32_t it0 = __builtin_amdgcn_readfirstlane(g.items[wg * 2]);
+        const int32_t it1 = __builtin_amdgcn_readfirstlane(g.items[wg * 2 + 1]);
+        const int32_t it = wv ? it1 : it0;
+        if (it0 >= 0 && it1 >= 0 && (it0 >> 1) == (it1 >> 1)) mm_row_pair<KIND, LEAF, BATCH, D>(g, it >> 1, it & 1, lane, lds);
+        else if (it >= 0) mm_row_ring<KIND, LEAF, BATCH, D>(g, it >> 1, it & 1, lane);
+    };
+    if constexpr (PERSIST) {
+        for (int64_t wg = blockIdx.x; wg < nwg; wg += gridDim.x) unit(wg);
+    } else {
+        unit(blockIdx.x);
+    }
+}
+
 // One wavefront per work item (a 32-row half of an output row segment), 4
 // per workgroup, in the dispatch order laid out by the host.  PERSIST: the
 // grid strides over the list's workgroups (fewer workgroups than slots; a
 // grid that is a multiple of the XCD count keeps each workgroup on its XCD's
 // range); otherwise one workgroup per 4 items.
-template <int KIND, bool LEAF, bool BATCH, bool PIPE, bool PERSIST, int NT>
+template <int KIND, bool LEAF, bool BATCH, int PIPE, bool PERSIST, int NT>
 __device__ inline void mm_body(const MmArgs &g) {
+    if constexpr (PIPE >= 4) {   // 32-wide tiles shared by the two halves of a row
+        static_assert(NT == 32, "tile sharing runs 32-wide tiles");
+        mm_pair_body<KIND, LEAF, BATCH, PIPE - 3, PERSIST>(g);
+        return;
+    }
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t nwg = g.nitems >> 2;
     auto one = [&](int32_t it) {
-        if constexpr (NT == 16) mm_row16<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
-        else mm_row<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
+        if constexpr (NT == 16) {
+            if constexpr (PIPE >= 2) mm_row16_ring<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
+            else mm_row16<KIND, LEAF, BATCH, PIPE == 1>(g, it >> 1, it & 1, lane);
+        } else {
+            if constexpr (PIPE >= 2) mm_row_ring<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
+            else mm_row<KIND, LEAF, BATCH, PIPE == 1>(g, it >> 1, it & 1, lane);
+        }
     };
     if constexpr (PERSIST) {
         for (int64_t wg = blockIdx.x; wg < nwg; wg += gridDim.x) {
-            const int32_t it = g.items[wg * 4 + wv];
+            // wave-uniform by construction; said explicitly so that the row's
+            // descriptors are read with scalar loads (a vector load of a
+            // descriptor would make every wait in the row a wait for all loads)
+            const int32_t it = __builtin_amdgcn_readfirstlane(g.items[wg * 4 + wv]);
             if (it >= 0) one(it);
         }
     } else {
@@ -506,9 +1090,18 @@ __device__ inline void mm_body(const MmArgs &g) {
 // One kernel name per phase, so that traces attribute time to phases:
 // leaf projection + upsweep and downsweep (FP32 bases), coupling + dense
 // streaming (block kind), leaf expansion + FP64 sum.
+// The descriptor arrays also come as __restrict__ parameters: the kernel never
+// writes them, and saying so lets the compiler read them with scalar loads
+// inside a persistent workgroup's loop, whose stores it could not otherwise
+// tell apart from them.
 #define H2_MM_PHASE_KERNEL(NAME, LEAF)                                                   \
-    template <int KIND, bool BATCH, bool PIPE, bool PERSIST, int NT>                     \
-    __global__ __launch_bounds__(256) void NAME(MmArgs g) {                              \
+    template <int KIND, bool BATCH, int PIPE, bool PERSIST, int NT>                      \
+    __global__ __launch_bounds__(256) void NAME(MmArgs g, const RowDesc *__restrict__ rows, \
+                                                const BlkDesc *__restrict__ blks,       \
+                                                const int32_t *__restrict__ items) {    \
+        g.rows = rows;                                                                   \
+        g.blks = blks;                                                                   \
+        g.items = items;                                                                 \
         mm_body<KIND, LEAF, BATCH, PIPE, PERSIST, NT>(g);                                \
     }
 H2_MM_PHASE_KERNEL(mm_upsweep_kernel, false)
@@ -546,31 +1139,46 @@ hipError_t launch_pack(const double *X, int64_t ldx, int j0, int nrhs, const int
     return hipGetLastError();
 }
 
-template <bool BATCH, bool PIPE, bool PERSIST, int NT>
+template <bool BATCH, int PIPE, bool PERSIST, int NT>
 static void launch_phase_nt(const MmArgs &g, int kind, int phase, unsigned grid, hipStream_t st) {
-    const dim3 gd(grid), bd(256);
+    const dim3 gd(grid), bd(PIPE >= 4 ? 128 : 256);   // tile sharing: two wavefronts per workgroup
     switch (phase) {
     case PHASE_UP:
-        hipLaunchKernelGGL((mm_upsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g);
+        hipLaunchKernelGGL((mm_upsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items);
         break;
     case PHASE_DOWN:
-        hipLaunchKernelGGL((mm_downsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g);
+        hipLaunchKernelGGL((mm_downsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items);
         break;
     case PHASE_LEAF:
-        hipLaunchKernelGGL((mm_leafexpand_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g);
+        hipLaunchKernelGGL((mm_leafexpand_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items);
         break;
     default:
         if (kind == ELEM_F32)
-            hipLaunchKernelGGL((mm_stream_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g);
+            hipLaunchKernelGGL((mm_stream_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items);
         else
-            hipLaunchKernelGGL((mm_stream_kernel<ELEM_BF16, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g);
+            hipLaunchKernelGGL((mm_stream_kernel<ELEM_BF16, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items);
     }
 }
 
-template <bool BATCH, bool PIPE, bool PERSIST>
-static void launch_phase(const MmArgs &g, int kind, int phase, int nt, unsigned grid, hipStream_t st) {
+template <bool BATCH, int PIPE, bool PERSIST>
+static void launch_phase_p(const MmArgs &g, int kind, int phase, int nt, unsigned grid, hipStream_t st) {
     if (nt == 16) launch_phase_nt<BATCH, PIPE, PERSIST, 16>(g, kind, phase, grid, st);
     else launch_phase_nt<BATCH, PIPE, PERSIST, 32>(g, kind, phase, grid, st);
+}
+
+// depth: 0 plain block loop, 1 one block ahead, 2 and 3 rings of that many
+// block slots; 4 and 5 the ring of 1 or 2 slots with the two halves of a row
+// sharing the tile (workgroups of two wavefronts over the pair list).
+template <bool BATCH, bool PERSIST>
+static void launch_phase(const MmArgs &g, int kind, int phase, int nt, int depth, unsigned grid, hipStream_t st) {
+    switch (depth) {
+        case 0: launch_phase_p<BATCH, 0, PERSIST>(g, kind, phase, nt, grid, st); break;
+        case 1: launch_phase_p<BATCH, 1, PERSIST>(g, kind, phase, nt, grid, st); break;
+        case 2: launch_phase_p<BATCH, 2, PERSIST>(g, kind, phase, nt, grid, st); break;
+        case 3: launch_phase_p<BATCH, 3, PERSIST>(g, kind, phase, nt, grid, st); break;
+        case 4: launch_phase_nt<BATCH, 4, PERSIST, 32>(g, kind, phase, grid, st); break;
+        default: launch_phase_nt<BATCH, 5, PERSIST, 32>(g, kind, phase, grid, st); break;
+    }
 }
 
 hipError_t launch_mm(const MmLaunch &L, int kind, int phase, const MmConfig &cfg, hipStream_t st) {
@@ -578,12 +1186,14 @@ hipError_t launch_mm(const MmLaunch &L, int kind, int phase, const MmConfig &cfg
     if (L.nitems % (4 * MM_XCDS) != 0) return hipErrorInvalidValue;
     if (phase != PHASE_STREAM && kind != ELEM_F32) return hipErrorInvalidValue;   // bases are FP32
     if (L.ncols < 1 || L.ncols > MM_TILE) return hipErrorInvalidValue;
-    MmArgs g{L.rows, L.items, L.nitems, L.blks, L.data, L.scales, L.in_tree, L.in_pts, L.init, L.out_tree,
-             L.out_pts, L.Y, L.ldy, nullptr, nullptr, L.ncols};
-    const unsigned grid = unsigned(L.nitems / 4);
-    const int nt = L.ncols <= 16 ? 16 : 32;
-    if (cfg.pipelined) launch_phase<false, true, false>(g, kind, phase, nt, grid, st);
-    else launch_phase<false, false, false>(g, kind, phase, nt, grid, st);
+    const bool pair = cfg.pipelined >= 4;
+    if (pair && (L.npitems <= 0 || L.npitems % (2 * MM_XCDS) != 0)) return hipErrorInvalidValue;
+    MmArgs g{L.rows, pair ? L.pitems : L.items, pair ? L.npitems : L.nitems, L.blks, L.data, L.scales, L.in_tree,
+             L.in_pts, L.init, L.out_tree, L.out_pts, L.Y, L.ldy, nullptr, nullptr, L.ncols};
+    const int nt = cfg.nt == 32 || L.ncols > 16 ? 32 : 16;
+    const int64_t slots = pair ? L.npitems / 2 : L.nitems / 4;
+    if (cfg.grid > 0 && cfg.grid < slots) launch_phase<false, true>(g, kind, phase, nt, cfg.pipelined, unsigned(cfg.grid), st);
+    else launch_phase<false, false>(g, kind, phase, nt, cfg.pipelined, unsigned(slots), st);
     return hipGetLastError();
 }
 
@@ -591,20 +1201,15 @@ hipError_t launch_mm_batch(const MmBatchLaunch &L, int kind, int phase, const Mm
     if (L.nitems <= 0) return hipSuccess;
     if (L.nitems % (4 * MM_XCDS) != 0) return hipErrorInvalidValue;
     if (phase != PHASE_STREAM && kind != ELEM_F32) return hipErrorInvalidValue;
-    MmArgs g{L.rows, L.items, L.nitems, L.blks, nullptr, L.scales, L.pool, L.pool, L.pool, L.pool, L.pool,
-             nullptr, 0, L.Ytab, L.ldytab, L.ncols};
+    const bool pair = cfg.pipelined >= 4;
+    if (pair && (L.npitems <= 0 || L.npitems % (2 * MM_XCDS) != 0)) return hipErrorInvalidValue;
+    MmArgs g{L.rows, pair ? L.pitems : L.items, pair ? L.npitems : L.nitems, L.blks, nullptr, L.scales, L.pool,
+             L.pool, L.pool, L.pool, L.pool, nullptr, 0, L.Ytab, L.ldytab, L.ncols};
     if (L.ncols < 1 || L.ncols > MM_TILE) return hipErrorInvalidValue;
-    const int nt = L.ncols <= 16 ? 16 : 32;
-    const int64_t slots = L.nitems / 4;
-    if (cfg.grid > 0 && cfg.grid < slots) {
-        const unsigned grid = unsigned(cfg.grid);
-        if (cfg.pipelined) launch_phase<true, true, true>(g, kind, phase, nt, grid, st);
-        else launch_phase<true, false, true>(g, kind, phase, nt, grid, st);
-    } else {
-        const unsigned grid = unsigned(slots);
-        if (cfg.pipelined) launch_phase<true, true, false>(g, kind, phase, nt, grid, st);
-        else launch_phase<true, false, false>(g, kind, phase, nt, grid, st);
-    }
+    const int nt = cfg.nt == 32 || L.ncols > 16 ? 32 : 16;
+    const int64_t slots = pair ? L.npitems / 2 : L.nitems / 4;
+    if (cfg.grid > 0 && cfg.grid < slots) launch_phase<true, true>(g, kind, phase, nt, cfg.pipelined, unsigned(cfg.grid), st);
+    else launch_phase<true, false>(g, kind, phase, nt, cfg.pipelined, unsigned(slots), st);
     return hipGetLastError();
 }
 

@@ -129,6 +129,8 @@ void run_tile_pass(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64
             L.rows = w.rows;
             L.items = w.items;
             L.nitems = w.nitems;
+            L.pitems = w.pitems;
+            L.npitems = w.npitems;
             L.blks = w.blks;
             L.data = w.data;
             L.scales = A.scales;

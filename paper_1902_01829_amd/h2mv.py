@@ -12,7 +12,8 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libh2mv.so")
+# H2MV_LIBRARY names another build of the library (the sanitizer test's)
+LIB_PATH = os.environ.get("H2MV_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libh2mv.so")
 
 H2_OK, H2_ERR_INVALID_ARG, H2_ERR_OOM, H2_ERR_DEVICE, H2_ERR_UNSUPPORTED, H2_ERR_INTERNAL = range(6)
 H2_FP64, H2_FP32, H2_BF16_SCALED = 0, 1, 2
@@ -23,7 +24,7 @@ STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
 # Every function declared in include/h2mv.h.
 EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_orthogonalize", "h2_compress", "h2_transpose", "h2_matvec", "h2_matvec_noalloc", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
            "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_batch_create", "h2_batch_matmat",
-           "h2_batch_tuning", "h2_batch_free", "h2_last_error")
+           "h2_batch_tuning", "h2_batch_set_tuning", "h2_matmat_tuning", "h2_matmat_set_tuning", "h2_batch_free", "h2_last_error")
 
 
 class h2_params(C.Structure):
@@ -92,7 +93,12 @@ def lib():
         L.h2_profile_read.argtypes = [vp, vp, C.POINTER(i64)]
         L.h2_batch_create.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(vp)]
         L.h2_batch_matmat.argtypes = [vp, vp, vp, vp, vp, vp]
-        L.h2_batch_tuning.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(i64), C.POINTER(C.c_double)]
+        L.h2_batch_tuning.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(i64), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_double)]
+        L.h2_batch_set_tuning.argtypes = [vp, C.c_int, i64, C.c_int]
+        L.h2_matmat_tuning.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(i64), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_double)]
+        L.h2_matmat_set_tuning.argtypes = [vp, C.c_int, C.c_int, i64, C.c_int]
         L.h2_batch_free.argtypes = [vp]
         L.h2_batch_free.restype = None
         L.h2_last_error.argtypes = []
@@ -280,9 +286,23 @@ def h2_batch_matmat(batch, X_ptrs, ldx, Y_ptrs, ldy, stream=0):
 
 
 def h2_batch_tuning(batch):
-    p, g, ms = C.c_int(), C.c_int64(), C.c_double()
-    _check(lib().h2_batch_tuning(C.c_void_p(batch), C.byref(p), C.byref(g), C.byref(ms)))
-    return {"pipelined": p.value, "grid": g.value, "tuned_ms": ms.value}
+    p, g, nt, ms = C.c_int(), C.c_int64(), C.c_int(), C.c_double()
+    _check(lib().h2_batch_tuning(C.c_void_p(batch), C.byref(p), C.byref(g), C.byref(nt), C.byref(ms)))
+    return {"pipelined": p.value, "grid": g.value, "tile_width": nt.value, "tuned_ms": ms.value}
+
+
+def h2_batch_set_tuning(batch, pipelined, grid, tile_width):
+    _check(lib().h2_batch_set_tuning(C.c_void_p(batch), pipelined, grid, tile_width))
+
+
+def h2_matmat_set_tuning(h, narrow, pipelined, grid, tile_width):
+    _check(lib().h2_matmat_set_tuning(C.c_void_p(h), narrow, pipelined, grid, tile_width))
+
+
+def h2_matmat_tuning(h, narrow):
+    p, g, nt, ms = C.c_int(), C.c_int64(), C.c_int(), C.c_double()
+    _check(lib().h2_matmat_tuning(C.c_void_p(h), narrow, C.byref(p), C.byref(g), C.byref(nt), C.byref(ms)))
+    return {"pipelined": p.value, "grid": g.value, "tile_width": nt.value, "tuned_ms": ms.value}
 
 
 def h2_batch_free(batch):
@@ -324,6 +344,9 @@ class H2Batch:
 
     def tuning(self):
         return h2_batch_tuning(self.handle)
+
+    def set_tuning(self, pipelined, grid, tile_width):
+        h2_batch_set_tuning(self.handle, pipelined, grid, tile_width)
 
 
 class H2Matrix:
@@ -400,6 +423,12 @@ class H2Matrix:
         y = out if out is not None else torch.empty_like(x)
         h2_matvec(self.handle, x.data_ptr(), y.data_ptr(), self._stream())
         return y
+
+    def matmat_tuning(self, narrow=0):
+        return h2_matmat_tuning(self.handle, narrow)
+
+    def set_matmat_tuning(self, narrow, pipelined, tile_width, grid=0):
+        h2_matmat_set_tuning(self.handle, narrow, pipelined, grid, tile_width)
 
     def matmat(self, X, out=None):
         """X: float64 CUDA tensor (nrhs, n) (each row one right-hand side, i.e.

@@ -176,3 +176,46 @@ def test_matmat_rejects_bad_sizes():
     with pytest.raises(h2mv.H2Error):
         h2mv.h2_matmat(A.handle, 0, w.n, Y.data_ptr(), w.n, 2, st)
     A.close()
+
+
+SHAPE_CASES = [
+    W.C1.with_(name="2d-n20000-m64-p8", n=20000, leaf=64, cheb_p=8, seed=82),
+    W.C1.with_(name="3d-n3000-m24-p3", n=3000, dim=3, leaf=24, cheb_p=3, corr_len=0.2, seed=77),
+]
+
+
+@pytest.mark.parametrize("storage", [1, 2], ids=["fp32", "bf16"])
+@pytest.mark.parametrize("w", SHAPE_CASES, ids=lambda w: w.name)
+def test_matmat_every_launch_shape(oracle_mod, w, storage):
+    """Each launch shape the tuner may pick (prefetch depth 0..3, and 4..5
+    with a row's halves sharing tiles; one workgroup per item group or a
+    persistent grid; 16- or 32-wide tiles for passes of at most 16
+    right-hand sides), on full-width
+    (64 x 64) and ragged (27- and 23-column) blocks: results equal bitwise
+    across depths for one tile width (the sums run in the same order), and
+    every shape matches the oracle on the same dequantized values."""
+    print(f"case {w.name} storage {storage}", flush=True)
+    A = _build(w, storage)
+    oq = oracle_mod.OracleH2(W.points(w), w.leaf, w.cheb_p, w.eta, w.corr_len, storage=storage,
+                             keep_blocks=False)
+    for nrhs in (8, 32):
+        X = _rhs(w.n, nrhs, 500 + nrhs)
+        Xd = torch.from_numpy(X).cuda()
+        refs = {j: oq.matvec(X[j]) for j in (0, nrhs - 1)}
+        narrow = 1 if nrhs <= 16 else 0
+        for tw in ((16, 32) if narrow else (32,)):
+            first = None
+            for depth in range(6 if tw == 32 else 4):
+                for grid in (0, 256):
+                    A.set_matmat_tuning(narrow, depth, tw, grid)
+                    Y = A.matmat(Xd)
+                    torch.cuda.synchronize()
+                    if first is None:
+                        first = Y
+                    else:
+                        assert torch.equal(Y, first), (nrhs, tw, depth, grid)
+                    Yh = Y.cpu().numpy()
+                    for j, ref in refs.items():
+                        rel = np.linalg.norm(Yh[j] - ref) / np.linalg.norm(ref)
+                        assert rel <= MM_VS_DEQUANT_TOL, (nrhs, tw, depth, grid, j, rel)
+    A.close()
