@@ -397,6 +397,15 @@ h2_status h2_batch_tuning(h2_batch B, int *pipelined, int64_t *grid, int *tile_w
 h2_status h2_batch_set_tuning(h2_batch B, int pipelined, int64_t grid, int tile_width);
 void h2_batch_free(h2_batch B);   /* NULL is a no-op; wait for running products first */
 
+/* Measurement aid: a plain streaming read of bytes (a positive multiple of
+ * 16) at buf (device) by grid (1 .. 65536) workgroups of 256 threads, with
+ * the 16-byte non-temporal loads of the product kernels (each wavefront load
+ * one contiguous kilobyte); the measured rate is the HBM read ceiling the
+ * products are compared with.  sink: device, grid 8-byte values written (an
+ * XOR of the data, so the loads cannot be dropped).  Asynchronous on stream.
+ * Errors: INVALID_ARG; DEVICE. */
+h2_status h2_read_probe(const void *buf, int64_t bytes, int grid, void *sink, void *stream);
+
 /* Text of the last failure on this thread ("" if none). */
 const char *h2_last_error(void);
 

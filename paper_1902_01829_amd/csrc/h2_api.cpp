@@ -69,4 +69,17 @@ h2_status h2_get_level_bsr(h2_handle A, int level, int64_t *count, int32_t *rowp
     return H2_OK;
 }
 
+h2_status h2_read_probe(const void *buf, int64_t bytes, int grid, void *sink, void *stream) {
+    try {
+        if (!buf || !sink) fail(H2_ERR_INVALID_ARG, "NULL argument");
+        if (bytes < 16 || bytes % 16 != 0) fail(H2_ERR_INVALID_ARG, "bytes must be a positive multiple of 16");
+        if (grid < 1 || grid > 65536) fail(H2_ERR_INVALID_ARG, "grid must be in [1, 65536]");
+        check_hip(h2::launch_read_probe(buf, bytes, grid, sink, static_cast<hipStream_t>(stream)), "read probe");
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    }
+}
+
 }  // extern "C"

@@ -692,4 +692,45 @@ hipError_t launch_blockrow(const RowLaunch &L, int kind, bool vec_f64, int phase
                     : run_blockrow<ELEM_BF16, float, float>(L, phase, st);
 }
 
+namespace {
+
+// A plain streaming read: consecutive lanes take consecutive 16-byte items
+// (each wavefront load is one contiguous kilobyte, like the product kernels'),
+// non-temporal, eight in flight per lane, grid-strided; one XOR per workgroup
+// reaches sink so that the loads stay.
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(256) void read_probe_kernel(const u64x2 *__restrict__ p, int64_t n16,
+                                                         unsigned long long *__restrict__ sink) {
+    __shared__ unsigned long long part[256];
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    unsigned long long acc = 0;
+    for (; i + 7 * stride < n16; i += 8 * stride) {
+        u64x2 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = __builtin_nontemporal_load(p + i + k * stride);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc ^= v[k].x ^ v[k].y;
+    }
+    for (; i < n16; i += stride) {
+        const u64x2 v = __builtin_nontemporal_load(p + i);
+        acc ^= v.x ^ v.y;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < 256; ++k) t ^= part[k];
+        sink[blockIdx.x] = t;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_read_probe(const void *buf, int64_t bytes, int grid, void *sink, hipStream_t st) {
+    hipLaunchKernelGGL(read_probe_kernel, dim3(unsigned(grid)), dim3(256), 0, st, static_cast<const u64x2 *>(buf),
+                       bytes / 16, static_cast<unsigned long long *>(sink));
+    return hipGetLastError();
+}
+
 }  // namespace h2

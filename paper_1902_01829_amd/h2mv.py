@@ -24,7 +24,7 @@ STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
 # Every function declared in include/h2mv.h.
 EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_orthogonalize", "h2_compress", "h2_transpose", "h2_matvec", "h2_matvec_noalloc", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
            "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_batch_create", "h2_batch_matmat",
-           "h2_batch_tuning", "h2_batch_set_tuning", "h2_matmat_tuning", "h2_matmat_set_tuning", "h2_batch_free", "h2_last_error")
+           "h2_batch_tuning", "h2_batch_set_tuning", "h2_matmat_tuning", "h2_matmat_set_tuning", "h2_batch_free", "h2_read_probe", "h2_last_error")
 
 
 class h2_params(C.Structure):
@@ -99,6 +99,7 @@ def lib():
         L.h2_matmat_tuning.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(i64), C.POINTER(C.c_int),
                                        C.POINTER(C.c_double)]
         L.h2_matmat_set_tuning.argtypes = [vp, C.c_int, C.c_int, i64, C.c_int]
+        L.h2_read_probe.argtypes = [vp, i64, C.c_int, vp, vp]
         L.h2_batch_free.argtypes = [vp]
         L.h2_batch_free.restype = None
         L.h2_last_error.argtypes = []
@@ -303,6 +304,10 @@ def h2_matmat_tuning(h, narrow):
     p, g, nt, ms = C.c_int(), C.c_int64(), C.c_int(), C.c_double()
     _check(lib().h2_matmat_tuning(C.c_void_p(h), narrow, C.byref(p), C.byref(g), C.byref(nt), C.byref(ms)))
     return {"pipelined": p.value, "grid": g.value, "tile_width": nt.value, "tuned_ms": ms.value}
+
+
+def h2_read_probe(buf_ptr, nbytes, grid, sink_ptr, stream=0):
+    _check(lib().h2_read_probe(C.c_void_p(buf_ptr), nbytes, grid, C.c_void_p(sink_ptr), C.c_void_p(stream)))
 
 
 def h2_batch_free(batch):

@@ -125,3 +125,10 @@ def test_build_from_arrays_rejects_wide_leaf():
     with pytest.raises(h2mv.H2Error) as e:
         h2mv.h2_build_from_arrays(a, 0)
     assert e.value.code == h2mv.H2_ERR_UNSUPPORTED
+
+
+def test_read_probe_rejects_bad_arguments():
+    for args in ((0, 16, 1, 8), (8, 16, 1, 0), (8, 8, 1, 8), (8, 24, 1, 8), (8, 16, 0, 8), (8, 16, 70000, 8)):
+        with pytest.raises(h2mv.H2Error) as e:
+            h2mv.h2_read_probe(*args)
+        assert e.value.code == h2mv.H2_ERR_INVALID_ARG
