@@ -686,6 +686,74 @@ def batch_modes(steps, warmup, nleaves=4):
     return out
 
 
+SCHEDULES = (("merged", 0, 0, 1.0), ("streamed", 1, 0, 1.0), ("streamed-cap3", 1, 3, 1.0),
+             ("streamed-cap2", 1, 2, 1.0), ("streamed-cap3-half-late", 1, 3, 0.5),
+             ("streamed-cap3-late", 1, 3, 0.0))
+SCHEDULE_CASES = (W.C1, W.C1.with_(name="2d-n16384-m64-k64", n=1 << 14, leaf=64, cheb_p=8, seed=1011),
+                  W.C1.with_(name="2d-n65536-m64-k64", n=1 << 16, leaf=64, cheb_p=8, seed=1012),
+                  W.C1.with_(name="2d-n262144-m64-k64", n=1 << 18, leaf=64, cheb_p=8, seed=1013),
+                  W.C2, W.C3)
+
+
+def schedule_section(trials=5, cases=SCHEDULE_CASES):
+    """The merged schedule (coupling and near field in one launch after the
+    upsweep) against the streamed one (near field on a second stream, Sec.
+    4.5) at sizes from 4096 to 2^20 points, FP64: time per product (median of
+    `trials` runs of many products each, the schedules interleaved), and the
+    same products replayed from a HIP graph at the smallest size.  All
+    schedules give bitwise the same product (checked here too)."""
+    import torch
+    from paper_1902_01829_amd import h2mv
+    out = {}
+    for w in cases:
+        A = h2mv.H2Matrix(W.points(w), w.dim, w.leaf, w.cheb_p, w.eta, w.corr_len, storage=0)
+        x = torch.from_numpy(np.ascontiguousarray(W.rhs(w)[A.perm()])).cuda()
+        y = torch.empty_like(x)
+        y0 = A.matvec(x)
+        reps = max(5, min(400, int(2e5 / max(1, w.n) * 40)))
+        times = {name: [] for name, *_ in SCHEDULES}
+        for _ in range(trials):
+            for name, sched, cap, early in SCHEDULES:
+                A.set_schedule(sched, cap, early)
+                times[name].append(_time_matvec(A, x, y, reps))
+                if not torch.equal(y, y0):
+                    raise RuntimeError(f"{w.name}: schedule {name} changed the product")
+        med = {k: float(np.median(v)) for k, v in times.items()}
+        res = {"n": w.n, "reps": reps, "trials": trials,
+               "ms": {k: round(v, 5) for k, v in med.items()},
+               "speedup_vs_merged": {k: round(med["merged"] / v, 4) for k, v in med.items() if k != "merged"}}
+        if w.n <= 1 << 14:
+            g_us = {}
+            for name in ("merged", "streamed-cap3"):
+                _, sched, cap, early = next(s for s in SCHEDULES if s[0] == name)
+                A.set_schedule(sched, cap, early)
+                A.matvec(x, out=y)
+                torch.cuda.synchronize()
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    A.matvec(x, out=y)
+                for _ in range(10):
+                    g.replay()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    g.replay()
+                torch.cuda.synchronize()
+                g_us[name] = round((time.perf_counter() - t0) * 1e6 / reps, 2)
+                del g
+                if not torch.equal(y, y0):
+                    raise RuntimeError(f"{w.name}: graph replay of {name} changed the product")
+            res["graph_us"] = g_us
+        best = min(med, key=med.get)
+        log(f"schedule {w.name}: " + ", ".join(f"{k} {v:.4f}" for k, v in med.items()) + f" ms; best {best}"
+            + (f"; graph us {res['graph_us']}" if "graph_us" in res else ""))
+        out[w.name] = res
+        A.close()
+        del x, y, y0
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -698,7 +766,7 @@ def main():
                     help="skip the storage-mode, many-right-hand-side and batch sections")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--only", choices=["small", "modes", "matmat", "batch", "orthogonalize", "compress",
-                                      "transpose", "half", "read"],
+                                      "transpose", "half", "read", "schedule"],
                     default=None,
                     help="run one section alone and print its JSON (for profiling runs); "
                          "the headline line is not printed")
@@ -740,6 +808,8 @@ def main():
             out = transpose_section()
         elif args.only == "read":
             out = read_ceiling()
+        elif args.only == "schedule":
+            out = schedule_section()
         elif args.only == "half":
             cases = HALF_CASES
             if args.half_case:

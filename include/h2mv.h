@@ -292,6 +292,36 @@ h2_status h2_matvec(h2_handle A, const double *x, double *y, void *stream);
 #define H2_NOALLOC_SCRATCH_BYTES (64ll << 20)
 h2_status h2_matvec_noalloc(h2_handle A, const double *x, double *y, void *stream);
 
+/* Schedule of the single-vector products (h2_matvec, h2_matvec_noalloc, and
+ * h2_matmat on FP64 handles) of a handle with full storage.
+ *  H2_SCHEDULE_MERGED (default): after the upsweep, one launch multiplies the
+ *    coupling blocks of every level and the dense near-field blocks.
+ *  H2_SCHEDULE_STREAMED: the near field y_near = D x, which does not need
+ *    x^, runs on a second stream owned by the handle, concurrently with the
+ *    upsweep, the coupling launch and the downsweep; the leaf phase waits for
+ *    it (the overlap of the dense and low-rank parts of Sec. 4.5).  Its rows
+ *    (longest first) are cut where their block count reaches the share
+ *    near_early of the near field's blocks: the first part starts with the
+ *    product, the rest when the coupling launch has finished (so that it
+ *    overlaps the downsweep).  near_wg_per_cu = 0 lets the near-field launch
+ *    fill the machine; c > 0 makes it request enough LDS that at most c of
+ *    its workgroups share a compute unit, so the other stream's launches
+ *    always find room (the paper gives the low-rank stream a higher priority
+ *    instead; stream priorities are not used here).
+ * The result is bitwise the same under both schedules (same rows, same
+ * summation order).  The product's phase events (h2_profile) are recorded on
+ * the caller's stream: under the streamed schedule the stream phase covers
+ * the coupling rows and the leaf phase includes the wait for the near field.
+ * A product under the streamed schedule may be captured into a HIP graph: the
+ * second stream joins the capture through events.  Errors: INVALID_ARG for a
+ * NULL or structure-only handle, an unknown schedule, near_wg_per_cu < 0, or
+ * near_early outside [0, 1]; UNSUPPORTED for H2_SCHEDULE_STREAMED on blocks
+ * stored by halves, or a cap the device's LDS sizes cannot express (the
+ * message gives them; 2 and 3 work on gfx950); DEVICE. */
+#define H2_SCHEDULE_MERGED 0
+#define H2_SCHEDULE_STREAMED 1
+h2_status h2_set_schedule(h2_handle A, int schedule, int near_wg_per_cu, double near_early);
+
 /* Y = A X for nrhs right-hand sides at once: the same phases with every
  * per-node vector replaced by a k x nrhs tile, so each block product becomes a
  * dense contraction.

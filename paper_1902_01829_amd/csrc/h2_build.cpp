@@ -630,6 +630,14 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
         std::stable_sort(L.begin(), L.end(), [](const LRow &a, const LRow &b) { return a.b.size() > b.b.size(); });
         int64_t nblk = 0;
         for (const LRow &r : L) nblk += int64_t(r.b.size());
+        // the streamed schedule's order: coupling rows, then near-field rows
+        std::vector<size_t> order;
+        for (size_t r = 0; r < L.size(); ++r)
+            if (!L[r].point) order.push_back(r);
+        const int64_t ncoup = int64_t(order.size());
+        for (size_t r = 0; r < L.size(); ++r)
+            if (L[r].point) order.push_back(r);
+        std::vector<int64_t> near_cum{0};
         if (int64_t(L.size()) < kSplitRows && nblk > int64_t(L.size())) {
             // few rows: every row cut into chunks of `chunk` blocks, one wavefront
             // each, writing FP64 partial sums that a second launch adds up per row
@@ -637,7 +645,9 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
             std::vector<RowDesc> rows;
             std::vector<BlkDesc> blks;
             std::vector<h2::ReduceDesc> red;
+            std::vector<size_t> first_chunk;   // per row of L: its first chunk in rows
             for (const LRow &r : L) {
+                first_chunk.push_back(rows.size());
                 const int nb = int(r.b.size()), nc = std::max(1, (nb + chunk - 1) / chunk);
                 red.push_back({mv_off(r.point, r.id), int32_t(rows.size()), int32_t(rows.size() + nc), r.R,
                                r.point ? 1 : 0});
@@ -665,9 +675,44 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
             w.nred = int64_t(red.size());
             w.partials_bytes = w.nrows * 64 * 8;
             w.partials = A.mem.alloc(w.partials_bytes);
+            first_chunk.push_back(rows.size());
+            std::vector<RowDesc> srows;
+            std::vector<h2::ReduceDesc> sred;
+            for (size_t o = 0; o < order.size(); ++o) {
+                const size_t r = order[o];
+                for (size_t c = first_chunk[r]; c < first_chunk[r + 1]; ++c) {
+                    srows.push_back(rows[c]);
+                    if (int64_t(o) >= ncoup) near_cum.push_back(near_cum.back() + (rows[c].b1 - rows[c].b0));
+                }
+                sred.push_back(red[r]);
+                if (int64_t(o) + 1 == ncoup) w.nsrows_coupling = int64_t(srows.size());
+            }
+            w.srows = A.mem.upload(srows, stream);
+            w.sred = A.mem.upload(sred, stream);
+            w.nsred_coupling = ncoup;
+            w.near_cum = std::move(near_cum);
             A.lists.push_back(w);
         } else {
             emit_one(0, PH_STREAM, sk, A.blocks, L);
+            std::vector<int64_t> b0(L.size() + 1, 0);
+            for (size_t r = 0; r < L.size(); ++r) b0[r + 1] = b0[r] + int64_t(L[r].b.size());
+            std::vector<RowDesc> srows;
+            for (size_t o = 0; o < order.size(); ++o) {
+                const LRow &r = L[order[o]];
+                RowDesc d;
+                d.out = mv_off(r.point, r.id);
+                d.init = -1;
+                d.b0 = int32_t(b0[order[o]]);
+                d.b1 = int32_t(b0[order[o] + 1]);
+                d.R = r.R;
+                d.sel = r.sel;
+                srows.push_back(d);
+                if (int64_t(o) >= ncoup) near_cum.push_back(near_cum.back() + int64_t(r.b.size()));
+            }
+            WorkList &w = A.lists.back();
+            w.srows = A.mem.upload(srows, stream);
+            w.nsrows_coupling = ncoup;
+            w.near_cum = std::move(near_cum);
         }
         L.clear();
     }

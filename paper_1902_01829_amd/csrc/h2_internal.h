@@ -114,6 +114,16 @@ struct WorkList {
     // stream list of a matrix stored by halves: partial slot of every block
     // (-1: diagonal block); red then adds the slots to the row sums
     const int32_t *slot = nullptr;
+    // single-vector stream list, full storage: the same rows (chunks, for a
+    // split list) with the coupling rows first and the near-field rows after,
+    // each part in the list's own order, and (split list) the row sums
+    // ordered the same way -- the near field can then run as a launch of its
+    // own (H2_SCHEDULE_STREAMED)
+    const h2::RowDesc *srows = nullptr;
+    int64_t nsrows_coupling = 0;
+    const h2::ReduceDesc *sred = nullptr;
+    int64_t nsred_coupling = 0;
+    std::vector<int64_t> near_cum;   // blocks of the near-field rows of srows, cumulative (size rows + 1)
 };
 
 // A single-vector stream list with fewer block rows than this is split into
@@ -179,6 +189,16 @@ struct h2_matrix_ {
     bool half = false;
     std::vector<int64_t> blk_store;
     int batch_refs = 0;                         // batches holding addresses into this matrix
+    // schedule of the single-vector product (h2_set_schedule): the near field
+    // on the handle's second stream, its launch's LDS request (caps its
+    // workgroups per compute unit; 0: no cap) and the share of its rows
+    // launched at the start of the product (the rest follows the coupling launch)
+    int schedule = H2_SCHEDULE_MERGED;
+    int near_wg_per_cu = 0;
+    int near_lds_bytes = 0;
+    double near_early = 1.0;
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_join = nullptr;
     // profiling: PH_COUNT + 1 events per recorded call
     bool prof = false;
     std::vector<hipEvent_t> pending, spare;
@@ -188,6 +208,9 @@ struct h2_matrix_ {
     ~h2_matrix_() {
         for (hipEvent_t e : pending) (void)hipEventDestroy(e);
         for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+        for (hipEvent_t e : {ev_fork, ev_mid, ev_join})
+            if (e) (void)hipEventDestroy(e);
+        if (aux) (void)hipStreamDestroy(aux);
     }
 };
 

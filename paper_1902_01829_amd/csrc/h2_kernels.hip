@@ -547,19 +547,19 @@ hipError_t run_blockrow(const RowLaunch &L, int phase, hipStream_t st) {
     auto *out1 = static_cast<TO1 *>(L.out1);
     switch (phase) {
         case PHASE_UP:
-            hipLaunchKernelGGL((upsweep_kernel<KIND, TV, TO1>), grid, block, 0, st, L.rows, L.nrows, L.blks, data,
+            hipLaunchKernelGGL((upsweep_kernel<KIND, TV, TO1>), grid, block, L.lds_bytes, st, L.rows, L.nrows, L.blks, data,
                                L.scales, in0, L.in1, init, out0, out1);
             break;
         case PHASE_STREAM:
-            hipLaunchKernelGGL((stream_kernel<KIND, TV, TO1>), grid, block, 0, st, L.rows, L.nrows, L.blks, data,
+            hipLaunchKernelGGL((stream_kernel<KIND, TV, TO1>), grid, block, L.lds_bytes, st, L.rows, L.nrows, L.blks, data,
                                L.scales, in0, L.in1, init, out0, out1);
             break;
         case PHASE_DOWN:
-            hipLaunchKernelGGL((downsweep_kernel<KIND, TV, TO1>), grid, block, 0, st, L.rows, L.nrows, L.blks,
+            hipLaunchKernelGGL((downsweep_kernel<KIND, TV, TO1>), grid, block, L.lds_bytes, st, L.rows, L.nrows, L.blks,
                                data, L.scales, in0, L.in1, init, out0, out1);
             break;
         default:
-            hipLaunchKernelGGL((leafexpand_kernel<KIND, TV, TO1>), grid, block, 0, st, L.rows, L.nrows, L.blks,
+            hipLaunchKernelGGL((leafexpand_kernel<KIND, TV, TO1>), grid, block, L.lds_bytes, st, L.rows, L.nrows, L.blks,
                                data, L.scales, in0, L.in1, init, out0, out1);
             break;
     }

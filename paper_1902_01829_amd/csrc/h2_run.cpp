@@ -65,8 +65,7 @@ void workspace_bytes(const h2_matrix_ &A, int64_t part[4]) {
 void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st, const Workspace *ws) {
     const Workspace own{A.xh, A.yh, A.ynear, nullptr};
     const Workspace &W = ws ? *ws : own;
-    run_lists(A, A.lists, st, [&](const WorkList &w) {
-        void *partials = ws ? ws->partials : w.partials;
+    auto row_launch = [&](const WorkList &w) {
         h2::RowLaunch L;
         L.rows = w.rows;
         L.nrows = w.nrows;
@@ -76,6 +75,71 @@ void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st, cons
         L.in1 = x;
         L.init = nullptr;
         L.out1 = nullptr;
+        return L;
+    };
+    // Streamed schedule: the near-field rows of the stream list run on the
+    // handle's second stream, a share from the start of the product and the
+    // rest after the coupling rows; the leaf phase waits for them.
+    const WorkList *sl = nullptr;
+    if (A.schedule == H2_SCHEDULE_STREAMED)
+        for (const WorkList &w : A.lists)
+            if (w.phase == PH_STREAM && w.srows) sl = &w;
+    int64_t nnear = 0, near_split = 0;
+    auto near_launch = [&](int64_t r0, int64_t r1) {
+        if (r1 <= r0) return;
+        h2::RowLaunch L = row_launch(*sl);
+        L.rows = sl->srows + sl->nsrows_coupling + r0;
+        L.nrows = r1 - r0;
+        L.in0 = W.xh;
+        L.out0 = W.yh;
+        L.out1 = W.ynear;
+        L.lds_bytes = A.near_lds_bytes;
+        if (sl->red) {
+            L.out0 = L.out1 = ws ? ws->partials : sl->partials;
+            check_hip(h2::launch_blockrow(L, sl->kind, A.vec_f64, PH_STREAM, A.aux, 1), "near-field launch");
+        } else {
+            check_hip(h2::launch_blockrow(L, sl->kind, A.vec_f64, PH_STREAM, A.aux), "near-field launch");
+        }
+    };
+    if (sl) {
+        nnear = int64_t(sl->near_cum.size()) - 1;
+        const int64_t target = std::llround(A.near_early * double(sl->near_cum.back()));
+        near_split = std::lower_bound(sl->near_cum.begin(), sl->near_cum.end(), target) - sl->near_cum.begin();
+        near_split = std::min(near_split, nnear);
+        check_hip(hipEventRecord(A.ev_fork, st), "hipEventRecord");
+        check_hip(hipStreamWaitEvent(A.aux, A.ev_fork, 0), "hipStreamWaitEvent");
+        near_launch(0, near_split);
+    }
+    run_lists(A, A.lists, st, [&](const WorkList &w) {
+        void *partials = ws ? ws->partials : w.partials;
+        h2::RowLaunch L = row_launch(w);
+        if (&w == sl) {
+            // coupling rows here; the rest of the near field on the second stream
+            L.rows = sl->srows;
+            L.nrows = sl->nsrows_coupling;
+            L.in0 = W.xh;
+            L.out0 = W.yh;
+            L.out1 = W.ynear;
+            if (w.red) {
+                L.out0 = L.out1 = partials;
+                check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, int(w.phase), st, 1), "blockrow launch");
+                check_hip(h2::launch_reduce_chunks(w.sred, w.nsred_coupling, partials, false, W.yh, W.ynear,
+                                                   A.vec_f64, st),
+                          "chunk sum launch");
+            } else {
+                check_hip(h2::launch_blockrow(L, w.kind, A.vec_f64, int(w.phase), st), "blockrow launch");
+            }
+            check_hip(hipEventRecord(A.ev_mid, st), "hipEventRecord");
+            check_hip(hipStreamWaitEvent(A.aux, A.ev_mid, 0), "hipStreamWaitEvent");
+            near_launch(near_split, nnear);
+            if (w.red)
+                check_hip(h2::launch_reduce_chunks(w.sred + w.nsred_coupling, w.nred - w.nsred_coupling, partials,
+                                                   false, W.yh, W.ynear, A.vec_f64, A.aux),
+                          "chunk sum launch");
+            check_hip(hipEventRecord(A.ev_join, A.aux), "hipEventRecord");
+            return;
+        }
+        if (sl && w.phase == PH_LEAF) check_hip(hipStreamWaitEvent(st, A.ev_join, 0), "hipStreamWaitEvent");
         switch (w.phase) {
             case PH_UP:
                 L.in0 = W.xh;
@@ -213,6 +277,60 @@ h2_status h2_matmat(h2_handle A, const double *X, int64_t ldx, double *Y, int64_
         } else {
             run_tiles(*A, X, ldx, Y, ldy, nrhs, st);
         }
+        return H2_OK;
+    } catch (const Failure &f) {
+        g_last_error = f.what;
+        return f.code;
+    } catch (...) {
+        g_last_error = "internal error";
+        return H2_ERR_INTERNAL;
+    }
+}
+
+h2_status h2_set_schedule(h2_handle A, int schedule, int near_wg_per_cu, double near_early) {
+    try {
+        if (!A) fail(H2_ERR_INVALID_ARG, "NULL handle");
+        if (A->structure_only) fail(H2_ERR_INVALID_ARG, "structure-only handle");
+        if (schedule != H2_SCHEDULE_MERGED && schedule != H2_SCHEDULE_STREAMED)
+            fail(H2_ERR_INVALID_ARG, "unknown schedule");
+        if (near_wg_per_cu < 0) fail(H2_ERR_INVALID_ARG, "near_wg_per_cu must be >= 0");
+        if (!(near_early >= 0.0 && near_early <= 1.0)) fail(H2_ERR_INVALID_ARG, "near_early must be in [0, 1]");
+        if (schedule == H2_SCHEDULE_MERGED) {
+            A->schedule = schedule;
+            return H2_OK;
+        }
+        if (A->half) fail(H2_ERR_UNSUPPORTED, "the streamed schedule needs full storage");
+        int lds_bytes = 0;
+        if (near_wg_per_cu > 0) {
+            // LDS request above 1 / (cap + 1) of a compute unit's LDS: at most
+            // cap of the launch's workgroups fit on one compute unit (the
+            // block-row kernels' own LDS is at most 4 KiB; 1 KiB of slack per
+            // workgroup for the allocation granularity)
+            int dev = 0, lds_cu = 0, lds_wg = 0;
+            check_hip(hipGetDevice(&dev), "hipGetDevice");
+            check_hip(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev),
+                      "hipDeviceGetAttribute");
+            check_hip(hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+                      "hipDeviceGetAttribute");
+            const int64_t own = 4096, pad = int64_t(lds_cu) / (near_wg_per_cu + 1) + 1;
+            if (lds_cu <= 0 || pad + own > lds_wg || int64_t(near_wg_per_cu) * (pad + own + 1024) > lds_cu)
+                fail(H2_ERR_UNSUPPORTED, "near_wg_per_cu = " + std::to_string(near_wg_per_cu) +
+                                             " cannot be set through the LDS request on this device (" +
+                                             std::to_string(lds_cu) + " bytes per compute unit, " +
+                                             std::to_string(lds_wg) + " per workgroup)");
+            lds_bytes = int(pad);
+        }
+        if (!A->aux) {
+            hipStream_t s = nullptr;
+            check_hip(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+            A->aux = s;
+        }
+        for (hipEvent_t *e : {&A->ev_fork, &A->ev_mid, &A->ev_join})
+            if (!*e) check_hip(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreateWithFlags");
+        A->schedule = schedule;
+        A->near_wg_per_cu = near_wg_per_cu;
+        A->near_lds_bytes = lds_bytes;
+        A->near_early = near_early;
         return H2_OK;
     } catch (const Failure &f) {
         g_last_error = f.what;

@@ -20,11 +20,13 @@ H2_FP64, H2_FP32, H2_BF16_SCALED = 0, 1, 2
 H2_FLAG_STRUCTURE_ONLY = 1
 H2_HALF_STORAGE = 16   # OR-ed into a storage value: blocks stored by halves (symmetric matrices)
 STORAGE_NAMES = {H2_FP64: "fp64", H2_FP32: "fp32", H2_BF16_SCALED: "bf16"}
+H2_SCHEDULE_MERGED, H2_SCHEDULE_STREAMED = 0, 1
 
 # Every function declared in include/h2mv.h.
 EXPORTS = ("h2_build_from_points", "h2_build_from_arrays", "h2_export_arrays", "h2_orthogonalize", "h2_compress", "h2_transpose", "h2_matvec", "h2_matvec_noalloc", "h2_matmat", "h2_free", "h2_get_info", "h2_get_perm",
            "h2_get_level_bsr", "h2_profile", "h2_profile_read", "h2_batch_create", "h2_batch_matmat",
-           "h2_batch_tuning", "h2_batch_set_tuning", "h2_matmat_tuning", "h2_matmat_set_tuning", "h2_batch_free", "h2_read_probe", "h2_last_error")
+           "h2_batch_tuning", "h2_batch_set_tuning", "h2_matmat_tuning", "h2_matmat_set_tuning", "h2_batch_free", "h2_read_probe", "h2_set_schedule",
+           "h2_last_error")
 
 
 class h2_params(C.Structure):
@@ -225,6 +227,10 @@ def h2_matvec(h, x_ptr, y_ptr, stream=0):
 
 def h2_matvec_noalloc(h, x_ptr, y_ptr, stream=0):
     _check(lib().h2_matvec_noalloc(C.c_void_p(h), C.c_void_p(x_ptr), C.c_void_p(y_ptr), C.c_void_p(stream)))
+
+
+def h2_set_schedule(h, schedule, near_wg_per_cu=0, near_early=1.0):
+    _check(lib().h2_set_schedule(C.c_void_p(h), int(schedule), int(near_wg_per_cu), C.c_double(near_early)))
 
 
 def h2_matmat(h, X_ptr, ldx, Y_ptr, ldy, nrhs, stream=0):
@@ -431,6 +437,9 @@ class H2Matrix:
 
     def matmat_tuning(self, narrow=0):
         return h2_matmat_tuning(self.handle, narrow)
+
+    def set_schedule(self, schedule, near_wg_per_cu=0, near_early=1.0):
+        h2_set_schedule(self.handle, schedule, near_wg_per_cu, near_early)
 
     def set_matmat_tuning(self, narrow, pipelined, tile_width, grid=0):
         h2_matmat_set_tuning(self.handle, narrow, pipelined, grid, tile_width)

@@ -132,3 +132,16 @@ def test_read_probe_rejects_bad_arguments():
         with pytest.raises(h2mv.H2Error) as e:
             h2mv.h2_read_probe(*args)
         assert e.value.code == h2mv.H2_ERR_INVALID_ARG
+
+
+def test_set_schedule_rejects_without_a_product_handle():
+    with pytest.raises(h2mv.H2Error) as e:
+        h2mv.h2_set_schedule(0, h2mv.H2_SCHEDULE_STREAMED)
+    assert e.value.code == h2mv.H2_ERR_INVALID_ARG
+    h = h2mv.h2_build_from_points(_pts(), 2, 16, 2, 0.9, 0.1, flags=h2mv.H2_FLAG_STRUCTURE_ONLY)
+    try:
+        with pytest.raises(h2mv.H2Error) as e:
+            h2mv.h2_set_schedule(h, h2mv.H2_SCHEDULE_STREAMED)
+        assert e.value.code == h2mv.H2_ERR_INVALID_ARG
+    finally:
+        h2mv.h2_free(h)
