@@ -478,8 +478,8 @@ def half_section(steps, warmup, full_ms=None, nleaves=16, cases=HALF_CASES):
     matrix and the 3-D 2^19-point matrix in its three storage modes.  Time per
     product, stored bytes, the streaming phase (stored blocks read once for
     both products, partial sums, their addition per segment) as GB/s of the
-    bytes it moves, the equivalent bandwidth (full-storage algorithmic bytes
-    over the product time), the speedup over full storage, and the error
+    bytes it moves, the product's GB/s of the bytes it stores, the speedup
+    over full storage, and the error
     against the FP64 oracle on sampled leaves.  full_ms: full-storage times
     by (workload, storage) already measured; the others are measured here.
     cases: the (workload, storage) pairs to run."""
