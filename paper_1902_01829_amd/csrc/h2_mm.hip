@@ -182,6 +182,41 @@ struct MmArgs {
     int ncols;
 };
 
+// A row's block descriptors (and BF16 block scales) held one per lane, the
+// first 64 blocks of the row, and read with lane reads: one vector load at
+// the start of the row instead of a scalar load (and its wait) per block.
+// Blocks past the 64th are read from memory.
+__device__ inline int64_t readlane64(int64_t v, int j) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(uint64_t(v))), j));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(uint64_t(v) >> 32)), j));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+template <int KIND>
+struct LaneDescs {
+    BlkDesc my;
+    float sc = 1.0f;
+    // nb > 0 blocks in the row
+    __device__ void load(const MmArgs &g, const RowDesc &rd, int nb, int lane) {
+        my = g.blks[rd.b0 + (lane < nb ? lane : nb - 1)];
+        if constexpr (KIND == ELEM_BF16) sc = g.scales[my.sidx];
+    }
+    // block k of the row (wave-uniform k)
+    __device__ BlkDesc get(const MmArgs &g, const RowDesc &rd, int k) const {
+        if (k >= 64) return g.blks[rd.b0 + k];
+        BlkDesc b;
+        b.a = readlane64(my.a, k);
+        b.in = readlane64(my.in, k);
+        b.C = __builtin_amdgcn_readlane(my.C, k);
+        b.sidx = __builtin_amdgcn_readlane(my.sidx, k);
+        return b;
+    }
+    __device__ double scale(const MmArgs &g, int k, const BlkDesc &b) const {
+        if constexpr (KIND != ELEM_BF16) return 1.0;
+        if (k >= 64) return double(g.scales[b.sidx]);
+        return double(__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sc), k)));
+    }
+};
+
 // One output row segment half (mt) of the list, for one wavefront.  Lane l
 // owns block row 32*mt + (l % 32) and right-hand side l % 32; for every 8
 // block columns 8p .. 8p+7, lane group g = l / 32 supplies columns 8p + 4g + t
@@ -209,20 +244,23 @@ __device__ inline void mm_row(const MmArgs &g, int64_t row, int mt, int lane) {
         if constexpr (BATCH) return reinterpret_cast<const void *>(bd.a);
         else return static_cast<const char *>(data) + bd.a * (KIND == ELEM_F32 ? 4 : 2);
     };
-    if (rd.b0 < rd.b1) {
-        bd_cur = g.blks[rd.b0];
+    const int nb = rd.b1 - rd.b0;
+    LaneDescs<KIND> ld;
+    if (nb > 0) {
+        ld.load(g, rd, nb, lane);
+        bd_cur = ld.get(g, rd, 0);
         load_a<KIND>(bd_cur, block_ptr(bd_cur), R, ic, lg, a_cur);
         load_b<KIND>(bd_cur, xbase, li, lg, b_cur);
     }
-    for (int b = rd.b0; b < rd.b1; ++b) {
-        const bool more = b + 1 < rd.b1;
+    for (int k = 0; k < nb; ++k) {
+        const bool more = k + 1 < nb;
         if (PIPE && more) {
-            bd_nxt = g.blks[b + 1];
+            bd_nxt = ld.get(g, rd, k + 1);
             load_a<KIND>(bd_nxt, block_ptr(bd_nxt), R, ic, lg, a_nxt);
             load_b<KIND>(bd_nxt, xbase, li, lg, b_nxt);
         }
         const f32x16 acc = block_products<KIND>(a_cur, b_cur, bd_cur.C);
-        const double sc = KIND == ELEM_BF16 ? double(g.scales[bd_cur.sidx]) : 1.0;
+        const double sc = ld.scale(g, k, bd_cur);
 #pragma unroll
         for (int r = 0; r < 16; ++r) tot[r] += sc * double(acc[r]);
         if (more) {
@@ -231,7 +269,7 @@ __device__ inline void mm_row(const MmArgs &g, int64_t row, int mt, int lane) {
                 b_cur = b_nxt;
                 bd_cur = bd_nxt;
             } else {
-                bd_cur = g.blks[b + 1];
+                bd_cur = ld.get(g, rd, k + 1);
                 load_a<KIND>(bd_cur, block_ptr(bd_cur), R, ic, lg, a_cur);
                 load_b<KIND>(bd_cur, xbase, li, lg, b_cur);
             }
@@ -392,11 +430,13 @@ __device__ inline void mm_row_ring(const MmArgs &g, int64_t row, int mt, int lan
     TileB b[D];
     BlkDesc bd[D];
     const int nb = rd.b1 - rd.b0;
+    LaneDescs<KIND> ld;
     if (nb > 0) {
+        ld.load(g, rd, nb, lane);
 #pragma unroll
         for (int s = 0; s < D; ++s) {
             const bool live = s < nb;   // wave-uniform
-            bd[s] = g.blks[rd.b0 + (live ? s : 0)];
+            bd[s] = ld.get(g, rd, live ? s : 0);
             const void *blk = block_ptr(bd[s]);
 #pragma unroll
             for (int p = 0; p < NCH; ++p) load_chunk32<KIND>(bd[s], blk, xbase, R, ic, li, lg, p, live, a[s], b[s]);
@@ -405,7 +445,7 @@ __device__ inline void mm_row_ring(const MmArgs &g, int64_t row, int mt, int lan
     // block k from slot s, whose registers then receive block k + D
     auto step = [&](const int s, const int k) {
         const bool refill = k + D < nb;
-        const BlkDesc nx = g.blks[rd.b0 + (refill ? k + D : k)];
+        const BlkDesc nx = ld.get(g, rd, refill ? k + D : k);
         const int np = used_chunks32<KIND>(bd[s].C);
         const void *nblk = block_ptr(nx);
         f32x16 acc;
@@ -416,7 +456,7 @@ __device__ inline void mm_row_ring(const MmArgs &g, int64_t row, int mt, int lan
             if (p < np) acc = chunk_products32<KIND>(a[s], b[s], p, acc);
             load_chunk32<KIND>(nx, nblk, xbase, R, ic, li, lg, p, refill, a[s], b[s]);
         }
-        const double sc = KIND == ELEM_BF16 ? double(g.scales[bd[s].sidx]) : 1.0;
+        const double sc = ld.scale(g, k, bd[s]);
 #pragma unroll
         for (int r = 0; r < 16; ++r) tot[r] += sc * double(acc[r]);
         bd[s] = nx;
@@ -594,21 +634,24 @@ __device__ inline void mm_row16(const MmArgs &g, int64_t row, int mt, int lane) 
         if constexpr (BATCH) return reinterpret_cast<const void *>(bd.a);
         else return static_cast<const char *>(data) + bd.a * (KIND == ELEM_F32 ? 4 : 2);
     };
-    if (rd.b0 < rd.b1) {
-        bd_cur = g.blks[rd.b0];
+    const int nb = rd.b1 - rd.b0;
+    LaneDescs<KIND> ld;
+    if (nb > 0) {
+        ld.load(g, rd, nb, lane);
+        bd_cur = ld.get(g, rd, 0);
         load_a16<KIND>(bd_cur, block_ptr(bd_cur), R, ic, nh, kq, a_cur);
         load_b16<KIND>(bd_cur, xbase, n, kq, b_cur);
     }
-    for (int b = rd.b0; b < rd.b1; ++b) {
-        const bool more = b + 1 < rd.b1;
+    for (int k = 0; k < nb; ++k) {
+        const bool more = k + 1 < nb;
         if (PIPE && more) {
-            bd_nxt = g.blks[b + 1];
+            bd_nxt = ld.get(g, rd, k + 1);
             load_a16<KIND>(bd_nxt, block_ptr(bd_nxt), R, ic, nh, kq, a_nxt);
             load_b16<KIND>(bd_nxt, xbase, n, kq, b_nxt);
         }
         f32x4 acc[2];
         block_products16<KIND>(a_cur, b_cur, bd_cur.C, nh, kq, acc);
-        const double sc = KIND == ELEM_BF16 ? double(g.scales[bd_cur.sidx]) : 1.0;
+        const double sc = ld.scale(g, k, bd_cur);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             tot[h][0] += sc * double(acc[h].x);
@@ -622,7 +665,7 @@ __device__ inline void mm_row16(const MmArgs &g, int64_t row, int mt, int lane) 
                 b_cur = b_nxt;
                 bd_cur = bd_nxt;
             } else {
-                bd_cur = g.blks[b + 1];
+                bd_cur = ld.get(g, rd, k + 1);
                 load_a16<KIND>(bd_cur, block_ptr(bd_cur), R, ic, nh, kq, a_cur);
                 load_b16<KIND>(bd_cur, xbase, n, kq, b_cur);
             }
@@ -802,11 +845,13 @@ __device__ inline void mm_row16_ring(const MmArgs &g, int64_t row, int mt, int l
     TileB16 b[D];
     BlkDesc bd[D];
     const int nb = rd.b1 - rd.b0;
+    LaneDescs<KIND> ld;
     if (nb > 0) {
+        ld.load(g, rd, nb, lane);
 #pragma unroll
         for (int s = 0; s < D; ++s) {
             const bool live = s < nb;   // wave-uniform
-            bd[s] = g.blks[rd.b0 + (live ? s : 0)];
+            bd[s] = ld.get(g, rd, live ? s : 0);
             const void *blk = block_ptr(bd[s]);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) load_chunk16<KIND>(bd[s], blk, xbase, R, ic, n, kq, c, live, a[s], b[s]);
@@ -814,7 +859,7 @@ __device__ inline void mm_row16_ring(const MmArgs &g, int64_t row, int mt, int l
     }
     auto step = [&](const int s, const int k) {
         const bool refill = k + D < nb;
-        const BlkDesc nx = g.blks[rd.b0 + (refill ? k + D : k)];
+        const BlkDesc nx = ld.get(g, rd, refill ? k + D : k);
         const int np = used_chunks16<KIND>(bd[s].C);
         const int Cp = round16(bd[s].C);
         const void *nblk = block_ptr(nx);
@@ -826,7 +871,7 @@ __device__ inline void mm_row16_ring(const MmArgs &g, int64_t row, int mt, int l
             if (c < np) chunk_products16<KIND>(a[s], b[s], c, Cp, nh, kq, acc);
             load_chunk16<KIND>(nx, nblk, xbase, R, ic, n, kq, c, refill, a[s], b[s]);
         }
-        const double sc = KIND == ELEM_BF16 ? double(g.scales[bd[s].sidx]) : 1.0;
+        const double sc = ld.scale(g, k, bd[s]);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             tot[h][0] += sc * double(acc[h].x);
@@ -867,19 +912,20 @@ __device__ inline void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// This wavefront's half of the tile of block bd: float4 item t*64 + lane of
-// the half's 16 x Cp/4 items (right-hand side 16*mt + q / (Cp/4), columns
-// 4*(q % (Cp/4)) ..), wrapped into range for narrow tiles (duplicates of
-// valid items).  With live == false the loads re-read the first items.
+// This wavefront's half of the tile of block bd: load t of lane l takes
+// right-hand side 16*mt + 4t + l/16 and columns 4*(l % 16) .. + 3, the
+// column group clamped to the tile's last one for narrow tiles (duplicates
+// of valid items, written to the same LDS place).  With live == false the
+// loads re-read the first items.  (Shifts and masks only: this index math
+// runs for every block, and the matrix cores leave the vector ALU little
+// room.)
 struct TileHalf {
     f32x4 v[4];
 };
 __device__ inline void half_index(int Cp, int mt, int lane, int t, int &r, int &c) {
-    const int q4 = Cp >> 2, nq = 16 * q4;
-    int q = lane + 64 * t;
-    q = q < nq ? q : q % nq;
-    r = 16 * mt + q / q4;
-    c = 4 * (q % q4);
+    const int cg = lane & 15, last = (Cp >> 2) - 1;
+    r = 16 * mt + 4 * t + (lane >> 4);
+    c = 4 * (cg < last ? cg : last);
 }
 __device__ inline void load_half(const BlkDesc &bd, const float *xbase, int mt, int lane, bool live, TileHalf &h) {
     const int Cp = round16(bd.C);
@@ -974,11 +1020,13 @@ __device__ inline void mm_row_pair(const MmArgs &g, int64_t row, int mt, int lan
     TileHalf th[D];
     BlkDesc bd[D];
     const int nb = rd.b1 - rd.b0;
+    LaneDescs<KIND> ld;
     if (nb > 0) {
+        ld.load(g, rd, nb, lane);
 #pragma unroll
         for (int s = 0; s < D; ++s) {
             const bool live = s < nb;   // wave-uniform
-            bd[s] = g.blks[rd.b0 + (live ? s : 0)];
+            bd[s] = ld.get(g, rd, live ? s : 0);
             load_half(bd[s], xbase, mt, lane, live, th[s]);
             const void *blk = block_ptr(bd[s]);
 #pragma unroll
@@ -991,7 +1039,7 @@ __device__ inline void mm_row_pair(const MmArgs &g, int64_t row, int mt, int lan
     // k + 1 goes to the other buffer
     auto step = [&](const int s, const int k) {
         const bool refill = k + D < nb;
-        const BlkDesc nx = g.blks[rd.b0 + (refill ? k + D : k)];
+        const BlkDesc nx = ld.get(g, rd, refill ? k + D : k);
         load_half(nx, xbase, mt, lane, refill, th[s]);
         const int np = used_chunks32<KIND>(bd[s].C);
         const void *nblk = block_ptr(nx);
@@ -1004,7 +1052,7 @@ __device__ inline void mm_row_pair(const MmArgs &g, int64_t row, int mt, int lan
             if (p < np) acc = chunk_products_lds<KIND>(a[s], buf, li, lg, p, acc);
             load_a_chunk<KIND>(nx, nblk, xbase, R, ic, lg, p, refill, a[s]);
         }
-        const double sc = KIND == ELEM_BF16 ? double(g.scales[bd[s].sidx]) : 1.0;
+        const double sc = ld.scale(g, k, bd[s]);
 #pragma unroll
         for (int r = 0; r < 16; ++r) tot[r] += sc * double(acc[r]);
         bd[s] = nx;
@@ -1090,18 +1138,20 @@ __device__ inline void mm_body(const MmArgs &g) {
 // One kernel name per phase, so that traces attribute time to phases:
 // leaf projection + upsweep and downsweep (FP32 bases), coupling + dense
 // streaming (block kind), leaf expansion + FP64 sum.
-// The descriptor arrays also come as __restrict__ parameters: the kernel never
-// writes them, and saying so lets the compiler read them with scalar loads
-// inside a persistent workgroup's loop, whose stores it could not otherwise
-// tell apart from them.
+// The descriptor arrays and the block scales also come as __restrict__
+// parameters: the kernel never writes them, and saying so lets the compiler
+// read them with scalar loads inside a persistent workgroup's loop, whose
+// stores it could not otherwise tell apart from them.
 #define H2_MM_PHASE_KERNEL(NAME, LEAF)                                                   \
     template <int KIND, bool BATCH, int PIPE, bool PERSIST, int NT>                      \
     __global__ __launch_bounds__(256) void NAME(MmArgs g, const RowDesc *__restrict__ rows, \
                                                 const BlkDesc *__restrict__ blks,       \
-                                                const int32_t *__restrict__ items) {    \
+                                                const int32_t *__restrict__ items,      \
+                                                const float *__restrict__ scales) {     \
         g.rows = rows;                                                                   \
         g.blks = blks;                                                                   \
         g.items = items;                                                                 \
+        g.scales = scales;                                                               \
         mm_body<KIND, LEAF, BATCH, PIPE, PERSIST, NT>(g);                                \
     }
 H2_MM_PHASE_KERNEL(mm_upsweep_kernel, false)
@@ -1144,19 +1194,19 @@ static void launch_phase_nt(const MmArgs &g, int kind, int phase, unsigned grid,
     const dim3 gd(grid), bd(PIPE >= 4 ? 128 : 256);   // tile sharing: two wavefronts per workgroup
     switch (phase) {
     case PHASE_UP:
-        hipLaunchKernelGGL((mm_upsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items);
+        hipLaunchKernelGGL((mm_upsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items, g.scales);
         break;
     case PHASE_DOWN:
-        hipLaunchKernelGGL((mm_downsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items);
+        hipLaunchKernelGGL((mm_downsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items, g.scales);
         break;
     case PHASE_LEAF:
-        hipLaunchKernelGGL((mm_leafexpand_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items);
+        hipLaunchKernelGGL((mm_leafexpand_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items, g.scales);
         break;
     default:
         if (kind == ELEM_F32)
-            hipLaunchKernelGGL((mm_stream_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items);
+            hipLaunchKernelGGL((mm_stream_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items, g.scales);
         else
-            hipLaunchKernelGGL((mm_stream_kernel<ELEM_BF16, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items);
+            hipLaunchKernelGGL((mm_stream_kernel<ELEM_BF16, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items, g.scales);
     }
 }
 
@@ -1186,7 +1236,7 @@ hipError_t launch_mm(const MmLaunch &L, int kind, int phase, const MmConfig &cfg
     if (L.nitems % (4 * MM_XCDS) != 0) return hipErrorInvalidValue;
     if (phase != PHASE_STREAM && kind != ELEM_F32) return hipErrorInvalidValue;   // bases are FP32
     if (L.ncols < 1 || L.ncols > MM_TILE) return hipErrorInvalidValue;
-    const bool pair = cfg.pipelined >= 4;
+    const bool pair = cfg.pipelined >= MM_FIRST_PAIR;
     if (pair && (L.npitems <= 0 || L.npitems % (2 * MM_XCDS) != 0)) return hipErrorInvalidValue;
     MmArgs g{L.rows, pair ? L.pitems : L.items, pair ? L.npitems : L.nitems, L.blks, L.data, L.scales, L.in_tree,
              L.in_pts, L.init, L.out_tree, L.out_pts, L.Y, L.ldy, nullptr, nullptr, L.ncols};
@@ -1201,7 +1251,7 @@ hipError_t launch_mm_batch(const MmBatchLaunch &L, int kind, int phase, const Mm
     if (L.nitems <= 0) return hipSuccess;
     if (L.nitems % (4 * MM_XCDS) != 0) return hipErrorInvalidValue;
     if (phase != PHASE_STREAM && kind != ELEM_F32) return hipErrorInvalidValue;
-    const bool pair = cfg.pipelined >= 4;
+    const bool pair = cfg.pipelined >= MM_FIRST_PAIR;
     if (pair && (L.npitems <= 0 || L.npitems % (2 * MM_XCDS) != 0)) return hipErrorInvalidValue;
     MmArgs g{L.rows, pair ? L.pitems : L.items, pair ? L.npitems : L.nitems, L.blks, nullptr, L.scales, L.pool,
              L.pool, L.pool, L.pool, L.pool, nullptr, 0, L.Ytab, L.ldytab, L.ncols};
