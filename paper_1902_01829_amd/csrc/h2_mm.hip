@@ -402,6 +402,39 @@ __device__ inline void mm_store32(const MmArgs &g, const RowDesc &rd, int mt, in
     }
 }
 
+// Leaf-phase epilogue of a pair wavefront through its LDS buffer (free once
+// the block loop's last barrier has passed): the 32 x 32 result half is
+// transposed so that each store instruction writes two 256-byte runs of
+// rows of two columns of Y, instead of scattering 8-byte values over 32
+// columns (the FP64 result matrix is the largest write of the product).
+// Same values as mm_store32 (y = y_near + far part, FP64).
+template <bool BATCH>
+__device__ inline void mm_store32_leaf_lds(const MmArgs &g, const RowDesc &rd, int mt, int lane,
+                                           const double (&tot)[16], float *buf) {
+    constexpr int LD = 33;   // doubles per right-hand side row (padded)
+    double *T = reinterpret_cast<double *>(buf);
+    const int li = lane & 31, lg = lane >> 5;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) T[li * LD + 8 * q + 4 * lg + e] = tot[4 * q + e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int R = rd.R, Rp = round16(R);
+    const int r = lane & 31, i = 32 * mt + r;
+    double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
+    const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
+    if (i < R) {
+#pragma unroll 4
+        for (int c = 0; c < 16; ++c) {
+            const int j = 2 * c + lg;
+            if (j < g.ncols)
+                Yb[int64_t(j) * ldy + rd.out + i] = double(g.init[rd.init + int64_t(j) * Rp + i]) + T[j * LD + r];
+        }
+    }
+}
+
 // The 32-wide block loop with a ring of D block slots: slot s holds block
 // b = s (mod D).  As each chunk of block b is consumed, the same registers
 // are refilled with that chunk of block b + D, so about D blocks of loads
@@ -1071,7 +1104,12 @@ __device__ inline void mm_row_pair(const MmArgs &g, int64_t row, int mt, int lan
     for (int s = 0; s < D - 1; ++s)
         if (base + s < nb) step(s, base + s);   // wave-uniform (the same on both wavefronts)
     __builtin_amdgcn_s_waitcnt(0);   // the dead refills land (see mm_row_ring)
-    mm_store32<LEAF, BATCH>(g, rd, mt, li, lg, tot);
+    if constexpr (LEAF) {
+        mm_store32_leaf_lds<BATCH>(g, rd, mt, lane, tot, lds + mt * kPairBuf);
+        lds_barrier();   // both buffers free again before a persistent workgroup's next row
+    } else {
+        mm_store32<LEAF, BATCH>(g, rd, mt, li, lg, tot);
+    }
 }
 
 // Two wavefronts per workgroup, one work unit (two items) each: both halves
