@@ -331,7 +331,7 @@ h2_status h2_set_schedule(h2_handle A, int schedule, int near_wg_per_cu, double 
  * products; other H2_FP32 and H2_BF16_SCALED handles
  * run on the matrix cores (FP32 MFMA), 32 right-hand sides per pass.  The first
  * such call on a handle times the candidate launch shapes (the block loop's
- * prefetch depth 0..5 as listed at h2_batch_tuning, one workgroup per item
+ * prefetch depth 0..7 as listed at h2_batch_tuning, one workgroup per item
  * group or a persistent grid of 1 or 2 workgroups per compute unit, and the
  * MFMA tile width 16 or 32 for passes of at most 16 right-hand sides) on its
  * first pass and keeps the
@@ -347,8 +347,8 @@ h2_status h2_matmat(h2_handle A, const double *X, int64_t ldx, double *Y, int64_
  * before the first such pass; 0 when the choice came from the cache). */
 h2_status h2_matmat_tuning(h2_handle A, int narrow, int *pipelined, int64_t *grid, int *tile_width,
                            double *tuned_ms);
-/* Fixes that shape instead of timing the candidates (pipelined 0..5, 4 and 5
- * with tile_width 32 only; grid >= 0; tile_width 32, or 16 for narrow passes).  Every shape gives the same
+/* Fixes that shape instead of timing the candidates (pipelined 0..7, 4 and 5
+ * with tile_width 32 only, 6 and 7 with tile_width 16 only; grid >= 0; tile_width 32, or 16 for narrow passes).  Every shape gives the same
  * products to rounding.  Errors: INVALID_ARG. */
 h2_status h2_matmat_set_tuning(h2_handle A, int narrow, int pipelined, int64_t grid, int tile_width);
 
@@ -416,14 +416,16 @@ h2_status h2_batch_matmat(h2_batch B, const double *const *X, const int64_t *ldx
  * 1 the next block, 2 or 3 a ring of that many blocks refilled chunk by
  * chunk; with 32-wide tiles also 4 or 5, a ring of 1 or 2 blocks with the
  * two 32-row halves of a row in one workgroup sharing each input tile
- * through LDS), grid
+ * through LDS; with 16-wide tiles also 6 or 7, a ring of 6 or 8 column
+ * chunks of 16 (FP32) or 32 (BF16) block columns, so that rows of narrow
+ * blocks keep more blocks in flight), grid
  * (workgroups; 0 = one per item group), tile_width (16: 16x16
  * MFMAs; 32: 32x32 MFMAs) and the tuned time in ms of one product (-1 before
  * the first product; 0 when the choice came from the cache or
  * h2_batch_set_tuning). */
 h2_status h2_batch_tuning(h2_batch B, int *pipelined, int64_t *grid, int *tile_width, double *tuned_ms);
-/* Fixes the configuration instead of timing the candidates: pipelined 0..5
- * (4 and 5 with tile_width 32 only), grid >= 0, tile_width 16 (at most 16
+/* Fixes the configuration instead of timing the candidates: pipelined 0..7
+ * (4 and 5 with tile_width 32 only, 6 and 7 with tile_width 16 only), grid >= 0, tile_width 16 (at most 16
  * right-hand sides) or 32; every choice
  * gives the members' products to rounding (the tile width changes the order
  * of a block's FP32 sums).  Waits for the batch's running products and drops

@@ -53,7 +53,7 @@ bool cached_config(const std::string &sig, h2::MmConfig &cfg) {
         long long grid = 0;
         const int got = std::sscanf(line, "%399s %d %lld %d", key, &pipe, &grid, &nt);
         if (got >= 3 && sig == key && pipe >= 0 && pipe <= h2::MM_MAX_PIPE && grid >= 0 &&
-            (nt == 0 || nt == 16 || nt == 32) && (pipe < h2::MM_FIRST_PAIR || nt == 32)) {
+            (nt == 0 ? pipe < h2::MM_FIRST_PAIR : (nt == 16 || nt == 32) && h2::mm_pipe_fits(pipe, nt))) {
             cfg = {pipe, grid, got == 4 ? nt : 0};
             found = true;
         }
@@ -76,12 +76,12 @@ void store_config(const std::string &sig, const h2::MmConfig &cfg) {
 
 // Launch shapes the tuners try: the block loop's prefetch depth (0 plain, 1
 // the next block, 2 and 3 rings of block slots in registers, 4 and 5 rings
-// with a row's halves sharing the input tile), and for
-// passes of at most 16 right-hand sides the MFMA tile width (16: 16x16 MFMAs,
-// half the matrix-core work and registers of 32, but every tile pads 8
-// right-hand sides to 16; 32: 32x32 MFMAs).  Depth 3 with 32-wide tiles runs
-// one wavefront per SIMD.
-constexpr int kDepths = h2::MM_MAX_PIPE + 1;   // from MM_FIRST_PAIR on only with 32-wide tiles
+// with a row's halves sharing the input tile (32-wide tiles), 6 and 7 rings
+// of 6 or 8 column chunks (16-wide tiles)), and for passes of at most 16
+// right-hand sides the MFMA tile width (16: 16x16 MFMAs, half the matrix-core
+// work and registers of 32, but every tile pads 8 right-hand sides to 16;
+// 32: 32x32 MFMAs).  Depth 3 with 32-wide tiles runs one wavefront per SIMD.
+constexpr int kDepths = h2::MM_MAX_PIPE + 1;   // each with the tile widths h2::mm_pipe_fits allows
 
 std::vector<int> tile_widths(int ncols) {
     return ncols <= 16 ? std::vector<int>{16, 32} : std::vector<int>{32};
@@ -106,7 +106,7 @@ void batch_autotune(h2_batch_ &B) {
     for (int nt : tile_widths(B.nrhs))
         for (int pipe = 0; pipe < kDepths; ++pipe)
             for (int64_t grid : grids) {
-                if (pipe >= h2::MM_FIRST_PAIR && nt != 32) continue;
+                if (!h2::mm_pipe_fits(pipe, nt)) continue;
                 const h2::MmConfig c{pipe, grid, nt};
                 batch_enqueue(B, c, B.own);   // warm-up
                 float ms_best = 1e30f;
@@ -313,7 +313,7 @@ void tune_tiles(h2_matrix_ &A, const double *X, int64_t ldx, double *Y, int64_t 
         for (int nt : tile_widths(ncols))
             for (int pipe = 0; pipe < kDepths; ++pipe)
                 for (int64_t grid : {int64_t(0), cu, 2 * cu}) {
-                    if (pipe >= h2::MM_FIRST_PAIR && nt != 32) continue;
+                    if (!h2::mm_pipe_fits(pipe, nt)) continue;
                     const h2::MmConfig c{pipe, grid, nt};
                     run_tile_pass(A, X, ldx, Y, ldy, nrhs, j0, c, st);   // warm-up
                     check_hip(hipEventRecord(t0, st), "hipEventRecord");
@@ -448,9 +448,9 @@ h2_status h2_batch_tuning(h2_batch B, int *pipelined, int64_t *grid, int *tile_w
 h2_status h2_batch_set_tuning(h2_batch B, int pipelined, int64_t grid, int tile_width) {
     try {
         if (!B) fail(H2_ERR_INVALID_ARG, "NULL batch");
-        if (pipelined < 0 || pipelined > h2::MM_MAX_PIPE) fail(H2_ERR_INVALID_ARG, "pipelined must be 0 .. 5");
-        if (pipelined >= h2::MM_FIRST_PAIR && tile_width != 32)
-            fail(H2_ERR_INVALID_ARG, "tile sharing (4, 5) needs 32-wide tiles");
+        if (pipelined < 0 || pipelined > h2::MM_MAX_PIPE) fail(H2_ERR_INVALID_ARG, "pipelined must be 0 .. 7");
+        if (!h2::mm_pipe_fits(pipelined, tile_width))
+            fail(H2_ERR_INVALID_ARG, "pipelined 4, 5 need 32-wide tiles, 6, 7 16-wide tiles");
         if (grid < 0) fail(H2_ERR_INVALID_ARG, "grid must be >= 0");
         if (tile_width != 16 && tile_width != 32) fail(H2_ERR_INVALID_ARG, "tile_width must be 16 or 32");
         if (tile_width == 16 && B->nrhs > 16) fail(H2_ERR_INVALID_ARG, "16-wide tiles take at most 16 right-hand sides");
@@ -491,9 +491,9 @@ h2_status h2_matmat_tuning(h2_handle A, int narrow, int *pipelined, int64_t *gri
 h2_status h2_matmat_set_tuning(h2_handle A, int narrow, int pipelined, int64_t grid, int tile_width) {
     if (!A || (narrow != 0 && narrow != 1) || pipelined < 0 || pipelined > h2::MM_MAX_PIPE || grid < 0 ||
         (tile_width != 16 && tile_width != 32) || (tile_width == 16 && narrow == 0) ||
-        (pipelined >= h2::MM_FIRST_PAIR && tile_width != 32)) {
-        g_last_error = "bad argument (narrow 0/1, pipelined 0..5 (4, 5 with 32-wide tiles), grid >= 0, "
-                       "tile_width 16 or 32, 16 only for narrow passes)";
+        !h2::mm_pipe_fits(pipelined, tile_width)) {
+        g_last_error = "bad argument (narrow 0/1, pipelined 0..7 (4, 5 with 32-wide tiles, 6, 7 with 16-wide), "
+                       "grid >= 0, tile_width 16 or 32, 16 only for narrow passes)";
         return H2_ERR_INVALID_ARG;
     }
     A->mm_cfg[narrow] = {pipelined, grid, tile_width};

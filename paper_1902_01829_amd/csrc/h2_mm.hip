@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "h2_device.h"
 
@@ -926,6 +927,138 @@ __device__ inline void mm_row16_ring(const MmArgs &g, int64_t row, int mt, int l
     mm_store16<LEAF, BATCH>(g, rd, mt, nh, n, kq, tot);
 }
 
+// ---- 16-wide loop with a ring of S column chunks instead of S blocks
+// The prefetch distance is counted in 16-column chunks (FP32; 32 columns
+// for BF16): a row of narrow blocks (rank 16 or 27, leaves of 32) keeps
+// S / 2 or more blocks in flight where a block ring would keep D, for the
+// registers of S chunks (a quarter of a full-width block each).  The chunks
+// of the row's blocks are consumed in order; slot s holds chunk i of the row
+// when i = s (mod S), and is refilled with chunk i + S as soon as its
+// products are issued.  A block's sum (times its BF16 scale) is added to the
+// FP64 totals after its last chunk, so the arithmetic and its order are those
+// of mm_row16 (bitwise the same results).
+template <int KIND>
+struct Chunk16 {
+    typename std::conditional<KIND == ELEM_F32, f32x4, u32x4>::type a[2];   // per row tile
+    f32x4 b[KIND == ELEM_F32 ? 1 : 2];
+};
+template <int KIND>
+__device__ inline void load_one_chunk16(const BlkDesc &bd, const void *blk, const float *xbase, int R,
+                                        const int (&ic)[2], int n, int kq, int c, bool live, Chunk16<KIND> &o) {
+    BlockA16<KIND> a;
+    TileB16 b;
+    load_chunk16<KIND>(bd, blk, xbase, R, ic, n, kq, c, live, a, b);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) o.a[h] = a.v[h][c];
+    if constexpr (KIND == ELEM_F32) {
+        o.b[0] = b.v[c];
+    } else {
+        o.b[0] = b.v[2 * c];
+        o.b[1] = b.v[2 * c + 1];
+    }
+}
+template <int KIND>
+__device__ inline void one_chunk_products16(const Chunk16<KIND> &o, int c, int Cp, int nh, int kq, f32x4 (&acc)[2]) {
+    BlockA16<KIND> a;
+    TileB16 b;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) a.v[h][c] = o.a[h];
+    if constexpr (KIND == ELEM_F32) {
+        b.v[c] = o.b[0];
+    } else {
+        b.v[2 * c] = o.b[0];
+        b.v[2 * c + 1] = o.b[1];
+    }
+    chunk_products16<KIND>(a, b, c, Cp, nh, kq, acc);
+}
+
+template <int KIND, bool LEAF, bool BATCH, int S>
+__device__ inline void mm_row16_cring(const MmArgs &g, int64_t row, int mt, int lane) {
+    const RowDesc rd = g.rows[row];
+    const int R = rd.R;
+    if (32 * mt >= R) return;
+    const int n = lane & 15, kq = lane >> 4;
+    const int nh = 32 * mt + 16 < R ? 2 : 1;   // wave-uniform
+    int ic[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = 32 * mt + 16 * h + n;
+        ic[h] = i < R ? i : R - 1;
+    }
+    const float *xbase = (rd.sel & ROW_IN_X) ? g.in_pts : g.in_tree;
+    auto block_ptr = [&](const BlkDesc &bd) -> const void * {
+        if constexpr (BATCH) return reinterpret_cast<const void *>(bd.a);
+        else return static_cast<const char *>(g.data) + bd.a * (KIND == ELEM_F32 ? 4 : 2);
+    };
+
+    double tot[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tot[h][e] = 0.0;
+
+    const int nb = rd.b1 - rd.b0;
+    if (nb > 0) {
+        LaneDescs<KIND> ld;
+        ld.load(g, rd, nb, lane);
+        // consumption cursor: chunk c of block k (descriptor bk); refill
+        // cursor: chunk c2 of block k2 (descriptor bk2), S chunks ahead
+        int k = 0, c = 0, k2 = 0, c2 = 0;
+        BlkDesc bk = ld.get(g, rd, 0), bk2 = bk;
+        int np = used_chunks16<KIND>(bk.C), np2 = np;
+        int total = 0;   // chunks in the row
+        for (int j = 0; j < nb; ++j) total += used_chunks16<KIND>(ld.get(g, rd, j).C);
+        Chunk16<KIND> ring[S];
+        auto refill = [&](int s) {
+            const bool live = k2 < nb;   // wave-uniform
+            load_one_chunk16<KIND>(bk2, block_ptr(bk2), xbase, R, ic, n, kq, live ? c2 : 0, live, ring[s]);
+            if (live && ++c2 == np2) {
+                c2 = 0;
+                if (++k2 < nb) {
+                    bk2 = ld.get(g, rd, k2);
+                    np2 = used_chunks16<KIND>(bk2.C);
+                }
+            }
+        };
+#pragma unroll
+        for (int s = 0; s < S; ++s) refill(s);
+        f32x4 acc[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        auto step = [&](int s) {
+            one_chunk_products16<KIND>(ring[s], c, round16(bk.C), nh, kq, acc);
+            refill(s);
+            if (++c == np) {   // the block's last chunk: its sum goes to the totals
+                const double sc = ld.scale(g, k, bk);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    tot[h][0] += sc * double(acc[h].x);
+                    tot[h][1] += sc * double(acc[h].y);
+                    tot[h][2] += sc * double(acc[h].z);
+                    tot[h][3] += sc * double(acc[h].w);
+                    acc[h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                }
+                c = 0;
+                if (++k < nb) {
+                    bk = ld.get(g, rd, k);
+                    np = used_chunks16<KIND>(bk.C);
+                }
+            }
+        };
+        // whole rounds of S chunks, then the last < S (see mm_row_ring)
+        int i = 0;
+        for (; i + S <= total; i += S) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) step(s);
+        }
+#pragma unroll
+        for (int s = 0; s < S - 1; ++s)
+            if (i + s < total) step(s);   // wave-uniform
+        __builtin_amdgcn_s_waitcnt(0);   // the dead refills land (see mm_row_ring)
+    }
+    mm_store16<LEAF, BATCH>(g, rd, mt, nh, n, kq, tot);
+}
+
 // ---- both halves of a row in one workgroup of two wavefronts, sharing each
 // block's input tile through LDS (32-wide tiles)
 // Each wavefront loads half of the tile (right-hand sides 16*mt .. 16*mt+15)
@@ -1143,16 +1276,18 @@ __device__ inline void mm_pair_body(const MmArgs &g) {
 // range); otherwise one workgroup per 4 items.
 template <int KIND, bool LEAF, bool BATCH, int PIPE, bool PERSIST, int NT>
 __device__ inline void mm_body(const MmArgs &g) {
-    if constexpr (PIPE >= 4) {   // 32-wide tiles shared by the two halves of a row
+    if constexpr (PIPE >= 4 && PIPE <= 5) {   // 32-wide tiles shared by the two halves of a row
         static_assert(NT == 32, "tile sharing runs 32-wide tiles");
         mm_pair_body<KIND, LEAF, BATCH, PIPE - 3, PERSIST>(g);
         return;
     }
+    static_assert(PIPE < 6 || NT == 16, "chunk rings run 16-wide tiles");
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t nwg = g.nitems >> 2;
     auto one = [&](int32_t it) {
         if constexpr (NT == 16) {
-            if constexpr (PIPE >= 2) mm_row16_ring<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
+            if constexpr (PIPE >= 6) mm_row16_cring<KIND, LEAF, BATCH, PIPE == 6 ? 6 : 8>(g, it >> 1, it & 1, lane);
+            else if constexpr (PIPE >= 2) mm_row16_ring<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
             else mm_row16<KIND, LEAF, BATCH, PIPE == 1>(g, it >> 1, it & 1, lane);
         } else {
             if constexpr (PIPE >= 2) mm_row_ring<KIND, LEAF, BATCH, PIPE>(g, it >> 1, it & 1, lane);
@@ -1229,7 +1364,7 @@ hipError_t launch_pack(const double *X, int64_t ldx, int j0, int nrhs, const int
 
 template <bool BATCH, int PIPE, bool PERSIST, int NT>
 static void launch_phase_nt(const MmArgs &g, int kind, int phase, unsigned grid, hipStream_t st) {
-    const dim3 gd(grid), bd(PIPE >= 4 ? 128 : 256);   // tile sharing: two wavefronts per workgroup
+    const dim3 gd(grid), bd(PIPE >= MM_FIRST_PAIR && PIPE < MM_FIRST_CRING ? 128 : 256);   // tile sharing: two wavefronts
     switch (phase) {
     case PHASE_UP:
         hipLaunchKernelGGL((mm_upsweep_kernel<ELEM_F32, BATCH, PIPE, PERSIST, NT>), gd, bd, 0, st, g, g.rows, g.blks, g.items, g.scales);
@@ -1256,7 +1391,8 @@ static void launch_phase_p(const MmArgs &g, int kind, int phase, int nt, unsigne
 
 // depth: 0 plain block loop, 1 one block ahead, 2 and 3 rings of that many
 // block slots; 4 and 5 the ring of 1 or 2 slots with the two halves of a row
-// sharing the tile (workgroups of two wavefronts over the pair list).
+// sharing the tile (workgroups of two wavefronts over the pair list, 32-wide
+// tiles); 6 and 7 rings of 6 or 8 column chunks (16-wide tiles).
 template <bool BATCH, bool PERSIST>
 static void launch_phase(const MmArgs &g, int kind, int phase, int nt, int depth, unsigned grid, hipStream_t st) {
     switch (depth) {
@@ -1265,7 +1401,9 @@ static void launch_phase(const MmArgs &g, int kind, int phase, int nt, int depth
         case 2: launch_phase_p<BATCH, 2, PERSIST>(g, kind, phase, nt, grid, st); break;
         case 3: launch_phase_p<BATCH, 3, PERSIST>(g, kind, phase, nt, grid, st); break;
         case 4: launch_phase_nt<BATCH, 4, PERSIST, 32>(g, kind, phase, grid, st); break;
-        default: launch_phase_nt<BATCH, 5, PERSIST, 32>(g, kind, phase, grid, st); break;
+        case 5: launch_phase_nt<BATCH, 5, PERSIST, 32>(g, kind, phase, grid, st); break;
+        case 6: launch_phase_nt<BATCH, 6, PERSIST, 16>(g, kind, phase, grid, st); break;
+        default: launch_phase_nt<BATCH, 7, PERSIST, 16>(g, kind, phase, grid, st); break;
     }
 }
 
@@ -1274,7 +1412,7 @@ hipError_t launch_mm(const MmLaunch &L, int kind, int phase, const MmConfig &cfg
     if (L.nitems % (4 * MM_XCDS) != 0) return hipErrorInvalidValue;
     if (phase != PHASE_STREAM && kind != ELEM_F32) return hipErrorInvalidValue;   // bases are FP32
     if (L.ncols < 1 || L.ncols > MM_TILE) return hipErrorInvalidValue;
-    const bool pair = cfg.pipelined >= MM_FIRST_PAIR;
+    const bool pair = cfg.pipelined >= MM_FIRST_PAIR && cfg.pipelined < MM_FIRST_CRING;
     if (pair && (L.npitems <= 0 || L.npitems % (2 * MM_XCDS) != 0)) return hipErrorInvalidValue;
     MmArgs g{L.rows, pair ? L.pitems : L.items, pair ? L.npitems : L.nitems, L.blks, L.data, L.scales, L.in_tree,
              L.in_pts, L.init, L.out_tree, L.out_pts, L.Y, L.ldy, nullptr, nullptr, L.ncols};
@@ -1289,7 +1427,7 @@ hipError_t launch_mm_batch(const MmBatchLaunch &L, int kind, int phase, const Mm
     if (L.nitems <= 0) return hipSuccess;
     if (L.nitems % (4 * MM_XCDS) != 0) return hipErrorInvalidValue;
     if (phase != PHASE_STREAM && kind != ELEM_F32) return hipErrorInvalidValue;
-    const bool pair = cfg.pipelined >= MM_FIRST_PAIR;
+    const bool pair = cfg.pipelined >= MM_FIRST_PAIR && cfg.pipelined < MM_FIRST_CRING;
     if (pair && (L.npitems <= 0 || L.npitems % (2 * MM_XCDS) != 0)) return hipErrorInvalidValue;
     MmArgs g{L.rows, pair ? L.pitems : L.items, pair ? L.npitems : L.nitems, L.blks, nullptr, L.scales, L.pool,
              L.pool, L.pool, L.pool, L.pool, nullptr, 0, L.Ytab, L.ldytab, L.ncols};

@@ -154,8 +154,9 @@ def test_batch_tuning_cache_file(tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("storage", [1, 2], ids=["fp32", "bf16"])
 def test_batch_every_launch_shape(oracle_mod, storage):
-    """Every configuration the tuner may pick -- prefetch depth 0..3, or 4..5
-    with tiles shared by a row's halves, one workgroup per item group or
+    """Every configuration the tuner may pick -- prefetch depth 0..3, 4..5
+    with tiles shared by a row's halves (32-wide), 6..7 with rings of column
+    chunks (16-wide), one workgroup per item group or
     persistent grids, 16- or 32-wide tiles -- gives
     each member's own product with the same tile width (to 1e-12: the same
     block arithmetic in the same order) and matches the oracle on the same
@@ -174,7 +175,7 @@ def test_batch_every_launch_shape(oracle_mod, storage):
         _pin_members(mats, nrhs, tw)
         refs[tw] = [m.matmat(X) for m, X in zip(mats, Xs)]
     for tw in (16, 32):
-        for depth in range(6 if tw == 32 else 4):
+        for depth in ((0, 1, 2, 3, 4, 5) if tw == 32 else (0, 1, 2, 3, 6, 7)):
             for grid in (0, 64, 2048):
                 batch.set_tuning(depth, grid, tw)
                 for call in range(2):
@@ -198,7 +199,7 @@ def test_batch_set_tuning_rejects():
     mats = [_build(MEMBERS[0], 1)]
     b8 = h2mv.H2Batch(mats, 8)
     b20 = h2mv.H2Batch(mats, 20)
-    for B, args in ((b8, (6, 0, 32)), (b8, (4, 0, 16)), (b8, (-1, 0, 16)), (b8, (1, -5, 16)), (b8, (1, 0, 24)),
+    for B, args in ((b8, (8, 0, 16)), (b8, (6, 0, 32)), (b8, (4, 0, 16)), (b8, (-1, 0, 16)), (b8, (1, -5, 16)), (b8, (1, 0, 24)),
                     (b20, (1, 0, 16))):
         with pytest.raises(h2mv.H2Error) as e:
             B.set_tuning(*args)

@@ -187,8 +187,9 @@ SHAPE_CASES = [
 @pytest.mark.parametrize("storage", [1, 2], ids=["fp32", "bf16"])
 @pytest.mark.parametrize("w", SHAPE_CASES, ids=lambda w: w.name)
 def test_matmat_every_launch_shape(oracle_mod, w, storage):
-    """Each launch shape the tuner may pick (prefetch depth 0..3, and 4..5
-    with a row's halves sharing tiles; one workgroup per item group or a
+    """Each launch shape the tuner may pick (prefetch depth 0..3, 4..5
+    with a row's halves sharing tiles (32-wide), 6..7 with rings of column
+    chunks (16-wide); one workgroup per item group or a
     persistent grid; 16- or 32-wide tiles for passes of at most 16
     right-hand sides), on full-width
     (64 x 64) and ragged (27- and 23-column) blocks: results equal bitwise
@@ -205,7 +206,7 @@ def test_matmat_every_launch_shape(oracle_mod, w, storage):
         narrow = 1 if nrhs <= 16 else 0
         for tw in ((16, 32) if narrow else (32,)):
             first = None
-            for depth in range(6 if tw == 32 else 4):
+            for depth in ((0, 1, 2, 3, 4, 5) if tw == 32 else (0, 1, 2, 3, 6, 7)):
                 for grid in (0, 256):
                     A.set_matmat_tuning(narrow, depth, tw, grid)
                     Y = A.matmat(Xd)
