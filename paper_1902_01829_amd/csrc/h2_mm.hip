@@ -1439,8 +1439,13 @@ hipError_t launch_mm_batch(const MmBatchLaunch &L, int kind, int phase, const Mm
     return hipGetLastError();
 }
 
-// Batch pack: every (member, leaf) entry copies right-hand sides 0 .. MM_TILE-1
-// of its member's X (device pointer table) into its point tile in the pool.
+// Batch pack: every (member, leaf) entry copies right-hand sides 0 .. nrhs-1
+// of its member's X (device pointer table) into its point tile in the pool,
+// with the rows past the leaf's size zero (they meet the clamped block
+// columns).  The tile's right-hand sides nrhs .. MM_TILE-1 are not written:
+// every product, sum and store keeps the right-hand sides (MFMA columns)
+// apart, and the leaf phase writes only the first nrhs, so whatever those
+// columns hold never reaches a result.
 __global__ __launch_bounds__(256) void batch_pack_kernel(const PackEntry *__restrict__ entries, int64_t count,
                                                          double const *const *__restrict__ Xtab,
                                                          const int64_t *__restrict__ ldxtab, int nrhs,
@@ -1451,12 +1456,10 @@ __global__ __launch_bounds__(256) void batch_pack_kernel(const PackEntry *__rest
         const int64_t ldx = ldxtab[e.member];
         const int mp = round16(e.m);
         float *t = pool + e.dst;
-        for (int idx = threadIdx.x; idx < NT * mp; idx += blockDim.x) {
-            const int j = idx / mp, c = idx - j * mp;
-            float v = 0.0f;
-            if (c < e.m && j < nrhs) v = float(X[(e.row + c) + int64_t(j) * ldx]);
-            t[idx] = v;
-        }
+        const int c = threadIdx.x & 63;   // leaves hold at most 64 points
+        if (c < mp)
+            for (int j = threadIdx.x >> 6; j < nrhs && j < NT; j += 4)
+                t[int64_t(j) * mp + c] = c < e.m ? float(X[(e.row + c) + int64_t(j) * ldx]) : 0.0f;
     }
 }
 
