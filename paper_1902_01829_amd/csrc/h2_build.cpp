@@ -3,6 +3,8 @@
 // export of its stored arrays.
 #include "h2_internal.h"
 
+#include <future>
+#include <numeric>
 #include <unordered_map>
 #include <unordered_set>
 
@@ -211,6 +213,12 @@ std::vector<h2::FillDesc> make_layout(h2_matrix_ &A, int64_t &ncoupling) {
     // blocks; stored by halves, only the blocks with column >= row
     std::vector<h2::FillDesc> fill;
     std::vector<int64_t> store;   // per block of the lists: stored index, or -1 until linked
+    {
+        int64_t total = s.dense.blocks();
+        for (int l = 0; l <= q; ++l) total += s.coupling[l].blocks();
+        fill.reserve(size_t(total));
+        store.reserve(size_t(total));
+    }
     int64_t ns = 0;
     // Stored by halves: each block below the diagonal takes the index of its
     // mirror; the pattern must be symmetric, with every pair listed once.
@@ -270,10 +278,10 @@ std::vector<h2::FillDesc> make_layout(h2_matrix_ &A, int64_t &ncoupling) {
     else
         A.blk_store.clear();
     const int64_t scale_bytes = sk == h2::ELEM_BF16 ? 4 : 0;
-    A.off_U = off_U;
-    A.off_VT = off_VT;
-    A.off_E = off_E;
-    A.off_FT = off_FT;
+    A.off_U = std::move(off_U);
+    A.off_VT = std::move(off_VT);
+    A.off_E = std::move(off_E);
+    A.off_FT = std::move(off_FT);
     A.off_blk.resize(fill.size());
     for (size_t i = 0; i < fill.size(); ++i) A.off_blk[i] = fill[i].a;
     A.bytes_coupling = coupling_elems * sb + scale_bytes * ncoupling;
@@ -438,19 +446,32 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
     // operand names either a tree node's vector (x^ / y^) or a leaf's segment of
     // the point vectors (x, y_near, y); they are then encoded twice, with
     // single-vector offsets and with tile offsets for many right-hand sides.
+    // A row's blocks are a range of one pool shared by the rows of a list
+    // (a list of the 2^20-point matrix holds ~1.3M blocks: one allocation,
+    // reused from list to list, instead of one per row).
     struct LBlk {
         int64_t a;
         int32_t C, sidx;
         bool point;
         int64_t id;
-        int32_t slot = -1;   // stored by halves: partial slot of the transposed product
+        int32_t slot;   // stored by halves: partial slot of the transposed product
     };
     struct LRow {
         bool point;      // output is a leaf segment (else a tree node)
         int64_t id;      // leaf index or node id
         bool has_init;   // add the current value (downsweep: y^; leaf phase: y_near)
         int R, sel;
-        std::vector<LBlk> b;
+        size_t b0, b1;   // its blocks: pool[b0, b1)
+        size_t nb() const { return b1 - b0; }
+    };
+    std::vector<LBlk> pool;
+    std::vector<LRow> L;
+    auto add_row = [&](bool point, int64_t id, bool has_init, int R, int sel) {
+        L.push_back({point, id, has_init, R, sel, pool.size(), pool.size()});
+    };
+    auto add_blk = [&](int64_t a, int32_t C, int32_t sidx, bool point, int64_t id) {
+        pool.push_back({a, C, sidx, point, id, -1});
+        L.back().b1 = pool.size();
     };
     const int64_t kp = (k + 15) / 16 * 16;
     int64_t mmax = 0;
@@ -458,11 +479,24 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
     A.tile_slot = (mmax + 15) / 16 * 16 * h2::MM_TILE;
     auto mv_off = [&](bool point, int64_t id) { return point ? s.begin[lf + id] : id * k; };
     auto mm_off = [&](bool point, int64_t id) { return point ? id * A.tile_slot : id * kp * h2::MM_TILE; };
-    // enc 0: single-vector offsets into A.lists; enc 1: tile offsets into A.mm_lists
-    auto emit_one = [&](int enc, Phase ph, int kind, const void *data, const std::vector<LRow> &L) {
+    // enc 0: single-vector offsets into A.lists; enc 1: tile offsets into A.mm_lists.
+    // Rows in the order of `order` (indices into L), else in L's order.
+    // encode only reads L and the pool (two encodings may run at once);
+    // commit uploads and records the list.
+    struct Encoded {
         std::vector<RowDesc> rows;
         std::vector<BlkDesc> blks;
-        for (const LRow &r : L) {
+        std::vector<int32_t> items, pitems;   // tile lists
+    };
+    auto encode = [&](int enc, Phase ph, const std::vector<size_t> *order) {
+        const size_t nr = order ? order->size() : L.size();
+        size_t nblk = 0;
+        for (size_t o = 0; o < nr; ++o) nblk += L[order ? (*order)[o] : o].nb();
+        Encoded e;
+        e.rows.reserve(nr);
+        e.blks.reserve(nblk);
+        for (size_t o = 0; o < nr; ++o) {
+            const LRow &r = L[order ? (*order)[o] : o];
             RowDesc d;
             if (ph == PH_LEAF) {   // out: rows of y; init: y_near
                 d.out = s.begin[lf + r.id];
@@ -471,54 +505,70 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
                 d.out = enc == 0 ? mv_off(r.point, r.id) : mm_off(r.point, r.id);
                 d.init = !r.has_init ? -1 : enc == 0 ? mv_off(r.point, r.id) : mm_off(r.point, r.id);
             }
-            d.b0 = int32_t(blks.size());
-            for (const LBlk &b : r.b)
-                blks.push_back({b.a, enc == 0 ? mv_off(b.point, b.id) : mm_off(b.point, b.id), b.C, b.sidx});
-            d.b1 = int32_t(blks.size());
+            d.b0 = int32_t(e.blks.size());
+            for (size_t i = r.b0; i < r.b1; ++i) {
+                const LBlk &b = pool[i];
+                e.blks.push_back({b.a, enc == 0 ? mv_off(b.point, b.id) : mm_off(b.point, b.id), b.C, b.sidx});
+            }
+            d.b1 = int32_t(e.blks.size());
             d.R = r.R;
             d.sel = r.sel;
-            rows.push_back(d);
+            e.rows.push_back(d);
         }
+        if (enc == 1) {
+            e.items = wave_items(e.rows, e.blks);
+            e.pitems = pair_items(e.rows, e.blks);
+        }
+        return e;
+    };
+    auto commit = [&](int enc, Phase ph, int kind, const void *data, Encoded &&e) {
         WorkList w;
         w.phase = ph;
         w.kind = kind;
         w.data = data;
-        w.nrows = int64_t(rows.size());
-        w.rows = A.mem.upload(rows, stream);
-        w.blks = A.mem.upload(blks, stream);
+        w.nrows = int64_t(e.rows.size());
+        w.rows = A.mem.upload(e.rows, stream);
+        w.blks = A.mem.upload(e.blks, stream);
         if (enc == 1) {
-            const std::vector<int32_t> it = wave_items(rows, blks), pit = pair_items(rows, blks);
-            w.items = A.mem.upload(it, stream);
-            w.nitems = int64_t(it.size());
-            w.pitems = A.mem.upload(pit, stream);
-            w.npitems = int64_t(pit.size());
+            w.items = A.mem.upload(e.items, stream);
+            w.nitems = int64_t(e.items.size());
+            w.pitems = A.mem.upload(e.pitems, stream);
+            w.npitems = int64_t(e.pitems.size());
         }
         (enc == 0 ? A.lists : A.mm_lists).push_back(w);
         if (enc == 1) {
-            A.mm_host_rows.push_back(std::move(rows));
-            A.mm_host_blks.push_back(std::move(blks));
+            A.mm_host_rows.push_back(std::move(e.rows));
+            A.mm_host_blks.push_back(std::move(e.blks));
         }
     };
-    auto emit = [&](Phase ph, int kind, const void *data, std::vector<LRow> &L) {
-        emit_one(0, ph, kind, data, L);
-        emit_one(1, ph, kind, data, L);
-        L.clear();
+    auto emit_one = [&](int enc, Phase ph, int kind, const void *data, const std::vector<size_t> *order) {
+        commit(enc, ph, kind, data, encode(enc, ph, order));
     };
-    std::vector<LRow> L;
+    auto clear = [&]() {
+        L.clear();
+        pool.clear();
+    };
+    auto emit = [&](Phase ph, int kind, const void *data) {
+        emit_one(0, ph, kind, data, nullptr);
+        emit_one(1, ph, kind, data, nullptr);
+        clear();
+    };
     if (lowrank) {
         // leaf projection x^_j = V_j^T x(j)   (Sec. 4.2)
         for (int64_t j = 0; j < nleaves; ++j) {
             const int64_t v = lf + j;
-            L.push_back({false, v, false, kl[q], h2::ROW_IN_X, {{off_VT[j], int32_t(s.size(v)), 0, true, j}}});
+            add_row(false, v, false, kl[q], h2::ROW_IN_X);
+            add_blk(off_VT[j], int32_t(s.size(v)), 0, true, j);
         }
-        emit(PH_UP, bk, A.basis, L);
+        emit(PH_UP, bk, A.basis);
         // upsweep x^_p = F_c1^T x^_c1 + F_c2^T x^_c2 for levels q .. lmin+1   (Sec. 4.2)
         for (int l = q; l > s.lmin; --l) {
-            for (int64_t p = Structure::first(l - 1); p < Structure::first(l); ++p)
-                L.push_back({false, p, false, kl[l - 1], 0,
-                             {{off_FT[2 * p + 1], kl[l], 0, false, 2 * p + 1},
-                              {off_FT[2 * p + 2], kl[l], 0, false, 2 * p + 2}}});
-            emit(PH_UP, bk, A.basis, L);
+            for (int64_t p = Structure::first(l - 1); p < Structure::first(l); ++p) {
+                add_row(false, p, false, kl[l - 1], 0);
+                add_blk(off_FT[2 * p + 1], kl[l], 0, false, 2 * p + 1);
+                add_blk(off_FT[2 * p + 2], kl[l], 0, false, 2 * p + 2);
+            }
+            emit(PH_UP, bk, A.basis);
         }
     }
     // tree multiplication y^_i = sum_j S_ij x^_j on all levels (Sec. 4.3) and the
@@ -526,31 +576,31 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
     {
         // blocks by their index in the lists (coupling levels, then dense);
         // stored by halves, the mirrors of stored blocks are left out
-        int64_t li = 0;
+        int64_t li = 0, total = s.dense.blocks();
         auto stored = [&](int64_t b) { return A.blk_store.empty() ? b : A.blk_store[size_t(b)]; };
+        for (int l = 0; l <= q; ++l) total += s.coupling[l].blocks();
+        pool.reserve(size_t(total));
         for (int l = 0; l < s.lmin && lowrank; ++l) li += s.coupling[l].blocks();
         if (lowrank)
             for (int l = s.lmin; l <= q; ++l) {
                 const h2::Bsr &B = s.coupling[l];
                 const int64_t f = Structure::first(l);
                 for (int64_t i = 0; i < (int64_t(1) << l); ++i) {
-                    LRow r{false, f + i, false, kl[l], 0, {}};
+                    add_row(false, f + i, false, kl[l], 0);
                     for (int32_t b = B.rowptr[i]; b < B.rowptr[i + 1]; ++b, ++li) {
                         const int64_t fi = stored(li);
-                        if (fi >= 0) r.b.push_back({fill[fi].a, kl[l], fill[fi].sidx, false, f + B.colidx[b]});
+                        if (fi >= 0) add_blk(fill[fi].a, kl[l], fill[fi].sidx, false, f + B.colidx[b]);
                     }
-                    L.push_back(std::move(r));
                 }
             }
         li = 0;
         for (int l = 0; l <= q; ++l) li += s.coupling[l].blocks();
         for (int64_t i = 0; i < nleaves; ++i) {
-            LRow r{true, i, false, int(s.size(lf + i)), h2::ROW_IN_X | h2::ROW_OUT_P, {}};
+            add_row(true, i, false, int(s.size(lf + i)), h2::ROW_IN_X | h2::ROW_OUT_P);
             for (int32_t b = s.dense.rowptr[i]; b < s.dense.rowptr[i + 1]; ++b, ++li) {
                 const int64_t t = s.dense.colidx[b], fi = stored(li);
-                if (fi >= 0) r.b.push_back({fill[fi].a, int32_t(s.size(lf + t)), fill[fi].sidx, true, t});
+                if (fi >= 0) add_blk(fill[fi].a, int32_t(s.size(lf + t)), fill[fi].sidx, true, t);
             }
-            L.push_back(std::move(r));
         }
         if (A.half) {
             // One launch reads every stored block once for both of its
@@ -560,29 +610,32 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
             struct Off {
                 bool point;
                 int64_t id;
-                size_t row, blk;
+                size_t blk;   // index in the pool
             };
             std::vector<Off> offd;
             for (size_t r = 0; r < L.size(); ++r)
-                for (size_t b = 0; b < L[r].b.size(); ++b)
-                    if (L[r].b[b].point != L[r].point || L[r].b[b].id != L[r].id)
-                        offd.push_back({L[r].b[b].point, L[r].b[b].id, r, b});
+                for (size_t b = L[r].b0; b < L[r].b1; ++b)
+                    if (pool[b].point != L[r].point || pool[b].id != L[r].id)
+                        offd.push_back({pool[b].point, pool[b].id, b});
             std::stable_sort(offd.begin(), offd.end(), [](const Off &x, const Off &y) {
                 return x.point != y.point ? x.point < y.point : x.id < y.id;
             });
             if (offd.size() >= (size_t(1) << 31)) fail(H2_ERR_UNSUPPORTED, "too many blocks stored by halves");
             std::vector<h2::ReduceDesc> red;
             for (size_t k = 0; k < offd.size(); ++k) {
-                LBlk &lb = L[offd[k].row].b[offd[k].blk];
+                LBlk &lb = pool[offd[k].blk];
                 lb.slot = int32_t(k);
                 if (k == 0 || offd[k].point != offd[k - 1].point || offd[k].id != offd[k - 1].id)
                     red.push_back({mv_off(lb.point, lb.id), int32_t(k), int32_t(k), lb.C, lb.point ? 1 : 0});
                 red.back().c1 = int32_t(k + 1);
             }
-            std::stable_sort(L.begin(), L.end(), [](const LRow &a, const LRow &b) { return a.b.size() > b.b.size(); });
+            std::stable_sort(L.begin(), L.end(), [](const LRow &a, const LRow &b) { return a.nb() > b.nb(); });
             std::vector<RowDesc> rows;
             std::vector<BlkDesc> blks;
             std::vector<int32_t> slots;
+            rows.reserve(L.size());
+            blks.reserve(pool.size());
+            slots.reserve(pool.size());
             for (const LRow &r : L) {
                 RowDesc d;
                 d.out = mv_off(r.point, r.id);
@@ -590,7 +643,8 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
                 d.R = r.R;
                 d.sel = r.sel;
                 d.b0 = int32_t(blks.size());
-                for (const LBlk &b : r.b) {
+                for (size_t i = r.b0; i < r.b1; ++i) {
+                    const LBlk &b = pool[i];
                     blks.push_back({b.a, mv_off(b.point, b.id), b.C, b.sidx});
                     slots.push_back(b.slot);
                 }
@@ -610,7 +664,7 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
             w.partials_bytes = int64_t(offd.size()) * 64 * (A.vec_f64 ? 8 : 4);
             w.partials = A.mem.alloc(w.partials_bytes);
             A.lists.push_back(w);
-            L.clear();
+            clear();
         }
     }
     if (!A.half) {
@@ -618,18 +672,33 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
         // outgrow the last-level cache, so rows stay in spatial order -- leaf rows
         // (dense) first, then coupling rows from the finest level up, each by
         // index -- and concurrently running rows share their input tiles.
-        std::vector<LRow> spatial;
-        for (const LRow &r : L)
-            if (r.point) spatial.push_back(r);
+        std::vector<size_t> spatial;
+        spatial.reserve(L.size());
+        for (size_t r = 0; r < L.size(); ++r)
+            if (L[r].point) spatial.push_back(r);
         for (int l = q; l >= s.lmin && lowrank; --l)
-            for (const LRow &r : L)
-                if (!r.point && r.id >= Structure::first(l) && r.id < Structure::first(l + 1)) spatial.push_back(r);
-        emit_one(1, PH_STREAM, sk, A.blocks, spatial);
+            for (size_t r = 0; r < L.size(); ++r)
+                if (!L[r].point && L[r].id >= Structure::first(l) && L[r].id < Structure::first(l + 1))
+                    spatial.push_back(r);
+        // (encoded on a second host thread while this one orders and encodes
+        // the single-vector list)
+        auto tiles = std::async(std::launch::async, [&] { return encode(1, PH_STREAM, &spatial); });
         // Single right-hand side: the vector trees fit in the caches; longest
         // rows first, so the wavefronts that start last are the short ones.
-        std::stable_sort(L.begin(), L.end(), [](const LRow &a, const LRow &b) { return a.b.size() > b.b.size(); });
-        int64_t nblk = 0;
-        for (const LRow &r : L) nblk += int64_t(r.b.size());
+        std::vector<size_t> by_len(L.size());
+        std::iota(by_len.begin(), by_len.end(), size_t(0));
+        std::stable_sort(by_len.begin(), by_len.end(), [&](size_t a, size_t b) { return L[a].nb() > L[b].nb(); });
+        const int64_t nblk = int64_t(pool.size());
+        const bool split = int64_t(L.size()) < kSplitRows && nblk > int64_t(L.size());
+        Encoded single;
+        if (!split) single = encode(0, PH_STREAM, &by_len);
+        commit(1, PH_STREAM, sk, A.blocks, tiles.get());
+        {
+            std::vector<LRow> sorted;
+            sorted.reserve(L.size());
+            for (size_t r : by_len) sorted.push_back(L[r]);
+            L.swap(sorted);
+        }
         // the streamed schedule's order: coupling rows, then near-field rows
         std::vector<size_t> order;
         for (size_t r = 0; r < L.size(); ++r)
@@ -638,7 +707,7 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
         for (size_t r = 0; r < L.size(); ++r)
             if (L[r].point) order.push_back(r);
         std::vector<int64_t> near_cum{0};
-        if (int64_t(L.size()) < kSplitRows && nblk > int64_t(L.size())) {
+        if (split) {
             // few rows: every row cut into chunks of `chunk` blocks, one wavefront
             // each, writing FP64 partial sums that a second launch adds up per row
             const int chunk = int(std::max<int64_t>(1, (nblk + kSplitWaves - 1) / kSplitWaves));
@@ -648,7 +717,7 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
             std::vector<size_t> first_chunk;   // per row of L: its first chunk in rows
             for (const LRow &r : L) {
                 first_chunk.push_back(rows.size());
-                const int nb = int(r.b.size()), nc = std::max(1, (nb + chunk - 1) / chunk);
+                const int nb = int(r.nb()), nc = std::max(1, (nb + chunk - 1) / chunk);
                 red.push_back({mv_off(r.point, r.id), int32_t(rows.size()), int32_t(rows.size() + nc), r.R,
                                r.point ? 1 : 0});
                 for (int c = 0; c < nc; ++c) {
@@ -658,8 +727,10 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
                     d.R = r.R;
                     d.sel = (r.sel & h2::ROW_IN_X) | h2::ROW_OUT_P;
                     d.b0 = int32_t(blks.size());
-                    for (int b = c * chunk; b < std::min(nb, (c + 1) * chunk); ++b)
-                        blks.push_back({r.b[b].a, mv_off(r.b[b].point, r.b[b].id), r.b[b].C, r.b[b].sidx});
+                    for (int b = c * chunk; b < std::min(nb, (c + 1) * chunk); ++b) {
+                        const LBlk &lb = pool[r.b0 + size_t(b)];
+                        blks.push_back({lb.a, mv_off(lb.point, lb.id), lb.C, lb.sidx});
+                    }
                     d.b1 = int32_t(blks.size());
                     rows.push_back(d);
                 }
@@ -693,10 +764,11 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
             w.near_cum = std::move(near_cum);
             A.lists.push_back(w);
         } else {
-            emit_one(0, PH_STREAM, sk, A.blocks, L);
+            commit(0, PH_STREAM, sk, A.blocks, std::move(single));
             std::vector<int64_t> b0(L.size() + 1, 0);
-            for (size_t r = 0; r < L.size(); ++r) b0[r + 1] = b0[r] + int64_t(L[r].b.size());
+            for (size_t r = 0; r < L.size(); ++r) b0[r + 1] = b0[r] + int64_t(L[r].nb());
             std::vector<RowDesc> srows;
+            srows.reserve(L.size());
             for (size_t o = 0; o < order.size(); ++o) {
                 const LRow &r = L[order[o]];
                 RowDesc d;
@@ -707,30 +779,31 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
                 d.R = r.R;
                 d.sel = r.sel;
                 srows.push_back(d);
-                if (int64_t(o) >= ncoup) near_cum.push_back(near_cum.back() + int64_t(r.b.size()));
+                if (int64_t(o) >= ncoup) near_cum.push_back(near_cum.back() + int64_t(r.nb()));
             }
             WorkList &w = A.lists.back();
             w.srows = A.mem.upload(srows, stream);
             w.nsrows_coupling = ncoup;
             w.near_cum = std::move(near_cum);
         }
-        L.clear();
+        clear();
     }
     if (lowrank) {
         // downsweep y^_c += E_c y^_parent for levels lmin+1 .. q   (Sec. 4.4)
         for (int l = s.lmin + 1; l <= q; ++l) {
-            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c)
-                L.push_back({false, c, true, kl[l], 0, {{off_E[c], kl[l - 1], 0, false, (c - 1) / 2}}});
-            emit(PH_DOWN, bk, A.basis, L);
+            for (int64_t c = Structure::first(l); c < Structure::first(l + 1); ++c) {
+                add_row(false, c, true, kl[l], 0);
+                add_blk(off_E[c], kl[l - 1], 0, false, (c - 1) / 2);
+            }
+            emit(PH_DOWN, bk, A.basis);
         }
     }
     // leaf expansion and sum: y(i) = y_near(i) + U_i y^_i   (Sec. 4.4, Sec. 4.1)
     for (int64_t j = 0; j < nleaves; ++j) {
-        LRow r{true, j, true, int(s.size(lf + j)), h2::ROW_OUT_P, {}};
-        if (lowrank) r.b.push_back({off_U[j], kl[q], 0, false, lf + j});
-        L.push_back(std::move(r));
+        add_row(true, j, true, int(s.size(lf + j)), h2::ROW_OUT_P);
+        if (lowrank) add_blk(off_U[j], kl[q], 0, false, lf + j);
     }
-    emit(PH_LEAF, bk, A.basis, L);
+    emit(PH_LEAF, bk, A.basis);
     std::vector<int64_t> lb(nleaves), le(nleaves);
     for (int64_t j = 0; j < nleaves; ++j) {
         lb[j] = s.begin[lf + j];

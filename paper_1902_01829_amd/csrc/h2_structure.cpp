@@ -57,15 +57,11 @@ void split_level(const double *points, int dim, int level, Structure &s) {
             s.end[2 * v + 2] = e;
         }
     };
-    const int64_t threads = std::min<int64_t>(count, std::max(1u, std::thread::hardware_concurrency()));
-    if (threads <= 1 || s.n < 50000) {
+    if (s.n < 50000) {
         work(0, count);
         return;
     }
-    std::vector<std::future<void>> jobs;
-    for (int64_t t = 0; t < threads; ++t)
-        jobs.push_back(std::async(std::launch::async, work, count * t / threads, count * (t + 1) / threads));
-    for (auto &f : jobs) f.get();
+    parallel_ranges(count, 1, work);
 }
 
 void compute_boxes(Structure &s) {

@@ -2,11 +2,35 @@
 // block-sparse-row partition.  Internal to libh2mv.
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
+#include <future>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace h2 {
+
+// Host threads of the library's set-up loops: the machine's, at most 16.
+inline int64_t host_threads() {
+    return std::max<int64_t>(1, std::min<int64_t>(16, int64_t(std::thread::hardware_concurrency())));
+}
+
+// Runs f(i0, i1) on contiguous pieces of [0, n), one per host thread, with
+// at least min_piece items per piece (all on the calling thread when n is
+// small).  An exception thrown by a piece reaches the caller.
+template <typename F>
+void parallel_ranges(int64_t n, int64_t min_piece, const F &f) {
+    const int64_t t = std::min(host_threads(), std::max<int64_t>(1, n / std::max<int64_t>(1, min_piece)));
+    if (t <= 1) {
+        f(int64_t(0), n);
+        return;
+    }
+    std::vector<std::future<void>> jobs;
+    for (int64_t i = 1; i < t; ++i) jobs.push_back(std::async(std::launch::async, f, n * i / t, n * (i + 1) / t));
+    f(int64_t(0), n / t);
+    for (auto &j : jobs) j.get();
+}
 
 struct Bsr {
     std::vector<int32_t> rowptr;   // rows + 1

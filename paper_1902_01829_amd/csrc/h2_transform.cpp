@@ -156,33 +156,34 @@ h2_matrix_ *transpose_matrix(h2_matrix_ &A, hipStream_t st) {
     B->vec_f64 = A.vec_f64;
     B->symmetric = A.symmetric;
     // transposed rows; for block t of B (fill order): the block of A it copies and that block's size
-    std::vector<int64_t> src_fill;
-    std::vector<int32_t> src_R, src_C;
-    auto transpose_bsr = [&](const h2::Bsr &in, int64_t rows, int64_t fill0, h2::Bsr &out,
-                             const std::function<void(int64_t, int64_t)> &dims) {
+    int64_t total = s.dense.blocks();
+    for (int l = 0; l <= q; ++l) total += s.coupling[l].blocks();
+    const size_t nblk = size_t(total);
+    std::vector<int64_t> src_fill(nblk);
+    std::vector<int32_t> src_R(nblk), src_C(nblk);
+    // out = in^T (rows: block columns of in); from[pos] = the block of in that block pos of out mirrors
+    auto transpose_bsr = [](const h2::Bsr &in, int64_t rows, h2::Bsr &out, std::vector<int32_t> &from) {
         out.rowptr.assign(size_t(rows + 1), 0);
         for (int32_t c : in.colidx) ++out.rowptr[size_t(c) + 1];
         for (int64_t i = 0; i < rows; ++i) out.rowptr[i + 1] += out.rowptr[i];
         out.colidx.assign(in.colidx.size(), 0);
+        from.assign(in.colidx.size(), 0);
         std::vector<int32_t> next(out.rowptr.begin(), out.rowptr.end() - 1);
-        std::vector<int64_t> from(in.colidx.size());
         for (int64_t i = 0; i < rows; ++i)
             for (int32_t t = in.rowptr[i]; t < in.rowptr[i + 1]; ++t) {
                 const int32_t pos = next[in.colidx[t]]++;
                 out.colidx[pos] = int32_t(i);
                 from[pos] = t;
             }
-        for (size_t pos = 0; pos < from.size(); ++pos) {
-            src_fill.push_back(fill0 + from[pos]);
-            dims(from[pos], int64_t(pos));
-        }
     };
+    std::vector<int32_t> from;
     int64_t fill0 = 0;
     for (int l = 0; l <= q; ++l) {
-        transpose_bsr(s.coupling[l], int64_t(1) << l, fill0, B->st.coupling[l], [&](int64_t, int64_t) {
-            src_R.push_back(kl[l]);
-            src_C.push_back(kl[l]);
-        });
+        transpose_bsr(s.coupling[l], int64_t(1) << l, B->st.coupling[l], from);
+        for (size_t pos = 0; pos < from.size(); ++pos) {
+            src_fill[size_t(fill0) + pos] = fill0 + from[pos];
+            src_R[size_t(fill0) + pos] = src_C[size_t(fill0) + pos] = kl[l];
+        }
         fill0 += s.coupling[l].blocks();
     }
     {
@@ -190,18 +191,24 @@ h2_matrix_ *transpose_matrix(h2_matrix_ &A, hipStream_t st) {
         std::vector<int32_t> row_of(s.dense.colidx.size());
         for (int64_t i = 0; i < nleaves; ++i)
             for (int32_t t = s.dense.rowptr[i]; t < s.dense.rowptr[i + 1]; ++t) row_of[t] = int32_t(i);
-        transpose_bsr(s.dense, nleaves, fill0, B->st.dense, [&](int64_t t, int64_t) {
-            src_R.push_back(int32_t(s.size(lf + row_of[t])));
-            src_C.push_back(int32_t(s.size(lf + s.dense.colidx[t])));
-        });
+        transpose_bsr(s.dense, nleaves, B->st.dense, from);
+        for (size_t pos = 0; pos < from.size(); ++pos) {
+            const int32_t t = from[pos];
+            src_fill[size_t(fill0) + pos] = fill0 + t;
+            src_R[size_t(fill0) + pos] = int32_t(s.size(lf + row_of[t]));
+            src_C[size_t(fill0) + pos] = int32_t(s.size(lf + s.dense.colidx[t]));
+        }
     }
     int64_t ncoupling = 0;
     const std::vector<h2::FillDesc> fill = make_layout(*B, ncoupling);
     DeviceArena scratch;
     std::vector<h2::TransDesc> tb(fill.size()), tbas;
-    for (size_t fb = 0; fb < fill.size(); ++fb)
-        tb[fb] = {A.off_blk[size_t(src_fill[fb])], B->off_blk[fb], src_R[fb], src_C[fb]};
+    h2::parallel_ranges(int64_t(fill.size()), 1 << 16, [&](int64_t f0, int64_t f1) {
+        for (int64_t fb = f0; fb < f1; ++fb)
+            tb[fb] = {A.off_blk[size_t(src_fill[fb])], B->off_blk[fb], src_R[fb], src_C[fb]};
+    });
     if (s.lmin <= q) {
+        tbas.reserve(size_t(2 * s.nnodes));
         for (int64_t j = 0; j < nleaves; ++j) {
             const int m = int(s.size(lf + j));
             tbas.push_back({A.off_VT[j], B->off_U[j], kl[q], m});   // U'_j = (V_j^T)^T
