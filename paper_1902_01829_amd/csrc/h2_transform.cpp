@@ -12,6 +12,11 @@ namespace {
 bool coupling_symmetric(h2_matrix_ &A, hipStream_t st) {
     const Structure &s = A.st;
     std::vector<h2::MirrorDesc> pairs;
+    {
+        int64_t total = 0;
+        for (const auto &B : s.coupling) total += B.blocks();
+        pairs.reserve(size_t(total / 2 + s.nnodes));
+    }
     int64_t fi = 0;
     for (int l = 0; l <= s.q; ++l) {
         const h2::Bsr &B = s.coupling[l];
@@ -102,6 +107,11 @@ void orthogonalize(h2_matrix_ &A, hipStream_t st) {
     for (int l = q; l > s.lmin; --l)
         if (2 * s.lrank[l] < s.lrank[l - 1]) fail(H2_ERR_UNSUPPORTED, "a level's rank exceeds twice its children's");
     std::vector<h2::ProjDesc> proj;
+    {
+        int64_t total = 0;
+        for (const auto &B : s.coupling) total += B.blocks();
+        proj.reserve(size_t(total));
+    }
     int64_t fi = 0;
     for (int l = 0; l <= q; ++l) {
         const h2::Bsr &B = s.coupling[l];
@@ -266,6 +276,9 @@ void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
         std::vector<h2::ProjDesc> blk;
         std::vector<int64_t> row_start(s.nnodes + 1);
         {
+            int64_t total = 0;
+            for (const auto &B : s.coupling) total += B.blocks();
+            blk.reserve(size_t(total));
             int64_t fi = 0;
             for (int l = 0; l <= q; ++l) {
                 const h2::Bsr &B = s.coupling[l];
@@ -392,11 +405,11 @@ void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
         check_hip(h2::launch_place(Lc.Unew, nbasis, scratch.upload(pv, st), int64_t(pv.size()), st), "place launch");
         check_hip(h2::launch_place(Lr.Enew, nbasis, scratch.upload(pe, st), int64_t(pe.size()), st), "place launch");
         check_hip(h2::launch_place(Lc.Enew, nbasis, scratch.upload(pf, st), int64_t(pf.size()), st), "place launch");
-        for (size_t i = 0; i < blk.size(); ++i) {
-            const int l = int(std::floor(std::log2(double(blk[i].row + 1))));
-            blk[i].out = B->off_blk[i];
-            blk[i].kout = kt[l];
-        }
+        for (int l = 0; l <= q; ++l)   // the blocks of level l: rows first(l) .. first(l + 1) - 1
+            for (int64_t i = row_start[Structure::first(l)]; i < row_start[Structure::first(l + 1)]; ++i) {
+                blk[size_t(i)].out = B->off_blk[size_t(i)];
+                blk[size_t(i)].kout = kt[l];
+            }
         check_hip(h2::launch_project(static_cast<const double *>(A.blocks), static_cast<double *>(B->blocks),
                                      scratch.upload(blk, st), int64_t(blk.size()), Lr.T, Lc.T, kmax, st),
                   "projection launch");
