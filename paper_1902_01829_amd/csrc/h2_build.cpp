@@ -682,7 +682,8 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
                     spatial.push_back(r);
         // (encoded on a second host thread while this one orders and encodes
         // the single-vector list)
-        auto tiles = std::async(std::launch::async, [&] { return encode(1, PH_STREAM, &spatial); });
+        auto tiles = std::async(std::launch::async | std::launch::deferred,
+                                [&] { return encode(1, PH_STREAM, &spatial); });
         // Single right-hand side: the vector trees fit in the caches; longest
         // rows first, so the wavefronts that start last are the short ones.
         std::vector<size_t> by_len(L.size());

@@ -18,7 +18,9 @@ inline int64_t host_threads() {
 
 // Runs f(i0, i1) on contiguous pieces of [0, n), one per host thread, with
 // at least min_piece items per piece (all on the calling thread when n is
-// small).  An exception thrown by a piece reaches the caller.
+// small; a piece whose thread cannot be started runs on the calling thread
+// when its result is collected).  An exception thrown by a piece reaches the
+// caller.
 template <typename F>
 void parallel_ranges(int64_t n, int64_t min_piece, const F &f) {
     const int64_t t = std::min(host_threads(), std::max<int64_t>(1, n / std::max<int64_t>(1, min_piece)));
@@ -27,7 +29,8 @@ void parallel_ranges(int64_t n, int64_t min_piece, const F &f) {
         return;
     }
     std::vector<std::future<void>> jobs;
-    for (int64_t i = 1; i < t; ++i) jobs.push_back(std::async(std::launch::async, f, n * i / t, n * (i + 1) / t));
+    for (int64_t i = 1; i < t; ++i)
+        jobs.push_back(std::async(std::launch::async | std::launch::deferred, f, n * i / t, n * (i + 1) / t));
     f(int64_t(0), n / t);
     for (auto &j : jobs) j.get();
 }
