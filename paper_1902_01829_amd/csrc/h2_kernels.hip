@@ -303,7 +303,14 @@ __global__ __launch_bounds__(256) void transpose_blocks_kernel(const T *__restri
 // streams its row's 16-byte items of the block with non-temporal loads and
 // accumulates the block's dot products.  One block's partial sum is kept in
 // the block arithmetic type, sums over blocks in FP64.
-template <int KIND, typename TV, typename TO1>
+// ONE_ROUND (the tree sweeps and the leaf launch, whose rows hold one or two
+// blocks): all of a lane's items of a block are requested at once, before
+// the input segment, so a block costs one memory round trip instead of one
+// per eight items; on the few rows of the levels near the root that chain is
+// the launch's whole duration.  The streaming launch's rows hold many blocks
+// and keep eight items in flight per round, which leaves room for more
+// wavefronts per SIMD.  Both take the same products in the same order.
+template <int KIND, typename TV, typename TO1, bool ONE_ROUND>
 __device__ __forceinline__ void blockrow_body(
     const RowDesc *__restrict__ rows, int64_t nrows, const BlkDesc *__restrict__ blks,
     const typename Elem<KIND>::T *__restrict__ data, const float *__restrict__ scales,
@@ -314,7 +321,11 @@ __device__ __forceinline__ void blockrow_body(
     constexpr int W = E::W;
     __shared__ __attribute__((aligned(16))) P xs[4][64];
     __shared__ double red[4][64];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // ONE_ROUND: the wave index made uniform, so that the row and block
+    // descriptors come through scalar loads and a block's base address is
+    // uniform (its loads then take 32-bit lane offsets)
+    const int wv = ONE_ROUND ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int64_t row = int64_t(blockIdx.x) * 4 + wv;
     if (row >= nrows) return;
     const RowDesc rd = rows[row];
@@ -324,24 +335,81 @@ __device__ __forceinline__ void blockrow_body(
     for (int b = rd.b0; b < rd.b1; ++b) {
         const BlkDesc bd = blks[b];
         const int C = bd.C, CW = (C + W - 1) / W;
-        P xv = P(0);
-        if (lane < C) xv = in_x ? P(in1[bd.in + lane]) : P(in0[bd.in + lane]);
-        xs[wv][lane] = xv;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        using V = typename E::V;
         P part = P(0);
-        if (grp < G) {
-            using V = typename E::V;
-            const V *p = reinterpret_cast<const V *>(data + bd.a) + (grp * R + rr);
-            const int stride = G * R;
-#pragma unroll 8
-            for (int cw = grp; cw < CW; cw += G, p += stride) {
-                const V raw = __builtin_nontemporal_load(p);
-                P v[W];
-                E::unpack(raw, v);
+        bool done = false;
+        if constexpr (ONE_ROUND) {
+            // Blocks of at most 8 items per lane: N items, a compile-time
+            // count (the smallest of 2, 4, 8 covering the block's ceil(CW / G)
+            // column groups per lane, a wave-uniform choice), so that they
+            // stay in registers.  Item t is column group grp + t G, clamped
+            // into the block (every load is valid; the clamped ones are not
+            // used).  Larger blocks take the streaming loop below (a fully
+            // unrolled round of 16 or 32 items made the kernel's code several
+            // times longer and the launches near the root slower).
+            auto round = [&](auto n) {
+                constexpr int N = decltype(n)::value;
+                V raw[N];
+                // a wave-uniform base and 32-bit lane offsets (a block is at
+                // most 32 KiB), so the loads need no 64-bit address per item
+                const char *base = reinterpret_cast<const char *>(data + bd.a);
 #pragma unroll
-                for (int w = 0; w < W; ++w) part = fma(v[w], xs[wv][cw * W + w], part);
+                for (int t = 0; t < N; ++t) {
+                    const int cw = grp + t * G;
+                    const uint32_t off = uint32_t((cw < CW ? cw : CW - 1) * R + rr) * 16u;
+                    raw[t] = __builtin_nontemporal_load(reinterpret_cast<const V *>(base + off));
+                }
+                P xv = P(0);
+                if (lane < C) xv = in_x ? P(in1[bd.in + lane]) : P(in0[bd.in + lane]);
+                xs[wv][lane] = xv;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                P s = P(0);
+                if (grp < G) {
+#pragma unroll
+                    for (int t = 0; t < N; ++t) {
+                        const int cw = grp + t * G;
+                        if (cw < CW) {
+                            P v[W];
+                            E::unpack(raw[t], v);
+#pragma unroll
+                            for (int w = 0; w < W; ++w) s = fma(v[w], xs[wv][cw * W + w], s);
+                        }
+                    }
+                }
+                return s;
+            };
+            const int ni = (CW + G - 1) / G;
+            using std::integral_constant;
+            done = ni <= 8;
+            if (ni <= 0)
+                ;   // a block without columns adds nothing
+            else if (ni <= 2)
+                part = round(integral_constant<int, 2>{});
+            else if (ni <= 4)
+                part = round(integral_constant<int, 4>{});
+            else if (ni <= 8)
+                part = round(integral_constant<int, 8>{});
+        }
+        if (!done) {
+            P xv = P(0);
+            if (lane < C) xv = in_x ? P(in1[bd.in + lane]) : P(in0[bd.in + lane]);
+            xs[wv][lane] = xv;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (grp < G) {
+                const V *p = reinterpret_cast<const V *>(data + bd.a) + (grp * R + rr);
+                const int stride = G * R;
+#pragma unroll 8
+                for (int cw = grp; cw < CW; cw += G, p += stride) {
+                    const V raw = __builtin_nontemporal_load(p);
+                    P v[W];
+                    E::unpack(raw, v);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) part = fma(v[w], xs[wv][cw * W + w], part);
+                }
             }
         }
         if constexpr (KIND == ELEM_BF16)
@@ -371,19 +439,19 @@ __device__ __forceinline__ void blockrow_body(
 
 // One kernel name per phase of the product, so that traces and per-kernel
 // statistics separate them; all share the block-row body.
-#define H2_BLOCKROW_KERNEL(NAME)                                                                         \
+#define H2_BLOCKROW_KERNEL(NAME, ONE_ROUND)                                                              \
     template <int KIND, typename TV, typename TO1>                                                      \
     __global__ __launch_bounds__(256) void NAME(                                                        \
         const RowDesc *__restrict__ rows, int64_t nrows, const BlkDesc *__restrict__ blks,              \
         const typename Elem<KIND>::T *__restrict__ data, const float *__restrict__ scales,               \
         const TV *__restrict__ in0, const double *__restrict__ in1, const TV *__restrict__ init,         \
         TV *__restrict__ out0, TO1 *__restrict__ out1) {                                                 \
-        blockrow_body<KIND, TV, TO1>(rows, nrows, blks, data, scales, in0, in1, init, out0, out1);      \
+        blockrow_body<KIND, TV, TO1, ONE_ROUND>(rows, nrows, blks, data, scales, in0, in1, init, out0, out1); \
     }
-H2_BLOCKROW_KERNEL(upsweep_kernel)
-H2_BLOCKROW_KERNEL(stream_kernel)
-H2_BLOCKROW_KERNEL(downsweep_kernel)
-H2_BLOCKROW_KERNEL(leafexpand_kernel)
+H2_BLOCKROW_KERNEL(upsweep_kernel, true)
+H2_BLOCKROW_KERNEL(stream_kernel, false)
+H2_BLOCKROW_KERNEL(downsweep_kernel, true)
+H2_BLOCKROW_KERNEL(leafexpand_kernel, true)
 #undef H2_BLOCKROW_KERNEL
 
 // ---------------------------------------------------------------- half storage
