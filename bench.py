@@ -360,6 +360,13 @@ def _time_matvec(A, x, y, steps):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
+# Seconds waited after releasing a call's matrix before the next timed call
+# of the transpose and compression sections: the HIP runtime's hipMalloc of
+# tens of GB right after freeing as much has taken 0.8-4.6 s (HIP API trace),
+# which is the driver returning the previous allocation, not the call.
+SETTLE_S = 2.0
+
+
 def compress_section(steps=10, reps=3, nrows=256):
     """Algebraic compression (Sec. 5) on the GPU, FP64: the 2-D 2^20-point
     workload at the paper's 2-D threshold 1e-7 and the 3-D 2^19-point one at
@@ -391,6 +398,7 @@ def compress_section(steps=10, reps=3, nrows=256):
             if rep + 1 < reps:
                 A.close()
                 torch.cuda.empty_cache()
+                time.sleep(SETTLE_S)
         info1 = A.info
         mv1 = _time_matvec(A, x, y, steps)
         y1 = y.cpu().numpy()
@@ -446,6 +454,7 @@ def transpose_section(reps=5):
         At.close()   # hipFree of its ~47 GB
         free_ms.append((time.perf_counter() - t0) * 1e3)
         torch.cuda.empty_cache()
+        time.sleep(SETTLE_S)
     A.close()
     nbytes = 2 * (info.bytes_coupling + info.bytes_dense + info.bytes_leaf_bases + info.bytes_transfers)
     med = float(np.median(ms))
@@ -754,6 +763,38 @@ def schedule_section(trials=5, cases=SCHEDULE_CASES):
     return out
 
 
+SECTIONS = ("small", "modes", "matmat", "batch", "orthogonalize", "compress", "transpose", "half", "read",
+            "schedule")
+
+
+def run_section(name, args):
+    """One section alone (--only), its JSON on one line."""
+    if name == "small":
+        out = small_case()
+    elif name == "modes":
+        out = storage_modes(args.steps, args.warmup)
+    elif name == "matmat":
+        out = matmat_modes(args.steps, args.warmup, None)
+    elif name == "orthogonalize":
+        out = orthogonalize_section()
+    elif name == "compress":
+        out = compress_section()
+    elif name == "transpose":
+        out = transpose_section()
+    elif name == "read":
+        out = read_ceiling()
+    elif name == "schedule":
+        out = schedule_section()
+    elif name == "half":
+        cases = HALF_CASES
+        if args.half_case:
+            cases = tuple((W.WORKLOADS[c.split("/")[0]], c.split("/")[1]) for c in args.half_case)
+        out = half_section(args.steps, args.warmup, cases=cases)
+    else:
+        out = batch_modes(args.steps, args.warmup)
+    print(json.dumps({"section": name, **out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -765,17 +806,20 @@ def main():
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the storage-mode, many-right-hand-side and batch sections")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--only", choices=["small", "modes", "matmat", "batch", "orthogonalize", "compress",
-                                      "transpose", "half", "read", "schedule"],
-                    default=None,
-                    help="run one section alone and print its JSON (for profiling runs); "
-                         "the headline line is not printed")
+    ap.add_argument("--only", default=None,
+                    help="run these sections alone, in this order (comma-separated: " + ", ".join(SECTIONS) +
+                         ") and print one JSON line per section (for profiling runs); the headline line is "
+                         "not printed")
     ap.add_argument("--half-case", action="append", default=None, metavar="WORKLOAD/STORAGE",
                     help="with --only half: run only these cases (e.g. 2d-n1048576-m64-k64/fp64)")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first run one device-to-device copy of this many GiB (a known-size "
                          "reference for hardware byte counters)")
     args = ap.parse_args()
+    only = [] if args.only is None else args.only.split(",")
+    for name in only:
+        if name not in SECTIONS:
+            ap.error(f"--only: unknown section {name!r} (sections: {', '.join(SECTIONS)})")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the per-GPU kernel at its real shape is what one GPU shows).", file=sys.stderr)
@@ -793,31 +837,9 @@ def main():
         log(f"calibration copy: {nel * 8} bytes read, {nel * 8} bytes written")
         del src, dst
 
-    if args.only is not None:
-        if args.only == "small":
-            out = small_case()
-        elif args.only == "modes":
-            out = storage_modes(args.steps, args.warmup)
-        elif args.only == "matmat":
-            out = matmat_modes(args.steps, args.warmup, None)
-        elif args.only == "orthogonalize":
-            out = orthogonalize_section()
-        elif args.only == "compress":
-            out = compress_section()
-        elif args.only == "transpose":
-            out = transpose_section()
-        elif args.only == "read":
-            out = read_ceiling()
-        elif args.only == "schedule":
-            out = schedule_section()
-        elif args.only == "half":
-            cases = HALF_CASES
-            if args.half_case:
-                cases = tuple((W.WORKLOADS[c.split("/")[0]], c.split("/")[1]) for c in args.half_case)
-            out = half_section(args.steps, args.warmup, cases=cases)
-        else:
-            out = batch_modes(args.steps, args.warmup)
-        print(json.dumps({"section": args.only, **out}), flush=True)
+    for name in only:
+        run_section(name, args)
+    if only:
         return
 
     ceiling = read_ceiling()
