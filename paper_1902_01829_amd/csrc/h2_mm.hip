@@ -223,10 +223,16 @@ struct LaneDescs {
 // block columns 8p .. 8p+7, lane group g = l / 32 supplies columns 8p + 4g + t
 // (t = 0..3), one per MFMA.  With PIPE the block loop is software-pipelined:
 // the loads of block b + 1 are in flight while block b's products run.
+template <bool LEAF, bool BATCH>
+__device__ inline void mm_store32(const MmArgs &g, const RowDesc &rd, int mt, int li, int lg, const double (&tot)[16]);
+template <bool LEAF, bool BATCH>
+__device__ inline void mm_store16(const MmArgs &g, const RowDesc &rd, int mt, int nh, int n, int kq,
+                                  const double (&tot)[2][4]);
+
 template <int KIND, bool LEAF, bool BATCH, bool PIPE>
 __device__ inline void mm_row(const MmArgs &g, int64_t row, int mt, int lane) {
     const RowDesc rd = g.rows[row];
-    const int R = rd.R, Rp = round16(R);
+    const int R = rd.R;
     if (32 * mt >= R) return;
     const int li = lane & 31, lg = lane >> 5;
     const int i = 32 * mt + li;   // block row of this lane's A operand
@@ -278,33 +284,7 @@ __device__ inline void mm_row(const MmArgs &g, int64_t row, int mt, int lane) {
     }
 
     // Lane l holds rows 32*mt + 8*q + 4*(l/32) + e (e = 0..3) of right-hand side l % 32.
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i0 = 32 * mt + 8 * q + 4 * lg;
-        if (i0 >= Rp) continue;
-        if constexpr (LEAF) {
-            // y(i, j) = y_near(i, j) + far part, written to the caller's FP64 matrix
-            if (li >= g.ncols) continue;
-            const f32x4 yn = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(li) * Rp + i0);
-            const double ynv[4] = {yn.x, yn.y, yn.z, yn.w};
-            double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
-            const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
-            double *yc = Yb + int64_t(li) * ldy + rd.out;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (i0 + e < R) yc[i0 + e] = ynv[e] + tot[4 * q + e];
-        } else {
-            double v[4];   // rows R .. Rp-1 are the tile's zero padding
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = i0 + e < R ? tot[4 * q + e] : 0.0;
-            if (rd.init >= 0) {
-                const f32x4 t = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(li) * Rp + i0);
-                v[0] += t.x; v[1] += t.y; v[2] += t.z; v[3] += t.w;
-            }
-            float *o = ((rd.sel & ROW_OUT_P) ? g.out_pts : g.out_tree) + rd.out + int64_t(li) * Rp + i0;
-            *reinterpret_cast<f32x4 *>(o) = f32x4{float(v[0]), float(v[1]), float(v[2]), float(v[3])};
-        }
-    }
+    mm_store32<LEAF, BATCH>(g, rd, mt, li, lg, tot);
 }
 
 // Chunks of the 32-wide loop: FP32 blocks have 8 (8 columns, four K = 2
@@ -372,16 +352,30 @@ __device__ inline f32x16 chunk_products32(const BlockA<KIND> &a_op, const TileB 
 
 // Epilogue shared by the 32-wide block loops: lane l holds rows
 // 32*mt + 8*q + 4*(l/32) + e (e = 0..3) of right-hand side l % 32 in tot.
+// The values added to the result (y_near in the leaf phase, the current y^
+// in the downsweep) are requested for every row group before any store: one
+// memory round trip per row instead of one per group (a load issued after a
+// store also waits for that store).  Rows and columns are clamped into the
+// tile, so every load is valid; the clamped ones are not used.
 template <bool LEAF, bool BATCH>
 __device__ inline void mm_store32(const MmArgs &g, const RowDesc &rd, int mt, int li, int lg, const double (&tot)[16]) {
     const int R = rd.R, Rp = round16(R);
+    f32x4 t[4] = {};
+    if (LEAF || rd.init >= 0) {   // wave-uniform
+        const int lic = LEAF && li >= g.ncols ? g.ncols - 1 : li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i0 = 32 * mt + 8 * q + 4 * lg, i0c = i0 < Rp ? i0 : Rp - 4;
+            t[q] = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(lic) * Rp + i0c);
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int i0 = 32 * mt + 8 * q + 4 * lg;
         if (i0 >= Rp) continue;
         if constexpr (LEAF) {
             if (li >= g.ncols) continue;
-            const f32x4 yn = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(li) * Rp + i0);
+            const f32x4 yn = t[q];
             const double ynv[4] = {yn.x, yn.y, yn.z, yn.w};
             double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
             const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
@@ -394,8 +388,7 @@ __device__ inline void mm_store32(const MmArgs &g, const RowDesc &rd, int mt, in
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[e] = i0 + e < R ? tot[4 * q + e] : 0.0;
             if (rd.init >= 0) {
-                const f32x4 t = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(li) * Rp + i0);
-                v[0] += t.x; v[1] += t.y; v[2] += t.z; v[3] += t.w;
+                v[0] += t[q].x; v[1] += t[q].y; v[2] += t[q].z; v[3] += t[q].w;
             }
             float *o = ((rd.sel & ROW_OUT_P) ? g.out_pts : g.out_tree) + rd.out + int64_t(li) * Rp + i0;
             *reinterpret_cast<f32x4 *>(o) = f32x4{float(v[0]), float(v[1]), float(v[2]), float(v[3])};
@@ -415,6 +408,21 @@ __device__ inline void mm_store32_leaf_lds(const MmArgs &g, const RowDesc &rd, i
     constexpr int LD = 33;   // doubles per right-hand side row (padded)
     double *T = reinterpret_cast<double *>(buf);
     const int li = lane & 31, lg = lane >> 5;
+    const int R = rd.R, Rp = round16(R);
+    const int r = lane & 31, i = 32 * mt + r;
+    // The lane's 16 near-field values, requested together before the
+    // transposition (one memory round trip per row instead of one per four
+    // columns); row and column are clamped into the tile, so every load is
+    // valid (the clamped ones are not used).
+    float yn[16];
+    {
+        const int ic = i < R ? i : R - 1;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int j = 2 * c + lg, jc = j < g.ncols ? j : g.ncols - 1;
+            yn[c] = g.init[rd.init + int64_t(jc) * Rp + ic];
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -422,16 +430,13 @@ __device__ inline void mm_store32_leaf_lds(const MmArgs &g, const RowDesc &rd, i
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int R = rd.R, Rp = round16(R);
-    const int r = lane & 31, i = 32 * mt + r;
     double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
     const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
     if (i < R) {
-#pragma unroll 4
+#pragma unroll
         for (int c = 0; c < 16; ++c) {
             const int j = 2 * c + lg;
-            if (j < g.ncols)
-                Yb[int64_t(j) * ldy + rd.out + i] = double(g.init[rd.init + int64_t(j) * Rp + i]) + T[j * LD + r];
+            if (j < g.ncols) Yb[int64_t(j) * ldy + rd.out + i] = double(yn[c]) + T[j * LD + r];
         }
     }
 }
@@ -642,7 +647,7 @@ __device__ inline void block_products16(const BlockA16<KIND> &a_op, const TileB1
 template <int KIND, bool LEAF, bool BATCH, bool PIPE>
 __device__ inline void mm_row16(const MmArgs &g, int64_t row, int mt, int lane) {
     const RowDesc rd = g.rows[row];
-    const int R = rd.R, Rp = round16(R);
+    const int R = rd.R;
     if (32 * mt >= R) return;
     const int n = lane & 15, kq = lane >> 4;
     const int nh = 32 * mt + 16 < R ? 2 : 1;   // wave-uniform
@@ -706,33 +711,7 @@ __device__ inline void mm_row16(const MmArgs &g, int64_t row, int mt, int lane) 
         }
     }
 
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (h >= nh) break;
-        const int i0 = 32 * mt + 16 * h + 4 * kq;
-        if (i0 >= Rp) continue;
-        if constexpr (LEAF) {
-            if (n >= g.ncols) continue;
-            const f32x4 yn = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(n) * Rp + i0);
-            const double ynv[4] = {yn.x, yn.y, yn.z, yn.w};
-            double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
-            const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
-            double *yc = Yb + int64_t(n) * ldy + rd.out;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (i0 + e < R) yc[i0 + e] = ynv[e] + tot[h][e];
-        } else {
-            double v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = i0 + e < R ? tot[h][e] : 0.0;
-            if (rd.init >= 0) {
-                const f32x4 t = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(n) * Rp + i0);
-                v[0] += t.x; v[1] += t.y; v[2] += t.z; v[3] += t.w;
-            }
-            float *o = ((rd.sel & ROW_OUT_P) ? g.out_pts : g.out_tree) + rd.out + int64_t(n) * Rp + i0;
-            *reinterpret_cast<f32x4 *>(o) = f32x4{float(v[0]), float(v[1]), float(v[2]), float(v[3])};
-        }
-    }
+    mm_store16<LEAF, BATCH>(g, rd, mt, nh, n, kq, tot);
 }
 
 // Chunks of the 16-wide loop: FP32 blocks have 4 (16 columns), BF16 blocks 2
@@ -819,6 +798,15 @@ template <bool LEAF, bool BATCH>
 __device__ inline void mm_store16(const MmArgs &g, const RowDesc &rd, int mt, int nh, int n, int kq,
                                   const double (&tot)[2][4]) {
     const int R = rd.R, Rp = round16(R);
+    f32x4 t[2] = {};   // requested together, as in mm_store32
+    if (LEAF || rd.init >= 0) {   // wave-uniform
+        const int nc = LEAF && n >= g.ncols ? g.ncols - 1 : n;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i0 = 32 * mt + 16 * h + 4 * kq, i0c = i0 < Rp ? i0 : Rp - 4;
+            t[h] = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(nc) * Rp + i0c);
+        }
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         if (h >= nh) break;
@@ -826,7 +814,7 @@ __device__ inline void mm_store16(const MmArgs &g, const RowDesc &rd, int mt, in
         if (i0 >= Rp) continue;
         if constexpr (LEAF) {
             if (n >= g.ncols) continue;
-            const f32x4 yn = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(n) * Rp + i0);
+            const f32x4 yn = t[h];
             const double ynv[4] = {yn.x, yn.y, yn.z, yn.w};
             double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
             const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
@@ -839,8 +827,7 @@ __device__ inline void mm_store16(const MmArgs &g, const RowDesc &rd, int mt, in
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[e] = i0 + e < R ? tot[h][e] : 0.0;
             if (rd.init >= 0) {
-                const f32x4 t = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(n) * Rp + i0);
-                v[0] += t.x; v[1] += t.y; v[2] += t.z; v[3] += t.w;
+                v[0] += t[h].x; v[1] += t[h].y; v[2] += t[h].z; v[3] += t[h].w;
             }
             float *o = ((rd.sel & ROW_OUT_P) ? g.out_pts : g.out_tree) + rd.out + int64_t(n) * Rp + i0;
             *reinterpret_cast<f32x4 *>(o) = f32x4{float(v[0]), float(v[1]), float(v[2]), float(v[3])};
