@@ -1331,12 +1331,19 @@ __global__ __launch_bounds__(256) void pack_kernel(const double *__restrict__ X,
     const int64_t b = leaf_begin[leaf];
     const int m = int(leaf_end[leaf] - b), mp = round16(m);
     float *t = tiles + leaf * slot;
-    for (int e = threadIdx.x; e < NT * mp; e += blockDim.x) {
-        const int j = e / mp, c = e - j * mp;
-        float v = 0.0f;
-        if (c < m && j0 + j < nrhs) v = float(X[(b + c) + int64_t(j0 + j) * ldx]);
-        t[e] = v;
+    // thread = (wavefront w, lane c): leaf row c of columns w, w + 4, ...
+    // (each load instruction reads one 512-byte run of a column of X; all of
+    // a thread's loads are issued before its stores)
+    const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (c >= mp) return;
+    float v[NT / 4];
+#pragma unroll
+    for (int k = 0; k < NT / 4; ++k) {
+        const int j = w + 4 * k;
+        v[k] = c < m && j0 + j < nrhs ? float(X[(b + c) + int64_t(j0 + j) * ldx]) : 0.0f;
     }
+#pragma unroll
+    for (int k = 0; k < NT / 4; ++k) t[int64_t(w + 4 * k) * mp + c] = v[k];
 }
 
 }  // namespace
