@@ -470,13 +470,11 @@ def transpose_section(reps=5):
 HALF = 16   # storage modifier: blocks stored by halves
 
 
-def half_partial_bytes(info, w):
-    """FP64 partial sums of the transposed products, written once and read
-    once: one per stored off-diagonal block, as long as its column segment."""
-    nleaves = 1 << info.levels_q
-    coupling_slots = info.coupling_blocks // 2
-    dense_slots = (info.dense_blocks - nleaves) // 2
-    return 2 * 8 * (coupling_slots * info.rank + dense_slots * w.leaf)
+def half_partial_bytes(info, vb):
+    """Partial sums of the transposed products (slots of 64 values in the
+    vector type, vb bytes each: one per column segment and row group, as the
+    library reports them), written once and read once."""
+    return 2 * vb * 64 * info.partial_slots
 
 
 HALF_CASES = ((W.C2, "fp64"), (W.C3, "fp64"), (W.C3, "fp32"), (W.C3, "bf16"))
@@ -505,7 +503,7 @@ def half_section(steps, warmup, full_ms=None, nleaves=16, cases=HALF_CASES):
         rows, ref = oracle_sample(w, r["perm"], r["xt"], nleaves)
         rel = float(np.linalg.norm(r["y"][rows] - ref) / np.linalg.norm(ref))
         vb = 8 if name == "fp64" else 4
-        phase_bytes = info.bytes_coupling + info.bytes_dense + 8 * w.n + 2 * vb * w.n + half_partial_bytes(info, w)
+        phase_bytes = info.bytes_coupling + info.bytes_dense + 8 * w.n + 2 * vb * w.n + half_partial_bytes(info, vb)
         stream_ms = float(r["phase_ms"][1])
         out[f"{w.name}/{name}"] = {
             "ms": round(r["ms"], 4), "ms_full_storage": round(ms_full, 4),
@@ -514,6 +512,7 @@ def half_section(steps, warmup, full_ms=None, nleaves=16, cases=HALF_CASES):
             "algorithmic_bytes": int(algorithmic_bytes(info, w.n)),
             "GB_per_s": round(algorithmic_bytes(info, w.n) / (r["ms"] * 1e-3) / 1e9, 1),
             "stream_phase_ms": round(stream_ms, 4), "stream_phase_bytes": int(phase_bytes),
+            "partial_slots": int(info.partial_slots),
             "stream_phase_GB_per_s": round(phase_bytes / (stream_ms * 1e-3) / 1e9, 1),
             "rel_err_vs_fp64_oracle": rel}
         log(f"half {w.name} {name}: {r['ms']:.3f} ms (full {ms_full:.3f} ms, x{ms_full / r['ms']:.2f}), stream "

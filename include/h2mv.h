@@ -71,9 +71,10 @@ typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16_SCALED = 2 } h2_storage;
  * blocks with column >= row are held (diagonal dense blocks in full), which
  * about halves the bytes a product streams; the product reads each stored
  * block once for both S_ij x_j and S_ij^T x_i, and adds the transposed
- * contributions of every segment (partial sums per stored off-diagonal block:
- * 64 FP64 values, or FP32 in the reduced modes, summed in FP64) in a second
- * launch.  Products match the full storage up
+ * contributions of every segment (partial slots of 64 FP64 values, or FP32 in
+ * the reduced modes, one per column segment and group of up to 4 consecutive
+ * block rows, summed in FP64; partial_slots in h2_info counts them) in a
+ * second launch.  Products match the full storage up
  * to rounding order.  h2_get_info reports the modifier in storage and the
  * stored bytes in bytes_coupling and bytes_dense.  Handles stored by halves
  * are rejected with UNSUPPORTED by h2_orthogonalize, h2_compress,
@@ -111,6 +112,8 @@ typedef struct {
     int64_t bytes_coupling, bytes_dense, bytes_leaf_bases, bytes_transfers;
     int64_t bytes_device_total; /* all device memory held by the handle           */
     int64_t near_ties;         /* admissibility tests within 1e-12 of equality     */
+    int64_t partial_slots;     /* stored by halves: partial slots of 64 values the
+                                  product writes and reads once (else 0)           */
 } h2_info;
 
 /* Build an H^2 matrix from points (Sec. 4.6).

@@ -43,6 +43,9 @@ h2_status h2_get_info(h2_handle A, h2_info *info) {
     r.bytes_transfers = A->bytes_transfer;
     r.bytes_device_total = A->mem.bytes;
     r.near_ties = s.near_ties;
+    if (A->half)
+        for (const WorkList &w : A->lists)
+            if (w.slot) r.partial_slots += w.partials_bytes / (64 * (A->vec_f64 ? 8 : 4));
     *info = r;
     return H2_OK;
 }

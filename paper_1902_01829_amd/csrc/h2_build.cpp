@@ -604,52 +604,124 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
         }
         if (A.half) {
             // One launch reads every stored block once for both of its
-            // products; the transposed ones land in partial slots, grouped by
-            // the segment they belong to, and a second launch adds each
-            // segment's slots to its row sum.
-            struct Off {
+            // products.  Its wavefronts take groups of up to HALF_GROUP_ROWS
+            // consecutive block rows of one kind (the list's spatial order:
+            // coupling rows level by level, then leaf rows), whose transposed
+            // products of one column segment are added in LDS, rows in order,
+            // and written to one partial slot per segment and group (a
+            // group's segments fit in HALF_LDS_SLOTS; a row alone that has
+            // more sends the rest to slots of their own).  Slots are numbered
+            // by segment, and a second launch adds each segment's slots to
+            // its row sum, in order (deterministic).
+            struct Col {
                 bool point;
                 int64_t id;
-                size_t blk;   // index in the pool
+                int32_t C;
             };
-            std::vector<Off> offd;
-            for (size_t r = 0; r < L.size(); ++r)
-                for (size_t b = L[r].b0; b < L[r].b1; ++b)
-                    if (pool[b].point != L[r].point || pool[b].id != L[r].id)
-                        offd.push_back({pool[b].point, pool[b].id, b});
-            std::stable_sort(offd.begin(), offd.end(), [](const Off &x, const Off &y) {
-                return x.point != y.point ? x.point < y.point : x.id < y.id;
-            });
-            if (offd.size() >= (size_t(1) << 31)) fail(H2_ERR_UNSUPPORTED, "too many blocks stored by halves");
-            std::vector<h2::ReduceDesc> red;
-            for (size_t k = 0; k < offd.size(); ++k) {
-                LBlk &lb = pool[offd[k].blk];
-                lb.slot = int32_t(k);
-                if (k == 0 || offd[k].point != offd[k - 1].point || offd[k].id != offd[k - 1].id)
-                    red.push_back({mv_off(lb.point, lb.id), int32_t(k), int32_t(k), lb.C, lb.point ? 1 : 0});
-                red.back().c1 = int32_t(k + 1);
+            struct Grp {
+                size_t r0, r1;
+                std::vector<Col> cols;   // merged segments, first appearance first
+                int64_t nblk;
+            };
+            auto off_diagonal = [&](const LRow &r, const LBlk &b) { return b.point != r.point || b.id != r.id; };
+            auto find_col = [](const std::vector<Col> &cols, const LBlk &b) {
+                for (size_t c = 0; c < cols.size(); ++c)
+                    if (cols[c].point == b.point && cols[c].id == b.id) return int(c);
+                return -1;
+            };
+            std::vector<Grp> groups;
+            for (size_t r = 0; r < L.size();) {
+                Grp G{r, r, {}, 0};
+                while (G.r1 < L.size() && G.r1 - G.r0 < size_t(h2::HALF_GROUP_ROWS)) {
+                    const LRow &row = L[G.r1];
+                    if (G.r1 > G.r0) {   // a further row joins only if its kind and new segments fit
+                        if (row.point != L[G.r0].point) break;
+                        size_t add = 0;
+                        for (size_t b = row.b0; b < row.b1; ++b)
+                            if (off_diagonal(row, pool[b]) && find_col(G.cols, pool[b]) < 0) ++add;
+                        if (G.cols.size() + add > size_t(h2::HALF_LDS_SLOTS)) break;
+                    }
+                    for (size_t b = row.b0; b < row.b1; ++b) {
+                        LBlk &lb = pool[b];
+                        if (!off_diagonal(row, lb)) {
+                            lb.slot = -1;
+                            continue;
+                        }
+                        int c = find_col(G.cols, lb);
+                        if (c < 0 && G.cols.size() < size_t(h2::HALF_LDS_SLOTS)) {
+                            c = int(G.cols.size());
+                            G.cols.push_back({lb.point, lb.id, lb.C});
+                        }
+                        lb.slot = c >= 0 ? c : -2;   // -2: a slot of its own, numbered below
+                    }
+                    G.nblk += int64_t(row.nb());
+                    ++G.r1;
+                }
+                groups.push_back(std::move(G));
+                r = groups.back().r1;
             }
-            std::stable_sort(L.begin(), L.end(), [](const LRow &a, const LRow &b) { return a.nb() > b.nb(); });
+            // longest groups first, so the wavefronts that start last are the short ones
+            std::stable_sort(groups.begin(), groups.end(), [](const Grp &x, const Grp &y) { return x.nblk > y.nblk; });
+            // partial slots: one per merged segment of a group, one per block without an LDS slot
+            struct Ent {
+                bool point;
+                int64_t id;
+                int32_t C;
+                size_t gslot_pos;   // merged: position in gslot; else SIZE_MAX
+                size_t blk;         // own slot: the block's pool index
+            };
+            std::vector<Ent> ents;
+            std::vector<int32_t> gslot;
+            std::vector<h2::HalfGroup> hg;
             std::vector<RowDesc> rows;
             std::vector<BlkDesc> blks;
             std::vector<int32_t> slots;
             rows.reserve(L.size());
             blks.reserve(pool.size());
             slots.reserve(pool.size());
-            for (const LRow &r : L) {
-                RowDesc d;
-                d.out = mv_off(r.point, r.id);
-                d.init = -1;
-                d.R = r.R;
-                d.sel = r.sel;
-                d.b0 = int32_t(blks.size());
-                for (size_t i = r.b0; i < r.b1; ++i) {
-                    const LBlk &b = pool[i];
-                    blks.push_back({b.a, mv_off(b.point, b.id), b.C, b.sidx});
-                    slots.push_back(b.slot);
+            for (const Grp &G : groups) {
+                h2::HalfGroup d;
+                d.r0 = int32_t(rows.size());
+                d.s0 = int32_t(gslot.size());
+                for (const Col &c : G.cols) {
+                    ents.push_back({c.point, c.id, c.C, gslot.size(), 0});
+                    gslot.push_back(-1);
                 }
-                d.b1 = int32_t(blks.size());
-                rows.push_back(d);
+                for (size_t r = G.r0; r < G.r1; ++r) {
+                    const LRow &row = L[r];
+                    RowDesc rd;
+                    rd.out = mv_off(row.point, row.id);
+                    rd.init = -1;
+                    rd.R = row.R;
+                    rd.sel = row.sel;
+                    rd.b0 = int32_t(blks.size());
+                    for (size_t i = row.b0; i < row.b1; ++i) {
+                        const LBlk &b = pool[i];
+                        if (b.slot == -2) ents.push_back({b.point, b.id, b.C, SIZE_MAX, blks.size()});
+                        blks.push_back({b.a, mv_off(b.point, b.id), b.C, b.sidx});
+                        slots.push_back(b.slot);
+                    }
+                    rd.b1 = int32_t(blks.size());
+                    rows.push_back(rd);
+                }
+                d.r1 = int32_t(rows.size());
+                d.s1 = int32_t(gslot.size());
+                hg.push_back(d);
+            }
+            std::stable_sort(ents.begin(), ents.end(), [](const Ent &x, const Ent &y) {
+                return x.point != y.point ? x.point < y.point : x.id < y.id;
+            });
+            if (ents.size() >= (size_t(1) << 30)) fail(H2_ERR_UNSUPPORTED, "too many blocks stored by halves");
+            std::vector<h2::ReduceDesc> red;
+            for (size_t k = 0; k < ents.size(); ++k) {
+                const Ent &e = ents[k];
+                if (e.gslot_pos != SIZE_MAX)
+                    gslot[e.gslot_pos] = int32_t(k);
+                else
+                    slots[e.blk] = -(int32_t(k) + 2);
+                if (k == 0 || e.point != ents[k - 1].point || e.id != ents[k - 1].id)
+                    red.push_back({mv_off(e.point, e.id), int32_t(k), int32_t(k), e.C, e.point ? 1 : 0});
+                red.back().c1 = int32_t(k + 1);
             }
             WorkList w;
             w.phase = PH_STREAM;
@@ -659,9 +731,12 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
             w.rows = A.mem.upload(rows, stream);
             w.blks = A.mem.upload(blks, stream);
             w.slot = A.mem.upload(slots, stream);
+            w.groups = A.mem.upload(hg, stream);
+            w.ngroups = int64_t(hg.size());
+            w.gslot = A.mem.upload(gslot, stream);
             w.red = A.mem.upload(red, stream);
             w.nred = int64_t(red.size());
-            w.partials_bytes = int64_t(offd.size()) * 64 * (A.vec_f64 ? 8 : 4);
+            w.partials_bytes = int64_t(ents.size()) * 64 * (A.vec_f64 ? 8 : 4);
             w.partials = A.mem.alloc(w.partials_bytes);
             A.lists.push_back(w);
             clear();

@@ -111,9 +111,13 @@ struct WorkList {
     int64_t nred = 0;
     void *partials = nullptr;   // FP64 (FP32 for the half-storage list of a reduced-storage matrix)
     int64_t partials_bytes = 0;
-    // stream list of a matrix stored by halves: partial slot of every block
-    // (-1: diagonal block); red then adds the slots to the row sums
+    // stream list of a matrix stored by halves: the wavefronts' row groups,
+    // every block's slot code and the groups' merged partial slots (see
+    // h2::HalfGroup); red then adds the slots to the row sums
     const int32_t *slot = nullptr;
+    const h2::HalfGroup *groups = nullptr;
+    int64_t ngroups = 0;
+    const int32_t *gslot = nullptr;
     // single-vector stream list, full storage: the same rows (chunks, for a
     // split list) with the coupling rows first and the near-field rows after,
     // each part in the list's own order, and (split list) the row sums

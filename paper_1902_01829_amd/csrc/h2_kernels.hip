@@ -481,8 +481,9 @@ __device__ __forceinline__ P fold_lanes(P (&v)[N], int lane) {
 }
 
 // Stream phase of a matrix stored by halves: block row i holds only its
-// blocks with j >= i (S_ji = S_ij^T, D_ji = D_ij^T).  One wavefront per block
-// row; with TR lanes per column strip, lane l = TR g + a holds, of every
+// blocks with j >= i (S_ji = S_ij^T, D_ji = D_ij^T).  One wavefront per group
+// of consecutive block rows (at most HALF_GROUP_ROWS, taken one after the
+// other); with TR lanes per column strip, lane l = TR g + a holds, of every
 // block, the tile of rows a + TR k (k < 64 / TR) and columns TR g + c
 // (c < TR), so each stored block is read once (all of a lane's 16-byte items
 // issued together; each load reads 64 / TR runs of TR consecutive rows) and
@@ -490,19 +491,25 @@ __device__ __forceinline__ P fold_lanes(P (&v)[N], int lane) {
 // S_ij x_j for its rows, accumulated over the row's blocks (FP64 across
 // blocks), and of S_ij^T x_i for its columns, summed over the TR lanes of its
 // strip (log2 TR folds), after which lane l holds column l of the transposed
-// product: off-diagonal blocks store it in their partial slot, in the vector
-// type (FP64, or FP32 in the reduced modes: half the partial writes, whose
-// cost on the read stream exceeds their share of the bytes).  At the end of
-// the row the row sums are folded over the strip bits (lane l: row l).
-// A second launch adds each segment's slots to its row sum.  The row's own
-// input segment has the offset of its output segment (x^ and y^ share the node
-// layout, x and y_near the point layout).
+// product.  The group's transposed products of one column segment are added
+// in the wavefront's LDS slot for that segment, rows in order (slot[b] >= 0;
+// lane l only ever touches element l of a slot, so no barrier), and each LDS
+// slot is written once, at the end of the group, to its partial slot
+// (gslot): adjacent block rows share many columns, so this writes fewer
+// partials, whose cost on the read stream exceeds their share of the bytes.
+// A block whose column found no LDS slot writes its own partial slot
+// -(slot[b] + 2); slot[b] == -1 marks a diagonal block (no transposed
+// product).  Partials are in the vector type (FP64, or FP32 in the reduced
+// modes).  At the end of each row the row sums are folded over the strip
+// bits (lane l: row l).  A second launch adds each segment's slots to its row
+// sum.  The row's own input segment has the offset of its output segment
+// (x^ and y^ share the node layout, x and y_near the point layout).
 template <int KIND, typename TV, int TR>
 __global__ __launch_bounds__(256) void stream_half_kernel(
-    const RowDesc *__restrict__ rows, int64_t nrows, const BlkDesc *__restrict__ blks,
-    const int32_t *__restrict__ slot, const typename Elem<KIND>::T *__restrict__ data,
-    const float *__restrict__ scales, const TV *__restrict__ in0, const double *__restrict__ in1,
-    TV *__restrict__ out0, TV *__restrict__ out1, TV *__restrict__ partials) {
+    const HalfGroup *__restrict__ groups, int64_t ngroups, const RowDesc *__restrict__ rows,
+    const BlkDesc *__restrict__ blks, const int32_t *__restrict__ slot, const int32_t *__restrict__ gslot,
+    const typename Elem<KIND>::T *__restrict__ data, const float *__restrict__ scales, const TV *__restrict__ in0,
+    const double *__restrict__ in1, TV *__restrict__ out0, TV *__restrict__ out1, TV *__restrict__ partials) {
     using E = Elem<KIND>;
     using P = typename E::P;
     using V = typename E::V;
@@ -511,95 +518,107 @@ __global__ __launch_bounds__(256) void stream_half_kernel(
     constexpr int IPR = TR / W;    // 16-byte items per row of a strip
     static_assert(IPR >= 1 && TR * NS == 64, "strip of whole 16-byte items");
     __shared__ __attribute__((aligned(16))) P xs[4][64];
-    // the wave index made uniform: row and block descriptors come through scalar loads
+    __shared__ TV acc[4][HALF_LDS_SLOTS][64];
+    // the wave index made uniform: group, row and block descriptors come through scalar loads
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int a = lane % TR, g = lane / TR;
-    const int64_t row = int64_t(blockIdx.x) * 4 + wv;
-    if (row >= nrows) return;
-    const RowDesc rd = rows[row];
-    const int R = rd.R;
-    double rp[NS] = {};   // partial sums of the lane's rows, over the row's blocks
-    // The block loop is pipelined: block b + 1's descriptor, slot and input
-    // are loaded while block b's items are in flight, the next block's input
-    // is staged before block b's partial store (so no wait covers that
-    // store), the LDS fences order LDS only, and the input vector is chosen
-    // once per row (the row is uniform, so one of two instantiations runs).
-    auto blocks = [&](auto input_is_x) {
-        constexpr bool IN_X = decltype(input_is_x)::value;
-        // element e of the input segment at off, zero from element n on (the
-        // load is clamped into the segment, so the loads issue back to back)
-        auto input = [&](int64_t off, int e, int n) {
-            const int ec = e < n ? e : n - 1;
-            P v;
-            if constexpr (IN_X) v = P(in1[off + ec]);
-            else v = P(in0[off + ec]);
-            return e < n ? v : P(0);
-        };
-        P xi[NS];   // the row's own input at the lane's rows
+    const int64_t gi = int64_t(blockIdx.x) * 4 + wv;
+    if (gi >= ngroups) return;
+    const HalfGroup gd = groups[gi];
+    const int ns = gd.s1 - gd.s0;
+    for (int s = 0; s < ns; ++s) acc[wv][s][lane] = TV(0);
+    for (int32_t row = gd.r0; row < gd.r1; ++row) {
+        const RowDesc rd = rows[row];
+        const int R = rd.R;
+        double rp[NS] = {};   // partial sums of the lane's rows, over the row's blocks
+        // The block loop is pipelined: block b + 1's descriptor, slot and input
+        // are loaded while block b's items are in flight, the next block's
+        // input is staged before block b's transposed product is stored, the
+        // LDS fences order LDS only, and the input vector is chosen once per
+        // row (the row is uniform, so one of two instantiations runs).
+        auto blocks = [&](auto input_is_x) {
+            constexpr bool IN_X = decltype(input_is_x)::value;
+            // element e of the input segment at off, zero from element n on (the
+            // load is clamped into the segment, so the loads issue back to back)
+            auto input = [&](int64_t off, int e, int n) {
+                const int ec = e < n ? e : n - 1;
+                P v;
+                if constexpr (IN_X) v = P(in1[off + ec]);
+                else v = P(in0[off + ec]);
+                return e < n ? v : P(0);
+            };
+            P xi[NS];   // the row's own input at the lane's rows
 #pragma unroll
-        for (int k = 0; k < NS; ++k) xi[k] = input(rd.out, a + TR * k, R);
-        if (rd.b0 >= rd.b1) return;
-        P xj[TR];   // the input at the lane's columns of the current block
-        auto stage = [&](const P xv) {
-            xs[wv][lane] = xv;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+            for (int k = 0; k < NS; ++k) xi[k] = input(rd.out, a + TR * k, R);
+            if (rd.b0 >= rd.b1) return;
+            P xj[TR];   // the input at the lane's columns of the current block
+            auto stage = [&](const P xv) {
+                xs[wv][lane] = xv;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 #pragma unroll
-            for (int c = 0; c < TR; ++c) xj[c] = xs[wv][TR * g + c];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-        };
-        BlkDesc bd = blks[rd.b0];
-        int32_t sl = slot[rd.b0];
-        stage(input(bd.in, lane, bd.C));
-        for (int b = rd.b0; b < rd.b1; ++b) {
-            const int C = bd.C, CW = (C + W - 1) / W;
-            const V *p = reinterpret_cast<const V *>(data + bd.a);   // item (cw, r) at cw * R + r
-            V raw[NS][IPR];
+                for (int c = 0; c < TR; ++c) xj[c] = xs[wv][TR * g + c];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+            };
+            BlkDesc bd = blks[rd.b0];
+            int32_t sl = slot[rd.b0];
+            stage(input(bd.in, lane, bd.C));
+            for (int b = rd.b0; b < rd.b1; ++b) {
+                const int C = bd.C, CW = (C + W - 1) / W;
+                const V *p = reinterpret_cast<const V *>(data + bd.a);   // item (cw, r) at cw * R + r
+                V raw[NS][IPR];
 #pragma unroll
-            for (int k = 0; k < NS; ++k)
+                for (int k = 0; k < NS; ++k)
 #pragma unroll
-                for (int i = 0; i < IPR; ++i) {
-                    const int r = a + TR * k, cw = g * IPR + i;
-                    raw[k][i] = V{};
-                    if (r < R && cw < CW) raw[k][i] = __builtin_nontemporal_load(p + cw * R + r);
+                    for (int i = 0; i < IPR; ++i) {
+                        const int r = a + TR * k, cw = g * IPR + i;
+                        raw[k][i] = V{};
+                        if (r < R && cw < CW) raw[k][i] = __builtin_nontemporal_load(p + cw * R + r);
+                    }
+                const bool more = b + 1 < rd.b1;
+                const BlkDesc nbd = blks[more ? b + 1 : b];
+                const int32_t nsl = slot[more ? b + 1 : b];
+                const P nxv = input(nbd.in, lane, nbd.C);   // unused after the last block
+                double scale = 1.0;
+                if constexpr (KIND == ELEM_BF16) scale = double(scales[bd.sidx]);
+                P cp[TR] = {};
+#pragma unroll
+                for (int k = 0; k < NS; ++k) {
+                    P v[TR];
+#pragma unroll
+                    for (int i = 0; i < IPR; ++i) E::unpack(raw[k][i], v + i * W);
+                    P s = P(0);
+#pragma unroll
+                    for (int c = 0; c < TR; ++c) {
+                        s = fma(v[c], xj[c], s);
+                        cp[c] = fma(v[c], xi[k], cp[c]);
+                    }
+                    rp[k] += double(s) * scale;
                 }
-            const bool more = b + 1 < rd.b1;
-            const BlkDesc nbd = blks[more ? b + 1 : b];
-            const int32_t nsl = slot[more ? b + 1 : b];
-            const P nxv = input(nbd.in, lane, nbd.C);   // unused after the last block
-            double scale = 1.0;
-            if constexpr (KIND == ELEM_BF16) scale = double(scales[bd.sidx]);
-            P cp[TR] = {};
-#pragma unroll
-            for (int k = 0; k < NS; ++k) {
-                P v[TR];
-#pragma unroll
-                for (int i = 0; i < IPR; ++i) E::unpack(raw[k][i], v + i * W);
-                P s = P(0);
-#pragma unroll
-                for (int c = 0; c < TR; ++c) {
-                    s = fma(v[c], xj[c], s);
-                    cp[c] = fma(v[c], xi[k], cp[c]);
+                P t = P(0);
+                if (sl != -1) t = fold_lanes<TR, TR / 2>(cp, lane);   // column TR g + a = lane
+                if (more) stage(nxv);
+                if (lane < C) {
+                    if (sl >= 0)
+                        acc[wv][sl][lane] += TV(double(t) * scale);
+                    else if (sl <= -2)
+                        partials[int64_t(-(sl + 2)) * 64 + lane] = TV(double(t) * scale);
                 }
-                rp[k] += double(s) * scale;
+                bd = nbd;
+                sl = nsl;
             }
-            P t = P(0);
-            if (sl >= 0) t = fold_lanes<TR, TR / 2>(cp, lane);   // column TR g + a = lane
-            if (more) stage(nxv);
-            if (sl >= 0 && lane < C) partials[int64_t(sl) * 64 + lane] = TV(double(t) * scale);
-            bd = nbd;
-            sl = nsl;
-        }
-    };
-    if (rd.sel & ROW_IN_X)
-        blocks(std::true_type{});
-    else
-        blocks(std::false_type{});
-    const double t = fold_lanes<NS, 32>(rp, lane);   // row a + TR g = lane
-    if (lane < R) ((rd.sel & ROW_OUT_P) ? out1 : out0)[rd.out + lane] = TV(t);
+        };
+        if (rd.sel & ROW_IN_X)
+            blocks(std::true_type{});
+        else
+            blocks(std::false_type{});
+        const double t = fold_lanes<NS, 32>(rp, lane);   // row a + TR g = lane
+        if (lane < R) ((rd.sel & ROW_OUT_P) ? out1 : out0)[rd.out + lane] = TV(t);
+    }
+    for (int s = 0; s < ns; ++s) partials[int64_t(gslot[gd.s0 + s]) * 64 + lane] = acc[wv][s][lane];
 }
 
 constexpr int kRowsPerBlock = 4;
@@ -711,23 +730,23 @@ hipError_t launch_reduce_chunks(const ReduceDesc *desc, int64_t n, const void *p
 // 32 measured no faster: 8 x 8 tiles in every storage mode).
 constexpr int kHalfStripF64 = 8, kHalfStripF32 = 8, kHalfStripBF16 = 8;
 
-hipError_t launch_stream_half(const RowLaunch &L, const int32_t *slot, void *partials, int kind, bool vec_f64,
-                              hipStream_t st) {
-    if (L.nrows <= 0) return hipSuccess;
-    const dim3 grid(unsigned((L.nrows + kRowsPerBlock - 1) / kRowsPerBlock)), block(256);
+hipError_t launch_stream_half(const RowLaunch &L, const HalfGroup *groups, int64_t ngroups, const int32_t *slot,
+                              const int32_t *gslot, void *partials, int kind, bool vec_f64, hipStream_t st) {
+    if (ngroups <= 0) return hipSuccess;
+    const dim3 grid(unsigned((ngroups + kRowsPerBlock - 1) / kRowsPerBlock)), block(256);
     if (vec_f64) {
-        hipLaunchKernelGGL((stream_half_kernel<ELEM_F64, double, kHalfStripF64>), grid, block, 0, st, L.rows, L.nrows,
-                           L.blks, slot, static_cast<const double *>(L.data), L.scales,
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_F64, double, kHalfStripF64>), grid, block, 0, st, groups, ngroups,
+                           L.rows, L.blks, slot, gslot, static_cast<const double *>(L.data), L.scales,
                            static_cast<const double *>(L.in0), L.in1, static_cast<double *>(L.out0),
                            static_cast<double *>(L.out1), static_cast<double *>(partials));
     } else if (kind == ELEM_F32) {
-        hipLaunchKernelGGL((stream_half_kernel<ELEM_F32, float, kHalfStripF32>), grid, block, 0, st, L.rows, L.nrows,
-                           L.blks, slot, static_cast<const float *>(L.data), L.scales,
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_F32, float, kHalfStripF32>), grid, block, 0, st, groups, ngroups,
+                           L.rows, L.blks, slot, gslot, static_cast<const float *>(L.data), L.scales,
                            static_cast<const float *>(L.in0), L.in1, static_cast<float *>(L.out0),
                            static_cast<float *>(L.out1), static_cast<float *>(partials));
     } else {
-        hipLaunchKernelGGL((stream_half_kernel<ELEM_BF16, float, kHalfStripBF16>), grid, block, 0, st, L.rows,
-                           L.nrows, L.blks, slot, static_cast<const uint16_t *>(L.data), L.scales,
+        hipLaunchKernelGGL((stream_half_kernel<ELEM_BF16, float, kHalfStripBF16>), grid, block, 0, st, groups,
+                           ngroups, L.rows, L.blks, slot, gslot, static_cast<const uint16_t *>(L.data), L.scales,
                            static_cast<const float *>(L.in0), L.in1, static_cast<float *>(L.out0),
                            static_cast<float *>(L.out1), static_cast<float *>(partials));
     }

@@ -150,7 +150,8 @@ void run_product(h2_matrix_ &A, const double *x, double *y, hipStream_t st, cons
                 L.out0 = W.yh;
                 L.out1 = W.ynear;
                 if (w.slot) {   // stored by halves: row sums and transposed partials, then their sums
-                    check_hip(h2::launch_stream_half(L, w.slot, partials, w.kind, A.vec_f64, st),
+                    check_hip(h2::launch_stream_half(L, w.groups, w.ngroups, w.slot, w.gslot, partials, w.kind,
+                                                     A.vec_f64, st),
                               "half-storage stream launch");
                     check_hip(h2::launch_reduce_chunks(w.red, w.nred, partials, !A.vec_f64, W.yh, W.ynear, A.vec_f64,
                                                        st, true),

@@ -53,7 +53,8 @@ class h2_info(C.Structure):
                 ("rank", C.c_int), ("levels_q", C.c_int), ("lmin", C.c_int), ("storage", C.c_int),
                 ("nnodes", C.c_int64), ("coupling_blocks", C.c_int64), ("dense_blocks", C.c_int64),
                 ("bytes_coupling", C.c_int64), ("bytes_dense", C.c_int64), ("bytes_leaf_bases", C.c_int64),
-                ("bytes_transfers", C.c_int64), ("bytes_device_total", C.c_int64), ("near_ties", C.c_int64)]
+                ("bytes_transfers", C.c_int64), ("bytes_device_total", C.c_int64), ("near_ties", C.c_int64),
+                ("partial_slots", C.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

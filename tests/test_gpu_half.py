@@ -100,6 +100,11 @@ def test_half_fp64_matches_oracle_and_full(oracle_mod, w):
     if fi.coupling_blocks:
         assert hi.bytes_coupling * 2 == fi.bytes_coupling   # no diagonal coupling blocks
     assert hi.bytes_dense <= fi.bytes_dense   # strictly less when a dense block is off the diagonal
+    # partial slots: at most one per stored off-diagonal block (a group of
+    # block rows shares one per column segment), none with full storage
+    off_diagonal = fi.coupling_blocks // 2 + (fi.dense_blocks - (1 << fi.levels_q)) // 2
+    assert fi.partial_slots == 0
+    assert (hi.partial_slots > 0) == (off_diagonal > 0) and hi.partial_slots <= off_diagonal
     H.close()
     F.close()
 

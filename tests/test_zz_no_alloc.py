@@ -68,10 +68,10 @@ def test_noalloc_headline_matrix_fits():
 
 
 def test_noalloc_rejects_what_does_not_fit():
-    """A half-stored 2^18-point rank-64 FP64 matrix needs ~84 MB of partial
+    """A half-stored 2^20-point rank-64 FP64 matrix needs ~150 MB of partial
     slots: refused with UNSUPPORTED before anything is enqueued."""
     h2mv = _h2mv()
-    w = W.C2.with_(name="2d-n262144-m64-k64", n=1 << 18, seed=91)
+    w = W.C2.with_(name="2d-n1048576-m64-k64-s91", seed=91)
     A = _build(w, h2mv.H2_HALF_STORAGE)
     x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
     y = torch.full_like(x, 7.0)
