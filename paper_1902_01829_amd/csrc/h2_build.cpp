@@ -608,11 +608,11 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
             // consecutive block rows of one kind (the list's spatial order:
             // coupling rows level by level, then leaf rows), whose transposed
             // products of one column segment are added in LDS, rows in order,
-            // and written to one partial slot per segment and group (a
-            // group's segments fit in HALF_LDS_SLOTS; a row alone that has
-            // more sends the rest to slots of their own).  Slots are numbered
-            // by segment, and a second launch adds each segment's slots to
-            // its row sum, in order (deterministic).
+            // and written to one partial slot per segment and group (when a
+            // group has more segments than HALF_LDS_SLOTS, the most shared
+            // ones get LDS slots and the blocks of the others slots of their
+            // own).  Slots are numbered by segment, and a second launch adds
+            // each segment's slots to its row sum, in order (deterministic).
             struct Col {
                 bool point;
                 int64_t id;
@@ -629,34 +629,63 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
                     if (cols[c].point == b.point && cols[c].id == b.id) return int(c);
                 return -1;
             };
+            // Rows per group: at most HALF_GROUP_ROWS, and few enough that the
+            // groups fill the wavefronts the device holds at least three times
+            // over (with fewer rounds the last one leaves compute units idle:
+            // measured on the 3-D 2^19-point matrix, whose 24,544 block rows
+            // in groups of four made the FP32 and BF16 products 6-12 %
+            // slower, 1.5 rounds, while the FP64 ones, at half the
+            // wavefronts per CU, gained 1-4 % in 2-D (6 rounds) and 3-D (3)).
+            size_t group_rows = 1;
+            {
+                int dev = 0, cus = 0, per_cu = 0;
+                check_hip(hipGetDevice(&dev), "hipGetDevice");
+                check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+                check_hip(h2::stream_half_workgroups_per_cu(sk, A.vec_f64, &per_cu), "occupancy query");
+                const size_t waves = size_t(std::max(1, cus)) * size_t(std::max(1, per_cu)) * 4;
+                group_rows = std::min(size_t(h2::HALF_GROUP_ROWS), std::max(size_t(1), L.size() / (3 * waves)));
+            }
             std::vector<Grp> groups;
+            std::vector<Col> all;   // a group's segments, first appearance first
+            std::vector<int> mult;  // and how many of its blocks fall in each
+            std::vector<size_t> ord;
             for (size_t r = 0; r < L.size();) {
                 Grp G{r, r, {}, 0};
-                while (G.r1 < L.size() && G.r1 - G.r0 < size_t(h2::HALF_GROUP_ROWS)) {
-                    const LRow &row = L[G.r1];
-                    if (G.r1 > G.r0) {   // a further row joins only if its kind and new segments fit
-                        if (row.point != L[G.r0].point) break;
-                        size_t add = 0;
-                        for (size_t b = row.b0; b < row.b1; ++b)
-                            if (off_diagonal(row, pool[b]) && find_col(G.cols, pool[b]) < 0) ++add;
-                        if (G.cols.size() + add > size_t(h2::HALF_LDS_SLOTS)) break;
+                while (G.r1 < L.size() && G.r1 - G.r0 < group_rows && L[G.r1].point == L[G.r0].point) {
+                    G.nblk += int64_t(L[G.r1].nb());
+                    ++G.r1;
+                }
+                all.clear();
+                mult.clear();
+                for (size_t q = G.r0; q < G.r1; ++q)
+                    for (size_t b = L[q].b0; b < L[q].b1; ++b) {
+                        if (!off_diagonal(L[q], pool[b])) continue;
+                        const int c = find_col(all, pool[b]);
+                        if (c >= 0) {
+                            ++mult[size_t(c)];
+                        } else {
+                            all.push_back({pool[b].point, pool[b].id, pool[b].C});
+                            mult.push_back(1);
+                        }
                     }
-                    for (size_t b = row.b0; b < row.b1; ++b) {
+                // LDS slots: every segment if they fit, else the most shared
+                // ones (a segment of a single block gains nothing from one)
+                ord.resize(all.size());
+                std::iota(ord.begin(), ord.end(), size_t(0));
+                std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return mult[x] > mult[y]; });
+                const bool fit = all.size() <= size_t(h2::HALF_LDS_SLOTS);
+                for (size_t i = 0; i < ord.size() && i < size_t(h2::HALF_LDS_SLOTS); ++i)
+                    if (fit || mult[ord[i]] > 1) G.cols.push_back(all[ord[i]]);
+                for (size_t q = G.r0; q < G.r1; ++q)
+                    for (size_t b = L[q].b0; b < L[q].b1; ++b) {
                         LBlk &lb = pool[b];
-                        if (!off_diagonal(row, lb)) {
+                        if (!off_diagonal(L[q], lb)) {
                             lb.slot = -1;
                             continue;
                         }
-                        int c = find_col(G.cols, lb);
-                        if (c < 0 && G.cols.size() < size_t(h2::HALF_LDS_SLOTS)) {
-                            c = int(G.cols.size());
-                            G.cols.push_back({lb.point, lb.id, lb.C});
-                        }
+                        const int c = find_col(G.cols, lb);
                         lb.slot = c >= 0 ? c : -2;   // -2: a slot of its own, numbered below
                     }
-                    G.nblk += int64_t(row.nb());
-                    ++G.r1;
-                }
                 groups.push_back(std::move(G));
                 r = groups.back().r1;
             }

@@ -730,6 +730,14 @@ hipError_t launch_reduce_chunks(const ReduceDesc *desc, int64_t n, const void *p
 // 32 measured no faster: 8 x 8 tiles in every storage mode).
 constexpr int kHalfStripF64 = 8, kHalfStripF32 = 8, kHalfStripBF16 = 8;
 
+hipError_t stream_half_workgroups_per_cu(int kind, bool vec_f64, int *n) {
+    if (vec_f64)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, stream_half_kernel<ELEM_F64, double, kHalfStripF64>, 256, 0);
+    if (kind == ELEM_F32)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, stream_half_kernel<ELEM_F32, float, kHalfStripF32>, 256, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, stream_half_kernel<ELEM_BF16, float, kHalfStripBF16>, 256, 0);
+}
+
 hipError_t launch_stream_half(const RowLaunch &L, const HalfGroup *groups, int64_t ngroups, const int32_t *slot,
                               const int32_t *gslot, void *partials, int kind, bool vec_f64, hipStream_t st) {
     if (ngroups <= 0) return hipSuccess;
