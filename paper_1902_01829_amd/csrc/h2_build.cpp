@@ -644,6 +644,12 @@ void build_lists(h2_matrix_ &A, const std::vector<h2::FillDesc> &fill, int64_t n
                 check_hip(h2::stream_half_workgroups_per_cu(sk, A.vec_f64, &per_cu), "occupancy query");
                 const size_t waves = size_t(std::max(1, cus)) * size_t(std::max(1, per_cu)) * 4;
                 group_rows = std::min(size_t(h2::HALF_GROUP_ROWS), std::max(size_t(1), L.size() / (3 * waves)));
+                // test-only override (environment variable H2MV_HALF_GROUP_ROWS,
+                // 1 .. HALF_GROUP_ROWS), so that small matrices run the grouped path
+                if (const char *e = std::getenv("H2MV_HALF_GROUP_ROWS")) {
+                    const long v = std::atol(e);
+                    if (v >= 1 && v <= h2::HALF_GROUP_ROWS) group_rows = size_t(v);
+                }
             }
             std::vector<Grp> groups;
             std::vector<Col> all;   // a group's segments, first appearance first

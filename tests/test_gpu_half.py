@@ -145,6 +145,32 @@ def _sampled(oracle_mod, w, storage, nleaves, tol):
         assert np.abs(y[rows] - ref).max() <= FP64_TOL * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("rows", [1, 2, 3, 4])
+@pytest.mark.parametrize("w", [SMALL[1], SMALL[2], SMALL[4], SMALL[5]], ids=lambda w: w.name)
+def test_half_row_groups(oracle_mod, monkeypatch, w, rows):
+    """The stored-by-halves product with the block rows taken in groups of
+    1 .. 4 rows per wavefront (forced on small matrices, which the library
+    would otherwise run one row per wavefront): the oracle's bound, and the
+    full-storage product up to rounding order, in FP64 and BF16."""
+    print(f"case half groups of {rows} {w.name}", flush=True)
+    monkeypatch.setenv("H2MV_HALF_GROUP_ROWS", str(rows))
+    o = oracle_mod.OracleH2(W.points(w), w.leaf, w.cheb_p, w.eta, w.corr_len, keep_blocks=False)
+    for storage in (0, 2):
+        H, F = _build(w, HALF | storage), _build(w, storage)
+        xt = W.rhs(w)[H.perm()]
+        y, yf = _matvec(H, xt), _matvec(F, xt)
+        if storage == 0:
+            _check_fp64(y, o.matvec(xt))
+            assert _rel(y, yf) <= FP64_VS_FULL_TOL
+        else:
+            assert _rel(y, yf) <= REDUCED_VS_FULL_TOL
+        assert np.array_equal(y, _matvec(H, xt))
+        off_diagonal = F.info.coupling_blocks // 2 + (F.info.dense_blocks - (1 << F.info.levels_q)) // 2
+        assert H.info.partial_slots <= off_diagonal
+        H.close()
+        F.close()
+
+
 def test_half_fp64_full_2d_1m(oracle_mod):
     _sampled(oracle_mod, W.C2, 0, 48, FP64_TOL)
 
