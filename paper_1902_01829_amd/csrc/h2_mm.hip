@@ -798,31 +798,59 @@ template <bool LEAF, bool BATCH>
 __device__ inline void mm_store16(const MmArgs &g, const RowDesc &rd, int mt, int nh, int n, int kq,
                                   const double (&tot)[2][4]) {
     const int R = rd.R, Rp = round16(R);
-    f32x4 t[2] = {};   // requested together, as in mm_store32
-    if (LEAF || rd.init >= 0) {   // wave-uniform
-        const int nc = LEAF && n >= g.ncols ? g.ncols - 1 : n;
+    if constexpr (LEAF) {
+        // The leaf phase transposes the wavefront's 32 x 16 FP64 result
+        // through its LDS slot, so that each store instruction writes two
+        // 256-byte runs of rows of Y (as the pair loop's leaf phase), not
+        // 8-byte values scattered over 16 columns; its y_near values are
+        // requested first, all together (rows and columns clamped into the
+        // tile; the clamped ones are not used).
+        constexpr int LD = 33;   // doubles per right-hand side (padded)
+        __shared__ double T16[4][16 * LD];
+        double *T = T16[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
+        const int lane = threadIdx.x & 63, r = lane & 31, jp = lane >> 5, i = 32 * mt + r;
+        float yn[8];
+        {
+            const int ic = i < R ? i : R - 1;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int j = 2 * c + jp, jc = j < g.ncols ? j : g.ncols - 1;
+                yn[c] = g.init[rd.init + int64_t(jc) * Rp + ic];
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) T[n * LD + 16 * h + 4 * kq + e] = tot[h][e];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
+        const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
+        if (i < R) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int j = 2 * c + jp;
+                if (j < g.ncols) Yb[int64_t(j) * ldy + rd.out + i] = double(yn[c]) + T[j * LD + r];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();   // T free again before a persistent wavefront's next row
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    } else {
+        f32x4 t[2] = {};   // requested together, as in mm_store32
+        if (rd.init >= 0) {   // wave-uniform
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int i0 = 32 * mt + 16 * h + 4 * kq, i0c = i0 < Rp ? i0 : Rp - 4;
+                t[h] = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(n) * Rp + i0c);
+            }
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int i0 = 32 * mt + 16 * h + 4 * kq, i0c = i0 < Rp ? i0 : Rp - 4;
-            t[h] = *reinterpret_cast<const f32x4 *>(g.init + rd.init + int64_t(nc) * Rp + i0c);
-        }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (h >= nh) break;
-        const int i0 = 32 * mt + 16 * h + 4 * kq;
-        if (i0 >= Rp) continue;
-        if constexpr (LEAF) {
-            if (n >= g.ncols) continue;
-            const f32x4 yn = t[h];
-            const double ynv[4] = {yn.x, yn.y, yn.z, yn.w};
-            double *Yb = BATCH ? g.Ytab[rd.sel >> 8] : g.Y;
-            const int64_t ldy = BATCH ? g.ldytab[rd.sel >> 8] : g.ldy;
-            double *yc = Yb + int64_t(n) * ldy + rd.out;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (i0 + e < R) yc[i0 + e] = ynv[e] + tot[h][e];
-        } else {
+            if (h >= nh) break;
+            const int i0 = 32 * mt + 16 * h + 4 * kq;
+            if (i0 >= Rp) continue;
             double v[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[e] = i0 + e < R ? tot[h][e] : 0.0;
@@ -1439,28 +1467,42 @@ hipError_t launch_mm_batch(const MmBatchLaunch &L, int kind, int phase, const Mm
 // columns).  The tile's right-hand sides nrhs .. MM_TILE-1 are not written:
 // every product, sum and store keeps the right-hand sides (MFMA columns)
 // apart, and the leaf phase writes only the first nrhs, so whatever those
-// columns hold never reaches a result.
+// columns hold never reaches a result.  One wavefront per entry (a leaf
+// holds at most 64 points: lane = row), four per workgroup, eight columns'
+// loads issued before their stores.
 __global__ __launch_bounds__(256) void batch_pack_kernel(const PackEntry *__restrict__ entries, int64_t count,
                                                          double const *const *__restrict__ Xtab,
                                                          const int64_t *__restrict__ ldxtab, int nrhs,
                                                          float *__restrict__ pool) {
-    for (int64_t k = blockIdx.x; k < count; k += gridDim.x) {
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), c = threadIdx.x & 63;
+    const int nc = nrhs < NT ? nrhs : NT;
+    for (int64_t k = int64_t(blockIdx.x) * 4 + wv; k < count; k += int64_t(gridDim.x) * 4) {
         const PackEntry e = entries[k];
         const double *X = Xtab[e.member];
         const int64_t ldx = ldxtab[e.member];
         const int mp = round16(e.m);
         float *t = pool + e.dst;
-        const int c = threadIdx.x & 63;   // leaves hold at most 64 points
-        if (c < mp)
-            for (int j = threadIdx.x >> 6; j < nrhs && j < NT; j += 4)
-                t[int64_t(j) * mp + c] = c < e.m ? float(X[(e.row + c) + int64_t(j) * ldx]) : 0.0f;
+        if (c >= mp) continue;
+        const double *xr = X + (e.row + (c < e.m ? c : 0));   // rows past the leaf read its first row
+        for (int j0 = 0; j0 < nc; j0 += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = j0 + u < nc ? j0 + u : nc - 1;
+                v[u] = float(xr[int64_t(j) * ldx]);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j0 + u < nc) t[int64_t(j0 + u) * mp + c] = c < e.m ? v[u] : 0.0f;
+        }
     }
 }
 
 hipError_t launch_batch_pack(const PackEntry *entries, int64_t count, double const *const *Xtab,
                              const int64_t *ldxtab, int nrhs, float *pool, int64_t grid, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    const int64_t g = grid > 0 && grid < count ? grid : count;
+    const int64_t wgs = (count + 3) / 4;
+    const int64_t g = grid > 0 && grid < wgs ? grid : wgs;
     hipLaunchKernelGGL(batch_pack_kernel, dim3(unsigned(g)), dim3(256), 0, st, entries, count, Xtab, ldxtab, nrhs,
                        pool);
     return hipGetLastError();
