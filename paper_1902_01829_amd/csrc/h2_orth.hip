@@ -132,7 +132,11 @@ __global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const in
 // and zero-padded to a multiple of 16; T_i and T_j are read as operands from
 // memory (column-major, leading dimension kmax).  Each workgroup takes one
 // contiguous run of the list: the blocks of a block row share T_i, which
-// then stays in the caches.
+// then stays in the caches.  TRI: T_i and T_j are upper triangular (the
+// orthogonalization's R factors), so the K steps that meet only their zeros
+// are skipped: below a wavefront's first row in T_i S, before an output
+// column tile's first column in W T_j^T (3/8 of the matrix-core work of a
+// rank-64 block).
 constexpr int PS_LD = 68;   // LDS leading dimension of S (spread over the banks)
 
 __device__ inline void proj_load(const double *blocks, const ProjDesc &d, f64x2 (&v)[8]) {
@@ -147,6 +151,7 @@ __device__ inline void proj_load(const double *blocks, const ProjDesc &d, f64x2 
     }
 }
 
+template <bool TRI>
 __global__ __launch_bounds__(256) void project_kernel(const double *in, double *outp, const ProjDesc *desc,
                                                       int64_t nblocks, const double *T, const double *Tcol, int kmax) {
     __shared__ double S[64 * PS_LD];     // column-major
@@ -173,11 +178,12 @@ __global__ __launch_bounds__(256) void project_kernel(const double *in, double *
         const double *Ti = T + d.row * kmax * kmax, *Tj = Tcol + d.col * kmax * kmax;
         const int r0 = 16 * wv;
         if (wv < nto) {
+            const int s0 = TRI ? 4 * wv : 0;   // T_i(rows r0 .., kk) = 0 for kk < r0
             double ta[16];   // T_i(r0 + lr, 4 s + lk)
 #pragma unroll
             for (int s4 = 0; s4 < 16; ++s4) {
                 const int kk = 4 * s4 + lk, row = r0 + lr;
-                ta[s4] = (row < ko && kk < k) ? Ti[int64_t(kk) * kmax + row] : 0.0;
+                ta[s4] = (s4 >= s0 && row < ko && kk < k) ? Ti[int64_t(kk) * kmax + row] : 0.0;
             }
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) {
@@ -186,6 +192,7 @@ __global__ __launch_bounds__(256) void project_kernel(const double *in, double *
 #pragma unroll
                 for (int s4 = 0; s4 < 16; ++s4) {
                     if (4 * s4 >= kp) break;
+                    if (s4 < s0) continue;   // wave-uniform
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[s4], S[(16 * ct + lr) * PS_LD + 4 * s4 + lk], acc, 0,
                                                                0, 0);
                 }
@@ -214,6 +221,7 @@ __global__ __launch_bounds__(256) void project_kernel(const double *in, double *
 #pragma unroll
                 for (int s4 = 0; s4 < 16; ++s4) {
                     if (4 * s4 >= kp) break;
+                    if (TRI && s4 < 4 * ct) continue;   // T_j(cols 16 ct .., kk) = 0 for kk < 16 ct
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wl[wv][(4 * s4 + lk) * 16 + lr], cur[s4], acc, 0, 0, 0);
                 }
 #pragma unroll
@@ -260,21 +268,26 @@ hipError_t launch_orthogonalize(const OrthLaunch &L, hipStream_t st) {
     if (!L.T_col) {   // one tree: U_j and V_j^T, E_c and F_c^T written together
         e = orthogonalize_tree<false>(L, L.off_U, L.off_U, L.off_VT, L.off_E, L.off_E, L.off_FT, L.T, st);
         if (e != hipSuccess) return e;
-        return launch_project(L.blocks, L.blocks, L.proj, L.nproj, L.T, L.T, L.kmax, st);
+        return launch_project(L.blocks, L.blocks, L.proj, L.nproj, L.T, L.T, L.kmax, st, true);
     }
     e = orthogonalize_tree<false>(L, L.off_U, L.off_U, nullptr, L.off_E, L.off_E, nullptr, L.T, st);
     if (e != hipSuccess) return e;
     e = orthogonalize_tree<true>(L, L.off_VT, nullptr, L.off_VT, L.off_FT, nullptr, L.off_FT, L.T_col, st);
     if (e != hipSuccess) return e;
-    return launch_project(L.blocks, L.blocks, L.proj, L.nproj, L.T, L.T_col, L.kmax, st);
+    return launch_project(L.blocks, L.blocks, L.proj, L.nproj, L.T, L.T_col, L.kmax, st, true);
 }
 
 hipError_t launch_project(const double *in, double *out, const ProjDesc *desc, int64_t n, const double *T,
-                          const double *T_col, int kmax, hipStream_t st) {
+                          const double *T_col, int kmax, hipStream_t st, bool triangular) {
     if (n <= 0) return hipSuccess;
     if (kmax < 1 || kmax > QR_MAXN) return hipErrorInvalidValue;
     const int64_t grid = n < 65536 ? n : 65536;
-    hipLaunchKernelGGL(project_kernel, dim3(unsigned(grid)), dim3(256), 0, st, in, out, desc, n, T, T_col, kmax);
+    if (triangular)
+        hipLaunchKernelGGL(project_kernel<true>, dim3(unsigned(grid)), dim3(256), 0, st, in, out, desc, n, T, T_col,
+                           kmax);
+    else
+        hipLaunchKernelGGL(project_kernel<false>, dim3(unsigned(grid)), dim3(256), 0, st, in, out, desc, n, T, T_col,
+                           kmax);
     return hipGetLastError();
 }
 

@@ -411,7 +411,7 @@ void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
                 blk[size_t(i)].kout = kt[l];
             }
         check_hip(h2::launch_project(static_cast<const double *>(A.blocks), static_cast<double *>(B->blocks),
-                                     scratch.upload(blk, st), int64_t(blk.size()), Lr.T, Lc.T, kmax, st),
+                                     scratch.upload(blk, st), int64_t(blk.size()), Lr.T, Lc.T, kmax, st, false),
                   "projection launch");
         if (int64_t(fill.size()) > ncoupling) {   // dense blocks: same sizes and order
             const int64_t from = A.off_blk[size_t(ncoupling)], to = B->off_blk[size_t(ncoupling)];
