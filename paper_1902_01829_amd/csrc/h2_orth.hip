@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "h2_device.h"
 #include "h2_lds_la.h"
@@ -124,119 +125,213 @@ __global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const in
 // rows (kout = k in the orthogonalization), on the FP64 matrix cores
 // (v_mfma_f64_16x16x4_f64: lane l supplies A(l % 16, l / 16) and B(l / 16,
 // l % 16) and holds D(l / 16 + 4 e, l % 16), e = 0..3 -- the rows of a lane's
-// four results are 4 apart, unlike the FP32 16 x 16 forms).  Wavefront w
-// owns output rows 16 w .. 16 w + 15: first W_w = T_i(rows, :) S, staged in
-// the wave's own LDS slice, then S'(rows, :) = W_w T_j^T, staged back in the
-// S buffer and stored as whole 16-byte items.  S is loaded as 16-byte items
-// (two columns of a row), the next block's while this one's products run,
-// and zero-padded to a multiple of 16; T_i and T_j are read as operands from
-// memory (column-major, leading dimension kmax).  Each workgroup takes one
-// contiguous run of the list: the blocks of a block row share T_i, which
-// then stays in the caches.  TRI: T_i and T_j are upper triangular (the
-// orthogonalization's R factors), so the K steps that meet only their zeros
-// are skipped: below a wavefront's first row in T_i S, before an output
-// column tile's first column in W T_j^T (3/8 of the matrix-core work of a
-// rank-64 block).
+// four results are 4 apart, unlike the FP32 16 x 16 forms).
+//
+// A wavefront owns one row tile of the output, rows r0 .. r0 + 15, and never
+// leaves registers between the two products: it forms W^T = S^T T_i^T one
+// 16-column tile of W at a time, and lane (lr, lk) then holds W(r0 + lr,
+// 16 ct + lk + 4 e) -- exactly the A operand of step 4 ct + e of
+// S'(rows, :) = W T_j^T.  S (column-major) and T_j (row kk of T_j^T
+// contiguous) are read from LDS, loaded for the next block while this one's
+// products run; the wavefront's rows of T_i (mostly cache hits: consecutive
+// blocks share the row) are loaded once its products are done.  The result goes
+// out as 16-byte items (two columns of a row) after one exchange between
+// neighbouring lanes, written once the next block is staged so that the
+// wait for the next loads does not also wait for these stores.  Row tiles
+// rotate over the wavefronts from block to block, which evens out the
+// triangular case.  Each workgroup takes one contiguous run of the list: the
+// blocks of a block row share T_i, which then stays in the caches.
+//
+// TRI: T_i and T_j are upper triangular (the orthogonalization's R factors,
+// stored with explicit zeros), so the K steps that meet only their zeros are
+// skipped -- below a row tile's first row in T_i S, before an output column
+// tile's first column in W T_j^T (3/8 of the matrix-core work of a rank-64
+// block) -- and T_j's zeros are not read.
 constexpr int PS_LD = 68;   // LDS leading dimension of S (spread over the banks)
+constexpr int PT_LD = 80;   // of T_j^T: rows of the four quarter-waves alternate between bank halves
 
-__device__ inline void proj_load(const double *blocks, const ProjDesc &d, f64x2 (&v)[8]) {
-    const int k = d.k, kp = (k + 15) & ~15, rows = kp, ng = kp >> 1;
-    const double *blk = blocks + d.off;
+// The loads below are unconditional: a wave-uniform base (scalar registers)
+// plus one 32-bit byte offset per lane.  S items are clamped into the block;
+// T_i and T_j are read as a 64 x 64 frame from their node's start, which
+// stays inside the array because it is allocated PROJ_T_PAD doubles longer.
+// What lies outside the block or the node's T is replaced by zeros where the
+// values are staged or used.
+__device__ inline const char *proj_at(const void *base, uint32_t off) { return static_cast<const char *>(base) + off; }
+
+// S item j of this thread: column pair g = wavefront + 4 j (wave-uniform),
+// row r = lane, valid when r < k and 2 g < k (a 64 x 64 frame: every slot of
+// the LDS copy is written, the padding with zeros).
+__device__ inline void proj_load(const double *blocks, const ProjDesc &d, int wv, f64x2 (&v)[8]) {
+    const int k = d.k;
+    const uint32_t off = uint32_t(min(int(threadIdx.x & 63), k - 1)) * 16u;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const int i = threadIdx.x + 256 * j, g = i / rows, r = i - g * rows;
-        v[j] = (g < ng && r < k && 2 * g < k) ? __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(
-                                                     blk + (int64_t(g) * k + r) * 2))
-                                               : f64x2{0.0, 0.0};
+        const int g = min(wv + 4 * j, (k - 1) >> 1);
+        v[j] = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(proj_at(blocks + d.off + 2 * g * k, off)));
+    }
+}
+
+// T_j(c, kk) as element kk * 64 + c of 256 threads x 16: one wavefront reads
+// one column of T_j (64 consecutive doubles).
+__device__ inline void proj_load_t(const double *Tj, int kmax, int wv, double (&v)[16]) {
+    const uint32_t off = uint32_t(threadIdx.x & 63) * 8u;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        v[j] = *reinterpret_cast<const double *>(proj_at(Tj + (wv + 4 * j) * kmax, off));
+}
+template <bool TRI>
+__device__ inline bool proj_t_ok(int k, int ko, int j) {
+    const int c = threadIdx.x & 63, kk = int(threadIdx.x >> 6) + 4 * j;
+    return kk < k && c < ko && (!TRI || c <= kk);
+}
+
+// T_i(r0 + lr, 4 s + lk) for row tile rt; the steps a triangular T_i skips
+// are not loaded.
+template <bool TRI>
+__device__ inline void proj_load_ti(const double *Ti, int rt, int kmax, int lr, int lk, double (&o)[16]) {
+    const uint32_t off = uint32_t(lk * kmax + 16 * rt + lr) * 8u;
+#pragma unroll
+    for (int s4 = 0; s4 < 16; ++s4) {
+        if (TRI && s4 < 4 * rt) continue;   // wave-uniform
+        o[s4] = *reinterpret_cast<const double *>(proj_at(Ti + 4 * s4 * kmax, off));
     }
 }
 
 template <bool TRI>
-__global__ __launch_bounds__(256) void project_kernel(const double *in, double *outp, const ProjDesc *desc,
-                                                      int64_t nblocks, const double *T, const double *Tcol, int kmax) {
-    __shared__ double S[64 * PS_LD];     // column-major
-    __shared__ double Wl[4][16 * 64];    // per wave: 16 x 64, column-major, ld 16
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+__global__ __launch_bounds__(256, 2) void project_kernel(const double *in, double *outp,
+                                                         const ProjDesc *__restrict__ desc, int64_t nblocks,
+                                                         const double *__restrict__ T,
+                                                         const double *__restrict__ Tcol, int kmax) {
+    // (desc, T and Tcol are never written here, so the descriptors are read
+    // through the scalar cache and no wait for them waits for the prefetch;
+    // in and outp may be the same array)
+    __shared__ double S[64 * PS_LD];    // column-major
+    __shared__ double Tt[64 * PT_LD];   // T_j(c, kk) at kk * PT_LD + c
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, lr = lane & 15,
+              lk = lane >> 4;
     const int64_t per = (nblocks + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = int64_t(blockIdx.x) * per, b1 = b0 + per < nblocks ? b0 + per : nblocks;
-    f64x2 nxt[8];
-    if (b0 < b1) proj_load(in, desc[b0], nxt);
-    for (int64_t b = b0; b < b1; ++b) {
+    if (b0 >= b1) return;   // the whole workgroup
+    auto row_tile = [&](int64_t b) { return (wv + int(b & 3)) & 3; };
+    f64x2 nxt[8];      // the next block's S items
+    double nxt_t[16];  // its T_j
+    auto prefetch = [&](int64_t b) {
+        const ProjDesc d = desc[b];
+        proj_load(in, d, wv, nxt);
+        proj_load_t(Tcol + d.col * kmax * kmax, kmax, wv, nxt_t);
+    };
+    double ta[16];     // T_i rows of this wavefront's row tile
+    auto load_ta = [&](int64_t b) { proj_load_ti<TRI>(T + desc[b].row * kmax * kmax, row_tile(b), kmax, lr, lk, ta); };
+    auto stage = [&](int64_t b) {   // the prefetched block into LDS (its S zero-padded)
+        const int k = desc[b].k, ko = desc[b].kout, r = lane;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int g = wv + 4 * j;
+            const bool ok = r < k && 2 * g < k;
+            S[(2 * g) * PS_LD + r] = ok ? nxt[j].x : 0.0;
+            S[(2 * g + 1) * PS_LD + r] = ok && 2 * g + 1 < k ? nxt[j].y : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int f = threadIdx.x + 256 * j;
+            Tt[(f >> 6) * PT_LD + (f & 63)] = proj_t_ok<TRI>(k, ko, j) ? nxt_t[j] : 0.0;
+        }
+    };
+    // block b; NEXT: block b + 1 exists (prefetched, then staged)
+    auto block = [&](int64_t b, auto next) {
+        constexpr bool NEXT = decltype(next)::value;
+        __syncthreads();   // block b staged
+        if constexpr (NEXT) prefetch(b + 1);   // in flight during the products
         const ProjDesc d = desc[b];
         const int k = d.k, kp = (k + 15) & ~15, nt = kp >> 4;   // input: k x k, nt column tiles
         const int ko = d.kout, nto = (ko + 15) >> 4;             // output: ko x ko, nto row tiles
+        const int rt = row_tile(b), r0 = 16 * rt;
+        f64x4 o[4];   // S'(r0 + lk + 4 e, 16 ct + lr)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {   // this block's items into LDS
-            const int i = threadIdx.x + 256 * j, g = i / kp, r = i - g * kp;
-            if (g < (kp >> 1)) {
-                S[(2 * g) * PS_LD + r] = nxt[j].x;
-                S[(2 * g + 1) * PS_LD + r] = nxt[j].y;
+        for (int ct = 0; ct < 4; ++ct) o[ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+        if (rt < nto) {
+#pragma unroll
+            for (int s4 = 0; s4 < 16; ++s4) {   // zeros outside T_i's ko x k block
+                const bool ok = (!TRI || s4 >= 4 * rt) && r0 + lr < ko && 4 * s4 + lk < k;
+                ta[s4] = ok ? ta[s4] : 0.0;
             }
-        }
-        __syncthreads();
-        if (b + 1 < b1) proj_load(in, desc[b + 1], nxt);   // in flight during the products
-        const double *Ti = T + d.row * kmax * kmax, *Tj = Tcol + d.col * kmax * kmax;
-        const int r0 = 16 * wv;
-        if (wv < nto) {
-            const int s0 = TRI ? 4 * wv : 0;   // T_i(rows r0 .., kk) = 0 for kk < r0
-            double ta[16];   // T_i(r0 + lr, 4 s + lk)
+            f64x4 w[4];   // W(r0 + lr, 16 ct + lk + 4 e)
+            // the products with the first K step S0 and the K extent KP (a
+            // multiple of 16) as constants, so that each is straight-line code
+            auto products = [&](auto s0c, auto kpc) {
+                constexpr int S0 = decltype(s0c)::value, KP = decltype(kpc)::value;
 #pragma unroll
-            for (int s4 = 0; s4 < 16; ++s4) {
-                const int kk = 4 * s4 + lk, row = r0 + lr;
-                ta[s4] = (s4 >= s0 && row < ko && kk < k) ? Ti[int64_t(kk) * kmax + row] : 0.0;
-            }
+                for (int ct = 0; ct < KP / 16; ++ct) {
+                    w[ct] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
-                if (ct >= nt) break;   // wave-uniform
-                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int s4 = 0; s4 < 16; ++s4) {
-                    if (4 * s4 >= kp) break;
-                    if (s4 < s0) continue;   // wave-uniform
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[s4], S[(16 * ct + lr) * PS_LD + 4 * s4 + lk], acc, 0,
-                                                               0, 0);
+                    for (int s4 = S0; s4 < KP / 4; ++s4)   // T_i(rows r0 .., kk) = 0 for kk < r0 (TRI)
+                        w[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(S[(16 * ct + lr) * PS_LD + 4 * s4 + lk], ta[s4],
+                                                                     w[ct], 0, 0, 0);
                 }
 #pragma unroll
-                for (int e = 0; e < 4; ++e) Wl[wv][(16 * ct + lr) * 16 + lk + 4 * e] = acc[e];
-            }
-        }
-        __syncthreads();   // S is free from here on: S' goes into it
-        if (wv < nto) {
-            double tb[2][16];   // T_j(16 ct + lr, 4 s + lk), one column tile ahead
-            auto load_tb = [&](int ct, double (&o)[16]) {
-                const int col = 16 * ct + lr;
+                for (int ct = 0; ct < 4; ++ct) {
+                    if (ct >= nto) break;   // wave-uniform
+                    o[ct] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int s4 = 0; s4 < 16; ++s4) {
-                    const int kk = 4 * s4 + lk;
-                    o[s4] = (col < ko && kk < k) ? Tj[int64_t(kk) * kmax + col] : 0.0;
+                    for (int s4 = TRI ? 4 * ct : 0; s4 < KP / 4; ++s4)   // T_j(cols 16 ct .., kk) = 0 for kk < 16 ct
+                        o[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[s4 >> 2][s4 & 3],
+                                                                     Tt[(4 * s4 + lk) * PT_LD + 16 * ct + lr], o[ct],
+                                                                     0, 0, 0);
                 }
             };
-            load_tb(0, tb[0]);
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
-                if (ct >= nto) break;   // unrolled, so the buffer indices are static
-                if (ct + 1 < nto) load_tb(ct + 1, tb[(ct + 1) & 1]);
-                const double(&cur)[16] = tb[ct & 1];
-                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int s4 = 0; s4 < 16; ++s4) {
-                    if (4 * s4 >= kp) break;
-                    if (TRI && s4 < 4 * ct) continue;   // T_j(cols 16 ct .., kk) = 0 for kk < 16 ct
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wl[wv][(4 * s4 + lk) * 16 + lr], cur[s4], acc, 0, 0, 0);
+            using std::integral_constant;
+            auto with_kp = [&](auto kpc) {
+                if constexpr (TRI) {
+                    switch (rt) {
+                    case 0: products(integral_constant<int, 0>{}, kpc); break;
+                    case 1: products(integral_constant<int, 4>{}, kpc); break;
+                    case 2: products(integral_constant<int, 8>{}, kpc); break;
+                    default: products(integral_constant<int, 12>{}, kpc); break;
+                    }
+                } else {
+                    products(integral_constant<int, 0>{}, kpc);
                 }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) S[(16 * ct + lr) * PS_LD + r0 + lk + 4 * e] = acc[e];
+            };
+            switch (nt) {
+            case 4: with_kp(integral_constant<int, 64>{}); break;
+            case 3: with_kp(integral_constant<int, 48>{}); break;
+            case 2: with_kp(integral_constant<int, 32>{}); break;
+            default: with_kp(integral_constant<int, 16>{}); break;
             }
         }
-        __syncthreads();
-        double *blk = outp + d.out;
-        for (int i = threadIdx.x; i < ko * ((ko + 1) >> 1); i += 256) {   // S' as 16-byte items
-            const int g = i / ko, r = i - g * ko;
-            const double hi = 2 * g + 1 < ko ? S[(2 * g + 1) * PS_LD + r] : 0.0;
-            *reinterpret_cast<f64x2 *>(blk + (int64_t(g) * ko + r) * 2) = f64x2{S[(2 * g) * PS_LD + r], hi};
+        if constexpr (NEXT) {
+            load_ta(b + 1);    // ta is free: in flight over the barrier and the staging
+            __syncthreads();   // every wavefront is done with S and T_j
+            stage(b + 1);
         }
-        __syncthreads();   // S is rewritten by the next block
-    }
+        if (rt < nto) {
+            // lanes lr = 2 h and 2 h + 1 hold columns 2 h and 2 h + 1 of rows
+            // r0 + lk + 4 e; the even lane writes the items of rows e = 0, 2,
+            // the odd lane those of e = 1, 3
+            double *blk = outp + d.out;
+            const bool odd = lr & 1;
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                if (ct >= nto) break;
+                const int g = 8 * ct + (lr >> 1);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const double a0 = o[ct][2 * q], a1 = o[ct][2 * q + 1];
+                    const double p0 = __shfl_xor(a0, 1), p1 = __shfl_xor(a1, 1);
+                    const double lo = odd ? p1 : a0, hi = odd ? a1 : p0;
+                    const int row = r0 + lk + 4 * (2 * q + (odd ? 1 : 0));
+                    if (row < ko && 2 * g < ko)
+                        *reinterpret_cast<f64x2 *>(blk + (int64_t(g) * ko + row) * 2) =
+                            f64x2{lo, 2 * g + 1 < ko ? hi : 0.0};
+                }
+            }
+        }
+    };
+    prefetch(b0);
+    load_ta(b0);
+    stage(b0);
+    for (int64_t b = b0; b + 1 < b1; ++b) block(b, std::true_type{});
+    block(b1 - 1, std::false_type{});
 }
 
 }  // namespace

@@ -125,8 +125,9 @@ void orthogonalize(h2_matrix_ &A, hipStream_t st) {
     h2::OrthLaunch L;
     L.basis = static_cast<double *>(A.basis);
     L.blocks = static_cast<double *>(A.blocks);
-    L.T = static_cast<double *>(scratch.alloc(s.nnodes * int64_t(kmax) * kmax * 8));
-    if (!A.symmetric) L.T_col = static_cast<double *>(scratch.alloc(s.nnodes * int64_t(kmax) * kmax * 8));
+    L.T = static_cast<double *>(scratch.alloc((s.nnodes * int64_t(kmax) * kmax + h2::PROJ_T_PAD) * 8));
+    if (!A.symmetric)
+        L.T_col = static_cast<double *>(scratch.alloc((s.nnodes * int64_t(kmax) * kmax + h2::PROJ_T_PAD) * 8));
     L.off_U = scratch.upload(A.off_U, st);
     L.off_VT = scratch.upload(A.off_VT, st);
     L.off_E = scratch.upload(A.off_E, st);
@@ -330,7 +331,7 @@ void compress(h2_matrix_ &A, double eps, hipStream_t st, int *ranks_out) {
             L.col_blk = scratch.upload(col_blk, st);
             L.col_start = scratch.upload(col_start, st);
             L.R = static_cast<double *>(scratch.alloc(tree * 8));
-            L.T = static_cast<double *>(scratch.alloc(tree * 8));
+            L.T = static_cast<double *>(scratch.alloc((tree + h2::PROJ_T_PAD) * 8));
             L.Enew = static_cast<double *>(scratch.alloc(tree * 8));
             L.X = static_cast<double *>(scratch.alloc(maxlevel * h2::COMP_XSLOT * 8));
             L.sigma = static_cast<double *>(scratch.alloc(maxlevel * 64 * 8));
