@@ -296,7 +296,7 @@ __device__ inline void form_z(const CompLaunch &L, int64_t p, int kc, int kt, in
 
 __global__ __launch_bounds__(256) void truncate_level_kernel(CompLaunch L, int l, int kc, int kt, int kp, double eps) {
     __shared__ double A[GEN_LD * QR_MAXN], G[64 * SQ_LD], Y[64 * SQ_LD];
-    __shared__ double tau[QR_MAXN], sgn[QR_MAXN], scal[2], s[64];
+    __shared__ double tau[QR_MAXN], sgn[QR_MAXN], s[64];
     __shared__ int rank[64], flag;
     const int t = threadIdx.x;
     const int64_t i0 = blockIdx.x, p = level_first(l - 1) + i0;
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void truncate_level_kernel(CompLaunch L, int l
     const bool tall = M > kp;
     int n, Lrows;
     if (tall) {   // W = Q R_w: Q in A, R_w in Y, then G = R_w^T (its rows as columns)
-        householder_qr(A, tau, scal, sgn, M, kp, Y, SQ_LD);
+        householder_qr(A, tau, sgn, M, kp, Y, SQ_LD);
         n = kp;
         Lrows = kp;
         for (int i = t; i < kp * kp; i += 256) {

@@ -26,87 +26,137 @@ __device__ inline double sum4(double v) {   // over the 4 threads of a column (c
     return v;
 }
 
-// In-place Householder QR of the M x N matrix A (column-major, ld M + QR_PAD, LDS),
-// M >= N.  R, with its rows' signs flipped so that diag(R) >= 0, goes to T
-// (ld ldt); then A is overwritten by the thin Q (M x N) with the matching
-// columns flipped.  Q is formed in place from the stored reflectors, the last
-// one first (column c of Q is final once reflectors c .. N-1 are applied).
-// Four threads share a column: thread t owns column t / 4 and rows
-// (t % 4) + 4 i, combining partial dot products with lane shuffles.
-__device__ inline void householder_qr(double *A, double *tau, double *scal, double *sgn, int M, int N, double *T,
-                                      int ldt) {
-    const int t = threadIdx.x, col = t >> 2, sub = t & 3, ld = M + QR_PAD;
-    for (int c = 0; c < N; ++c) {
-        if (col == c) {   // norm of A[c:M, c] over the column's four threads, then the reflector
-            double s = 0.0;
-            for (int r = c + sub; r < M; r += 4) s += A[c * ld + r] * A[c * ld + r];
-            s = sum4(s);
-            if (sub == 0) {
-                const double alpha = A[c * ld + c], nrm = sqrt(s);
-                double tc = 0.0, beta = alpha, sc = 0.0;
-                if (nrm > 0.0) {
-                    beta = alpha >= 0.0 ? -nrm : nrm;
-                    tc = (beta - alpha) / beta;
-                    sc = 1.0 / (alpha - beta);
-                }
-                tau[c] = tc;
-                scal[0] = sc;
-                scal[1] = beta;
-            }
-        }
-        __syncthreads();
-        const double sc = scal[0], tc = tau[c];
-        if (col == c) {   // v below the diagonal (v_c = 1 implicit), beta on it
-            for (int r = c + 1 + sub; r < M; r += 4) A[c * ld + r] *= sc;
-            if (sub == 0) A[c * ld + c] = scal[1];
-        }
-        __syncthreads();
-        if (col > c && col < N && tc != 0.0) {   // H_c = I - tau v v^T on the columns to the right
-            double w = sub == 0 ? A[col * ld + c] : 0.0;
-            for (int r = c + 1 + sub; r < M; r += 4) w += A[c * ld + r] * A[col * ld + r];
-            w = sum4(w) * tc;
-            if (sub == 0) A[col * ld + c] -= w;
-            for (int r = c + 1 + sub; r < M; r += 4) A[col * ld + r] -= w * A[c * ld + r];
-        }
-        __syncthreads();
-    }
-    for (int i = t; i < N * N; i += blockDim.x) {   // R with diag(R) >= 0
-        const int c = i / N, r = i - c * N;
-        const double sr = A[r * ld + r] < 0.0 ? -1.0 : 1.0;
-        T[int64_t(c) * ldt + r] = r <= c ? sr * A[c * ld + r] : 0.0;
-    }
-    for (int c = t; c < N; c += blockDim.x) sgn[c] = A[c * ld + c] < 0.0 ? -1.0 : 1.0;
-    __syncthreads();
-    for (int c = N - 1; c >= 0; --c) {
-        const double tc = tau[c];
-        if (col > c && col < N) {   // apply H_c to the finished columns (their rows < col are zero)
-            double w = sub == 0 ? A[col * ld + c] : 0.0;
-            for (int r = c + 1 + sub; r < M; r += 4) w += A[c * ld + r] * A[col * ld + r];
-            w = sum4(w) * tc;
-            if (sub == 0) A[col * ld + c] -= w;
-            for (int r = c + 1 + sub; r < M; r += 4) A[col * ld + r] -= w * A[c * ld + r];
-        }
-        __syncthreads();
-        if (col == c) {   // column c of Q: H_c e_c
-            for (int r = c + 1 + sub; r < M; r += 4) A[c * ld + r] *= -tc;
-            for (int r = sub; r < c; r += 4) A[c * ld + r] = 0.0;
-            if (sub == 0) A[c * ld + c] = 1.0 - tc;
-        }
-        __syncthreads();
-    }
-    for (int i = t; i < M * N; i += blockDim.x) {
-        const int c = i / M, r = i - c * M;
-        A[c * ld + r] *= sgn[c];
-    }
-    __syncthreads();
-}
-
 template <int CTRL>
 __device__ inline double dpp_f64(double x) {   // a DPP move of a double (two 32-bit halves)
     const int64_t b = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double((int64_t(hi) << 32) | uint32_t(lo));
+}
+
+__device__ inline double quad_sum(double v) {   // over lanes 4 j .. 4 j + 3 (all active), by DPP
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    return v + dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+}
+
+// v(rows of this thread) of the reflector stored in column j of A: the LDS
+// reads are all issued before any use, zeros outside rows j .. M - 1.
+template <int MR>
+__device__ __forceinline__ void qr_load_v(const double *A, int j, int ld, int M, int sub, double (&v)[MR]) {
+#pragma unroll
+    for (int i = 0; i < MR; ++i) v[i] = A[j * ld + sub + 4 * i];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < MR; ++i) {
+        const int r = sub + 4 * i;
+        v[i] = (r >= j && r < M) ? v[i] : 0.0;
+    }
+}
+// a -= tau (v . a) v over the column's four threads (four partial sums)
+template <int MR>
+__device__ __forceinline__ void qr_reflect(const double (&v)[MR], double tau, double (&a)[MR]) {
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < MR; ++i) p[i & 3] += v[i] * a[i];
+    const double w = quad_sum((p[0] + p[1]) + (p[2] + p[3])) * tau;
+#pragma unroll
+    for (int i = 0; i < MR; ++i) a[i] -= w * v[i];
+}
+
+// In-place Householder QR of the M x N matrix A (column-major, ld M + QR_PAD,
+// LDS), N <= M <= MAXM, N <= 64, with the whole workgroup (256 threads).  R,
+// with its rows' signs flipped so that diag(R) >= 0, goes to T (ld ldt); then
+// A is overwritten by the thin Q (M x N) with the matching columns flipped.
+//
+// Thread t keeps column t / 4 of the matrix in registers, rows (t % 4) + 4 i
+// (the four threads of a column are consecutive lanes and combine partial
+// sums with lane shuffles), so the only LDS traffic is the reflectors: step
+// c, column c's threads form v_c (v_c(c) = 1) and tau_c and write them over
+// column c of A, one barrier, and every column to the right reads v_c and
+// applies H_c = I - tau_c v_c v_c^T to itself.  Each column of A is written
+// once, so one barrier per step suffices.  Q = H_0 .. H_(N-1) [I; 0] is then
+// formed column by column in registers from the stored reflectors, without
+// barriers (H_j leaves e_c unchanged for c < j).  MAXM bounds the rows a
+// thread reads (rows up to MAXM - 1 of a column, past M only into the LDS
+// array); the caller's array holds (MAXM + QR_PAD) x 64 doubles or more.
+template <int MAXM = QR_MAXM>
+__device__ __forceinline__ void householder_qr(double *A, double *tau, double *sgn, int M, int N, double *T, int ldt) {
+    static_assert(MAXM % 4 == 0 && MAXM <= QR_MAXM, "rows per thread");
+    constexpr int MR = MAXM / 4;
+    const int t = threadIdx.x, col = t >> 2, sub = t & 3, ld = M + QR_PAD;
+    const bool mine = col < N;
+    double a[MR];
+#pragma unroll
+    for (int i = 0; i < MR; ++i) {
+        const int r = sub + 4 * i;
+        a[i] = (mine && r < M) ? A[col * ld + r] : 0.0;
+    }
+    for (int c = 0; c < N; ++c) {
+        if (col == c) {   // the reflector of column c (the four threads of the column)
+            double p[4] = {0.0, 0.0, 0.0, 0.0}, al = 0.0;
+#pragma unroll
+            for (int i = 0; i < MR; ++i) {
+                const int r = sub + 4 * i;
+                p[i & 3] += r >= c ? a[i] * a[i] : 0.0;
+                al = r == c ? a[i] : al;
+            }
+            const double s = quad_sum((p[0] + p[1]) + (p[2] + p[3]));
+            const double alpha = quad_sum(al), nrm = sqrt(s);
+            double tc = 0.0, beta = alpha, sc = 0.0;
+            if (nrm > 0.0) {
+                beta = alpha >= 0.0 ? -nrm : nrm;
+                tc = (beta - alpha) / beta;
+                sc = 1.0 / (alpha - beta);
+            }
+            // v_c over all of this thread's rows, unconditionally: rows past
+            // M land in the next column's rows above its diagonal (or past
+            // column N - 1, inside the array), which nothing reads
+#pragma unroll
+            for (int i = 0; i < MR; ++i) {
+                const int r = sub + 4 * i;
+                A[c * ld + r] = r == c ? 1.0 : a[i] * sc;
+                a[i] = r == c ? beta : a[i];   // R(c, c)
+            }
+            if (sub == 0) {
+                tau[c] = tc;
+                sgn[c] = beta < 0.0 ? -1.0 : 1.0;
+            }
+        }
+        __syncthreads();
+        if (mine && col > c) {   // H_c applied to this column
+            double v[MR];
+            qr_load_v<MR>(A, c, ld, M, sub, v);
+            qr_reflect<MR>(v, tau[c], a);
+        }
+    }
+    // R with diag(R) >= 0 (rows above the diagonal of this column, and R(c, c))
+    if (mine) {
+#pragma unroll
+        for (int i = 0; i < MR; ++i) {
+            const int r = sub + 4 * i;
+            if (r < N) T[int64_t(col) * ldt + r] = r <= col ? sgn[r] * a[i] : 0.0;
+        }
+    }
+    // column col of Q: H_col .. H_0 applied in reverse order to e_col
+    if (mine) {
+#pragma unroll
+        for (int i = 0; i < MR; ++i) a[i] = sub + 4 * i == col ? 1.0 : 0.0;
+        for (int j = col; j >= 0; --j) {
+            double v[MR];
+            qr_load_v<MR>(A, j, ld, M, sub, v);
+            qr_reflect<MR>(v, tau[j], a);
+        }
+    }
+    __syncthreads();   // every reflector read
+    if (mine) {
+        const double sc = sgn[col];
+#pragma unroll
+        for (int i = 0; i < MR; ++i) {
+            const int r = sub + 4 * i;
+            if (r < M) A[col * ld + r] = sc * a[i];
+        }
+    }
+    __syncthreads();
 }
 
 __device__ inline double dpp_sum8(double v) {   // over lanes 8 j .. 8 j + 7 (all active)

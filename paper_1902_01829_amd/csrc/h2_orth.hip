@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void orth_leaf_kernel(double *basis, const int
                                                         const int64_t *out_n, const int64_t *out_t,
                                                         const int64_t *leaf_begin, const int64_t *leaf_end, int kq,
                                                         double *T, int kmax, int64_t first_leaf) {
-    __shared__ double A[(64 + QR_PAD) * QR_MAXN], tau[QR_MAXN], sgn[QR_MAXN], scal[2];
+    __shared__ double A[(64 + QR_PAD) * QR_MAXN], tau[QR_MAXN], sgn[QR_MAXN];
     const int64_t j = blockIdx.x;
     const int M = int(leaf_end[j] - leaf_begin[j]), N = kq;
     const double *B = basis + in[j];
@@ -46,11 +46,14 @@ __global__ __launch_bounds__(256) void orth_leaf_kernel(double *basis, const int
         A[c * ld + r] = IN_T ? B[at2(N, c, r)] : B[at2(M, r, c)];
     }
     __syncthreads();
-    householder_qr(A, tau, scal, sgn, M, N, T + (first_leaf + j) * kmax * kmax, kmax);
+    householder_qr<64>(A, tau, sgn, M, N, T + (first_leaf + j) * kmax * kmax, kmax);
+    // the offsets read once: the stores into basis could alias them for all
+    // the compiler knows, and would each wait for a reload
+    const int64_t on = out_n ? out_n[j] : -1, ot = out_t ? out_t[j] : -1;
     for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
         const int c = i / M, r = i - c * M;
-        if (out_n) basis[out_n[j] + at2(M, r, c)] = A[c * ld + r];   // M x N
-        if (out_t) basis[out_t[j] + at2(N, c, r)] = A[c * ld + r];   // N x M
+        if (on >= 0) basis[on + at2(M, r, c)] = A[c * ld + r];   // M x N
+        if (ot >= 0) basis[ot + at2(N, c, r)] = A[c * ld + r];   // N x M
     }
 }
 
@@ -61,7 +64,7 @@ template <bool IN_T>
 __global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const int64_t *in,
                                                          const int64_t *out_n, const int64_t *out_t, int kc, int kp,
                                                          double *T, int kmax, int64_t first_parent) {
-    __shared__ double A[(QR_MAXM + QR_PAD) * QR_MAXN], tau[QR_MAXN], sgn[QR_MAXN], scal[2];
+    __shared__ double A[(QR_MAXM + QR_PAD) * QR_MAXN], tau[QR_MAXN], sgn[QR_MAXN];
     const int64_t p = first_parent + blockIdx.x;
     const int M = 2 * kc, N = kp, ld = M + QR_PAD;
     // Z = [T_c1 E_c1; T_c2 E_c2] on the FP64 matrix cores (the lane layout of
@@ -109,14 +112,17 @@ __global__ __launch_bounds__(256) void orth_level_kernel(double *basis, const in
         }
     }
     __syncthreads();
-    householder_qr(A, tau, scal, sgn, M, N, T + p * kmax * kmax, kmax);
+    householder_qr(A, tau, sgn, M, N, T + p * kmax * kmax, kmax);
     for (int h = 0; h < 2; ++h) {
         const int64_t ch = 2 * p + 1 + h;
+        // the offsets read once: the stores into basis could alias them for
+        // all the compiler knows, and would each wait for a reload
+        const int64_t on = out_n ? out_n[ch] : -1, ot = out_t ? out_t[ch] : -1;
         for (int i = threadIdx.x; i < kc * kp; i += blockDim.x) {
             const int c = i / kc, r = i - c * kc;
             const double v = A[c * ld + h * kc + r];
-            if (out_n) basis[out_n[ch] + at2(kc, r, c)] = v;   // kc x kp
-            if (out_t) basis[out_t[ch] + at2(kp, c, r)] = v;   // kp x kc
+            if (on >= 0) basis[on + at2(kc, r, c)] = v;   // kc x kp
+            if (ot >= 0) basis[ot + at2(kp, c, r)] = v;   // kp x kc
         }
     }
 }
