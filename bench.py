@@ -331,6 +331,7 @@ def orthogonalize_section(reps=3):
         A.close()
         del x, y0, y1
         torch.cuda.empty_cache()
+        time.sleep(SETTLE_S)
     k, q, lmin = info.rank, info.levels_q, info.lmin
     nleaves, m = 1 << q, w.leaf
     qr = lambda M, N: 4.0 * M * N * N - 4.0 * N ** 3 / 3.0
@@ -360,10 +361,12 @@ def _time_matvec(A, x, y, steps):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-# Seconds waited after releasing a call's matrix before the next timed call
-# of the transpose and compression sections: the HIP runtime's hipMalloc of
-# tens of GB right after freeing as much has taken 0.8-4.6 s (HIP API trace),
-# which is the driver returning the previous allocation, not the call.
+# Seconds waited, outside the timed region, after releasing a matrix (the
+# orthogonalization, compression and transpose sections) and after building
+# the matrix a compression call is timed on: the HIP runtime's hipMalloc of
+# tens of GB right after freeing or allocating as much has taken 0.8-4.6 s
+# (HIP API trace), which is the driver returning the previous allocation,
+# not the call.
 SETTLE_S = 2.0
 
 
@@ -392,6 +395,7 @@ def compress_section(steps=10, reps=3, nrows=256):
                 mv0 = _time_matvec(A, x, y, steps)
                 y0 = y.cpu().numpy()
             torch.cuda.synchronize()
+            time.sleep(SETTLE_S)   # after the construction's allocations, as after a release
             t0 = time.perf_counter()
             ranks = A.compress(eps)   # returns when the device work is done
             ms.append((time.perf_counter() - t0) * 1e3)
