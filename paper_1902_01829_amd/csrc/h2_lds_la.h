@@ -39,18 +39,14 @@ __device__ inline double quad_sum(double v) {   // over lanes 4 j .. 4 j + 3 (al
     return v + dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
 }
 
-// v(rows of this thread) of the reflector stored in column j of A: the LDS
-// reads are all issued before any use, zeros outside rows j .. M - 1.
-template <int MR>
-__device__ __forceinline__ void qr_load_v(const double *A, int j, int ld, int M, int sub, double (&v)[MR]) {
+// v(rows of this thread) of the reflector stored in column j of the
+// reflector array (zeros above row j and past row M - 1 are stored, so the
+// reads need no masks); all LDS reads are issued before any use.
+template <int MR, int LDV>
+__device__ __forceinline__ void qr_load_v(const double *V, int j, int sub, double (&v)[MR]) {
 #pragma unroll
-    for (int i = 0; i < MR; ++i) v[i] = A[j * ld + sub + 4 * i];
+    for (int i = 0; i < MR; ++i) v[i] = V[j * LDV + sub + 4 * i];
     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int i = 0; i < MR; ++i) {
-        const int r = sub + 4 * i;
-        v[i] = (r >= j && r < M) ? v[i] : 0.0;
-    }
 }
 // a -= tau (v . a) v over the column's four threads (four partial sums)
 template <int MR>
@@ -70,35 +66,43 @@ __device__ __forceinline__ void qr_reflect(const double (&v)[MR], double tau, do
 //
 // Thread t keeps column t / 4 of the matrix in registers, rows (t % 4) + 4 i
 // (the four threads of a column are consecutive lanes and combine partial
-// sums with lane shuffles), so the only LDS traffic is the reflectors: step
-// c, column c's threads form v_c (v_c(c) = 1) and tau_c and write them over
-// column c of A, one barrier, and every column to the right reads v_c and
-// applies H_c = I - tau_c v_c v_c^T to itself.  Each column of A is written
-// once, so one barrier per step suffices.  Q = H_0 .. H_(N-1) [I; 0] is then
-// formed column by column in registers from the stored reflectors, without
-// barriers (H_j leaves e_c unchanged for c < j).  MAXM bounds the rows a
-// thread reads (rows up to MAXM - 1 of a column, past M only into the LDS
-// array); the caller's array holds (MAXM + QR_PAD) x 64 doubles or more.
+// sums by DPP), so the only LDS traffic is the reflectors: step c, column
+// c's threads form v_c (v_c(c) = 1) and tau_c and store v_c whole (zeros
+// above row c and past row M - 1) in the array's space, now laid out with
+// leading dimension MAXM + QR_PAD; one barrier; every column to the right
+// reads v_c and applies H_c = I - tau_c v_c v_c^T to itself.  Each stored
+// column is written once, so one barrier per step suffices.  Q = H_0 ..
+// H_(N-1) [I; 0] is then formed column by column in registers from the
+// stored reflectors, without barriers (H_j leaves e_c unchanged for c < j).
+// The caller's array holds (MAXM + QR_PAD) x 64 doubles or more.  The step
+// of column c is serial (one wavefront's four lanes), so it is kept short:
+// no masks on rows past M, R(c, c) in a register of its own.
 template <int MAXM = QR_MAXM>
 __device__ __forceinline__ void householder_qr(double *A, double *tau, double *sgn, int M, int N, double *T, int ldt) {
     static_assert(MAXM % 4 == 0 && MAXM <= QR_MAXM, "rows per thread");
-    constexpr int MR = MAXM / 4;
+    constexpr int MR = MAXM / 4, LDV = MAXM + QR_PAD;
     const int t = threadIdx.x, col = t >> 2, sub = t & 3, ld = M + QR_PAD;
     const bool mine = col < N;
     double a[MR];
 #pragma unroll
     for (int i = 0; i < MR; ++i) {
         const int r = sub + 4 * i;
-        a[i] = (mine && r < M) ? A[col * ld + r] : 0.0;
+        a[i] = (mine && r < M) ? A[col * ld + r] : 0.0;   // rows past M stay zero throughout
     }
+    __syncthreads();   // A's space holds reflectors (leading dimension LDV) from here on
+    double rcc = 0.0;  // R(col, col)
     for (int c = 0; c < N; ++c) {
         if (col == c) {   // the reflector of column c (the four threads of the column)
+            // (cu: c as a value the compiler cannot equate with col, or it
+            // hoists every row's mask out of the loop and spills them)
+            const int cu = __builtin_amdgcn_readfirstlane(c);
             double p[4] = {0.0, 0.0, 0.0, 0.0}, al = 0.0;
 #pragma unroll
             for (int i = 0; i < MR; ++i) {
                 const int r = sub + 4 * i;
-                p[i & 3] += r >= c ? a[i] * a[i] : 0.0;
-                al = r == c ? a[i] : al;
+                const double x = r >= cu ? a[i] : 0.0;
+                p[i & 3] += x * x;
+                al = r == cu ? a[i] : al;
             }
             const double s = quad_sum((p[0] + p[1]) + (p[2] + p[3]));
             const double alpha = quad_sum(al), nrm = sqrt(s);
@@ -108,15 +112,12 @@ __device__ __forceinline__ void householder_qr(double *A, double *tau, double *s
                 tc = (beta - alpha) / beta;
                 sc = 1.0 / (alpha - beta);
             }
-            // v_c over all of this thread's rows, unconditionally: rows past
-            // M land in the next column's rows above its diagonal (or past
-            // column N - 1, inside the array), which nothing reads
 #pragma unroll
             for (int i = 0; i < MR; ++i) {
                 const int r = sub + 4 * i;
-                A[c * ld + r] = r == c ? 1.0 : a[i] * sc;
-                a[i] = r == c ? beta : a[i];   // R(c, c)
+                A[cu * LDV + r] = r > cu ? a[i] * sc : (r == cu ? 1.0 : 0.0);
             }
+            rcc = beta;
             if (sub == 0) {
                 tau[c] = tc;
                 sgn[c] = beta < 0.0 ? -1.0 : 1.0;
@@ -125,16 +126,17 @@ __device__ __forceinline__ void householder_qr(double *A, double *tau, double *s
         __syncthreads();
         if (mine && col > c) {   // H_c applied to this column
             double v[MR];
-            qr_load_v<MR>(A, c, ld, M, sub, v);
+            qr_load_v<MR, LDV>(A, c, sub, v);
             qr_reflect<MR>(v, tau[c], a);
         }
     }
-    // R with diag(R) >= 0 (rows above the diagonal of this column, and R(c, c))
+    // R with diag(R) >= 0: rows above the diagonal of this column (final
+    // since their steps) and R(col, col)
     if (mine) {
 #pragma unroll
         for (int i = 0; i < MR; ++i) {
             const int r = sub + 4 * i;
-            if (r < N) T[int64_t(col) * ldt + r] = r <= col ? sgn[r] * a[i] : 0.0;
+            if (r < N) T[int64_t(col) * ldt + r] = r < col ? sgn[r] * a[i] : (r == col ? sgn[col] * rcc : 0.0);
         }
     }
     // column col of Q: H_col .. H_0 applied in reverse order to e_col
@@ -143,7 +145,7 @@ __device__ __forceinline__ void householder_qr(double *A, double *tau, double *s
         for (int i = 0; i < MR; ++i) a[i] = sub + 4 * i == col ? 1.0 : 0.0;
         for (int j = col; j >= 0; --j) {
             double v[MR];
-            qr_load_v<MR>(A, j, ld, M, sub, v);
+            qr_load_v<MR, LDV>(A, j, sub, v);
             qr_reflect<MR>(v, tau[j], a);
         }
     }
